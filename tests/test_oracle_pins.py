@@ -1,0 +1,418 @@
+"""Pins of the CPU oracle against brute force, dense linear algebra, closed
+forms and the paper's worked example (no GPU needed)."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from tests import _brute as B
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    out = {}
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *v = line.split()
+            out[k] = [float(t) for t in v]
+    return out
+
+
+def _mk(O_mod, A, **kw):
+    S = sp.csr_matrix(A)
+    S.sort_indices()
+    return O_mod.Oracle(S.indptr, S.indices, S.data, **kw)
+
+
+# ---------------------------------------------------------------- aggregation
+def test_counter_example_restriction(oracle_mod):
+    """Section 2.1 worked example: G1={1,3}, G2={2,4}; printed P^T; P^T x = 0."""
+    g = _read_golden("counter_example_n4.txt")
+    n = int(g["N"][0])
+    agg = np.array(g["agg"], dtype=np.int32)
+    A = 4 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)          # SPD
+    O = _mk(oracle_mod, A, agg=agg)
+    aptr, amem = O.members()
+    PT = np.zeros((O.nc, n))
+    for I in range(O.nc):
+        PT[I, amem[aptr[I]:aptr[I + 1]]] = 1.0
+    assert np.array_equal(PT, np.array([g["PT_row0"], g["PT_row1"]]))
+    x = np.array(g["x"])
+    assert np.array_equal(PT @ x, np.array(g["PTx"]))
+    # A_c = P^T A P stays SPD (Theorem: A > 0 implies A_c > 0) ...
+    rp, ci, cv = O.coarse()
+    Ac = B.dense(rp, ci, cv, O.nc)
+    np.linalg.cholesky(Ac)
+    # ... while M = P A_c P^T is singular on x (the theorem's point)
+    P = PT.T
+    assert abs(x @ (P @ Ac @ P.T) @ x) == 0.0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_handshake_equals_greedy_and_is_maximal(oracle_mod, seed):
+    """One handshake pass == sequential greedy matching by descending key
+    (locally dominant edges), and it is a valid maximal matching."""
+    rng = np.random.default_rng(seed)
+    nv = int(rng.integers(2, 200))
+    dens = float(rng.uniform(0.01, 0.2))
+    M = rng.random((nv, nv)) < dens
+    M = np.triu(M, 1)
+    kind = seed % 4
+    if kind == 0:
+        W_ = rng.uniform(0.1, 10.0, size=(nv, nv))
+    elif kind == 1:      # many exact ties: hash decides
+        W_ = rng.integers(1, 3, size=(nv, nv)).astype(float)
+    elif kind == 2:      # a path with increasing weights: long chains
+        M = np.eye(nv, k=1, dtype=bool)
+        W_ = np.tile(np.arange(nv, dtype=float) + 1.0, (nv, 1))
+    else:                # weights within one quantisation bin: hash decides
+        W_ = 1.0 + 1e-3 * rng.random((nv, nv))
+    Wm = np.where(M, W_, 0.0)
+    Wm = Wm + Wm.T
+    S = sp.csr_matrix(Wm)
+    S.sort_indices()
+    for qbits in (4, 52):
+        mate, rounds = oracle_mod.match_once(S.indptr, S.indices, S.data, qbits=qbits)
+        edges = B.dict_graph(S.indptr, S.indices, S.data)
+        seedv = oracle_mod.default_options()["seed"]
+        ref = B.greedy_matching(nv, edges, qbits, seedv)
+        assert list(mate) == ref
+        for v in range(nv):
+            if mate[v] >= 0:
+                assert mate[mate[v]] == v and (v, int(mate[v])) in edges
+        assert B.is_maximal(nv, edges, list(mate))
+
+
+@pytest.mark.parametrize("case", ["fv2d_16", "fv3d_6", "rand_mm", "rand_int"])
+def test_multipass_aggregation_matches_reference(oracle_mod, case):
+    """The full multi-pass aggregation equals iterated greedy matching on
+    aggregate graphs built from the fine graph (brute force)."""
+    rng = np.random.default_rng(7)
+    if case == "fv2d_16":
+        p = W.scaled("fv2d", 16)
+        rp, ci, v = p.rowptr, p.col, p.val
+    elif case == "fv3d_6":
+        p = W.fv_problem(6, 3, 1, -6, 6, W.velocity_const((1, 1, 1)), 3)
+        rp, ci, v = p.rowptr, p.col, p.val
+    elif case == "rand_mm":
+        rp, ci, v, _ = B.random_mmatrix(150, rng, 0.05)
+    else:
+        rp, ci, v, _ = B.random_mmatrix(120, rng, 0.06, integer=True)
+    opts = oracle_mod.default_options()
+    for cf in (2.0, 4.0, 8.0):
+        O = oracle_mod.Oracle(rp, ci, v, cf=cf)
+        ref, passes = B.multipass_aggregation(rp, ci, v, cf, opts["max_passes"], opts["qbits"],
+                                              opts["seed"])
+        agg = O.aggregates()
+        assert np.array_equal(agg, ref)
+        assert O.passes == passes
+        # P: one 1 per row (P 1 = 1), columns non-empty, ids ordered by first member
+        assert agg.min() == 0 and agg.max() == O.nc - 1
+        firsts = [np.flatnonzero(agg == I)[0] for I in range(O.nc)]
+        assert np.all(np.diff(firsts) > 0)
+        aptr, amem = O.members()
+        assert np.array_equal(np.diff(aptr), np.bincount(agg, minlength=O.nc))
+
+
+# ------------------------------------------------------------------ galerkin
+@pytest.mark.parametrize("integer", [True, False])
+def test_galerkin_equals_dense_PtAP(oracle_mod, integer):
+    rng = np.random.default_rng(3 + integer)
+    rp, ci, v, A = B.random_mmatrix(160, rng, 0.05, integer=integer)
+    O = oracle_mod.Oracle(rp, ci, v, cf=3.0)
+    P = B.prolongation(O.aggregates(), O.nc)
+    Ac_dense = P.T @ A @ P
+    crp, cci, cv = O.coarse()
+    Ac = B.dense(crp, cci, cv, O.nc)
+    if integer:
+        assert np.array_equal(Ac, Ac_dense)          # exact sums of integers
+    else:
+        assert np.max(np.abs(Ac - Ac_dense)) <= 1e-15 * np.max(np.abs(Ac_dense)) * 8
+    # pattern: (I,J) stored iff some a_kl with k in G_I, l in G_J is stored
+    Pat = (P.T @ (A != 0).astype(float) @ P) != 0
+    assert np.array_equal(Pat, Ac != 0 if integer else Pat)
+    S = sp.csr_matrix((np.ones_like(cv), cci, crp), shape=(O.nc, O.nc)).toarray() != 0
+    assert np.array_equal(S, Pat)
+    # M-matrix preserved (Theorem Th:Mprop): positive diagonal, non-positive off-diagonal,
+    # diagonally dominant rows
+    d = np.diag(Ac)
+    off = Ac - np.diag(d)
+    assert np.all(d > 0) and np.all(off <= 0)
+    assert np.all(d >= np.abs(off).sum(axis=1) * (1 - 1e-14))
+
+
+def test_galerkin_spd(oracle_mod):
+    """A SPD implies A_c SPD (Section 2.1)."""
+    rng = np.random.default_rng(11)
+    rp, ci, v, A = B.random_mmatrix(140, rng, 0.05, sym=True)
+    np.linalg.cholesky(A)
+    O = oracle_mod.Oracle(rp, ci, v, cf=4.0)
+    crp, cci, cv = O.coarse()
+    Ac = B.dense(crp, cci, cv, O.nc)
+    # symmetric up to the summation order of the two mirrored double sums
+    assert np.abs(Ac - Ac.T).max() <= 1e-14 * np.abs(Ac).max()
+    np.linalg.cholesky(0.5 * (Ac + Ac.T))
+
+
+# ------------------------------------------------------------------ ILU(0)
+@pytest.mark.parametrize("case", ["fv2d", "rand"])
+def test_ilu0_reproduces_A_on_pattern(oracle_mod, case):
+    if case == "fv2d":
+        p = W.scaled("fv2d", 24)
+        rp, ci, v = p.rowptr, p.col, p.val
+        A = B.dense(rp, ci, v)
+    else:
+        rp, ci, v, A = B.random_mmatrix(120, np.random.default_rng(5), 0.08)
+    O = oracle_mod.Oracle(rp, ci, v)
+    F = B.dense(rp, ci, O.ilu0())
+    n = A.shape[0]
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    mask = A != 0
+    # pattern of the factors is pattern(A)
+    assert np.all((F != 0) <= mask)
+    err = np.abs((L @ U - A)[mask]).max() / np.abs(A).max()
+    assert err < 1e-14
+
+
+def test_ilu0_tridiagonal_is_exact_lu(oracle_mod):
+    n = 50
+    rng = np.random.default_rng(2)
+    A = np.diag(rng.uniform(3, 4, n)) - np.diag(rng.uniform(0.1, 1, n - 1), 1) \
+        - np.diag(rng.uniform(0.1, 1, n - 1), -1)
+    O = _mk(oracle_mod, A)
+    S = sp.csr_matrix(A)
+    F = B.dense(S.indptr, S.indices, O.ilu0())
+    L, U = B.lu_nopivot(A)
+    assert np.allclose(np.tril(F, -1) + np.eye(n), L, rtol=1e-14, atol=1e-15)
+    assert np.allclose(np.triu(F), U, rtol=1e-14, atol=1e-15)
+
+
+# ------------------------------------------------------------------ ILUT
+def _ilut_dense(O):
+    (lrp, lci, lv), (urp, uci, uv) = O.ilut()
+    nc = O.nc
+    L = B.dense(lrp, lci, lv, nc) + np.eye(nc)
+    U = B.dense(urp, uci, uv, nc)
+    return L, U
+
+
+def test_ilut_tau0_is_dense_lu(oracle_mod):
+    p = W.scaled("fv2d", 16)
+    O = oracle_mod.Oracle(p.rowptr, p.col, p.val, ilut_tau=0.0)
+    crp, cci, cv = O.coarse()
+    Ac = B.dense(crp, cci, cv, O.nc)
+    L, U = _ilut_dense(O)
+    Lr, Ur = B.lu_nopivot(Ac)
+    assert np.allclose(L, Lr, rtol=1e-12, atol=1e-14)
+    assert np.allclose(U, Ur, rtol=1e-12, atol=1e-12 * np.abs(Ur).max())
+
+
+def test_ilut_huge_tau_is_diagonal(oracle_mod):
+    p = W.scaled("fv2d", 16)
+    O = oracle_mod.Oracle(p.rowptr, p.col, p.val, ilut_tau=1e300)
+    crp, cci, cv = O.coarse()
+    Ac = B.dense(crp, cci, cv, O.nc)
+    L, U = _ilut_dense(O)
+    assert np.array_equal(L, np.eye(O.nc))
+    assert np.array_equal(U, np.diag(np.diag(Ac)))
+
+
+def test_ilut_nnz_monotone_and_error_magnitude(oracle_mod):
+    """Fill shrinks as tau grows; on the DC1 3D problem at h = 1/30 the
+    ILUT(1e-4) factor error has the paper's magnitude (Table T:norm)."""
+    n = 30
+    kap = W.dc1_kappa(n, 3)
+    rp, ci, v = W.fv_matrix(n, 3, kap, None)
+    g = _read_golden("ilut_factor_error_jump3d.txt")
+    prev = None
+    for tau in (0.0, 1e-6, 1e-4, 1e-2):
+        O = oracle_mod.Oracle(rp, ci, v, ilut_tau=tau, cf=4.0)
+        nz = O.nnz_lc + O.nnz_uc
+        if prev is not None:
+            assert nz <= prev
+        prev = nz
+        if tau == 1e-4:
+            crp, cci, cv = O.coarse()
+            Ac = sp.csr_matrix((cv, cci, crp), shape=(O.nc, O.nc))
+            (lrp, lci, lv), (urp, uci, uv) = O.ilut()
+            L = sp.csr_matrix((lv, lci, lrp), shape=(O.nc, O.nc)) + sp.identity(O.nc)
+            U = sp.csr_matrix((uv, uci, urp), shape=(O.nc, O.nc))
+            err = sp.linalg.norm(L @ U - Ac) / sp.linalg.norm(Ac)
+            paper = g["rel_err_NO"][0]
+            assert paper / 10 < err < paper * 10, err
+
+
+# ------------------------------------------------------------ preconditioner
+def _dense_parts(O, rp, ci, v):
+    n = O.n
+    A = B.dense(rp, ci, v)
+    F = B.dense(rp, ci, O.ilu0())
+    S = (np.tril(F, -1) + np.eye(n)) @ np.triu(F)
+    L, U = _ilut_dense(O)
+    P = B.prolongation(O.aggregates(), O.nc)
+    Mi = P @ np.linalg.inv(L @ U) @ P.T
+    Si = np.linalg.inv(S)
+    return A, S, Si, Mi, P
+
+
+@pytest.mark.parametrize("case", ["fv2d", "rgg"])
+def test_preconditioner_matches_dense_twogrid(oracle_mod, case):
+    """Apply == dense B~^{-1} = S^{-1} + M~^{-1} - M~^{-1} A S^{-1} (Eq. (twogrid),
+    Algorithm 1); the two-solve form agrees; the error propagator factors as
+    (I - M~^{-1} A)(I - S^{-1} A); the adjoint apply is the exact transpose."""
+    if case == "fv2d":
+        p = W.scaled("fv2d", 20)
+    else:
+        p = W.scaled("rgg", 400)
+    rp, ci, v = p.rowptr, p.col, p.val
+    O = oracle_mod.Oracle(rp, ci, v)
+    A, S, Si, Mi, P = _dense_parts(O, rp, ci, v)
+    Binv = Si + Mi - Mi @ A @ Si
+    rng = np.random.default_rng(0)
+    Z = rng.standard_normal((O.n, 4))
+    for z in Z.T:
+        ref = Binv @ z
+        sc = np.abs(ref).max()
+        assert np.abs(O.apply(z) - ref).max() <= 1e-11 * sc
+        assert np.abs(O.apply_twosolve(z) - ref).max() <= 1e-11 * sc
+        reft = Binv.T @ z
+        assert np.abs(O.apply_adjoint(z) - reft).max() <= 1e-11 * np.abs(reft).max()
+    I = np.eye(O.n)
+    E = I - Binv @ A
+    E2 = (I - Mi @ A) @ (I - Si @ A)
+    assert np.abs(E - E2).max() <= 1e-9 * max(1.0, np.abs(E).max())
+    # coarse correction annihilates the coarse space when exact: (I - P Ac^-1 P^T A) P = 0
+    crp, cci, cv = O.coarse()
+    Ac = B.dense(crp, cci, cv, O.nc)
+    assert np.abs((I - P @ np.linalg.inv(Ac) @ P.T @ A) @ P).max() < 1e-9
+
+
+def test_preconditioner_fp32_close_to_fp64(oracle_mod):
+    p = W.scaled("fv2d", 32)
+    O = oracle_mod.Oracle(p.rowptr, p.col, p.val)
+    z = np.random.default_rng(1).uniform(-1, 1, O.n)
+    q64 = O.apply(z, 0)
+    q32 = O.apply(z, 1)
+    rel = np.linalg.norm(q32 - q64) / np.linalg.norm(q64)
+    assert 0 < rel < 1e-3
+
+
+def test_coarse_jacobi_mode_converges_to_exact(oracle_mod):
+    """Jacobi sweeps on a triangular factor are exact after (levels) sweeps."""
+    p = W.scaled("fv2d", 12)
+    O0 = oracle_mod.Oracle(p.rowptr, p.col, p.val)
+    O1 = oracle_mod.Oracle(p.rowptr, p.col, p.val, coarse_mode=1, coarse_sweeps=O0.nc)
+    z = np.random.default_rng(4).standard_normal(O0.n)
+    a, b = O0.apply(z), O1.apply(z)
+    assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
+
+
+# -------------------------------------------------------------------- FGMRES
+@pytest.mark.parametrize("case", ["fv2d_64", "rgg_1500", "fv3d_10"])
+def test_solve_matches_dense_solution(oracle_mod, case):
+    if case == "fv2d_64":
+        p = W.make("fv2d_64")
+    elif case == "rgg_1500":
+        p = W.scaled("rgg", 1500)
+    else:
+        p = W.scaled("fv3d", 12)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr))
+    b = p.b[:, 0]
+    O = oracle_mod.Oracle(p.rowptr, p.col, p.val)
+    tol = 1e-8
+    x, info = O.solve(b, tol=tol)
+    assert info.status == oracle_mod.OK
+    r = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert r < tol and abs(r - info.relres) <= 1e-12
+    xd = sp.linalg.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(A @ (x - xd)) / np.linalg.norm(b) <= tol * 1.01
+    lam, info2 = O.solve(b, tol=tol, adjoint=True)
+    assert info2.status == oracle_mod.OK
+    assert np.linalg.norm(b - A.T @ lam) / np.linalg.norm(b) < tol
+
+
+def test_fgmres_iterate_is_least_squares_minimiser(oracle_mod):
+    """x_j minimises ||b - A x|| over x0 + span(Z_j) (one cycle, tiny N);
+    residual estimates are non-increasing and equal the true residual."""
+    p = W.scaled("fv2d", 10)
+    A = B.dense(p.rowptr, p.col, p.val)
+    b = p.b[:, 0]
+    O = oracle_mod.Oracle(p.rowptr, p.col, p.val)
+    for j in (1, 3, 7):
+        x, info, ex = O.solve(b, tol=0.0, maxit=j, restart=30, zdump=True, history=True)
+        Z = ex["Z"][:j].T
+        y, *_ = np.linalg.lstsq(A @ Z, b, rcond=None)
+        xls = Z @ y
+        assert np.linalg.norm(A @ (x - xls)) <= 1e-10 * np.linalg.norm(b)
+        h = ex["history"]
+        assert np.all(np.diff(h) <= 1e-15)
+        assert abs(h[-1] - np.linalg.norm(b - A @ x) / np.linalg.norm(b)) < 1e-10
+
+
+def test_fgmres_exact_preconditioner_one_step(oracle_mod):
+    """B~^{-1} = A^{-1} in two special cases, so one step converges:
+    (i) tridiagonal A (ILU(0) is exact LU); (ii) P = I with ILUT(0)."""
+    n = 60
+    rng = np.random.default_rng(8)
+    A = np.diag(rng.uniform(3, 4, n)) - np.diag(rng.uniform(0.1, 1, n - 1), 1) \
+        - np.diag(rng.uniform(0.1, 1, n - 1), -1)
+    b = rng.uniform(-1, 1, n)
+    O = _mk(oracle_mod, A)
+    x, info = O.solve(b, tol=1e-12)
+    assert info.steps == 1 and info.status == 0
+    p = W.scaled("rgg", 300)
+    O2 = oracle_mod.Oracle(p.rowptr, p.col, p.val, agg=np.arange(300, dtype=np.int32), ilut_tau=0.0)
+    x, info = O2.solve(p.b[:, 0], tol=1e-12)
+    assert info.steps == 1 and info.status == 0
+
+
+def test_fgmres_full_space_converges(oracle_mod):
+    """With restart >= N, GMRES reaches the exact solution in <= N steps."""
+    rp, ci, v, A = B.random_mmatrix(40, np.random.default_rng(9), 0.1)
+    O = oracle_mod.Oracle(rp, ci, v, ilut_tau=1e30)     # weak coarse solve
+    b = np.random.default_rng(10).uniform(-1, 1, 40)
+    x, info = O.solve(b, tol=1e-13, restart=40, maxit=40)
+    assert info.steps <= 40 and info.status == 0
+
+
+def test_fgmres_fp32_preconditioner_converges(oracle_mod):
+    p = W.make("fv2d_64")
+    A = sp.csr_matrix((p.val, p.col, p.rowptr))
+    b = p.b[:, 0]
+    O = oracle_mod.Oracle(p.rowptr, p.col, p.val)
+    x64, _ = O.solve(b)
+    x32, info = O.solve(b, precision=1)
+    assert info.status == 0
+    assert np.linalg.norm(b - A @ x32) / np.linalg.norm(b) < 1e-8
+    assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) < 1e-5
+
+
+def test_error_codes(oracle_mod):
+    # zero pivot: a 2x2 matrix with a zero leading entry (pivoting would be needed)
+    A = np.array([[0.0, 1.0], [1.0, 1.0]])
+    with pytest.raises(oracle_mod.OracleError) as e:
+        _mk(oracle_mod, A, agg=np.array([0, 1], dtype=np.int32))
+    assert e.value.code in (oracle_mod.ERR_ZERO_PIVOT, oracle_mod.ERR_INVALID)
+    # missing diagonal
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.Oracle(rp, np.array([1, 0], dtype=np.int32), np.array([1.0, 1.0]))
+    # non-finite entry
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.Oracle(np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32),
+                          np.array([np.nan]))
+    assert e.value.code == oracle_mod.ERR_NONFINITE
+    # not converged within maxit
+    p = W.scaled("fv2d", 16)
+    O = oracle_mod.Oracle(p.rowptr, p.col, p.val)
+    _, info = O.solve(p.b[:, 0], tol=1e-12, maxit=2)
+    assert info.status == oracle_mod.NOT_CONVERGED and info.steps == 2
