@@ -1,0 +1,197 @@
+/*
+ * gmg.h -- C ABI of the MI355X two-grid matching-aggregation AMG solver.
+ *
+ * The library solves A x = b, A in R^{N x N} sparse, x, b in R^N (the paper's
+ * statement of the problem, Eq. (system) and the caption of Algorithm 1) with
+ * flexible GMRES(m) right-preconditioned by the two-grid operator B~ of
+ * Eq. (twogrid) / Algorithm 1:
+ *   - aggregates G_i from deterministic multi-pass handshake graph matching
+ *     (the paper calls a graph partitioner; Section 2, "Aggregation based on
+ *     graph matching"), boolean prolongation P (Eq. (interp), Eq. (aggr));
+ *   - Galerkin coarse matrix A_c = P^T A P (Eq. (E:galerkin));
+ *   - smoother S = L0 U0 = ILU(0)(A), one application, no post-smoothing
+ *     (Section 2, the paragraph defining S and Eq. (twogrid));
+ *   - inexact coarse solve with ILUT(tau) factors of A_c (Section 2, the
+ *     ILU(t) paragraph; Algorithm 1 "SOLVE M~g=h").
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers (HIP device memory, e.g. torch CUDA
+ *     tensors on ROCm) unless the parameter says "host".  The caller keeps
+ *     ownership; the library never frees caller memory.
+ *   - CSR matrices use int32 row pointers and column indices and float64
+ *     values; columns strictly ascending within each row; every row stores its
+ *     diagonal.  Violations return GMG_ERR_INVALID_ARG, non-finite values
+ *     GMG_ERR_NONFINITE.
+ *   - Multi-vector arguments (b, x, g, lambda) are (N, nrhs) row-major.
+ *   - All device work is enqueued on the stream given to gmg_setup (or set with
+ *     gmg_set_stream).  Entry points return after their results are complete on
+ *     that stream.  A handle must not be used from two threads at once.
+ *   - Every function returns a gmg_status; on an error gmg_last_error() gives a
+ *     thread-local message.  A status > 0 is a warning whose outputs are valid.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmg_solver* gmg_handle;
+
+typedef enum {
+  GMG_OK = 0,
+  GMG_NOT_CONVERGED = 1,     /* maxit reached; the best iterate is returned (the paper's NC) */
+  GMG_ERR_INVALID_ARG = -1,
+  GMG_ERR_HIP = -2,          /* a HIP runtime call failed                               */
+  GMG_ERR_OOM = -3,          /* device or host allocation failed (the paper's ME)       */
+  GMG_ERR_ZERO_PIVOT = -4,   /* ILU(0) or ILUT met a zero pivot                         */
+  GMG_ERR_BREAKDOWN = -5,    /* Givens rotation with a zero column                      */
+  GMG_ERR_NONFINITE = -6,    /* NaN/Inf in an input or in a residual                    */
+  GMG_ERR_NOT_SETUP = -7,
+  GMG_ERR_STALLED = -8       /* a dependency wait in a triangular sweep exceeded its
+                                time limit (internal error; results are invalid)        */
+} gmg_status;
+
+typedef struct {
+  double cf;            /* coarsening factor N / N_c: matching passes stop once
+                           N_c <= floor(N / cf) (default 4)                          */
+  int max_passes;       /* matching passes at most (default 8)                       */
+  int match_qbits;      /* mantissa bits of an edge weight kept in the matching key;
+                           ties inside a bin are broken by a hash (default 4; 52 =
+                           exact weights)                                             */
+  uint64_t hash_seed;   /* seed of that hash                                         */
+  double ilut_tau;      /* ILUT drop tolerance relative to the row 2-norm (1e-4)     */
+  int coarse_mode;      /* 0: exact triangular sweeps with the ILUT factors;
+                           1: coarse_sweeps Jacobi sweeps per factor                 */
+  int coarse_sweeps;    /* (default 3)                                               */
+  int restart;          /* FGMRES restart length m (default 30, at most 64)          */
+  int maxit;            /* total FGMRES steps at most (default 600)                  */
+  int precond_fp32;     /* 1: the whole preconditioner runs in FP32 on FP32 copies of
+                           A and of the factors; the Krylov part stays FP64          */
+  int x0_given;         /* 1: x holds the initial guess on entry, else x0 = 0         */
+  int sweep_waves;      /* resident waves of the triangular-sweep kernels (0: auto)  */
+} gmg_options;
+
+typedef struct {
+  int iters;            /* FGMRES steps of the last solve (summed over RHS)           */
+  int restarts;
+  int converged;        /* number of right-hand sides that reached tol               */
+  int passes;           /* matching passes                                           */
+  int rounds;           /* handshake rounds, summed over passes                      */
+  int levels_L0, levels_U0, levels_Lc, levels_Uc;  /* dependency depths of the sweeps */
+  int64_t n, nnz, n_coarse, nnz_coarse, nnz_lc, nnz_uc;
+  double relres_true;   /* max over RHS of ||b - A x|| / ||b|| after the solve       */
+  double relres_est;    /* FGMRES estimate at exit                                   */
+  double setup_ms, solve_ms;
+} gmg_info;
+
+/* Fill *opts with the defaults listed above. */
+void gmg_default_options(gmg_options* opts);
+
+/* Setup phase of Algorithm 1: copies A (device CSR, n rows, nnz entries) into
+ * library memory, builds the aggregates, A_c, ILU(0)(A), ILUT(A_c) and the
+ * schedules of the triangular sweeps.  `stream` is a hipStream_t (NULL = the
+ * default stream).  On success *h owns all library memory; free it with
+ * gmg_destroy.  The caller may free A after return. */
+gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowptr,
+                     const int32_t* col, const double* val, const gmg_options* opts,
+                     void* stream);
+
+/* Solve A x = b to ||b - A x|| / ||b|| < tol for each of nrhs columns
+ * (device arrays of N*nrhs doubles, row-major).  Uses the options given to
+ * gmg_setup, except x0_given/maxit/restart/precond_fp32, taken from `opts`
+ * when it is not NULL.  `info` (host, may be NULL) receives statistics. */
+gmg_status gmg_solve(gmg_handle h, const double* b, double* x, int nrhs, double tol,
+                     const gmg_options* opts, gmg_info* info);
+
+/* Adjoint solve A^T lambda = g, preconditioned by B~^{-T} (the exact transpose
+ * of the two-grid operator: coarse correction with the transposed ILUT
+ * factors, residual with A^T, transposed ILU(0) sweeps).  Requires
+ * coarse_mode 0 and FP64. */
+gmg_status gmg_solve_adjoint(gmg_handle h, const double* g, double* lambda, int nrhs,
+                             double tol, const gmg_options* opts, gmg_info* info);
+
+/* One application q = B~^{-1} z (adjoint: q = B~^{-T} z) of the preconditioner
+ * (device vectors of N doubles).  precision 0: FP64; 1: FP32 internally. */
+gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int precision,
+                             int adjoint);
+
+/* y = A x (transposed != 0: y = A^T x), device vectors of N doubles. */
+gmg_status gmg_spmv(gmg_handle h, int transposed, const double* x, double* y);
+
+/* Setup statistics (sizes, passes, levels, setup time) into *info (host). */
+gmg_status gmg_get_info(gmg_handle h, gmg_info* info);
+
+/* Aggregate of every fine unknown: agg device int32[N]; ids 0..N_c-1 ordered
+ * by each aggregate's smallest fine index. */
+gmg_status gmg_get_aggregates(gmg_handle h, int32_t* agg);
+
+/* A_c as CSR into device arrays rowptr[N_c+1], col[nnz_coarse], val[nnz_coarse]. */
+gmg_status gmg_get_coarse(gmg_handle h, int32_t* rowptr, int32_t* col, double* val);
+
+/* ILU(0) factors as values on A's pattern (device double[nnz]): the strictly
+ * lower part is L0 (unit diagonal implied), the rest is U0. */
+gmg_status gmg_get_ilu0(gmg_handle h, double* val);
+
+/* ILUT factors of A_c: L~ strictly lower (unit diagonal implied) and U~ with
+ * its diagonal first in each row; device arrays sized by gmg_get_info. */
+gmg_status gmg_get_ilut(gmg_handle h, int32_t* lrowptr, int32_t* lcol, double* lval,
+                        int32_t* urowptr, int32_t* ucol, double* uval);
+
+/* Change the stream used by later calls on h. */
+gmg_status gmg_set_stream(gmg_handle h, void* stream);
+
+/* Per-kernel-class timing with HIP events on the handle's stream.
+ * gmg_profile_enable(h, 1) starts recording (resets the counters);
+ * gmg_profile_read fills up to `cap` records (host arrays) with the class
+ * name index, launch count, total milliseconds and algorithmic bytes moved,
+ * and returns the number of classes in *count.  Names: gmg_profile_name. */
+gmg_status gmg_profile_enable(gmg_handle h, int enable);
+gmg_status gmg_profile_read(gmg_handle h, int cap, int* count, int64_t* launches,
+                            double* ms, double* bytes);
+const char* gmg_profile_name(int cls);
+
+/* Release everything owned by h (NULL is ignored). */
+void gmg_destroy(gmg_handle h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* gmg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Finite-volume convection-diffusion assembly and its gradient, for the
+ * differentiable solve.  Discretisation of Eq. (pde) on [0,1]^dim with
+ * n cells per direction, unknown i + n j (+ n^2 k), Dirichlet faces y = 0, 1,
+ * Neumann elsewhere; harmonic face transmissibilities 2 k_c k_m / ((k_c+k_m) h^2),
+ * Dirichlet faces 2 k_c / h^2, first-order upwind convection with the given
+ * face-averaged velocities.
+ *   kappa: device double[n^dim]; vel_x, vel_y(, vel_z): device face velocities,
+ *   direction d array has n+1 entries along d (x fastest memory order);
+ *   rowptr/col/val: device outputs sized for the 5-/7-point pattern
+ *   (gmg_fv_nnz gives nnz); pattern identical to the one the Python
+ *   generator builds.
+ * ------------------------------------------------------------------------- */
+int64_t gmg_fv_nnz(int n, int dim);
+gmg_status gmg_fv_assemble(int n, int dim, const double* kappa, const double* vel_x,
+                           const double* vel_y, const double* vel_z, int32_t* rowptr,
+                           int32_t* col, double* val, void* stream);
+
+/* dL/dkappa for L(x(kappa)) given the adjoint lambda = A^{-T} dL/dx and the
+ * solution x, nrhs columns (device (N, nrhs) row-major each), summed over the
+ * right-hand sides: dL/dkappa_c = -sum_r lambda_r^T (dA/dkappa_c) x_r.
+ * grad: device double[N], overwritten. */
+gmg_status gmg_fv_kappa_grad(int n, int dim, const double* kappa, const double* lambda,
+                             const double* x, int nrhs, double* grad, void* stream);
+
+/* dL/dA on A's pattern: gval[p] = -sum_r lambda[i(p), r] * x[j(p), r]
+ * (device arrays; gval double[nnz], overwritten). */
+gmg_status gmg_pattern_grad(int64_t n, const int32_t* rowptr, const int32_t* col,
+                            const double* lambda, const double* x, int nrhs, double* gval,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMG_H */

@@ -1,0 +1,987 @@
+// C ABI, setup pipeline and the FGMRES driver of the two-grid matching-AMG
+// solver.  The host only sequences kernels and reads back a handful of
+// scalars per Krylov step; every vector operation runs on the GPU.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "gmg_internal.h"
+
+namespace gmg {
+
+static thread_local std::string g_last_error;
+
+[[noreturn]] void fail(gmg_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  (void)hipGetLastError();
+  gmg_status code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? GMG_ERR_OOM : GMG_ERR_HIP;
+  fail(code, std::string(what) + " failed: " + hipGetErrorString(e) + " (" + file + ":" + std::to_string(line) + ")");
+}
+
+constexpr uint64_t kSent64 = 0x7FF8DEADBEEFF00DULL;
+constexpr uint32_t kSent32 = 0x7FC0FEEDu;
+constexpr int kMaxRestart = 32;
+
+static const char* kProfNames[PC_COUNT] = {"spmv", "sweep_fine", "sweep_coarse", "resid_restrict",
+                                           "prolong", "ortho", "vector"};
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct Solver {
+  hipStream_t s = nullptr;
+  gmg_options opt{};
+  int n = 0;
+  int64_t nnz = 0;
+  DCsr A, AT;
+  DBuf<int> agg, aptr, amem;
+  int nc = 0, passes = 0, rounds = 0;
+  DCsr Ac;
+  DBuf<double> ilu;
+  DBuf<int> dpos;
+  HCsr hLc, hUc;
+  Sweep L0, U0, Lc, Uc;        // forward factors
+  Sweep U0t, L0t, Uct, Lct;    // transposed factors (adjoint)
+  DCsr dLc, dUc;               // coarse factors as CSR (Jacobi mode)
+  DBuf<double> ucdinv, jzero, jtmp;
+  // forward V-cycle work vectors
+  DBuf<double> y, t, r, rc, yc, ec;
+  DBuf<float> y32, t32, r32, rc32, yc32, ec32;
+  // adjoint V-cycle work vectors
+  DBuf<double> abc, auc, aec, as, aw, at;
+  // Krylov workspace
+  int mcap = 0;
+  size_t ld = 0;
+  DBuf<double> V, Z, w, xcol, bcol, coef;
+  RedWork rw;
+  DBuf<int> abort_flag;
+  double* hpin = nullptr;      // pinned host scalars
+  gmg_info info{};
+  // profiling
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  int64_t pc_launch[PC_COUNT] = {};
+  double pc_ms[PC_COUNT] = {}, pc_bytes[PC_COUNT] = {};
+
+  ~Solver() {
+    for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    if (hpin) (void)hipHostFree(hpin);
+  }
+
+  hipEvent_t ev() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    HIPCK(hipEventCreate(&e));
+    return e;
+  }
+};
+
+// RAII timing of one launch (or a group) when profiling is on
+struct Prof {
+  Solver& S;
+  int cls;
+  double bytes;
+  hipEvent_t a = nullptr;
+  Prof(Solver& s_, int c, double b) : S(s_), cls(c), bytes(b) {
+    if (S.prof) { a = S.ev(); HIPCK(hipEventRecord(a, S.s)); }
+  }
+  ~Prof() noexcept(false) {
+    if (S.prof && a) {
+      hipEvent_t b = S.ev();
+      HIPCK(hipEventRecord(b, S.s));
+      S.recs.push_back({cls, a, b, bytes});
+    }
+  }
+};
+
+static void prof_flush(Solver& S) {
+  if (S.recs.empty()) return;
+  HIPCK(hipStreamSynchronize(S.s));
+  for (auto& r : S.recs) {
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, r.a, r.b));
+    S.pc_ms[r.cls] += ms;
+    S.pc_launch[r.cls] += 1;
+    S.pc_bytes[r.cls] += r.bytes;
+    S.pool.push_back(r.a);
+    S.pool.push_back(r.b);
+  }
+  S.recs.clear();
+}
+
+// ----------------------------------------------------------------- sweeps
+// Build a sweep from host dependency lists.  dep_rp/dep_ci/dep_src list, per
+// row, the dependency columns and the index of each value in `src_vals`
+// (device) or the value itself (host_vals, when src_vals is null).
+static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const std::vector<int>& dep_ci,
+                        const std::vector<int>& dep_src, const std::vector<double>* host_vals,
+                        const double* src_vals_dev, bool lower, bool has_diag,
+                        const std::vector<double>* host_dinv, const double* dev_dinv, hipStream_t s) {
+  std::vector<int> sched, lptr;
+  int levels = 0;
+  make_schedule(dep_rp, dep_ci, lower, sched, lptr, &levels);
+  const int ns = (int)sched.size();
+  std::vector<int> dp(ns + 1, 0);
+  for (int p = 0; p < ns; ++p) {
+    const int r = sched[p];
+    dp[p + 1] = dp[p] + (r >= 0 ? dep_rp[r + 1] - dep_rp[r] : 0);
+  }
+  const int64_t ne = dp[ns];
+  std::vector<int> dcol(ne > 0 ? ne : 1), dsrc(ne > 0 ? ne : 1);
+  std::vector<double> dval_h;
+  if (host_vals) dval_h.resize(ne > 0 ? ne : 1);
+  for (int p = 0; p < ns; ++p) {
+    const int r = sched[p];
+    if (r < 0) continue;
+    int o = dp[p];
+    for (int q = dep_rp[r]; q < dep_rp[r + 1]; ++q, ++o) {
+      dcol[o] = dep_ci[q];
+      dsrc[o] = dep_src[q];
+      if (host_vals) dval_h[o] = (*host_vals)[dep_src[q]];
+    }
+  }
+  sw.n = n;
+  sw.nsched = ns;
+  sw.levels = levels;
+  sw.nnz = ne;
+  sw.has_diag = has_diag;
+  sw.sched.alloc(ns > 0 ? ns : 1);
+  sw.dp.alloc(ns + 1);
+  sw.dcol.alloc(ne > 0 ? ne : 1);
+  sw.dval.alloc(ne > 0 ? ne : 1);
+  h2d(sw.sched.p, sched.data(), ns, s);
+  h2d(sw.dp.p, dp.data(), ns + 1, s);
+  h2d(sw.dcol.p, dcol.data(), ne, s);
+  if (host_vals) {
+    h2d(sw.dval.p, dval_h.data(), ne, s);
+  } else {
+    DBuf<int> src;
+    src.alloc(ne > 0 ? ne : 1);
+    h2d(src.p, dsrc.data(), ne, s);
+    launch_gather_f64(src_vals_dev, src.p, sw.dval.p, ne, s);
+    HIPCK(hipStreamSynchronize(s));
+  }
+  sw.dval32.alloc(ne > 0 ? ne : 1);
+  launch_cast_f32(sw.dval.p, sw.dval32.p, ne, s);
+  if (has_diag) {
+    sw.dinv.alloc(n > 0 ? n : 1);
+    sw.dinv32.alloc(n > 0 ? n : 1);
+    if (host_dinv) h2d(sw.dinv.p, host_dinv->data(), n, s);
+    else d2d(sw.dinv.p, dev_dinv, n, s);
+    launch_cast_f32(sw.dinv.p, sw.dinv32.p, n, s);
+  }
+  sw.ticket.alloc(1);
+  launch_fill_u32(sw.ticket.p, 0u, 1, s);
+  sw.ticket_base = 0;
+  HIPCK(hipStreamSynchronize(s));  // host vectors above go out of scope
+}
+
+__global__ void k_recip_diag(int n, const double* __restrict__ a, const int* __restrict__ dpos,
+                             double* __restrict__ dinv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dinv[i] = 1.0 / a[dpos[i]];
+}
+
+static double sweep_bytes(const Sweep& sw, size_t sz, size_t szr, bool reset) {
+  // structure + dependency values + rhs + result write + result reads + diag
+  return (double)sw.nnz * (4 + sz) + (double)sw.n * (8 + szr + 2 * sz + (sw.has_diag ? sz : 0) + (reset ? szr : 0));
+}
+
+static void check_abort(Solver& S) {
+  int f = 0;
+  d2h(&f, S.abort_flag.p, 1, S.s);
+  HIPCK(hipStreamSynchronize(S.s));
+  if (f) {
+    launch_fill_u32(reinterpret_cast<unsigned*>(S.abort_flag.p), 0u, 1, S.s);
+    fail(GMG_ERR_STALLED, "a triangular-sweep dependency wait timed out");
+  }
+}
+
+static void reset_cycle_buffers(Solver& S) {
+  hipStream_t s = S.s;
+  launch_fill_f64_bits(S.y.p, kSent64, S.n, s);
+  launch_fill_f64_bits(S.t.p, kSent64, S.n, s);
+  launch_fill_f64_bits(S.yc.p, kSent64, S.nc, s);
+  launch_fill_f64_bits(S.ec.p, kSent64, S.nc, s);
+  launch_fill_f32_bits(S.y32.p, kSent32, S.n, s);
+  launch_fill_f32_bits(S.t32.p, kSent32, S.n, s);
+  launch_fill_f32_bits(S.yc32.p, kSent32, S.nc, s);
+  launch_fill_f32_bits(S.ec32.p, kSent32, S.nc, s);
+  launch_fill_f64_bits(S.auc.p, kSent64, S.nc, s);
+  launch_fill_f64_bits(S.aec.p, kSent64, S.nc, s);
+  launch_fill_f64_bits(S.aw.p, kSent64, S.n, s);
+  launch_fill_f64_bits(S.at.p, kSent64, S.n, s);
+}
+
+// ------------------------------------------------------ preconditioner apply
+// q = B~^{-1} z: t = U0^{-1} L0^{-1} z; r = z - A t; rc = P^T r;
+// ec = U~^{-1} L~^{-1} rc; q = t + P ec  (precision T)
+template <class T>
+static void vcycle(Solver& S, const double* z, double* q) {
+  constexpr bool F32 = sizeof(T) == 4;
+  hipStream_t s = S.s;
+  T* y = F32 ? (T*)S.y32.p : (T*)S.y.p;
+  T* t = F32 ? (T*)S.t32.p : (T*)S.t.p;
+  T* r = F32 ? (T*)S.r32.p : (T*)S.r.p;
+  T* rc = F32 ? (T*)S.rc32.p : (T*)S.rc.p;
+  T* yc = F32 ? (T*)S.yc32.p : (T*)S.yc.p;
+  T* ec = F32 ? (T*)S.ec32.p : (T*)S.ec.p;
+  auto dv = [&](Sweep& sw) { return F32 ? (const T*)sw.dval32.p : (const T*)sw.dval.p; };
+  auto di = [&](Sweep& sw) { return F32 ? (const T*)sw.dinv32.p : (const T*)sw.dinv.p; };
+  const T* Av = F32 ? (const T*)S.A.v32.p : (const T*)S.A.v.p;
+  const size_t sz = sizeof(T);
+  const int waves = S.opt.sweep_waves;
+  {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false));
+    launch_sweep<T>(S.L0, dv(S.L0), nullptr, z, true, y, nullptr, waves, S.abort_flag.p, s);
+  }
+  {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0, sz, sz, true));
+    launch_sweep<T>(S.U0, dv(S.U0), di(S.U0), y, false, t, y, waves, S.abort_flag.p, s);
+  }
+  {
+    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 8 + 3 * sz + 4) +
+                                     (double)S.nc * (4 + 2 * sz));
+    launch_resid_fine<T>(S.n, S.A.rp.p, S.A.ci.p, Av, t, z, r, s);
+    launch_restrict<T>(S.nc, S.aptr.p, S.amem.p, r, rc, ec, 0, s);
+  }
+  if (S.opt.coarse_mode == 0) {
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lc, sz, sz, false));
+      launch_sweep<T>(S.Lc, dv(S.Lc), nullptr, rc, false, yc, nullptr, waves, S.abort_flag.p, s);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uc, sz, sz, true));
+      launch_sweep<T>(S.Uc, dv(S.Uc), di(S.Uc), yc, false, ec, yc, waves, S.abort_flag.p, s);
+    }
+  } else {
+    if (F32) fail(GMG_ERR_INVALID_ARG, "coarse_mode 1 runs in FP64 only");
+    // Jacobi sweeps on each factor: y <- rc - (L~ - I) y from y = rc, then
+    // e <- D^{-1} (y - (U~ - D) e) from e = D^{-1} y
+    Prof p(S, PC_SWEEP_COARSE, 0.0);
+    const double* rcd = (const double*)rc;
+    double* a0 = (double*)yc;
+    double* a1 = S.jtmp.p;
+    d2d(a0, rcd, S.nc, s);
+    for (int k = 0; k < S.opt.coarse_sweeps; ++k) {
+      launch_jacobi(S.nc, S.dLc.rp.p, S.dLc.ci.p, S.dLc.v.p, nullptr, rcd, a0, a1, s);
+      std::swap(a0, a1);
+    }
+    double* e0 = (double*)ec;
+    double* e1 = a1;  // the L iterate buffer not holding the result
+    launch_jacobi(S.nc, S.dUc.rp.p, S.dUc.ci.p, S.dUc.v.p, S.ucdinv.p, a0, S.jzero.p, e0, s);
+    for (int k = 0; k < S.opt.coarse_sweeps; ++k) {
+      launch_jacobi(S.nc, S.dUc.rp.p, S.dUc.ci.p, S.dUc.v.p, S.ucdinv.p, a0, e0, e1, s);
+      std::swap(e0, e1);
+    }
+    if (e0 != (double*)ec) d2d((double*)ec, e0, S.nc, s);
+  }
+  {
+    Prof p(S, PC_PROLONG, (double)S.n * (4 + 2 * sz + 8) + (double)S.nc * sz);
+    launch_prolong<T>(S.n, S.agg.p, t, ec, q, 0, s);
+  }
+}
+
+// q = B~^{-T} z (FP64): ec = L~^{-T} U~^{-T} P^T z; s = z - A^T P ec;
+// t = L0^{-T} U0^{-T} s; q = P ec + t
+static void vcycle_adjoint(Solver& S, const double* z, double* q) {
+  hipStream_t s = S.s;
+  const int waves = S.opt.sweep_waves;
+  {
+    Prof p(S, PC_RESID_RESTRICT, (double)S.n * 12 + (double)S.nc * 16);
+    launch_restrict_plain(S.nc, S.aptr.p, S.amem.p, z, S.abc.p, S.aec.p, 0, s);
+  }
+  {
+    Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
+    launch_sweep<double>(S.Uct, S.Uct.dval.p, S.Uct.dinv.p, S.abc.p, false, S.auc.p, nullptr, waves,
+                         S.abort_flag.p, s);
+  }
+  {
+    Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
+    launch_sweep<double>(S.Lct, S.Lct.dval.p, nullptr, S.auc.p, false, S.aec.p, S.auc.p, waves, S.abort_flag.p, s);
+  }
+  {
+    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * 12 + (double)S.n * 24);
+    launch_resid_adj(S.n, S.AT.rp.p, S.AT.ci.p, S.AT.v.p, S.agg.p, S.aec.p, z, S.as.p, s);
+  }
+  {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
+    launch_sweep<double>(S.U0t, S.U0t.dval.p, S.U0t.dinv.p, S.as.p, false, S.aw.p, nullptr, waves,
+                         S.abort_flag.p, s);
+  }
+  {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
+    launch_sweep<double>(S.L0t, S.L0t.dval.p, nullptr, S.aw.p, false, S.at.p, S.aw.p, waves, S.abort_flag.p, s);
+  }
+  {
+    Prof p(S, PC_PROLONG, (double)S.n * 28 + (double)S.nc * 8);
+    launch_prolong<double>(S.n, S.agg.p, S.at.p, S.aec.p, q, 0, s);
+  }
+}
+
+static void apply_op(Solver& S, bool adjoint, const double* x, double* y) {
+  Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)S.n * 20);
+  const DCsr& M = adjoint ? S.AT : S.A;
+  launch_spmv<double>(S.n, M.rp.p, M.ci.p, M.v.p, x, y, S.s);
+}
+
+static void ensure_krylov(Solver& S, int m) {
+  if (m <= S.mcap && S.V.p) return;
+  S.mcap = m;
+  S.ld = ((size_t)S.n + 63) / 64 * 64;
+  S.V.alloc(S.ld * (m + 1));
+  S.Z.alloc(S.ld * m);
+  S.w.alloc(S.ld);
+  S.coef.alloc(kMaxRestart + 8);
+}
+
+// ------------------------------------------------------------------ FGMRES
+struct OneResult {
+  gmg_status st;
+  int steps, restarts;
+  double relres, est;
+};
+
+// Flexible GMRES(m) with right preconditioning (Algorithm 1's accelerator with
+// z_j = B~^{-1} v_j kept), classical Gram-Schmidt applied twice, Givens
+// rotations on the host (O(m) scalars per step).
+static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b, double* x, double tol,
+                        int maxit, int m, bool x0_given) {
+  hipStream_t s = S.s;
+  const int64_t n = S.n;
+  ensure_krylov(S, m);
+  const size_t ld = S.ld;
+  double* V = S.V.p;
+  double* Z = S.Z.p;
+  double* w = S.w.p;
+  double* res = S.rw.result.p;
+  double* hp = S.hpin;
+  OneResult out{GMG_NOT_CONVERGED, 0, 0, 0.0, 0.0};
+  if (!x0_given) HIPCK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+  {
+    Prof p(S, PC_VECTOR, (double)n * 8);
+    launch_norm2(b, n, S.rw, res, s);
+  }
+  d2h(hp, res, 1, s);
+  HIPCK(hipStreamSynchronize(s));
+  const double bnorm = std::sqrt(hp[0]);
+  if (!std::isfinite(bnorm)) { out.st = GMG_ERR_NONFINITE; return out; }
+  if (bnorm == 0.0) {
+    HIPCK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    HIPCK(hipStreamSynchronize(s));
+    out.st = GMG_OK;
+    return out;
+  }
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m + 1), sn(m + 1), g(m + 2), yv(m + 1);
+  auto HH = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  int total = 0;
+  for (;;) {
+    {
+      Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)n * 28);
+      const DCsr& M = adjoint ? S.AT : S.A;
+      launch_residual(S.n, M.rp.p, M.ci.p, M.v.p, x, b, w, s);
+    }
+    {
+      Prof p(S, PC_VECTOR, (double)n * 8);
+      launch_norm2(w, n, S.rw, res, s);
+    }
+    d2h(hp, res, 1, s);
+    HIPCK(hipStreamSynchronize(s));
+    const double beta = std::sqrt(hp[0]);
+    out.relres = beta / bnorm;
+    if (!std::isfinite(out.relres)) { out.st = GMG_ERR_NONFINITE; break; }
+    if (out.relres < tol) { out.st = GMG_OK; break; }
+    if (total >= maxit) { out.st = GMG_NOT_CONVERGED; break; }
+    if (total > 0) ++out.restarts;
+    {
+      Prof p(S, PC_VECTOR, (double)n * 16);
+      launch_scale(w, 1.0 / beta, V, n, s);
+    }
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (size_t)j * ld;
+      double* zj = Z + (size_t)j * ld;
+      if (adjoint) vcycle_adjoint(S, vj, zj);
+      else if (precision == 1) vcycle<float>(S, vj, zj);
+      else vcycle<double>(S, vj, zj);
+      apply_op(S, adjoint, zj, w);
+      const int kc = j + 1;
+      {
+        Prof p(S, PC_ORTHO, 8.0 * n * (3 * kc + 6));
+        launch_multidot(V, ld, kc, w, n, S.rw, res, s);
+        launch_update_dot(V, ld, kc, res, w, n, S.rw, res + kMaxRestart, s);
+        launch_update_norm(V, ld, kc, res + kMaxRestart, w, n, S.rw, res + 2 * kMaxRestart, s);
+      }
+      d2h(hp, res, 2 * kMaxRestart + 1, s);
+      HIPCK(hipStreamSynchronize(s));
+      for (int i = 0; i <= j; ++i) HH(i, j) = hp[i] + hp[kMaxRestart + i];
+      const double hn = std::sqrt(hp[2 * kMaxRestart]);
+      HH(j + 1, j) = hn;
+      if (hn != 0.0) {
+        Prof p(S, PC_VECTOR, (double)n * 16);
+        launch_scale(w, 1.0 / hn, V + (size_t)(j + 1) * ld, n, s);
+      }
+      for (int i = 0; i < j; ++i) {
+        const double a = HH(i, j), c = HH(i + 1, j);
+        HH(i, j) = cs[i] * a + sn[i] * c;
+        HH(i + 1, j) = -sn[i] * a + cs[i] * c;
+      }
+      const double rho = std::hypot(HH(j, j), HH(j + 1, j));
+      if (rho == 0.0 || !std::isfinite(rho)) {
+        out.st = std::isfinite(rho) ? GMG_ERR_BREAKDOWN : GMG_ERR_NONFINITE;
+        breakdown = true;
+        break;
+      }
+      cs[j] = HH(j, j) / rho;
+      sn[j] = HH(j + 1, j) / rho;
+      HH(j, j) = rho;
+      HH(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      k = j + 1;
+      out.est = std::fabs(g[j + 1]) / bnorm;
+      if (out.est < tol || hn == 0.0 || total >= maxit) break;
+    }
+    check_abort(S);
+    if (breakdown) break;
+    for (int i = k - 1; i >= 0; --i) {
+      double sum = g[i];
+      for (int l = i + 1; l < k; ++l) sum -= HH(i, l) * yv[l];
+      yv[i] = sum / HH(i, i);
+    }
+    h2d(S.coef.p, yv.data(), k, s);
+    {
+      Prof p(S, PC_VECTOR, 8.0 * n * (k + 2));
+      launch_xupdate(x, Z, ld, k, S.coef.p, n, s);
+    }
+  }
+  out.steps = total;
+  HIPCK(hipStreamSynchronize(s));
+  return out;
+}
+
+static gmg_status solve_impl(Solver& S, bool adjoint, const double* b, double* x, int nrhs, double tol,
+                             const gmg_options* o, gmg_info* info) {
+  if (!b || !x || nrhs < 1) fail(GMG_ERR_INVALID_ARG, "solve: null vector or nrhs < 1");
+  if (!(tol >= 0.0)) fail(GMG_ERR_INVALID_ARG, "solve: tol must be >= 0");
+  gmg_options opt = S.opt;
+  if (o) {
+    opt.x0_given = o->x0_given;
+    opt.maxit = o->maxit;
+    opt.restart = o->restart;
+    opt.precond_fp32 = o->precond_fp32;
+  }
+  if (opt.restart < 1 || opt.restart > kMaxRestart) fail(GMG_ERR_INVALID_ARG, "restart must be in [1, 32]");
+  if (opt.maxit < 0) fail(GMG_ERR_INVALID_ARG, "maxit must be >= 0");
+  if (adjoint && (opt.precond_fp32 || S.opt.coarse_mode != 0))
+    fail(GMG_ERR_INVALID_ARG, "the adjoint solve needs coarse_mode 0 and FP64");
+  auto t0 = std::chrono::steady_clock::now();
+  reset_cycle_buffers(S);
+  gmg_status worst = GMG_OK;
+  int iters = 0, restarts = 0, conv = 0;
+  double rel = 0.0, est = 0.0;
+  ensure_krylov(S, opt.restart);
+  if (nrhs > 1 && !S.xcol.p) {
+    S.xcol.alloc(S.n);
+    S.bcol.alloc(S.n);
+  }
+  for (int c = 0; c < nrhs; ++c) {
+    const double* bc = b;
+    double* xc = x;
+    if (nrhs > 1) {
+      launch_get_col(b, nrhs, c, S.bcol.p, S.n, S.s);
+      if (opt.x0_given) launch_get_col(x, nrhs, c, S.xcol.p, S.n, S.s);
+      bc = S.bcol.p;
+      xc = S.xcol.p;
+    }
+    OneResult r = fgmres(S, adjoint, opt.precond_fp32 ? 1 : 0, bc, xc, tol, opt.maxit, opt.restart,
+                         opt.x0_given != 0);
+    if (nrhs > 1) launch_set_col(x, nrhs, c, S.xcol.p, S.n, S.s);
+    iters += r.steps;
+    restarts += r.restarts;
+    rel = std::max(rel, r.relres);
+    est = std::max(est, r.est);
+    if (r.st == GMG_OK) ++conv;
+    if (r.st < 0) { worst = r.st; break; }
+    if (r.st > 0 && worst == GMG_OK) worst = r.st;
+  }
+  HIPCK(hipStreamSynchronize(S.s));
+  auto t1 = std::chrono::steady_clock::now();
+  S.info.iters = iters;
+  S.info.restarts = restarts;
+  S.info.converged = conv;
+  S.info.relres_true = rel;
+  S.info.relres_est = est;
+  S.info.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  if (info) *info = S.info;
+  if (worst == GMG_ERR_BREAKDOWN) fail(worst, "FGMRES breakdown (zero Givens column)");
+  if (worst == GMG_ERR_NONFINITE) fail(worst, "non-finite residual");
+  return worst;
+}
+
+// ------------------------------------------------------------------- setup
+static std::vector<int> to_host_int(const int* d, size_t n, hipStream_t s) {
+  std::vector<int> h(n);
+  d2h(h.data(), d, n, s);
+  return h;
+}
+
+static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* rowptr, const int32_t* col,
+                       const double* val) {
+  hipStream_t s = S.s;
+  if (n64 <= 0 || n64 >= (1LL << 31) - 64 || nnz64 < n64 || nnz64 >= (1LL << 31))
+    fail(GMG_ERR_INVALID_ARG, "setup: need 0 < n, n <= nnz < 2^31");
+  if (!rowptr || !col || !val) fail(GMG_ERR_INVALID_ARG, "setup: null matrix pointer");
+  const gmg_options& o = S.opt;
+  if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
+      o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0)
+    fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = (int)n64;
+  S.n = n;
+  S.nnz = nnz64;
+  HIPCK(hipHostMalloc(&S.hpin, sizeof(double) * 256, hipHostMallocDefault));
+  S.abort_flag.alloc(1);
+  launch_fill_u32(reinterpret_cast<unsigned*>(S.abort_flag.p), 0u, 1, s);
+  // ---- validate and copy A
+  {
+    int64_t rp_end = 0;
+    int first = 0;
+    int rpn = 0;
+    d2h(&first, rowptr, 1, s);
+    d2h(&rpn, rowptr + n, 1, s);
+    HIPCK(hipStreamSynchronize(s));
+    rp_end = rpn;
+    if (first != 0 || rp_end != nnz64) fail(GMG_ERR_INVALID_ARG, "setup: rowptr[0] != 0 or rowptr[n] != nnz");
+  }
+  DBuf<int> flags;
+  flags.alloc(2);
+  launch_fill_u32(reinterpret_cast<unsigned*>(flags.p), 0u, 2, s);
+  launch_validate(n, rowptr, col, val, flags.p, s);
+  int hflags[2] = {0, 0};
+  d2h(hflags, flags.p, 2, s);
+  HIPCK(hipStreamSynchronize(s));
+  if (hflags[0]) fail(GMG_ERR_INVALID_ARG, "setup: columns must be in range, strictly ascending, diagonal stored");
+  if (hflags[1]) fail(GMG_ERR_NONFINITE, "setup: non-finite matrix entry");
+  S.A.n = S.A.m = n;
+  S.A.nnz = nnz64;
+  S.A.rp.alloc(n + 1);
+  S.A.ci.alloc(nnz64);
+  S.A.v.alloc(nnz64);
+  S.A.v32.alloc(nnz64);
+  d2d(S.A.rp.p, rowptr, n + 1, s);
+  d2d(S.A.ci.p, col, nnz64, s);
+  d2d(S.A.v.p, val, nnz64, s);
+  launch_cast_f32(S.A.v.p, S.A.v32.p, nnz64, s);
+  // ---- A^T (graph, adjoint)
+  S.AT.n = S.AT.m = n;
+  S.AT.nnz = nnz64;
+  DBuf<int> at_src;
+  transpose_csr(n, n, nnz64, S.A.rp.p, S.A.ci.p, S.A.v.p, S.AT.rp, S.AT.ci, &S.AT.v, &at_src, s);
+  // ---- aggregation
+  {
+    DBuf<int> grp, gci;
+    DBuf<double> gw;
+    build_graph(n, S.A.rp.p, S.A.ci.p, S.A.v.p, S.AT.rp.p, S.AT.ci.p, S.AT.v.p, grp, gci, gw, s);
+    S.nc = aggregate(n, grp, gci, gw, o.cf, o.max_passes, o.match_qbits, o.hash_seed, S.agg, &S.passes,
+                     &S.rounds, s);
+  }
+  build_members(n, S.nc, S.agg.p, S.aptr, S.amem, s);
+  galerkin(n, S.nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
+  // ---- host copy of A's pattern for the analysis
+  std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
+  std::vector<int> hci = to_host_int(S.A.ci.p, nnz64, s);
+  std::vector<int> hat_rp = to_host_int(S.AT.rp.p, n + 1, s);
+  std::vector<int> hat_ci = to_host_int(S.AT.ci.p, nnz64, s);
+  std::vector<int> hat_src = to_host_int(at_src.p, nnz64, s);
+  HIPCK(hipStreamSynchronize(s));
+  std::vector<int> hdpos(n);
+  for (int i = 0; i < n; ++i)
+    for (int p = hrp[i]; p < hrp[i + 1]; ++p)
+      if (hci[p] == i) hdpos[i] = p;
+  S.dpos.alloc(n);
+  h2d(S.dpos.p, hdpos.data(), n, s);
+  // dependency lists of the four fine sweeps
+  std::vector<int> l_rp(n + 1, 0), l_ci, l_src, u_rp(n + 1, 0), u_ci, u_src;
+  l_ci.reserve(nnz64 / 2);
+  l_src.reserve(nnz64 / 2);
+  u_ci.reserve(nnz64 / 2);
+  u_src.reserve(nnz64 / 2);
+  for (int i = 0; i < n; ++i) {
+    for (int p = hrp[i]; p < hrp[i + 1]; ++p) {
+      if (hci[p] < i) { l_ci.push_back(hci[p]); l_src.push_back(p); }
+      else if (hci[p] > i) { u_ci.push_back(hci[p]); u_src.push_back(p); }
+    }
+    l_rp[i + 1] = (int)l_ci.size();
+    u_rp[i + 1] = (int)u_ci.size();
+  }
+  // transposed: row j of U0^T lists i < j with (i, j) in strict U; of L0^T lists i > j with (i, j) in strict L
+  std::vector<int> ut_rp(n + 1, 0), ut_ci, ut_src, lt_rp(n + 1, 0), lt_ci, lt_src;
+  for (int j = 0; j < n; ++j) {
+    for (int q = hat_rp[j]; q < hat_rp[j + 1]; ++q) {
+      const int i = hat_ci[q], p = hat_src[q];
+      if (i < j) { ut_ci.push_back(i); ut_src.push_back(p); }
+      else if (i > j) { lt_ci.push_back(i); lt_src.push_back(p); }
+    }
+    ut_rp[j + 1] = (int)ut_ci.size();
+    lt_rp[j + 1] = (int)lt_ci.size();
+  }
+  // ---- ILU(0), one launch per level of L0
+  S.ilu.alloc(nnz64);
+  d2d(S.ilu.p, S.A.v.p, nnz64, s);
+  {
+    std::vector<int> sched, lptr;
+    int levels = 0;
+    make_schedule(l_rp, l_ci, true, sched, lptr, &levels);
+    DBuf<int> dsched, bad;
+    dsched.alloc(sched.size() > 0 ? sched.size() : 1);
+    bad.alloc(1);
+    h2d(dsched.p, sched.data(), sched.size(), s);
+    launch_fill_u32(reinterpret_cast<unsigned*>(bad.p), 0u, 1, s);
+    for (int l = 0; l < levels; ++l)
+      launch_ilu0_level(dsched.p + lptr[l], lptr[l + 1] - lptr[l], S.A.rp.p, S.A.ci.p, S.dpos.p, S.ilu.p, bad.p, s);
+    int hb = 0;
+    d2h(&hb, bad.p, 1, s);
+    HIPCK(hipStreamSynchronize(s));
+    if (hb & 1) fail(GMG_ERR_ZERO_PIVOT, "ILU(0): zero pivot");
+    if (hb & 2) fail(GMG_ERR_NONFINITE, "ILU(0): non-finite pivot");
+  }
+  DBuf<double> u0dinv;
+  u0dinv.alloc(n);
+  hipLaunchKernelGGL(k_recip_diag, dim3((n + 255) / 256), dim3(256), 0, s, n, S.ilu.p, S.dpos.p, u0dinv.p);
+  HIPCK(hipGetLastError());
+  build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, s);
+  build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, u0dinv.p, s);
+  build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, u0dinv.p, s);
+  build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, s);
+  // ---- ILUT of A_c on the host
+  {
+    HCsr hAc;
+    hAc.n = S.nc;
+    hAc.rp = to_host_int(S.Ac.rp.p, S.nc + 1, s);
+    hAc.ci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
+    hAc.v.resize(S.Ac.nnz);
+    d2h(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
+    HIPCK(hipStreamSynchronize(s));
+    gmg_status st = host_ilut(hAc, o.ilut_tau, S.hLc, S.hUc);
+    if (st == GMG_ERR_ZERO_PIVOT) fail(st, "ILUT: zero pivot");
+    if (st != GMG_OK) fail(st, "ILUT: non-finite pivot");
+  }
+  {
+    const int nc = S.nc;
+    const HCsr &L = S.hLc, &U = S.hUc;
+    std::vector<int> lsrc(L.ci.size()), us_rp(nc + 1, 0), us_ci, us_src;
+    for (size_t q = 0; q < L.ci.size(); ++q) lsrc[q] = (int)q;
+    std::vector<double> udinv(nc);
+    for (int i = 0; i < nc; ++i) {
+      udinv[i] = 1.0 / U.v[U.rp[i]];
+      for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) { us_ci.push_back(U.ci[q]); us_src.push_back(q); }
+      us_rp[i + 1] = (int)us_ci.size();
+    }
+    build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, s);
+    build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, s);
+    // transposes: U~^T row j lists i < j (strict part), L~^T row j lists i > j
+    std::vector<int> uct_cnt(nc + 1, 0), lct_cnt(nc + 1, 0);
+    for (size_t q = 0; q < us_ci.size(); ++q) uct_cnt[us_ci[q] + 1]++;
+    for (size_t q = 0; q < L.ci.size(); ++q) lct_cnt[L.ci[q] + 1]++;
+    for (int j = 0; j < nc; ++j) { uct_cnt[j + 1] += uct_cnt[j]; lct_cnt[j + 1] += lct_cnt[j]; }
+    std::vector<int> uct_ci(us_ci.size()), uct_src(us_ci.size()), lct_ci(L.ci.size()), lct_src(L.ci.size());
+    std::vector<int> fu(uct_cnt.begin(), uct_cnt.end() - 1), fl(lct_cnt.begin(), lct_cnt.end() - 1);
+    for (int i = 0; i < nc; ++i) {
+      for (int q = us_rp[i]; q < us_rp[i + 1]; ++q) {
+        const int j = us_ci[q], o2 = fu[j]++;
+        uct_ci[o2] = i;
+        uct_src[o2] = us_src[q];
+      }
+      for (int q = L.rp[i]; q < L.rp[i + 1]; ++q) {
+        const int j = L.ci[q], o2 = fl[j]++;
+        lct_ci[o2] = i;
+        lct_src[o2] = q;
+      }
+    }
+    build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, s);
+    build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, s);
+    if (o.coarse_mode == 1) {
+      auto up = [&](DCsr& D, const HCsr& H) {
+        D.n = D.m = nc;
+        D.nnz = (int64_t)H.ci.size();
+        D.rp.alloc(nc + 1);
+        D.ci.alloc(D.nnz > 0 ? D.nnz : 1);
+        D.v.alloc(D.nnz > 0 ? D.nnz : 1);
+        h2d(D.rp.p, H.rp.data(), nc + 1, s);
+        h2d(D.ci.p, H.ci.data(), D.nnz, s);
+        h2d(D.v.p, H.v.data(), D.nnz, s);
+      };
+      up(S.dLc, L);
+      up(S.dUc, U);
+      S.ucdinv.alloc(nc);
+      h2d(S.ucdinv.p, udinv.data(), nc, s);
+      S.jzero.alloc(nc);
+      S.jtmp.alloc(nc);
+      HIPCK(hipMemsetAsync(S.jzero.p, 0, sizeof(double) * nc, s));
+      HIPCK(hipStreamSynchronize(s));
+    }
+  }
+  // ---- work vectors
+  S.y.alloc(n); S.t.alloc(n); S.r.alloc(n);
+  S.rc.alloc(S.nc); S.yc.alloc(S.nc); S.ec.alloc(S.nc);
+  S.y32.alloc(n); S.t32.alloc(n); S.r32.alloc(n);
+  S.rc32.alloc(S.nc); S.yc32.alloc(S.nc); S.ec32.alloc(S.nc);
+  S.abc.alloc(S.nc); S.auc.alloc(S.nc); S.aec.alloc(S.nc);
+  S.as.alloc(n); S.aw.alloc(n); S.at.alloc(n);
+  red_init(S.rw, s);
+  reset_cycle_buffers(S);
+  HIPCK(hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  gmg_info& I = S.info;
+  I.passes = S.passes;
+  I.rounds = S.rounds;
+  I.levels_L0 = S.L0.levels;
+  I.levels_U0 = S.U0.levels;
+  I.levels_Lc = S.Lc.levels;
+  I.levels_Uc = S.Uc.levels;
+  I.n = n;
+  I.nnz = nnz64;
+  I.n_coarse = S.nc;
+  I.nnz_coarse = S.Ac.nnz;
+  I.nnz_lc = (int64_t)S.hLc.ci.size();
+  I.nnz_uc = (int64_t)S.hUc.ci.size();
+  I.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+}  // namespace gmg
+
+using gmg::Error;
+using gmg::Solver;
+
+struct gmg_solver {
+  Solver S;
+};
+
+template <class F>
+static gmg_status guarded(F&& f) {
+  try {
+    gmg::g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    gmg::g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    gmg::g_last_error = "host allocation failed";
+    return GMG_ERR_OOM;
+  } catch (const std::exception& e) {
+    gmg::g_last_error = e.what();
+    return GMG_ERR_HIP;
+  }
+}
+
+#define REQUIRE_HANDLE(h)                                           \
+  do {                                                              \
+    if (!(h)) gmg::fail(GMG_ERR_NOT_SETUP, "null solver handle");   \
+  } while (0)
+
+extern "C" {
+
+void gmg_default_options(gmg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->cf = 4.0;
+  o->max_passes = 8;
+  o->match_qbits = 4;
+  o->hash_seed = 0x9E3779B97F4A7C15ULL;
+  o->ilut_tau = 1e-4;
+  o->coarse_mode = 0;
+  o->coarse_sweeps = 3;
+  o->restart = 30;
+  o->maxit = 600;
+  o->precond_fp32 = 0;
+  o->x0_given = 0;
+  o->sweep_waves = 0;
+}
+
+gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                     const double* val, const gmg_options* opts, void* stream) {
+  return guarded([&]() -> gmg_status {
+    if (!h) gmg::fail(GMG_ERR_INVALID_ARG, "setup: null handle pointer");
+    *h = nullptr;
+    std::unique_ptr<gmg_solver> sv(new gmg_solver());
+    sv->S.s = (hipStream_t)stream;
+    if (opts) sv->S.opt = *opts;
+    else gmg_default_options(&sv->S.opt);
+    gmg::setup_impl(sv->S, n, nnz, rowptr, col, val);
+    *h = sv.release();
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_solve(gmg_handle h, const double* b, double* x, int nrhs, double tol, const gmg_options* opts,
+                     gmg_info* info) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    return gmg::solve_impl(h->S, false, b, x, nrhs, tol, opts, info);
+  });
+}
+
+gmg_status gmg_solve_adjoint(gmg_handle h, const double* g, double* lambda, int nrhs, double tol,
+                             const gmg_options* opts, gmg_info* info) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    return gmg::solve_impl(h->S, true, g, lambda, nrhs, tol, opts, info);
+  });
+}
+
+gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int precision, int adjoint) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!z || !q) gmg::fail(GMG_ERR_INVALID_ARG, "apply: null vector");
+    Solver& S = h->S;
+    gmg::reset_cycle_buffers(S);
+    if (adjoint) {
+      if (precision != 0 || S.opt.coarse_mode != 0) gmg::fail(GMG_ERR_INVALID_ARG, "adjoint apply is FP64, coarse_mode 0");
+      gmg::vcycle_adjoint(S, z, q);
+    } else if (precision == 1) {
+      gmg::vcycle<float>(S, z, q);
+    } else {
+      gmg::vcycle<double>(S, z, q);
+    }
+    HIPCK(hipStreamSynchronize(S.s));
+    gmg::check_abort(S);
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_spmv(gmg_handle h, int transposed, const double* x, double* y) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!x || !y) gmg::fail(GMG_ERR_INVALID_ARG, "spmv: null vector");
+    gmg::apply_op(h->S, transposed != 0, x, y);
+    HIPCK(hipStreamSynchronize(h->S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_info(gmg_handle h, gmg_info* info) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!info) gmg::fail(GMG_ERR_INVALID_ARG, "null info");
+    *info = h->S.info;
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_aggregates(gmg_handle h, int32_t* agg) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!agg) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    gmg::d2d(agg, h->S.agg.p, h->S.n, h->S.s);
+    HIPCK(hipStreamSynchronize(h->S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_coarse(gmg_handle h, int32_t* rowptr, int32_t* col, double* val) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!rowptr || !col || !val) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    Solver& S = h->S;
+    gmg::d2d(rowptr, S.Ac.rp.p, S.nc + 1, S.s);
+    gmg::d2d(col, S.Ac.ci.p, S.Ac.nnz, S.s);
+    gmg::d2d(val, S.Ac.v.p, S.Ac.nnz, S.s);
+    HIPCK(hipStreamSynchronize(S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_ilu0(gmg_handle h, double* val) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!val) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    gmg::d2d(val, h->S.ilu.p, h->S.nnz, h->S.s);
+    HIPCK(hipStreamSynchronize(h->S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_ilut(gmg_handle h, int32_t* lrp, int32_t* lci, double* lv, int32_t* urp, int32_t* uci,
+                        double* uv) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!lrp || !lci || !lv || !urp || !uci || !uv) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    Solver& S = h->S;
+    gmg::h2d(lrp, S.hLc.rp.data(), S.hLc.rp.size(), S.s);
+    gmg::h2d(lci, S.hLc.ci.data(), S.hLc.ci.size(), S.s);
+    gmg::h2d(lv, S.hLc.v.data(), S.hLc.v.size(), S.s);
+    gmg::h2d(urp, S.hUc.rp.data(), S.hUc.rp.size(), S.s);
+    gmg::h2d(uci, S.hUc.ci.data(), S.hUc.ci.size(), S.s);
+    gmg::h2d(uv, S.hUc.v.data(), S.hUc.v.size(), S.s);
+    HIPCK(hipStreamSynchronize(S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_set_stream(gmg_handle h, void* stream) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    HIPCK(hipStreamSynchronize(h->S.s));
+    h->S.s = (hipStream_t)stream;
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_profile_enable(gmg_handle h, int enable) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    Solver& S = h->S;
+    gmg::prof_flush(S);
+    for (int c = 0; c < gmg::PC_COUNT; ++c) { S.pc_launch[c] = 0; S.pc_ms[c] = 0; S.pc_bytes[c] = 0; }
+    S.prof = enable != 0;
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_profile_read(gmg_handle h, int cap, int* count, int64_t* launches, double* ms, double* bytes) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    Solver& S = h->S;
+    gmg::prof_flush(S);
+    if (count) *count = gmg::PC_COUNT;
+    for (int c = 0; c < gmg::PC_COUNT && c < cap; ++c) {
+      if (launches) launches[c] = S.pc_launch[c];
+      if (ms) ms[c] = S.pc_ms[c];
+      if (bytes) bytes[c] = S.pc_bytes[c];
+    }
+    return GMG_OK;
+  });
+}
+
+const char* gmg_profile_name(int cls) {
+  if (cls < 0 || cls >= gmg::PC_COUNT) return "";
+  return gmg::kProfNames[cls];
+}
+
+void gmg_destroy(gmg_handle h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->S.s);
+  delete h;
+}
+
+const char* gmg_last_error(void) { return gmg::g_last_error.c_str(); }
+
+}  // extern "C"

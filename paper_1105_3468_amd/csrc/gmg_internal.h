@@ -1,0 +1,217 @@
+// Internal declarations of the MI355X two-grid matching-AMG library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gmg.h"
+
+namespace gmg {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  gmg_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(gmg_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define HIPCK(x) ::gmg::hip_check((x), #x, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------- memory
+// Owning device buffer (library-allocated).
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      n = 0;
+      (void)hipGetLastError();
+      fail(GMG_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  T* get() const { return p; }
+};
+
+template <class T>
+void h2d(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) HIPCK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
+void d2h(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) HIPCK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+template <class T>
+void d2d(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) HIPCK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+}
+
+// Device CSR matrix owned by the library.
+struct DCsr {
+  int n = 0, m = 0;          // rows, columns
+  int64_t nnz = 0;
+  DBuf<int> rp, ci;
+  DBuf<double> v;
+  DBuf<float> v32;
+};
+
+// Host CSR (for analysis steps).
+struct HCsr {
+  int n = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+};
+
+// A triangular factor prepared for the synchronisation-free sweep.
+// Rows are visited in `sched` order (dependency levels, each level padded to a
+// multiple of 64 with -1).  Position p holds row sched[p]; its dependency
+// entries are dcol[dp[p] .. dp[p+1]) with values dval[...].  diag (optional)
+// is indexed by row: out[r] = (rhs[r] - sum dval * out[dcol]) * dinv[r].
+struct Sweep {
+  int n = 0;                 // rows of the factor
+  int nsched = 0;            // schedule length incl. padding (multiple of 64)
+  int levels = 0;
+  int64_t nnz = 0;           // dependency entries
+  DBuf<int> sched, dp, dcol;
+  DBuf<double> dval, dinv;
+  DBuf<float> dval32, dinv32;
+  DBuf<unsigned> ticket;     // dynamic chunk counter
+  unsigned ticket_base = 0;  // host copy of the counter value at the next launch
+  bool has_diag = false;
+};
+
+// Per-kernel-class profiling with events.
+enum ProfClass {
+  PC_SPMV = 0, PC_SWEEP_FINE, PC_SWEEP_COARSE, PC_RESID_RESTRICT, PC_PROLONG,
+  PC_ORTHO, PC_VECTOR, PC_COUNT
+};
+
+struct Solver;
+
+// ---------------------------------------------------------------- kernels
+// Sparse kernels (k_sparse.hip)
+void launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s);
+void launch_fill_f64_bits(double* p, uint64_t bits, size_t n, hipStream_t s);
+void launch_fill_f32_bits(float* p, uint32_t bits, size_t n, hipStream_t s);
+void launch_validate(int n, const int* rp, const int* ci, const double* v, int* flags,
+                     hipStream_t s);
+void launch_cast_f32(const double* x, float* y, size_t n, hipStream_t s);
+// CSR SpMV y = A x; T = value/vector type
+template <class T>
+void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y,
+                 hipStream_t s);
+// r = b - A x  (r may alias nothing); FP64 only
+void launch_residual(int n, const int* rp, const int* ci, const double* v, const double* x,
+                     const double* b, double* r, hipStream_t s);
+// Fine residual of the smoothed iterate: r[k] = z[k] - (A t)[k]  (Tz = input type)
+template <class T>
+void launch_resid_fine(int n, const int* rp, const int* ci, const T* v, const T* t,
+                       const double* z, T* r, hipStream_t s);
+// rc[I] = sum_{k in G_I} r[k]; also writes the sentinel into reset[I]
+template <class T>
+void launch_restrict(int nc, const int* aptr, const int* amem, const T* r, T* rc, T* reset,
+                     uint64_t sentinel_bits, hipStream_t s);
+// q[k] = t[k] + ec[agg[k]] (q in double); t[k] <- sentinel
+template <class T>
+void launch_prolong(int n, const int* agg, T* t, const T* ec, double* q, uint64_t sentinel_bits,
+                    hipStream_t s);
+// Adjoint helpers
+void launch_restrict_plain(int nc, const int* aptr, const int* amem, const double* z,
+                           double* bc, double* reset, uint64_t sentinel_bits, hipStream_t s);
+// s[k] = z[k] - sum_l AT[k,l] ec[agg[l]]
+void launch_resid_adj(int n, const int* rp, const int* ci, const double* v, const int* agg,
+                      const double* ec, const double* z, double* out, hipStream_t s);
+// Transpose a device CSR (n rows, m cols) into T (m rows, n cols); columns ascending.
+void transpose_csr(int n, int m, int64_t nnz, const int* rp, const int* ci, const double* v,
+                   DBuf<int>& trp, DBuf<int>& tci, DBuf<double>* tv, DBuf<int>* tsrc,
+                   hipStream_t s);
+void launch_gather_f64(const double* src, const int* idx, double* dst, int64_t n, hipStream_t s);
+void launch_exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, DBuf<int>& tmp);
+
+// Triangular sweeps (k_sweep.hip)
+template <class T>
+void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64,
+                  T* out, T* reset_rhs, int waves, int* abort_flag, hipStream_t s);
+void launch_ilu0_level(const int* rows, int count, const int* rp, const int* ci, const int* dpos,
+                       double* a, int* bad, hipStream_t s);
+// yout[i] = (b[i] - sum_{j != i} F_ij yin[j]) * (dinv ? dinv[i] : 1)
+void launch_jacobi(int n, const int* rp, const int* ci, const double* v, const double* dinv, const double* b,
+                   const double* yin, double* yout, hipStream_t s);
+
+// Krylov kernels (k_krylov.hip)
+struct RedWork {  // scratch for deterministic two-level reductions
+  DBuf<double> partial;
+  DBuf<unsigned> counter;
+  DBuf<double> result;   // up to 2*64+2 values
+  int blocks = 0;
+};
+void red_init(RedWork& rw, hipStream_t s);
+// result[0..k) = V[0..k)^T w   (V rows with stride ld)
+void launch_multidot(const double* V, size_t ld, int k, const double* w, int64_t n,
+                     RedWork& rw, double* result, hipStream_t s);
+// w -= V[0..k)^T h  (h device), then result[0..k) = V^T w_new
+void launch_update_dot(const double* V, size_t ld, int k, const double* h, double* w, int64_t n,
+                       RedWork& rw, double* result, hipStream_t s);
+// w -= V^T h, then result[0] = ||w||^2
+void launch_update_norm(const double* V, size_t ld, int k, const double* h, double* w, int64_t n,
+                        RedWork& rw, double* result, hipStream_t s);
+// result[0] = ||x||^2
+void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s);
+// y = alpha * x
+void launch_scale(const double* x, double alpha, double* y, int64_t n, hipStream_t s);
+// x += sum_i c[i] Z[i]  (c device)
+void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n,
+                    hipStream_t s);
+// strided column gather/scatter for multi-RHS
+void launch_get_col(const double* X, int nrhs, int col, double* x, int64_t n, hipStream_t s);
+void launch_set_col(double* X, int nrhs, int col, const double* x, int64_t n, hipStream_t s);
+
+// Setup kernels (k_setup.hip)
+void build_graph(int n, const int* rp, const int* ci, const double* v, const int* trp,
+                 const int* tci, const double* tv, DBuf<int>& grp, DBuf<int>& gci,
+                 DBuf<double>& gw, hipStream_t s);
+// Multi-pass handshake matching; returns N_c, fills agg (device int[n]).
+int aggregate(int n, const DBuf<int>& grp, const DBuf<int>& gci, const DBuf<double>& gw,
+              double cf, int max_passes, int qbits, uint64_t seed, DBuf<int>& agg,
+              int* passes, int* rounds, hipStream_t s);
+// Member lists (P^T as CSR) of agg.
+void build_members(int n, int nc, const int* agg, DBuf<int>& aptr, DBuf<int>& amem,
+                   hipStream_t s);
+// Galerkin A_c = P^T A P with sums in the fine CSR order.
+void galerkin(int n, int nc, const int* rp, const int* ci, const double* v, const int* agg,
+              const int* aptr, const int* amem, DCsr& Ac, hipStream_t s);
+
+// Host analysis (host_analysis.cpp)
+// Level schedule of a triangular dependency structure given as per-row
+// dependency lists (host CSR): lower = dependencies have smaller index.
+// level_ptr[l] is the first schedule position of level l (levels padded to 64).
+void make_schedule(const std::vector<int>& dep_rp, const std::vector<int>& dep_ci, bool lower,
+                   std::vector<int>& sched, std::vector<int>& level_ptr, int* levels);
+// Row-wise ILUT(tau) without pivoting on a host CSR; L strictly lower,
+// U with the diagonal first.  Returns GMG_OK / GMG_ERR_ZERO_PIVOT / NONFINITE.
+gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U);
+
+}  // namespace gmg

@@ -1,0 +1,231 @@
+// Krylov-subspace vector kernels of FGMRES: block multi-dot products, the two
+// fused classical Gram-Schmidt passes (CGS2), norms, scaling and the solution
+// update.  Reductions are deterministic: every block writes its partial sums
+// in a fixed order and the last block to finish adds the partials in block
+// order (no floating-point atomics), so repeated runs are bitwise identical.
+#include "gmg_internal.h"
+#include "kcommon.h"
+
+namespace gmg {
+
+constexpr int KB = 256;          // threads per block
+constexpr int KGRID = 512;       // blocks of the reduction kernels
+constexpr int KMAX = 32;         // vectors per fused pass (restart <= 32)
+
+template <int K>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount, double* partial,
+                                                   unsigned* counter, double* result) {
+  __shared__ double sh[KB / 64][K];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kcount) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < KB / 64; ++w) s += sh[w][threadIdx.x];
+    partial[(size_t)blockIdx.x * KMAX + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = atomicAdd(counter, 1u);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    if (threadIdx.x < kcount) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += ld_agent(&partial[(size_t)b * KMAX + threadIdx.x]);
+      result[threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+}
+
+// result[k] = sum_i V[k][i] w[i], k < kc
+template <int K>
+__global__ __launch_bounds__(KB) void k_multidot(const double* __restrict__ V, size_t ld, int kc,
+                                                 const double* __restrict__ w, int64_t n, double* partial,
+                                                 unsigned* counter, double* result) {
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < kc) acc[k] += V[k * ld + i] * wi;
+  }
+  block_reduce_store<K>(acc, kc, partial, counter, result);
+}
+
+// w <- w - sum_k h[k] V[k]; result[k] = V[k] . w_new
+template <int K>
+__global__ __launch_bounds__(KB) void k_update_dot(const double* __restrict__ V, size_t ld, int kc,
+                                                   const double* __restrict__ h, double* __restrict__ w,
+                                                   int64_t n, double* partial, unsigned* counter,
+                                                   double* result) {
+  double acc[K], hk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) { acc[k] = 0.0; hk[k] = k < kc ? h[k] : 0.0; }
+  for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+    double v[K];
+    double s = w[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      v[k] = k < kc ? V[k * ld + i] : 0.0;
+      s -= hk[k] * v[k];
+    }
+    w[i] = s;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += v[k] * s;
+  }
+  block_reduce_store<K>(acc, kc, partial, counter, result);
+}
+
+// w <- w - sum_k h[k] V[k]; result[0] = ||w_new||^2
+template <int K>
+__global__ __launch_bounds__(KB) void k_update_norm(const double* __restrict__ V, size_t ld, int kc,
+                                                    const double* __restrict__ h, double* __restrict__ w,
+                                                    int64_t n, double* partial, unsigned* counter,
+                                                    double* result) {
+  double acc[1] = {0.0}, hk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) hk[k] = k < kc ? h[k] : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+    double s = w[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < kc) s -= hk[k] * V[k * ld + i];
+    w[i] = s;
+    acc[0] += s * s;
+  }
+  block_reduce_store<1>(acc, 1, partial, counter, result);
+}
+
+void red_init(RedWork& rw, hipStream_t s) {
+  rw.blocks = KGRID;
+  rw.partial.alloc((size_t)KGRID * KMAX);
+  rw.counter.alloc(1);
+  rw.result.alloc(4 * KMAX + 8);
+  launch_fill_u32(rw.counter.p, 0u, 1, s);
+}
+
+static unsigned red_grid(int64_t n) {
+  int64_t g = (n + KB - 1) / KB;
+  if (g > KGRID) g = KGRID;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+#define GMG_DISPATCH_K(kc, KERNEL, ...)                                                    \
+  do {                                                                                     \
+    if ((kc) <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                             \
+    else if ((kc) <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);                      \
+    else if ((kc) <= 24) hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__);                      \
+    else hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);                                      \
+  } while (0)
+
+void launch_multidot(const double* V, size_t ld, int k, const double* w, int64_t n, RedWork& rw,
+                     double* result, hipStream_t s) {
+  if (k < 1 || k > KMAX) fail(GMG_ERR_INVALID_ARG, "multidot: bad vector count");
+  GMG_DISPATCH_K(k, k_multidot, dim3(red_grid(n)), dim3(KB), 0, s, V, ld, k, w, n, rw.partial.p, rw.counter.p,
+                 result);
+  HIPCK(hipGetLastError());
+}
+void launch_update_dot(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
+                       double* result, hipStream_t s) {
+  if (k < 1 || k > KMAX) fail(GMG_ERR_INVALID_ARG, "update_dot: bad vector count");
+  GMG_DISPATCH_K(k, k_update_dot, dim3(red_grid(n)), dim3(KB), 0, s, V, ld, k, h, w, n, rw.partial.p,
+                 rw.counter.p, result);
+  HIPCK(hipGetLastError());
+}
+void launch_update_norm(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
+                        double* result, hipStream_t s) {
+  if (k < 1 || k > KMAX) fail(GMG_ERR_INVALID_ARG, "update_norm: bad vector count");
+  GMG_DISPATCH_K(k, k_update_norm, dim3(red_grid(n)), dim3(KB), 0, s, V, ld, k, h, w, n, rw.partial.p,
+                 rw.counter.p, result);
+  HIPCK(hipGetLastError());
+}
+
+__global__ __launch_bounds__(KB) void k_norm2(const double* __restrict__ x, int64_t n, double* partial,
+                                              unsigned* counter, double* result) {
+  double acc[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+    const double v = x[i];
+    acc[0] += v * v;
+  }
+  block_reduce_store<1>(acc, 1, partial, counter, result);
+}
+void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2, dim3(red_grid(n)), dim3(KB), 0, s, x, n, rw.partial.p, rw.counter.p, result);
+  HIPCK(hipGetLastError());
+}
+
+__global__ void k_scale(const double* __restrict__ x, double a, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+void launch_scale(const double* x, double a, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)g), dim3(256), 0, s, x, a, y, n);
+  HIPCK(hipGetLastError());
+}
+
+template <int K>
+__global__ void k_xupdate(double* __restrict__ x, const double* __restrict__ Z, size_t ld, int kc,
+                          const double* __restrict__ c, int64_t n) {
+  double ck[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) ck[k] = k < kc ? c[k] : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = x[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < kc) s += ck[k] * Z[k * ld + i];
+    x[i] = s;
+  }
+}
+void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n, hipStream_t s) {
+  if (n <= 0 || k <= 0) return;
+  if (k > KMAX) fail(GMG_ERR_INVALID_ARG, "xupdate: bad vector count");
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  GMG_DISPATCH_K(k, k_xupdate, dim3((unsigned)g), dim3(256), 0, s, x, Z, ld, k, c, n);
+  HIPCK(hipGetLastError());
+}
+
+__global__ void k_get_col(const double* __restrict__ X, int nrhs, int col, double* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = X[i * nrhs + col];
+}
+__global__ void k_set_col(double* __restrict__ X, int nrhs, int col, const double* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    X[i * nrhs + col] = x[i];
+}
+void launch_get_col(const double* X, int nrhs, int col, double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_get_col, dim3((unsigned)g), dim3(256), 0, s, X, nrhs, col, x, n);
+  HIPCK(hipGetLastError());
+}
+void launch_set_col(double* X, int nrhs, int col, const double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_set_col, dim3((unsigned)g), dim3(256), 0, s, X, nrhs, col, x, n);
+  HIPCK(hipGetLastError());
+}
+
+}  // namespace gmg

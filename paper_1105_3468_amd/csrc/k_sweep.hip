@@ -1,0 +1,192 @@
+// Synchronisation-free triangular sweeps (smoother and coarse solve) and the
+// level-synchronous ILU(0) factorisation.
+//
+// A sweep computes out[r] = (rhs[r] - sum_q dval[q] * out[dcol[q]]) * dinv[r]
+// for every row of a triangular factor.  Rows are visited in a schedule of
+// dependency levels; each level is padded to a multiple of 64 so a wave never
+// holds two rows where one depends on the other.  Waves take 64-row chunks
+// from a global ticket counter in schedule order, so every row a wave waits
+// for belongs to a chunk that an already-running wave holds: the sweep always
+// makes progress.  A result is published with one relaxed agent-scope store
+// and doubles as its own ready flag: consumers poll with relaxed agent-scope
+// loads until the value differs from the NaN sentinel the buffer was reset to.
+// Every wait is bounded by a wall-clock limit; a timeout raises a device flag
+// that makes all other waits give up, so the grid always drains.
+#include "gmg_internal.h"
+#include "kcommon.h"
+
+namespace gmg {
+
+template <class T>
+__device__ __forceinline__ T wait_ready(const T* p, int* abort_flag, uint64_t limit) {
+  T v = ld_agent(p);
+  if (!is_sentinel(v)) return v;
+  const uint64_t t0 = wall_clock64();
+  unsigned it = 0;
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    v = ld_agent(p);
+    if (!is_sentinel(v)) return v;
+    if ((++it & 31u) == 0) {
+      if (ld_agent(abort_flag)) return __builtin_nan("");
+      if (wall_clock64() - t0 > limit) {
+        st_agent(abort_flag, 1);
+        return __builtin_nan("");
+      }
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T not_sentinel(T v) {
+  // a computed value equal to the sentinel's bits would never be seen as
+  // ready; replace it by the canonical NaN (only reachable from NaN inputs)
+  return is_sentinel(v) ? (T)__builtin_nan("") : v;
+}
+
+template <class T, class TR, bool DIAG>
+__global__ __launch_bounds__(256) void k_sweep(const int* __restrict__ sched, const int* __restrict__ dp,
+                                               const int* __restrict__ dcol, const T* __restrict__ dval,
+                                               const T* __restrict__ dinv, const TR* rhs,
+                                               T* out, TR* reset_rhs, unsigned nchunks,
+                                               unsigned* ticket, unsigned base, int* abort_flag,
+                                               uint64_t limit) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    unsigned t = 0;
+    if (lane == 0) t = atomicAdd(ticket, 1u) - base;
+    t = __shfl(t, 0, 64);
+    if (t >= nchunks) break;
+    const int p = (int)(t * 64u) + lane;
+    const int r = sched[p];
+    if (r >= 0) {
+      // rhs and reset_rhs may be the same buffer: read before the reset
+      T acc = (T)rhs[r];
+      if (reset_rhs) reset_rhs[r] = sentinel_of<TR>(0);
+      const int q1 = dp[p + 1];
+      for (int q = dp[p]; q < q1; ++q) {
+        const T v = wait_ready(out + dcol[q], abort_flag, limit);
+        acc -= dval[q] * v;
+      }
+      if (DIAG) acc *= dinv[r];
+      st_agent(out + r, not_sentinel(acc));
+    }
+  }
+}
+
+static uint64_t wall_limit_ticks() {
+  static uint64_t ticks = 0;
+  if (!ticks) {
+    int dev = 0, khz = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
+      (void)hipGetLastError();
+      khz = 100000;  // 100 MHz
+    }
+    ticks = (uint64_t)khz * 1000ull * 4ull;  // 4 seconds
+  }
+  return ticks;
+}
+
+template <class T>
+void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64, T* out,
+                  T* reset_rhs, int waves, int* abort_flag, hipStream_t s) {
+  const unsigned nchunks = (unsigned)(sw.nsched / 64);
+  if (nchunks == 0) return;
+  unsigned w = waves > 0 ? (unsigned)waves : 2048u;
+  if (w > nchunks) w = nchunks;
+  const unsigned blocks = (w + 3) / 4;
+  const unsigned used = blocks * 4;  // every wave takes exactly one ticket that ends it
+  const uint64_t lim = wall_limit_ticks();
+  if (rhs_is_f64 && sizeof(T) == 4) {
+    // FP32 sweep with an FP64 right-hand side (first sweep of the FP32 cycle)
+    if (sw.has_diag)
+      hipLaunchKernelGGL((k_sweep<T, double, true>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
+                         sw.dcol.p, dval, dinv, (const double*)rhs, out, (double*)nullptr, nchunks,
+                         sw.ticket.p, sw.ticket_base, abort_flag, lim);
+    else
+      hipLaunchKernelGGL((k_sweep<T, double, false>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
+                         sw.dcol.p, dval, dinv, (const double*)rhs, out, (double*)nullptr, nchunks,
+                         sw.ticket.p, sw.ticket_base, abort_flag, lim);
+  } else {
+    if (sw.has_diag)
+      hipLaunchKernelGGL((k_sweep<T, T, true>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
+                         sw.dcol.p, dval, dinv, (const T*)rhs, out, reset_rhs, nchunks, sw.ticket.p,
+                         sw.ticket_base, abort_flag, lim);
+    else
+      hipLaunchKernelGGL((k_sweep<T, T, false>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
+                         sw.dcol.p, dval, dinv, (const T*)rhs, out, reset_rhs, nchunks, sw.ticket.p,
+                         sw.ticket_base, abort_flag, lim);
+  }
+  HIPCK(hipGetLastError());
+  sw.ticket_base += nchunks + used;
+}
+template void launch_sweep<double>(Sweep&, const double*, const double*, const void*, bool, double*, double*,
+                                   int, int*, hipStream_t);
+template void launch_sweep<float>(Sweep&, const float*, const float*, const void*, bool, float*, float*, int,
+                                  int*, hipStream_t);
+
+// ------------------------------------------------------------------ ILU(0)
+// One launch per dependency level of L0: every row of the level runs the IKJ
+// elimination on its own entries, reading only rows of earlier levels, which
+// are final.  Operation order and rounding follow the plain definition (no
+// FMA contraction), so the factors are reproducible bit for bit.
+#pragma clang fp contract(off)
+__global__ void k_ilu0_level(const int* __restrict__ rows, int count, const int* __restrict__ rp,
+                             const int* __restrict__ ci, const int* __restrict__ dpos, double* a, int* bad) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int i = rows[t];
+  if (i < 0) return;
+  const int p0 = rp[i], p1 = rp[i + 1], di = dpos[i];
+  for (int p = p0; p < di; ++p) {
+    const int k = ci[p];
+    const double lik = a[p] / a[dpos[k]];
+    a[p] = lik;
+    int lo = p + 1;  // entries of row i with column > k start after p
+    for (int r = dpos[k] + 1; r < rp[k + 1]; ++r) {
+      const int j = ci[r];
+      // row i columns ascending and U row k ascending: merge walk
+      while (lo < p1 && ci[lo] < j) ++lo;
+      if (lo >= p1) break;
+      if (ci[lo] == j) a[lo] = a[lo] - lik * a[r];
+    }
+  }
+  const double d = a[di];
+  if (d == 0.0) atomicOr(bad, 1);
+  else if (!isfinite(d)) atomicOr(bad, 2);
+}
+#pragma clang fp contract(on)
+
+void launch_ilu0_level(const int* rows, int count, const int* rp, const int* ci, const int* dpos, double* a,
+                       int* bad, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ilu0_level, dim3((count + 255) / 256), dim3(256), 0, s, rows, count, rp, ci, dpos, a,
+                     bad);
+  HIPCK(hipGetLastError());
+}
+
+// ------------------------------------------------- Jacobi sweep on a factor
+// yout[i] = (b[i] - sum_{j != i} F_ij yin[j]) * (dinv ? dinv[i] : 1)
+__global__ void k_jacobi(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                         const double* __restrict__ v, const double* __restrict__ dinv,
+                         const double* __restrict__ b, const double* __restrict__ yin,
+                         double* __restrict__ yout) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = b[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    const int j = ci[p];
+    if (j != i) s -= v[p] * yin[j];
+  }
+  yout[i] = dinv ? s * dinv[i] : s;
+}
+
+void launch_jacobi(int n, const int* rp, const int* ci, const double* v, const double* dinv, const double* b,
+                   const double* yin, double* yout, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_jacobi, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, ci, v, dinv, b, yin, yout);
+  HIPCK(hipGetLastError());
+}
+
+}  // namespace gmg

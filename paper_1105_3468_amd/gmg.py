@@ -1,0 +1,335 @@
+"""ctypes binding of libgmg.so (the C ABI in include/gmg.h).
+
+Argument marshalling only: every step of setup and solve runs in the HIP
+library.  Device arrays are torch tensors on the ROCm device; PyTorch provides
+the memory and the stream, nothing else.  There is no fallback: if the
+library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmg.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_INVALID_ARG, ERR_HIP, ERR_OOM, ERR_ZERO_PIVOT = -1, -2, -3, -4
+ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOT_SETUP, ERR_STALLED = -5, -6, -7, -8
+
+EXPORTED = [
+    "gmg_default_options", "gmg_setup", "gmg_solve", "gmg_solve_adjoint", "gmg_apply_precond",
+    "gmg_spmv", "gmg_get_info", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
+    "gmg_get_ilut", "gmg_set_stream", "gmg_profile_enable", "gmg_profile_read",
+    "gmg_profile_name", "gmg_destroy", "gmg_last_error", "gmg_fv_nnz", "gmg_fv_assemble",
+    "gmg_fv_kappa_grad", "gmg_pattern_grad",
+]
+
+
+class Options(C.Structure):
+    _fields_ = [("cf", C.c_double), ("max_passes", C.c_int), ("match_qbits", C.c_int),
+                ("hash_seed", C.c_uint64), ("ilut_tau", C.c_double), ("coarse_mode", C.c_int),
+                ("coarse_sweeps", C.c_int), ("restart", C.c_int), ("maxit", C.c_int),
+                ("precond_fp32", C.c_int), ("x0_given", C.c_int), ("sweep_waves", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("passes", C.c_int), ("rounds", C.c_int), ("levels_L0", C.c_int),
+                ("levels_U0", C.c_int), ("levels_Lc", C.c_int), ("levels_Uc", C.c_int),
+                ("n", C.c_int64), ("nnz", C.c_int64), ("n_coarse", C.c_int64),
+                ("nnz_coarse", C.c_int64), ("nnz_lc", C.c_int64), ("nnz_uc", C.c_int64),
+                ("relres_true", C.c_double), ("relres_est", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class GmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gmg status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libgmg.so (built by ``paper_1105_3468_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1105_3468_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "gmg_default_options": (None, [C.POINTER(Options)]),
+        "gmg_setup": (I, [C.POINTER(P), I64, I64, P, P, P, C.POINTER(Options), P]),
+        "gmg_solve": (I, [P, P, P, I, D, C.POINTER(Options), C.POINTER(Info)]),
+        "gmg_solve_adjoint": (I, [P, P, P, I, D, C.POINTER(Options), C.POINTER(Info)]),
+        "gmg_apply_precond": (I, [P, P, P, I, I]),
+        "gmg_spmv": (I, [P, I, P, P]),
+        "gmg_get_info": (I, [P, C.POINTER(Info)]),
+        "gmg_get_aggregates": (I, [P, P]),
+        "gmg_get_coarse": (I, [P, P, P, P]),
+        "gmg_get_ilu0": (I, [P, P]),
+        "gmg_get_ilut": (I, [P, P, P, P, P, P, P]),
+        "gmg_set_stream": (I, [P, P]),
+        "gmg_profile_enable": (I, [P, I]),
+        "gmg_profile_read": (I, [P, I, P, P, P, P]),
+        "gmg_profile_name": (C.c_char_p, [I]),
+        "gmg_destroy": (None, [P]),
+        "gmg_last_error": (C.c_char_p, []),
+        "gmg_fv_nnz": (I64, [I, I]),
+        "gmg_fv_assemble": (I, [I, I, P, P, P, P, P, P, P, P]),
+        "gmg_fv_kappa_grad": (I, [I, I, P, P, P, I, P, P]),
+        "gmg_pattern_grad": (I, [I64, P, P, P, P, I, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code, what=""):
+    if code < 0:
+        msg = load().gmg_last_error().decode(errors="replace")
+        raise GmgError(code, f"{what}: {msg}" if what else msg)
+    return code
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().gmg_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the gmg library needs a ROCm GPU; none is visible")
+    return torch
+
+
+def _dev(t, dtype):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    t = t.to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class SolveResult:
+    status: int
+    info: dict
+
+
+class Solver:
+    """Two-grid matching-AMG preconditioned FGMRES on one GPU.
+
+    ``Solver(rowptr, col, val, **options)`` runs the setup (aggregation,
+    Galerkin, ILU(0), ILUT, sweep schedules) in libgmg; ``solve`` and
+    ``solve_adjoint`` run the Krylov iteration.
+    """
+
+    def __init__(self, rowptr, col, val, stream=None, **opts):
+        torch = _torch()
+        lib = load()
+        self._torch = torch
+        self.rowptr = _dev(rowptr, torch.int32)
+        self.col = _dev(col, torch.int32)
+        self.val = _dev(val, torch.float64)
+        self.n = self.rowptr.numel() - 1
+        self.nnz = self.col.numel()
+        self.opts = default_options(**opts)
+        self._stream = stream
+        h = C.c_void_p()
+        code = lib.gmg_setup(C.byref(h), self.n, self.nnz, _ptr(self.rowptr), _ptr(self.col),
+                             _ptr(self.val), C.byref(self.opts), _stream(stream))
+        _check(code, "setup")
+        self._h = h
+        self.setup_info = self.info()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- queries
+    def info(self) -> dict:
+        i = Info()
+        _check(load().gmg_get_info(self._h, C.byref(i)), "info")
+        return i.as_dict()
+
+    def aggregates(self):
+        a = self._torch.empty(self.n, dtype=self._torch.int32, device="cuda")
+        _check(load().gmg_get_aggregates(self._h, _ptr(a)), "aggregates")
+        return a
+
+    def coarse(self):
+        inf = self.info()
+        nc, nz = inf["n_coarse"], inf["nnz_coarse"]
+        t = self._torch
+        rp = t.empty(nc + 1, dtype=t.int32, device="cuda")
+        ci = t.empty(max(nz, 1), dtype=t.int32, device="cuda")
+        v = t.empty(max(nz, 1), dtype=t.float64, device="cuda")
+        _check(load().gmg_get_coarse(self._h, _ptr(rp), _ptr(ci), _ptr(v)), "coarse")
+        return rp, ci[:nz], v[:nz]
+
+    def ilu0(self):
+        v = self._torch.empty(self.nnz, dtype=self._torch.float64, device="cuda")
+        _check(load().gmg_get_ilu0(self._h, _ptr(v)), "ilu0")
+        return v
+
+    def ilut(self):
+        inf = self.info()
+        nc, nl, nu = inf["n_coarse"], inf["nnz_lc"], inf["nnz_uc"]
+        t = self._torch
+        lrp = t.empty(nc + 1, dtype=t.int32, device="cuda")
+        lci = t.empty(max(nl, 1), dtype=t.int32, device="cuda")
+        lv = t.empty(max(nl, 1), dtype=t.float64, device="cuda")
+        urp = t.empty(nc + 1, dtype=t.int32, device="cuda")
+        uci = t.empty(max(nu, 1), dtype=t.int32, device="cuda")
+        uv = t.empty(max(nu, 1), dtype=t.float64, device="cuda")
+        _check(load().gmg_get_ilut(self._h, _ptr(lrp), _ptr(lci), _ptr(lv), _ptr(urp), _ptr(uci),
+                                   _ptr(uv)), "ilut")
+        return (lrp, lci[:nl], lv[:nl]), (urp, uci[:nu], uv[:nu])
+
+    # ------------------------------------------------------------- compute
+    def _opts(self, x0_given=None, maxit=None, restart=None, precond_fp32=None):
+        o = Options.from_buffer_copy(self.opts)
+        if x0_given is not None:
+            o.x0_given = int(x0_given)
+        if maxit is not None:
+            o.maxit = int(maxit)
+        if restart is not None:
+            o.restart = int(restart)
+        if precond_fp32 is not None:
+            o.precond_fp32 = int(precond_fp32)
+        return o
+
+    def _solve(self, fn, b, tol, x0, maxit, restart, fp32):
+        t = self._torch
+        b = _dev(b, t.float64)
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        if x0 is not None:
+            x = _dev(x0, t.float64).clone()
+        else:
+            x = t.empty_like(b)
+        o = self._opts(x0 is not None, maxit, restart, fp32)
+        info = Info()
+        code = fn(self._h, _ptr(b), _ptr(x), nrhs, float(tol), C.byref(o), C.byref(info))
+        _check(code, "solve")
+        return x, SolveResult(code, info.as_dict())
+
+    def solve(self, b, tol=1e-8, x0=None, maxit=None, restart=None, precond_fp32=None):
+        """x with ||b - A x|| / ||b|| < tol (per column of b, shape (N,) or (N, nrhs))."""
+        return self._solve(load().gmg_solve, b, tol, x0, maxit, restart, precond_fp32)
+
+    def solve_adjoint(self, g, tol=1e-8, x0=None, maxit=None, restart=None):
+        """lambda with A^T lambda = g."""
+        return self._solve(load().gmg_solve_adjoint, g, tol, x0, maxit, restart, 0)
+
+    def apply(self, z, precision=0, adjoint=False):
+        t = self._torch
+        z = _dev(z, t.float64)
+        q = t.empty_like(z)
+        _check(load().gmg_apply_precond(self._h, _ptr(z), _ptr(q), int(precision), int(adjoint)), "apply")
+        return q
+
+    def spmv(self, x, transposed=False):
+        t = self._torch
+        x = _dev(x, t.float64)
+        y = t.empty_like(x)
+        _check(load().gmg_spmv(self._h, int(transposed), _ptr(x), _ptr(y)), "spmv")
+        return y
+
+    # ----------------------------------------------------------- profiling
+    def profile(self, enable: bool):
+        _check(load().gmg_profile_enable(self._h, int(enable)), "profile")
+
+    def profile_read(self) -> dict:
+        cap = 16
+        cnt = C.c_int(0)
+        launches = (C.c_int64 * cap)()
+        ms = (C.c_double * cap)()
+        by = (C.c_double * cap)()
+        lib = load()
+        _check(lib.gmg_profile_read(self._h, cap, C.cast(C.pointer(cnt), C.c_void_p),
+                                    C.cast(launches, C.c_void_p), C.cast(ms, C.c_void_p),
+                                    C.cast(by, C.c_void_p)), "profile_read")
+        out = {}
+        for c in range(min(cnt.value, cap)):
+            out[lib.gmg_profile_name(c).decode()] = dict(launches=int(launches[c]), ms=float(ms[c]),
+                                                         bytes=float(by[c]))
+        return out
+
+
+# ------------------------------------------------------------------ FV ops
+def fv_assemble(n, dim, kappa, vel, stream=None):
+    """A(kappa) of the FV discretisation on the GPU; vel = list of face-velocity
+    tensors (x, y[, z]).  Returns (rowptr, col, val) device tensors."""
+    torch = _torch()
+    lib = load()
+    kap = _dev(kappa, torch.float64)
+    vs = [_dev(v, torch.float64).reshape(-1) for v in vel]
+    N = n ** dim
+    nnz = lib.gmg_fv_nnz(n, dim)
+    rp = torch.empty(N + 1, dtype=torch.int32, device="cuda")
+    ci = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    va = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    vz = _ptr(vs[2]) if dim == 3 else None
+    _check(lib.gmg_fv_assemble(n, dim, _ptr(kap), _ptr(vs[0]), _ptr(vs[1]), vz, _ptr(rp), _ptr(ci),
+                               _ptr(va), _stream(stream)), "fv_assemble")
+    return rp, ci, va
+
+
+def fv_kappa_grad(n, dim, kappa, lam, x, stream=None):
+    torch = _torch()
+    kap = _dev(kappa, torch.float64)
+    lam = _dev(lam, torch.float64)
+    x = _dev(x, torch.float64)
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    g = torch.empty(n ** dim, dtype=torch.float64, device="cuda")
+    _check(load().gmg_fv_kappa_grad(n, dim, _ptr(kap), _ptr(lam), _ptr(x), nrhs, _ptr(g),
+                                    _stream(stream)), "fv_kappa_grad")
+    return g
+
+
+def pattern_grad(rowptr, col, lam, x, stream=None):
+    torch = _torch()
+    rowptr = _dev(rowptr, torch.int32)
+    col = _dev(col, torch.int32)
+    lam = _dev(lam, torch.float64)
+    x = _dev(x, torch.float64)
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    g = torch.empty(col.numel(), dtype=torch.float64, device="cuda")
+    _check(load().gmg_pattern_grad(rowptr.numel() - 1, _ptr(rowptr), _ptr(col), _ptr(lam), _ptr(x),
+                                   nrhs, _ptr(g), _stream(stream)), "pattern_grad")
+    return g

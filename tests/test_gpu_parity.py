@@ -1,0 +1,250 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: integer results (aggregates, patterns) bit-exact; setup values that the
+definition fixes in FP64 without multiplications (A_c sums) bit-exact; ILU(0)
+and ILUT values bit-exact (same operation order, no contraction); one
+preconditioner application in FP64 within 1e-12 relative (FMA contraction and
+reciprocal-multiply in the sweeps: a few ulps per row, amplified by at most the
+factors' growth); iterates at equal step counts within ||A (x - x_oracle)|| /
+||b|| <= 1e-10; converged solves at true relative residual < tol.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_1105_3468_amd import GmgError, Solver  # noqa: E402
+from paper_1105_3468_amd import gmg as G  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "fv2d_64": lambda: W.make("fv2d_64"),
+    "fv2d_rot_96": lambda: W.scaled("fv2d_rot", 96),
+    "fv3d_20": lambda: W.scaled("fv3d", 20),
+    "rgg_3001": lambda: W.scaled("rgg", 3001),
+    "fv2d_37": lambda: W.fv_problem(37, 2, 1, -2, 2, W.velocity_const((1.0, 0.5)), 5),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    name = request.param
+    _say(f"[case] {name}")
+    p = CASES[name]()
+    O = oracle.Oracle(p.rowptr, p.col, p.val)
+    S = Solver(p.rowptr, p.col, p.val)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    return name, p, O, S, A
+
+
+def test_aggregates_bit_exact(case):
+    name, p, O, S, A = case
+    agg = S.aggregates().cpu().numpy()
+    assert np.array_equal(agg, O.aggregates())
+    inf = S.info()
+    assert inf["n_coarse"] == O.nc and inf["passes"] == O.passes and inf["rounds"] == O.rounds
+
+
+def test_coarse_matrix_bit_exact(case):
+    name, p, O, S, A = case
+    rp, ci, v = (t.cpu().numpy() for t in S.coarse())
+    orp, oci, ov = O.coarse()
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    assert np.array_equal(v.view(np.uint64), ov.view(np.uint64))
+
+
+def test_ilu0_bit_exact(case):
+    name, p, O, S, A = case
+    v = S.ilu0().cpu().numpy()
+    assert np.array_equal(v.view(np.uint64), O.ilu0().view(np.uint64))
+
+
+def test_ilut_bit_exact(case):
+    name, p, O, S, A = case
+    (lrp, lci, lv), (urp, uci, uv) = S.ilut()
+    (olrp, olci, olv), (ourp, ouci, ouv) = O.ilut()
+    assert np.array_equal(lrp.cpu().numpy(), olrp) and np.array_equal(lci.cpu().numpy(), olci)
+    assert np.array_equal(urp.cpu().numpy(), ourp) and np.array_equal(uci.cpu().numpy(), ouci)
+    assert np.array_equal(lv.cpu().numpy(), olv) and np.array_equal(uv.cpu().numpy(), ouv)
+
+
+def test_spmv(case):
+    name, p, O, S, A = case
+    x = np.random.default_rng(1).uniform(-1, 1, p.n_rows)
+    for tr in (False, True):
+        y = S.spmv(torch.as_tensor(x, device="cuda"), transposed=tr).cpu().numpy()
+        ref = O.spmv(x, transposed=tr)
+        sc = np.abs(A).dot(np.abs(x)) if not tr else np.abs(A).T.dot(np.abs(x))
+        assert np.all(np.abs(y - ref) <= 1e-14 * sc + 1e-300)
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_preconditioner_fp64(case, adjoint):
+    name, p, O, S, A = case
+    rng = np.random.default_rng(2)
+    for _ in range(2):
+        z = rng.uniform(-1, 1, p.n_rows)
+        q = S.apply(torch.as_tensor(z, device="cuda"), precision=0, adjoint=adjoint).cpu().numpy()
+        ref = O.apply_adjoint(z) if adjoint else O.apply(z, 0)
+        assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref), name
+
+
+def test_preconditioner_fp32(case):
+    """FP32 cycle vs the oracle's FP32 cycle (same roundings of the data, same
+    operations, different summation order/contraction): agree to a few FP32
+    ulps amplified by the sweeps; and both within FP32 accuracy of FP64."""
+    name, p, O, S, A = case
+    z = np.random.default_rng(3).uniform(-1, 1, p.n_rows)
+    q = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
+    ref32 = O.apply(z, 1)
+    ref64 = O.apply(z, 0)
+    e32 = np.linalg.norm(q - ref32) / np.linalg.norm(ref32)
+    e64 = np.linalg.norm(ref32 - ref64) / np.linalg.norm(ref64)
+    assert e32 <= max(1e-4, 10 * e64), (e32, e64)
+
+
+def test_solve_converges_and_matches_oracle(case):
+    name, p, O, S, A = case
+    b = p.b[:, 0]
+    tol = 1e-8
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=tol)
+    xh = x.cpu().numpy()
+    rel = np.linalg.norm(b - A @ xh) / np.linalg.norm(b)
+    assert res.status == G.OK and rel < tol, (name, rel, res.info)
+    xo, info = O.solve(b, tol=tol)
+    assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
+    assert np.linalg.norm(A @ (xh - xo)) / np.linalg.norm(b) <= 2 * tol
+
+
+@pytest.mark.parametrize("steps", [1, 7, 45])
+def test_iterates_equal_steps(case, steps):
+    """Same number of FGMRES steps (tol = 0), including a restart at 30."""
+    name, p, O, S, A = case
+    b = p.b[:, 0]
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=0.0, maxit=steps)
+    xo, info = O.solve(b, tol=0.0, maxit=steps)
+    assert res.info["iters"] == info.steps == steps
+    d = np.linalg.norm(A @ (x.cpu().numpy() - xo)) / np.linalg.norm(b)
+    assert d <= 1e-10, (name, steps, d)
+
+
+def test_adjoint_solve(case):
+    name, p, O, S, A = case
+    g = np.random.default_rng(4).uniform(-1, 1, p.n_rows)
+    lam, res = S.solve_adjoint(torch.as_tensor(g, device="cuda"), tol=1e-10)
+    lh = lam.cpu().numpy()
+    assert np.linalg.norm(g - A.T @ lh) / np.linalg.norm(g) < 1e-10
+    lo, info = O.solve(g, tol=0.0, maxit=5, adjoint=True)
+    l5, r5 = S.solve_adjoint(torch.as_tensor(g, device="cuda"), tol=0.0, maxit=5)
+    assert np.linalg.norm(A.T @ (l5.cpu().numpy() - lo)) / np.linalg.norm(g) <= 1e-10
+
+
+def test_fp32_preconditioned_solve(case):
+    name, p, O, S, A = case
+    b = p.b[:, 0]
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, precond_fp32=1)
+    xh = x.cpu().numpy()
+    assert res.status == G.OK
+    assert np.linalg.norm(b - A @ xh) / np.linalg.norm(b) < 1e-8
+    xo, _ = O.solve(b, tol=1e-8)
+    assert np.linalg.norm(A @ (xh - xo)) / np.linalg.norm(b) <= 2e-8
+
+
+def test_multi_rhs_and_x0(case):
+    name, p, O, S, A = case
+    B = np.random.default_rng(5).uniform(-1, 1, (p.n_rows, 3))
+    X, res = S.solve(torch.as_tensor(B, device="cuda"), tol=1e-9)
+    Xh = X.cpu().numpy()
+    for c in range(3):
+        assert np.linalg.norm(B[:, c] - A @ Xh[:, c]) / np.linalg.norm(B[:, c]) < 1e-9
+    # restart from the solution: converges with zero steps
+    X2, res2 = S.solve(torch.as_tensor(B, device="cuda"), tol=1e-9, x0=X)
+    assert res2.info["iters"] == 0
+
+
+def test_deterministic(case):
+    name, p, O, S, A = case
+    b = torch.as_tensor(p.b[:, 0], device="cuda")
+    x1, r1 = S.solve(b, tol=1e-8)
+    x2, r2 = S.solve(b, tol=1e-8)
+    assert torch.equal(x1, x2) and r1.info["iters"] == r2.info["iters"]
+
+
+# ------------------------------------------------------------- edge cases
+def test_tiny_and_degenerate():
+    _say("[case] tiny")
+    # 1x1, diagonal matrices, a 2x2 that needs no pivoting
+    for A in (np.array([[3.0]]), np.diag([1.0, 2.0, 3.0, 4.0]),
+              np.array([[4.0, -1.0], [-2.0, 5.0]])):
+        S_ = sp.csr_matrix(A)
+        S_.sort_indices()
+        rp, ci, v = S_.indptr.astype(np.int32), S_.indices.astype(np.int32), S_.data
+        s = Solver(rp, ci, v)
+        o = oracle.Oracle(rp, ci, v)
+        assert np.array_equal(s.aggregates().cpu().numpy(), o.aggregates())
+        b = np.arange(1, A.shape[0] + 1, dtype=float)
+        x, res = s.solve(torch.as_tensor(b, device="cuda"), tol=1e-12)
+        assert np.allclose(A @ x.cpu().numpy(), b, rtol=1e-11)
+    # zero right-hand side: x = 0 without iterations
+    p = W.scaled("fv2d", 16)
+    s = Solver(p.rowptr, p.col, p.val)
+    x, res = s.solve(torch.zeros(p.n_rows, dtype=torch.float64, device="cuda"))
+    assert res.info["iters"] == 0 and float(x.abs().max()) == 0.0
+
+
+def test_error_paths():
+    _say("[case] errors")
+    p = W.scaled("fv2d", 16)
+    # unsorted columns
+    ci = p.col.copy()
+    ci[1], ci[2] = ci[2], ci[1]
+    with pytest.raises(GmgError) as e:
+        Solver(p.rowptr, ci, p.val)
+    assert e.value.code == G.ERR_INVALID_ARG
+    # missing diagonal
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    with pytest.raises(GmgError) as e:
+        Solver(rp, np.array([1, 0], dtype=np.int32), np.array([1.0, 1.0]))
+    assert e.value.code == G.ERR_INVALID_ARG
+    # non-finite entry
+    v = p.val.copy()
+    v[5] = np.inf
+    with pytest.raises(GmgError) as e:
+        Solver(p.rowptr, p.col, v)
+    assert e.value.code == G.ERR_NONFINITE
+    # zero pivot in ILU(0)
+    with pytest.raises(GmgError) as e:      # explicit zero diagonal entry
+        Solver(np.array([0, 2, 4], dtype=np.int32), np.array([0, 1, 0, 1], dtype=np.int32),
+               np.array([0.0, 1.0, 1.0, 1.0]), cf=1.0)
+    assert e.value.code == G.ERR_ZERO_PIVOT
+    # NaN right-hand side, maxit, bad restart
+    s = Solver(p.rowptr, p.col, p.val)
+    b = np.ones(p.n_rows)
+    b[3] = np.nan
+    with pytest.raises(GmgError) as e:
+        s.solve(torch.as_tensor(b, device="cuda"))
+    assert e.value.code == G.ERR_NONFINITE
+    x, res = s.solve(torch.as_tensor(p.b[:, 0], device="cuda"), tol=1e-14, maxit=2)
+    assert res.status == G.NOT_CONVERGED and res.info["iters"] == 2
+    with pytest.raises(GmgError):
+        s.solve(torch.as_tensor(p.b[:, 0], device="cuda"), restart=100)
+    # the handle still works after errors
+    x, res = s.solve(torch.as_tensor(p.b[:, 0], device="cuda"), tol=1e-8)
+    assert res.status == G.OK
