@@ -1,0 +1,223 @@
+"""Benchmark: time to a 1e-8 relative residual of the two-grid matching-AMG
+FGMRES solve on one MI355X, with per-kernel HBM roofline figures.
+
+A step is one full pass of the hot path on the workload: setup (graph,
+handshake matching, Galerkin, ILU(0), ILUT, sweep schedules) plus the FGMRES
+solve to ||b - A x|| / ||b|| < 1e-8, in FP64 (the metric) and then in the
+FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
+before the timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--no-cpu-baseline] [--profile-steps]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Settings of the benchmarked solve: no restart (the paper's GMRES runs without
+# restarting) and ILUT drop tolerance 1e-6 (the value the paper reports as
+# working well in practice); see the design doc for why the workload needs both.
+SOLVE_OPTS = dict(cf=4.0, ilut_tau=1e-6, restart=600, maxit=600)
+TOL = 1e-8
+
+WORKLOAD_DESC = {
+    "fv2d_1024": ("2D cell-centred FV convection-diffusion, 1024x1024 cells (1,048,576 unknowns, "
+                  "5,238,784 nnz), kappa log-uniform in [1e-4,1e4] on 64x64 blocks, rotating "
+                  "velocity x10, Dirichlet y=0,1, Neumann elsewhere, one RHS U(-1,1), seed 0"),
+    "fv3d_128": ("3D cell-centred FV convection-diffusion, 128^3 cells (2,097,152 unknowns, "
+                 "14,581,760 nnz), kappa log-uniform in [1e-6,1e6] on 16^3 blocks, a=(1,1,1)"),
+    "rgg_500k": ("random geometric graph, 500k nodes, directed kNN k in {6..14}, nonsymmetric "
+                 "diagonally dominant M-matrix"),
+    "fv2d_64": "2D FV convection-diffusion 64x64 (4096 unknowns), small oracle-sized case",
+}
+
+
+def _alg_bytes_doc():
+    return ("spmv 12*nnz+20*N (FP64 CSR, int32 indices); sweep: 12 per dependency entry + "
+            "(8 + rhs + 2*val [+ diag] [+ reset]) per row; resid_restrict 12*nnz + 40*N + 20*N_c; "
+            "ortho 8*N*(3k+6) for k basis vectors")
+
+
+def run_cpu_baseline(p, budget_s=30.0):
+    """The oracle, as it stands, on this host: setup plus a bounded number of
+    FGMRES steps, scaled to the full step count of the GPU solve."""
+    import oracle
+    import numpy as np
+    oracle.build()
+    t0 = time.perf_counter()
+    O = oracle.Oracle(p.rowptr, p.col, p.val, cf=SOLVE_OPTS["cf"], ilut_tau=SOLVE_OPTS["ilut_tau"])
+    t_setup = time.perf_counter() - t0
+    # time a first bounded chunk to size the sample
+    k0 = 5
+    t0 = time.perf_counter()
+    _, info = O.solve(p.b[:, 0], tol=0.0, maxit=k0, restart=SOLVE_OPTS["restart"])
+    t_k0 = time.perf_counter() - t0
+    per = t_k0 / k0
+    k = max(k0, min(SOLVE_OPTS["maxit"], int((budget_s - t_setup) / max(per, 1e-9) / 2)))
+    t0 = time.perf_counter()
+    _, info = O.solve(p.b[:, 0], tol=TOL, maxit=k, restart=SOLVE_OPTS["restart"])
+    t_k = time.perf_counter() - t0
+    return dict(t_setup=t_setup, steps=info.steps, t_steps=t_k, converged=info.status == 0,
+                relres=info.relres)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fv2d_1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1105_3468_amd import Solver
+
+    dev = torch.device("cuda:0")
+    p = W.make(args.workload)
+    rp = torch.as_tensor(p.rowptr, device=dev)
+    ci = torch.as_tensor(p.col, device=dev)
+    va = torch.as_tensor(p.val, device=dev)
+    b = torch.as_tensor(p.b[:, 0], device=dev)
+    torch.cuda.synchronize()
+
+    def one_step(fp32: bool, profile: bool):
+        S = Solver(rp, ci, va, **{k: v for k, v in SOLVE_OPTS.items() if k in ("cf", "ilut_tau")})
+        if profile:
+            S.profile(True)
+        x, res = S.solve(b, tol=TOL, restart=SOLVE_OPTS["restart"], maxit=SOLVE_OPTS["maxit"],
+                         precond_fp32=int(fp32))
+        prof = S.profile_read() if profile else None
+        return S, x, res, prof
+
+    for w in range(args.warmup):
+        one_step(False, False)
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    # timed: FP64 (the metric)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, profs = [], []
+    for k in range(args.steps):
+        S, x, res, prof = one_step(False, True)
+        infos.append(res.info)
+        profs.append(prof)
+        print(f"[bench] step {k + 1}/{args.steps}: its={res.info['iters']} relres={res.info['relres_true']:.2e} "
+              f"setup={S.setup_info['setup_ms']:.1f}ms solve={res.info['solve_ms']:.1f}ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec_per_step = (t1 - t0) / args.steps
+
+    # check the answer with an independent residual on the host
+    import scipy.sparse as sp
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    xh = x.cpu().numpy()
+    rel = float(np.linalg.norm(p.b[:, 0] - A @ xh) / np.linalg.norm(p.b[:, 0]))
+
+    # aggregate the per-kernel event timings of the timed region
+    agg = {}
+    for pr in profs:
+        for name, d in pr.items():
+            a = agg.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0))
+            a["launches"] += d["launches"]
+            a["ms"] += d["ms"]
+            a["bytes"] += d["bytes"]
+    kernels = {}
+    for name, a in agg.items():
+        if a["launches"] == 0:
+            continue
+        avg_ms = a["ms"] / a["launches"]
+        kernels[name] = dict(launches=a["launches"], total_ms=round(a["ms"], 4), avg_us=round(avg_ms * 1e3, 3),
+                             gbs=round(a["bytes"] / (a["ms"] * 1e-3) / 1e9, 2) if a["ms"] > 0 else None)
+    dom = max(agg.items(), key=lambda kv: kv[1]["ms"])[0]
+    d = agg[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                    avg_launch_us=round(d["ms"] / d["launches"] * 1e3, 3),
+                    bytes_per_launch=round(d["bytes"] / d["launches"]))
+    spmv = agg.get("spmv")
+
+    out = {
+        "metric": "time_to_1e-8_residual_s",
+        "value": round(sec_per_step, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec_per_step * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {WORKLOAD_DESC.get(args.workload, '')}",
+            "method": "two-grid matching-AMG (ILU(0) smoother, ILUT coarse) + FGMRES, setup+solve per step",
+            "options": dict(SOLVE_OPTS, tol=TOL),
+            "iters": infos[-1]["iters"],
+            "setup_ms": round(S.setup_info["setup_ms"], 2),
+            "solve_ms": round(infos[-1]["solve_ms"], 2),
+            "n_coarse": S.setup_info["n_coarse"],
+            "levels": {k: S.setup_info[k] for k in ("levels_L0", "levels_U0", "levels_Lc", "levels_Uc")},
+            "relres_host_check": rel,
+        },
+        "roofline": roofline,
+        "kernels": kernels,
+        "alg_bytes": _alg_bytes_doc(),
+    }
+    if spmv and spmv["ms"] > 0:
+        out["spmv_gbs"] = round(spmv["bytes"] / (spmv["ms"] * 1e-3) / 1e9, 2)
+
+    if not args.no_fp32:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S32, x32, r32, pr32 = one_step(True, True)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        x32h = x32.cpu().numpy()
+        out["fp32_precond"] = dict(
+            time_s=round(t32, 6), iters=r32.info["iters"], solve_ms=round(r32.info["solve_ms"], 2),
+            relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ x32h) / np.linalg.norm(p.b[:, 0])),
+            rel_diff_vs_fp64=float(np.linalg.norm(x32h - xh) / np.linalg.norm(xh)),
+            kernels={k: dict(launches=v["launches"], total_ms=round(v["ms"], 4)) for k, v in pr32.items()
+                     if v["launches"]})
+        print(f"[bench] fp32-preconditioned step: {t32:.3f}s its={r32.info['iters']}", file=sys.stderr,
+              flush=True)
+
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cb = run_cpu_baseline(p)
+        gpu_steps = infos[-1]["iters"]
+        est = cb["t_setup"] + cb["t_steps"] * (gpu_steps / max(cb["steps"], 1))
+        out["cpu_baseline"] = dict(
+            value=round(est, 3), unit="s", cores=1, kind="oracle",
+            sample=(f"oracle setup ({cb['t_setup']:.2f}s) + {cb['steps']} FGMRES steps ({cb['t_steps']:.2f}s) "
+                    f"on the same workload, steps scaled to the GPU's {gpu_steps} "
+                    f"(per-step cost grows with the basis, so this underestimates)"))
+        print(f"[bench] cpu baseline done: {json.dumps(out['cpu_baseline'])}", file=sys.stderr, flush=True)
+
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -66,12 +66,15 @@ typedef struct {
   int coarse_mode;      /* 0: exact triangular sweeps with the ILUT factors;
                            1: coarse_sweeps Jacobi sweeps per factor                 */
   int coarse_sweeps;    /* (default 3)                                               */
-  int restart;          /* FGMRES restart length m (default 30, at most 64)          */
+  int restart;          /* FGMRES restart length m (default 30, at most 2048)        */
   int maxit;            /* total FGMRES steps at most (default 600)                  */
   int precond_fp32;     /* 1: the whole preconditioner runs in FP32 on FP32 copies of
                            A and of the factors; the Krylov part stays FP64          */
   int x0_given;         /* 1: x holds the initial guess on entry, else x0 = 0         */
-  int sweep_waves;      /* resident waves of the triangular-sweep kernels (0: auto)  */
+  int sweep_waves;      /* resident waves of the triangular sweeps (0: auto)          */
+  int coarse_order;     /* numbering of the aggregates, hence of A_c and its ILUT
+                           factors: 0 by smallest fine index; 1 nested dissection
+                           of A_c's graph (default)                                   */
 } gmg_options;
 
 typedef struct {

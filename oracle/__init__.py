@@ -40,7 +40,7 @@ def build(force: bool = False) -> str:
 class _Opts(C.Structure):
     _fields_ = [("cf", C.c_double), ("max_passes", C.c_int), ("qbits", C.c_int),
                 ("seed", C.c_uint64), ("ilut_tau", C.c_double), ("coarse_mode", C.c_int),
-                ("coarse_sweeps", C.c_int)]
+                ("coarse_sweeps", C.c_int), ("coarse_order", C.c_int)]
 
 
 _lib = None

@@ -45,6 +45,7 @@ typedef struct {
     double ilut_tau;     /* ILUT drop tolerance (relative to the row 2-norm)      */
     int coarse_mode;     /* 0: exact triangular sweeps, 1: Jacobi sweeps          */
     int coarse_sweeps;   /* Jacobi sweeps per factor when coarse_mode == 1        */
+    int coarse_order;    /* 0: aggregates by smallest fine index; 1: nested dissection */
 } or_opts;
 
 typedef struct {
@@ -338,6 +339,160 @@ static int galerkin(or_solver *S) {
     return st;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Nested-dissection numbering of the coarse unknowns (the paper reorders by  */
+/* nested dissection so that incomplete factors can be computed and applied  */
+/* in parallel, Section 3 comments; Table T:norm factors the coarse matrix   */
+/* under that ordering).  Graph: i ~ j (i != j) when (A_c)_ij or (A_c)_ji is */
+/* stored.  ND(S), S a vertex set:                                           */
+/*   |S| <= 64: S ascending.                                                 */
+/*   S disconnected: its connected components, ordered by smallest vertex,   */
+/*     each numbered by ND.                                                  */
+/*   otherwise: BFS from min S; r = smallest vertex at the largest distance; */
+/*     d = BFS distance from r within S, L = max d; L < 2: S ascending;       */
+/*     m = smallest level with #{d <= m} >= |S|/2, clamped to [1, L-1];       */
+/*     ND({d < m}), then ND({d > m}), then {d == m} ascending.               */
+/* ------------------------------------------------------------------------ */
+#define ND_LEAF 64
+
+static int bfs_in_set(const int *rp, const int *ci, const int *stamp, int tag, int src, int *dist, int *queue) {
+    int head = 0, tail = 0;
+    dist[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        int u = queue[head++];
+        for (int p = rp[u]; p < rp[u + 1]; ++p) {
+            int v = ci[p];
+            if (stamp[v] == tag && dist[v] < 0) { dist[v] = dist[u] + 1; queue[tail++] = v; }
+        }
+    }
+    return tail;
+}
+
+/* stable partition of seg[0..len) by key[v] in {0,1,2}: returns counts */
+static void part3(int *seg, int len, const int *key, int *tmp, int *c0, int *c1) {
+    int n0 = 0, n1 = 0, k = 0;
+    for (int i = 0; i < len; ++i) if (key[seg[i]] == 0) tmp[k++] = seg[i];
+    n0 = k;
+    for (int i = 0; i < len; ++i) if (key[seg[i]] == 1) tmp[k++] = seg[i];
+    n1 = k - n0;
+    for (int i = 0; i < len; ++i) if (key[seg[i]] == 2) tmp[k++] = seg[i];
+    memcpy(seg, tmp, sizeof(int) * (size_t)len);
+    *c0 = n0; *c1 = n1;
+}
+
+/* perm[k] = coarse vertex placed at position k */
+static int nd_order(const csr_t *Ac, int *perm) {
+    int n = Ac->n;
+    csr_t T = {0};
+    int st = transpose(Ac, &T);
+    if (st) { csr_free(&T); return st; }
+    int *rp = malloc(sizeof(int) * ((size_t)n + 1));
+    int *ci = malloc(sizeof(int) * (size_t)(2 * Ac->rp[n] + 1));
+    int *seq = malloc(sizeof(int) * (size_t)(n + 1)), *tmp = malloc(sizeof(int) * (size_t)(n + 1));
+    int *stamp = malloc(sizeof(int) * (size_t)(n + 1)), *dist = malloc(sizeof(int) * (size_t)(n + 1));
+    int *queue = malloc(sizeof(int) * (size_t)(n + 1)), *key = malloc(sizeof(int) * (size_t)(n + 1));
+    int *cnt = malloc(sizeof(int) * (size_t)(n + 2));
+    /* task stack: (kind, start, len); kind 0 = number by ND, 1 = emit */
+    int cap = 64, top = 0;
+    int *tk = malloc(sizeof(int) * 3 * (size_t)cap);
+    if (!rp || !ci || !seq || !tmp || !stamp || !dist || !queue || !key || !cnt || !tk) return OR_ERR_OOM;
+    /* symmetric pattern without the diagonal */
+    int e = 0;
+    rp[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        int p = Ac->rp[i], pe = Ac->rp[i + 1], q = T.rp[i], qe = T.rp[i + 1];
+        while (p < pe || q < qe) {
+            int a = p < pe ? Ac->ci[p] : n, b = q < qe ? T.ci[q] : n;
+            int j = a < b ? a : b;
+            if (a == j) ++p;
+            if (b == j) ++q;
+            if (j != i) ci[e++] = j;
+        }
+        rp[i + 1] = e;
+    }
+    csr_free(&T);
+    for (int i = 0; i < n; ++i) { seq[i] = i; stamp[i] = -1; dist[i] = -1; }
+    int out = 0, tag = 0;
+    tk[0] = 0; tk[1] = 0; tk[2] = n; top = 1;
+    while (top > 0) {
+        --top;
+        int kind = tk[3 * top], s0 = tk[3 * top + 1], len = tk[3 * top + 2];
+        int *seg = seq + s0;
+        if (len == 0) continue;
+        if (kind == 1 || len <= ND_LEAF) {
+            for (int i = 0; i < len; ++i) perm[out++] = seg[i];
+            continue;
+        }
+        ++tag;
+        for (int i = 0; i < len; ++i) { stamp[seg[i]] = tag; dist[seg[i]] = -1; }
+        int reached = bfs_in_set(rp, ci, stamp, tag, seg[0], dist, queue);
+        int push[9], np = 0;   /* up to three tasks, pushed in reverse processing order */
+        if (reached < len) {
+            /* component of min S first, the rest after */
+            for (int i = 0; i < len; ++i) key[seg[i]] = dist[seg[i]] >= 0 ? 0 : 1;
+            int c0, c1;
+            part3(seg, len, key, tmp, &c0, &c1);
+            push[np++] = 0; push[np++] = s0 + c0; push[np++] = c1;
+            push[np++] = 0; push[np++] = s0; push[np++] = c0;
+        } else {
+            int far = 0, r = -1;
+            for (int i = 0; i < len; ++i) {
+                int v = seg[i];
+                if (dist[v] > far || (dist[v] == far && (r < 0 || v < r))) { far = dist[v]; r = v; }
+            }
+            for (int i = 0; i < len; ++i) dist[seg[i]] = -1;
+            bfs_in_set(rp, ci, stamp, tag, r, dist, queue);
+            int L = 0;
+            for (int i = 0; i < len; ++i) if (dist[seg[i]] > L) L = dist[seg[i]];
+            if (L < 2) {
+                push[np++] = 1; push[np++] = s0; push[np++] = len;
+            } else {
+                for (int l = 0; l <= L; ++l) cnt[l] = 0;
+                for (int i = 0; i < len; ++i) cnt[dist[seg[i]]]++;
+                int m = 0, cum = cnt[0];
+                while ((double)cum < (double)len / 2.0) { ++m; cum += cnt[m]; }
+                if (m < 1) m = 1;
+                if (m > L - 1) m = L - 1;
+                for (int i = 0; i < len; ++i) {
+                    int d = dist[seg[i]];
+                    key[seg[i]] = d < m ? 0 : (d > m ? 1 : 2);
+                }
+                int c0, c1;
+                part3(seg, len, key, tmp, &c0, &c1);
+                push[np++] = 1; push[np++] = s0 + c0 + c1; push[np++] = len - c0 - c1;
+                push[np++] = 0; push[np++] = s0 + c0; push[np++] = c1;
+                push[np++] = 0; push[np++] = s0; push[np++] = c0;
+            }
+        }
+        if (top + 3 > cap) { cap *= 2; tk = realloc(tk, sizeof(int) * 3 * (size_t)cap); if (!tk) return OR_ERR_OOM; }
+        for (int t = 0; t < np; t += 3) {
+            tk[3 * top] = push[t]; tk[3 * top + 1] = push[t + 1]; tk[3 * top + 2] = push[t + 2]; ++top;
+        }
+    }
+    free(rp); free(ci); free(seq); free(tmp); free(stamp); free(dist); free(queue); free(key); free(cnt); free(tk);
+    return out == n ? OR_OK : OR_ERR_INVALID;
+}
+
+/* renumber aggregates so that A_c's rows follow perm; rebuild P^T and A_c */
+static int renumber_coarse(or_solver *S) {
+    int nc = S->nc;
+    int *perm = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1)), *rank = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    if (!perm || !rank) return OR_ERR_OOM;
+    int st = nd_order(&S->Ac, perm);
+    if (!st) {
+        for (int k = 0; k < nc; ++k) rank[perm[k]] = k;
+        for (int k = 0; k < S->A.n; ++k) S->agg[k] = rank[S->agg[k]];
+        free(S->aptr); free(S->amem); S->aptr = NULL; S->amem = NULL;
+        csr_free(&S->Ac);
+        st = members(S);
+        if (!st) st = galerkin(S);
+    }
+    free(perm); free(rank);
+    return st;
+}
+
 /* ------------------------------------------------------------------------ */
 /* ILU(0): incomplete LU restricted to the pattern of A (IKJ form).          */
 /* ------------------------------------------------------------------------ */
@@ -494,6 +649,7 @@ void or_default_opts(or_opts *o) {
     o->ilut_tau = 1e-4;
     o->coarse_mode = 0;
     o->coarse_sweeps = 3;
+    o->coarse_order = 1;
 }
 
 void or_destroy(or_solver *S) {
@@ -513,7 +669,10 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, const or_opts
     or_solver *S = calloc(1, sizeof(or_solver));
     if (!S) return OR_ERR_OOM;
     S->o = *opts;
-    if (S->o.qbits < 0 || S->o.qbits > 52 || !(S->o.cf >= 1.0)) { or_destroy(S); return OR_ERR_INVALID; }
+    if (S->o.qbits < 0 || S->o.qbits > 52 || !(S->o.cf >= 1.0) || S->o.coarse_order < 0 || S->o.coarse_order > 1) {
+        or_destroy(S);
+        return OR_ERR_INVALID;
+    }
     if (rp[0] != 0) { or_destroy(S); return OR_ERR_INVALID; }
     for (int i = 0; i < n; ++i) if (rp[i + 1] < rp[i]) { or_destroy(S); return OR_ERR_INVALID; }
     int nnz = rp[n];
@@ -545,6 +704,7 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, const or_opts
     }
     if (!st) st = members(S);
     if (!st) st = galerkin(S);
+    if (!st && !agg_given && S->o.coarse_order == 1) st = renumber_coarse(S);
     if (!st) st = ilu0(S);
     if (!st) st = ilut(&S->Ac, S->o.ilut_tau, &S->Lc, &S->Uc);
     if (!st) {

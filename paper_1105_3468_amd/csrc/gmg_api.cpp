@@ -28,7 +28,8 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 
 constexpr uint64_t kSent64 = 0x7FF8DEADBEEFF00DULL;
 constexpr uint32_t kSent32 = 0x7FC0FEEDu;
-constexpr int kMaxRestart = 32;
+constexpr int kMaxRestart = 2048;   // longest Krylov basis (vectors)
+constexpr int kFused = 32;          // basis size handled by the fused CGS2 kernels
 
 static const char* kProfNames[PC_COUNT] = {"spmv", "sweep_fine", "sweep_coarse", "resid_restrict",
                                            "prolong", "ortho", "vector"};
@@ -68,6 +69,7 @@ struct Solver {
   DBuf<int> abort_flag;
   double* hpin = nullptr;      // pinned host scalars
   gmg_info info{};
+  int log_every = 0;           // GMG_LOG=k prints the residual estimate every k steps
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -133,37 +135,56 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
   std::vector<int> sched, lptr;
   int levels = 0;
   make_schedule(dep_rp, dep_ci, lower, sched, lptr, &levels);
-  const int ns = (int)sched.size();
-  std::vector<int> dp(ns + 1, 0);
-  for (int p = 0; p < ns; ++p) {
-    const int r = sched[p];
-    dp[p + 1] = dp[p] + (r >= 0 ? dep_rp[r + 1] - dep_rp[r] : 0);
+  std::vector<int> rows, chunk;
+  rows.reserve(n);
+  for (int l = 0; l < levels; ++l) {
+    const int first = (int)rows.size();
+    int maxdeps = 0;
+    for (int p = lptr[l]; p < lptr[l + 1]; ++p) {
+      const int r = sched[p];
+      if (r < 0) continue;
+      rows.push_back(r);
+      maxdeps = std::max(maxdeps, dep_rp[r + 1] - dep_rp[r]);
+    }
+    // lanes per row: enough that one lane reads at most one batch of 8 entries
+    int lg = 0;
+    while ((1 << lg) * 8 < maxdeps && lg < 6) ++lg;
+    const int per = 64 >> lg;
+    const int cnt = (int)rows.size() - first;
+    for (int c = 0; c < cnt; c += per) {
+      chunk.push_back(first + c);
+      chunk.push_back(std::min(per, cnt - c));
+      chunk.push_back(lg);
+    }
   }
-  const int64_t ne = dp[ns];
+  const int ne_rows = (int)rows.size();
+  std::vector<int> dp(ne_rows + 1, 0);
+  for (int e = 0; e < ne_rows; ++e) dp[e + 1] = dp[e] + dep_rp[rows[e] + 1] - dep_rp[rows[e]];
+  const int64_t ne = dp[ne_rows];
   std::vector<int> dcol(ne > 0 ? ne : 1), dsrc(ne > 0 ? ne : 1);
   std::vector<double> dval_h;
   if (host_vals) dval_h.resize(ne > 0 ? ne : 1);
-  for (int p = 0; p < ns; ++p) {
-    const int r = sched[p];
-    if (r < 0) continue;
-    int o = dp[p];
-    for (int q = dep_rp[r]; q < dep_rp[r + 1]; ++q, ++o) {
+  for (int e = 0; e < ne_rows; ++e) {
+    int o = dp[e];
+    for (int q = dep_rp[rows[e]]; q < dep_rp[rows[e] + 1]; ++q, ++o) {
       dcol[o] = dep_ci[q];
       dsrc[o] = dep_src[q];
       if (host_vals) dval_h[o] = (*host_vals)[dep_src[q]];
     }
   }
   sw.n = n;
-  sw.nsched = ns;
+  sw.nchunks = (int)chunk.size() / 3;
   sw.levels = levels;
   sw.nnz = ne;
   sw.has_diag = has_diag;
-  sw.sched.alloc(ns > 0 ? ns : 1);
-  sw.dp.alloc(ns + 1);
+  sw.chunk.alloc(chunk.size() > 0 ? chunk.size() : 1);
+  sw.rows.alloc(ne_rows > 0 ? ne_rows : 1);
+  sw.dp.alloc(ne_rows + 1);
   sw.dcol.alloc(ne > 0 ? ne : 1);
   sw.dval.alloc(ne > 0 ? ne : 1);
-  h2d(sw.sched.p, sched.data(), ns, s);
-  h2d(sw.dp.p, dp.data(), ns + 1, s);
+  h2d(sw.chunk.p, chunk.data(), chunk.size(), s);
+  h2d(sw.rows.p, rows.data(), ne_rows, s);
+  h2d(sw.dp.p, dp.data(), ne_rows + 1, s);
   h2d(sw.dcol.p, dcol.data(), ne, s);
   if (host_vals) {
     h2d(sw.dval.p, dval_h.data(), ne, s);
@@ -186,6 +207,11 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
   sw.ticket.alloc(1);
   launch_fill_u32(sw.ticket.p, 0u, 1, s);
   sw.ticket_base = 0;
+  {
+    // a few levels of look-ahead: more resident waves would only poll
+    const double per_level = levels > 0 ? (double)sw.nchunks / levels : 1.0;
+    sw.waves = std::min(2048, std::max(16, (int)std::ceil(4.0 * per_level)));
+  }
   HIPCK(hipStreamSynchronize(s));  // host vectors above go out of scope
 }
 
@@ -208,6 +234,16 @@ static void check_abort(Solver& S) {
     launch_fill_u32(reinterpret_cast<unsigned*>(S.abort_flag.p), 0u, 1, S.s);
     fail(GMG_ERR_STALLED, "a triangular-sweep dependency wait timed out");
   }
+}
+
+// One triangular sweep of a factor.
+template <class T>
+static void run_tri(Solver& S, Sweep& sw, const void* rhs, bool rhs_f64, T* out, T* reset) {
+  constexpr bool F32 = sizeof(T) == 4;
+  const T* di = sw.has_diag ? (F32 ? (const T*)sw.dinv32.p : (const T*)sw.dinv.p) : nullptr;
+  const int waves = S.opt.sweep_waves > 0 ? S.opt.sweep_waves : sw.waves;
+  launch_sweep<T>(sw, F32 ? (const T*)sw.dval32.p : (const T*)sw.dval.p, di, rhs, rhs_f64, out, reset, waves,
+                  S.abort_flag.p, S.s);
 }
 
 static void reset_cycle_buffers(Solver& S) {
@@ -239,18 +275,15 @@ static void vcycle(Solver& S, const double* z, double* q) {
   T* rc = F32 ? (T*)S.rc32.p : (T*)S.rc.p;
   T* yc = F32 ? (T*)S.yc32.p : (T*)S.yc.p;
   T* ec = F32 ? (T*)S.ec32.p : (T*)S.ec.p;
-  auto dv = [&](Sweep& sw) { return F32 ? (const T*)sw.dval32.p : (const T*)sw.dval.p; };
-  auto di = [&](Sweep& sw) { return F32 ? (const T*)sw.dinv32.p : (const T*)sw.dinv.p; };
   const T* Av = F32 ? (const T*)S.A.v32.p : (const T*)S.A.v.p;
   const size_t sz = sizeof(T);
-  const int waves = S.opt.sweep_waves;
   {
     Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false));
-    launch_sweep<T>(S.L0, dv(S.L0), nullptr, z, true, y, nullptr, waves, S.abort_flag.p, s);
+    run_tri<T>(S, S.L0, z, true, y, nullptr);
   }
   {
     Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0, sz, sz, true));
-    launch_sweep<T>(S.U0, dv(S.U0), di(S.U0), y, false, t, y, waves, S.abort_flag.p, s);
+    run_tri<T>(S, S.U0, y, false, t, y);
   }
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 8 + 3 * sz + 4) +
@@ -261,11 +294,11 @@ static void vcycle(Solver& S, const double* z, double* q) {
   if (S.opt.coarse_mode == 0) {
     {
       Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lc, sz, sz, false));
-      launch_sweep<T>(S.Lc, dv(S.Lc), nullptr, rc, false, yc, nullptr, waves, S.abort_flag.p, s);
+      run_tri<T>(S, S.Lc, rc, false, yc, nullptr);
     }
     {
       Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uc, sz, sz, true));
-      launch_sweep<T>(S.Uc, dv(S.Uc), di(S.Uc), yc, false, ec, yc, waves, S.abort_flag.p, s);
+      run_tri<T>(S, S.Uc, yc, false, ec, yc);
     }
   } else {
     if (F32) fail(GMG_ERR_INVALID_ARG, "coarse_mode 1 runs in FP64 only");
@@ -299,19 +332,17 @@ static void vcycle(Solver& S, const double* z, double* q) {
 // t = L0^{-T} U0^{-T} s; q = P ec + t
 static void vcycle_adjoint(Solver& S, const double* z, double* q) {
   hipStream_t s = S.s;
-  const int waves = S.opt.sweep_waves;
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.n * 12 + (double)S.nc * 16);
     launch_restrict_plain(S.nc, S.aptr.p, S.amem.p, z, S.abc.p, S.aec.p, 0, s);
   }
   {
     Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
-    launch_sweep<double>(S.Uct, S.Uct.dval.p, S.Uct.dinv.p, S.abc.p, false, S.auc.p, nullptr, waves,
-                         S.abort_flag.p, s);
+    run_tri<double>(S, S.Uct, S.abc.p, false, S.auc.p, nullptr);
   }
   {
     Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
-    launch_sweep<double>(S.Lct, S.Lct.dval.p, nullptr, S.auc.p, false, S.aec.p, S.auc.p, waves, S.abort_flag.p, s);
+    run_tri<double>(S, S.Lct, S.auc.p, false, S.aec.p, S.auc.p);
   }
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * 12 + (double)S.n * 24);
@@ -319,12 +350,11 @@ static void vcycle_adjoint(Solver& S, const double* z, double* q) {
   }
   {
     Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
-    launch_sweep<double>(S.U0t, S.U0t.dval.p, S.U0t.dinv.p, S.as.p, false, S.aw.p, nullptr, waves,
-                         S.abort_flag.p, s);
+    run_tri<double>(S, S.U0t, S.as.p, false, S.aw.p, nullptr);
   }
   {
     Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
-    launch_sweep<double>(S.L0t, S.L0t.dval.p, nullptr, S.aw.p, false, S.at.p, S.aw.p, waves, S.abort_flag.p, s);
+    run_tri<double>(S, S.L0t, S.aw.p, false, S.at.p, S.aw.p);
   }
   {
     Prof p(S, PC_PROLONG, (double)S.n * 28 + (double)S.nc * 8);
@@ -422,16 +452,28 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       else vcycle<double>(S, vj, zj);
       apply_op(S, adjoint, zj, w);
       const int kc = j + 1;
-      {
+      // classical Gram-Schmidt, twice: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2
+      double* h1 = res;
+      double* h2 = res + kc;
+      double* nrm = res + 2 * kc;
+      if (kc <= kFused) {
         Prof p(S, PC_ORTHO, 8.0 * n * (3 * kc + 6));
-        launch_multidot(V, ld, kc, w, n, S.rw, res, s);
-        launch_update_dot(V, ld, kc, res, w, n, S.rw, res + kMaxRestart, s);
-        launch_update_norm(V, ld, kc, res + kMaxRestart, w, n, S.rw, res + 2 * kMaxRestart, s);
+        launch_multidot(V, ld, kc, w, n, S.rw, h1, s);
+        launch_update_dot(V, ld, kc, h1, w, n, S.rw, h2, s);
+        launch_update_norm(V, ld, kc, h2, w, n, S.rw, nrm, s);
+      } else {
+        Prof p(S, PC_ORTHO, 8.0 * n * (4 * kc + 4 * ((kc + kFused - 1) / kFused) + 4));
+        for (int c0 = 0; c0 < kc; c0 += kFused)
+          launch_multidot(V + (size_t)c0 * ld, ld, std::min(kFused, kc - c0), w, n, S.rw, h1 + c0, s);
+        launch_update_many(V, ld, kc, h1, w, n, false, S.rw, nullptr, s);
+        for (int c0 = 0; c0 < kc; c0 += kFused)
+          launch_multidot(V + (size_t)c0 * ld, ld, std::min(kFused, kc - c0), w, n, S.rw, h2 + c0, s);
+        launch_update_many(V, ld, kc, h2, w, n, true, S.rw, nrm, s);
       }
-      d2h(hp, res, 2 * kMaxRestart + 1, s);
+      d2h(hp, res, 2 * kc + 1, s);
       HIPCK(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) HH(i, j) = hp[i] + hp[kMaxRestart + i];
-      const double hn = std::sqrt(hp[2 * kMaxRestart]);
+      for (int i = 0; i <= j; ++i) HH(i, j) = hp[i] + hp[kc + i];
+      const double hn = std::sqrt(hp[2 * kc]);
       HH(j + 1, j) = hn;
       if (hn != 0.0) {
         Prof p(S, PC_VECTOR, (double)n * 16);
@@ -457,6 +499,10 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       ++total;
       k = j + 1;
       out.est = std::fabs(g[j + 1]) / bnorm;
+      if (S.log_every > 0 && total % S.log_every == 0) {
+        std::fprintf(stderr, "[gmg] step %d  estimated relres %.3e\n", total, out.est);
+        std::fflush(stderr);
+      }
       if (out.est < tol || hn == 0.0 || total >= maxit) break;
     }
     check_abort(S);
@@ -488,7 +534,7 @@ static gmg_status solve_impl(Solver& S, bool adjoint, const double* b, double* x
     opt.restart = o->restart;
     opt.precond_fp32 = o->precond_fp32;
   }
-  if (opt.restart < 1 || opt.restart > kMaxRestart) fail(GMG_ERR_INVALID_ARG, "restart must be in [1, 32]");
+  if (opt.restart < 1 || opt.restart > kMaxRestart) fail(GMG_ERR_INVALID_ARG, "restart must be in [1, 2048]");
   if (opt.maxit < 0) fail(GMG_ERR_INVALID_ARG, "maxit must be >= 0");
   if (adjoint && (opt.precond_fp32 || S.opt.coarse_mode != 0))
     fail(GMG_ERR_INVALID_ARG, "the adjoint solve needs coarse_mode 0 and FP64");
@@ -551,13 +597,14 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   if (!rowptr || !col || !val) fail(GMG_ERR_INVALID_ARG, "setup: null matrix pointer");
   const gmg_options& o = S.opt;
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
-      o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0)
+      o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
+      o.coarse_order < 0 || o.coarse_order > 1)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
   auto t0 = std::chrono::steady_clock::now();
   const int n = (int)n64;
   S.n = n;
   S.nnz = nnz64;
-  HIPCK(hipHostMalloc(&S.hpin, sizeof(double) * 256, hipHostMallocDefault));
+  HIPCK(hipHostMalloc(&S.hpin, sizeof(double) * (2 * kMaxRestart + 8), hipHostMallocDefault));
   S.abort_flag.alloc(1);
   launch_fill_u32(reinterpret_cast<unsigned*>(S.abort_flag.p), 0u, 1, s);
   // ---- validate and copy A
@@ -605,6 +652,34 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   }
   build_members(n, S.nc, S.agg.p, S.aptr, S.amem, s);
   galerkin(n, S.nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
+  if (o.coarse_order == 1 && S.nc > 1) {
+    // number the aggregates in nested-dissection order of A_c's graph, then
+    // rebuild P^T and A_c (same sums, permuted rows and columns)
+    const int nc = S.nc;
+    std::vector<int> crp = to_host_int(S.Ac.rp.p, nc + 1, s);
+    std::vector<int> cci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
+    HIPCK(hipStreamSynchronize(s));
+    std::vector<int> cnt(nc + 1, 0);
+    for (int i = 0; i < nc; ++i)
+      for (int p = crp[i]; p < crp[i + 1]; ++p)
+        if (cci[p] != i) { cnt[i + 1]++; cnt[cci[p] + 1]++; }
+    for (int i = 0; i < nc; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int> gci(cnt[nc]), fillp(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < nc; ++i)
+      for (int p = crp[i]; p < crp[i + 1]; ++p)
+        if (cci[p] != i) { gci[fillp[i]++] = cci[p]; gci[fillp[cci[p]]++] = i; }
+    // duplicates (both (i,j) and (j,i) stored) are harmless for the traversal
+    std::vector<int> perm = nd_numbering(nc, cnt, gci);
+    std::vector<int> rank(nc);
+    for (int k = 0; k < nc; ++k) rank[perm[k]] = k;
+    DBuf<int> drank;
+    drank.alloc(nc);
+    h2d(drank.p, rank.data(), nc, s);
+    relabel(n, S.agg.p, drank.p, s);
+    HIPCK(hipStreamSynchronize(s));
+    build_members(n, nc, S.agg.p, S.aptr, S.amem, s);
+    galerkin(n, nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
+  }
   // ---- host copy of A's pattern for the analysis
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
   std::vector<int> hci = to_host_int(S.A.ci.p, nnz64, s);
@@ -814,6 +889,7 @@ void gmg_default_options(gmg_options* o) {
   o->precond_fp32 = 0;
   o->x0_given = 0;
   o->sweep_waves = 0;
+  o->coarse_order = 1;
 }
 
 gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
@@ -823,6 +899,7 @@ gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowpt
     *h = nullptr;
     std::unique_ptr<gmg_solver> sv(new gmg_solver());
     sv->S.s = (hipStream_t)stream;
+    if (const char* e = std::getenv("GMG_LOG")) sv->S.log_every = std::max(0, std::atoi(e));
     if (opts) sv->S.opt = *opts;
     else gmg_default_options(&sv->S.opt);
     gmg::setup_impl(sv->S, n, nnz, rowptr, col, val);

@@ -85,22 +85,24 @@ struct HCsr {
   std::vector<double> v;
 };
 
-// A triangular factor prepared for the synchronisation-free sweep.
-// Rows are visited in `sched` order (dependency levels, each level padded to a
-// multiple of 64 with -1).  Position p holds row sched[p]; its dependency
-// entries are dcol[dp[p] .. dp[p+1]) with values dval[...].  diag (optional)
-// is indexed by row: out[r] = (rhs[r] - sum dval * out[dcol]) * dinv[r].
+// A triangular factor prepared for the synchronisation-free sweep: row rows[e]
+// (entries e in schedule order: by dependency level, ascending row inside a
+// level) has dependency entries dcol[dp[e] .. dp[e+1]) with values dval.
+// chunk[3c .. 3c+2] = (first entry, rows, log2 lanes per row) of wave chunk c;
+// a chunk holds rows of a single level.  out[r] = (rhs[r] - sum dval *
+// out[dcol]) * dinv[r] (dinv only for factors with a stored diagonal).
 struct Sweep {
   int n = 0;                 // rows of the factor
-  int nsched = 0;            // schedule length incl. padding (multiple of 64)
+  int nchunks = 0;
   int levels = 0;
   int64_t nnz = 0;           // dependency entries
-  DBuf<int> sched, dp, dcol;
+  DBuf<int> chunk, rows, dp, dcol;
   DBuf<double> dval, dinv;
   DBuf<float> dval32, dinv32;
   DBuf<unsigned> ticket;     // dynamic chunk counter
   unsigned ticket_base = 0;  // host copy of the counter value at the next launch
   bool has_diag = false;
+  int waves = 0;             // resident waves (a few dependency levels of look-ahead)
 };
 
 // Per-kernel-class profiling with events.
@@ -165,7 +167,7 @@ void launch_jacobi(int n, const int* rp, const int* ci, const double* v, const d
 struct RedWork {  // scratch for deterministic two-level reductions
   DBuf<double> partial;
   DBuf<unsigned> counter;
-  DBuf<double> result;   // up to 2*64+2 values
+  DBuf<double> result;   // two coefficient blocks of up to 2048 values + norms
   int blocks = 0;
 };
 void red_init(RedWork& rw, hipStream_t s);
@@ -177,6 +179,9 @@ void launch_update_dot(const double* V, size_t ld, int k, const double* h, doubl
                        RedWork& rw, double* result, hipStream_t s);
 // w -= V^T h, then result[0] = ||w||^2
 void launch_update_norm(const double* V, size_t ld, int k, const double* h, double* w, int64_t n,
+                        RedWork& rw, double* result, hipStream_t s);
+// any k (<= 2048): w -= V^T h (h device); if want_norm, result[0] = ||w_new||^2
+void launch_update_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
                         RedWork& rw, double* result, hipStream_t s);
 // result[0] = ||x||^2
 void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s);
@@ -200,6 +205,8 @@ int aggregate(int n, const DBuf<int>& grp, const DBuf<int>& gci, const DBuf<doub
 // Member lists (P^T as CSR) of agg.
 void build_members(int n, int nc, const int* agg, DBuf<int>& aptr, DBuf<int>& amem,
                    hipStream_t s);
+// agg[k] <- rank[agg[k]]
+void relabel(int n, int* agg, const int* rank, hipStream_t s);
 // Galerkin A_c = P^T A P with sums in the fine CSR order.
 void galerkin(int n, int nc, const int* rp, const int* ci, const double* v, const int* agg,
               const int* aptr, const int* amem, DCsr& Ac, hipStream_t s);
@@ -210,6 +217,8 @@ void galerkin(int n, int nc, const int* rp, const int* ci, const double* v, cons
 // level_ptr[l] is the first schedule position of level l (levels padded to 64).
 void make_schedule(const std::vector<int>& dep_rp, const std::vector<int>& dep_ci, bool lower,
                    std::vector<int>& sched, std::vector<int>& level_ptr, int* levels);
+// Nested-dissection numbering (position -> vertex) of a symmetric graph.
+std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci);
 // Row-wise ILUT(tau) without pivoting on a host CSR; L strictly lower,
 // U with the diagonal first.  Returns GMG_OK / GMG_ERR_ZERO_PIVOT / NONFINITE.
 gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U);

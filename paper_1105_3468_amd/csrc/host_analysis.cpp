@@ -118,4 +118,83 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U) {
   return GMG_OK;
 }
 
+
+// Nested-dissection numbering of the vertices of a symmetric graph (CSR
+// without diagonal).  ND(S): at most 64 vertices -> ascending; disconnected
+// -> its components in order of their smallest vertex, each by ND; otherwise
+// BFS from min S, r = smallest vertex at the largest distance, d = distance
+// from r inside S, L = max d (L < 2 -> ascending); m = smallest level holding
+// at least half of S cumulatively, clamped to [1, L-1]; then ND(d < m),
+// ND(d > m), and the separator d == m ascending.  Returns perm (position ->
+// vertex).
+std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci) {
+  struct Task { int kind, start, len; };  // kind 0: dissect, 1: emit as is
+  std::vector<int> seq(n), perm;
+  perm.reserve(n);
+  for (int i = 0; i < n; ++i) seq[i] = i;
+  std::vector<int> mark(n, -1), dist(n, -1), queue;
+  queue.reserve(n);
+  std::vector<Task> stack{{0, 0, n}};
+  int tag = 0;
+  auto bfs = [&](int src) {
+    queue.clear();
+    dist[src] = 0;
+    queue.push_back(src);
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const int u = queue[h];
+      for (int p = rp[u]; p < rp[u + 1]; ++p) {
+        const int v = ci[p];
+        if (mark[v] == tag && dist[v] < 0) {
+          dist[v] = dist[u] + 1;
+          queue.push_back(v);
+        }
+      }
+    }
+  };
+  while (!stack.empty()) {
+    const Task t = stack.back();
+    stack.pop_back();
+    if (t.len == 0) continue;
+    int* b = seq.data() + t.start;
+    int* e = b + t.len;
+    if (t.kind == 1 || t.len <= 64) {
+      perm.insert(perm.end(), b, e);
+      continue;
+    }
+    ++tag;
+    for (int* q = b; q != e; ++q) { mark[*q] = tag; dist[*q] = -1; }
+    bfs(*b);  // segments are kept ascending, so *b is the smallest vertex
+    if ((int)queue.size() < t.len) {
+      int* mid = std::stable_partition(b, e, [&](int v) { return dist[v] >= 0; });
+      const int c0 = (int)(mid - b);
+      stack.push_back({0, t.start + c0, t.len - c0});
+      stack.push_back({0, t.start, c0});
+      continue;
+    }
+    int r = *b, far = 0;
+    for (int* q = b; q != e; ++q)
+      if (dist[*q] > far || (dist[*q] == far && *q < r)) { far = dist[*q]; r = *q; }
+    for (int* q = b; q != e; ++q) dist[*q] = -1;
+    bfs(r);
+    int L = 0;
+    for (int* q = b; q != e; ++q) L = std::max(L, dist[*q]);
+    if (L < 2) {
+      stack.push_back({1, t.start, t.len});
+      continue;
+    }
+    std::vector<int> cnt(L + 1, 0);
+    for (int* q = b; q != e; ++q) cnt[dist[*q]]++;
+    int m = 0, cum = cnt[0];
+    while (2.0 * cum < (double)t.len) cum += cnt[++m];
+    m = std::min(std::max(m, 1), L - 1);
+    int* m1 = std::stable_partition(b, e, [&](int v) { return dist[v] < m; });
+    int* m2 = std::stable_partition(m1, e, [&](int v) { return dist[v] > m; });
+    const int c0 = (int)(m1 - b), c1 = (int)(m2 - m1);
+    stack.push_back({1, t.start + c0 + c1, t.len - c0 - c1});
+    stack.push_back({0, t.start + c0, c1});
+    stack.push_back({0, t.start, c0});
+  }
+  return perm;
+}
+
 }  // namespace gmg

@@ -10,7 +10,8 @@ namespace gmg {
 
 constexpr int KB = 256;          // threads per block
 constexpr int KGRID = 512;       // blocks of the reduction kernels
-constexpr int KMAX = 32;         // vectors per fused pass (restart <= 32)
+constexpr int KMAX = 32;         // vectors per fused register-resident pass
+constexpr int KLDS = 2048;       // vectors per LDS-staged pass (longest basis)
 
 template <int K>
 __device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount, double* partial,
@@ -115,7 +116,7 @@ void red_init(RedWork& rw, hipStream_t s) {
   rw.blocks = KGRID;
   rw.partial.alloc((size_t)KGRID * KMAX);
   rw.counter.alloc(1);
-  rw.result.alloc(4 * KMAX + 8);
+  rw.result.alloc(2 * KLDS + 8);
   launch_fill_u32(rw.counter.p, 0u, 1, s);
 }
 
@@ -196,13 +197,63 @@ __global__ void k_xupdate(double* __restrict__ x, const double* __restrict__ Z, 
     x[i] = s;
   }
 }
-void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n, hipStream_t s) {
-  if (n <= 0 || k <= 0) return;
-  if (k > KMAX) fail(GMG_ERR_INVALID_ARG, "xupdate: bad vector count");
-  int64_t g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
-  GMG_DISPATCH_K(k, k_xupdate, dim3((unsigned)g), dim3(256), 0, s, x, Z, ld, k, c, n);
+
+
+
+// Any number of vectors: w <- w - sum_k h[k] V[k] with the coefficients staged
+// in LDS; optionally result[0] = ||w_new||^2.  Used when the basis has more
+// vectors than one fused pass holds in registers.
+__global__ __launch_bounds__(KB) void k_update_many(const double* __restrict__ V, size_t ld, int kc,
+                                                    const double* __restrict__ h, double* __restrict__ w,
+                                                    int64_t n, int want_norm, double* partial,
+                                                    unsigned* counter, double* result) {
+  __shared__ double hs[KLDS];
+  for (int k = threadIdx.x; k < kc; k += KB) hs[k] = h[k];
+  __syncthreads();
+  double acc[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+    double s = w[i];
+    int k = 0;
+    for (; k + 8 <= kc; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(k + u) * ld + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s -= hs[k + u] * v[u];
+    }
+    for (; k < kc; ++k) s -= hs[k] * V[(size_t)k * ld + i];
+    w[i] = s;
+    acc[0] += s * s;
+  }
+  if (want_norm) block_reduce_store<1>(acc, 1, partial, counter, result);
+}
+
+void launch_update_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
+                        RedWork& rw, double* result, hipStream_t s) {
+  if (k < 1 || k > KLDS) fail(GMG_ERR_INVALID_ARG, "update_many: bad vector count");
+  hipLaunchKernelGGL(k_update_many, dim3(red_grid(n)), dim3(KB), 0, s, V, ld, k, h, w, n, want_norm ? 1 : 0,
+                     rw.partial.p, rw.counter.p, result);
   HIPCK(hipGetLastError());
+}
+
+__global__ __launch_bounds__(KB) void k_xupdate_many(double* __restrict__ x, const double* __restrict__ Z, size_t ld,
+                                                     int kc, const double* __restrict__ c, int64_t n) {
+  __shared__ double cs[KLDS];
+  for (int k = threadIdx.x; k < kc; k += KB) cs[k] = c[k];
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+    double s = x[i];
+    int k = 0;
+    for (; k + 8 <= kc; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Z[(size_t)(k + u) * ld + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += cs[k + u] * v[u];
+    }
+    for (; k < kc; ++k) s += cs[k] * Z[(size_t)k * ld + i];
+    x[i] = s;
+  }
 }
 
 __global__ void k_get_col(const double* __restrict__ X, int nrhs, int col, double* __restrict__ x, int64_t n) {
@@ -225,6 +276,19 @@ void launch_set_col(double* X, int nrhs, int col, const double* x, int64_t n, hi
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
   hipLaunchKernelGGL(k_set_col, dim3((unsigned)g), dim3(256), 0, s, X, nrhs, col, x, n);
+  HIPCK(hipGetLastError());
+}
+
+void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n, hipStream_t s) {
+  if (n <= 0 || k <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (k <= KMAX) {
+    GMG_DISPATCH_K(k, k_xupdate, dim3((unsigned)g), dim3(256), 0, s, x, Z, ld, k, c, n);
+  } else {
+    if (k > KLDS) fail(GMG_ERR_INVALID_ARG, "xupdate: bad vector count");
+    hipLaunchKernelGGL(k_xupdate_many, dim3((unsigned)g), dim3(KB), 0, s, x, Z, ld, k, c, n);
+  }
   HIPCK(hipGetLastError());
 }
 

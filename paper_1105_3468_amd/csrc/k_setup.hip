@@ -388,6 +388,12 @@ int aggregate(int n, const DBuf<int>& grp0, const DBuf<int>& gci0, const DBuf<do
   return nv;
 }
 
+void relabel(int n, int* agg, const int* rank, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_compose, dim3(g1(n)), dim3(256), 0, s, n, agg, rank);
+  HIPCK(hipGetLastError());
+}
+
 void galerkin(int n, int nc, const int* rp, const int* ci, const double* v, const int* agg, const int* aptr,
               const int* amem, DCsr& Ac, hipStream_t s) {
   (void)n;

@@ -3,11 +3,14 @@
 //
 // A sweep computes out[r] = (rhs[r] - sum_q dval[q] * out[dcol[q]]) * dinv[r]
 // for every row of a triangular factor.  Rows are visited in a schedule of
-// dependency levels; each level is padded to a multiple of 64 so a wave never
-// holds two rows where one depends on the other.  Waves take 64-row chunks
-// from a global ticket counter in schedule order, so every row a wave waits
-// for belongs to a chunk that an already-running wave holds: the sweep always
-// makes progress.  A result is published with one relaxed agent-scope store
+// dependency levels, cut into wave-sized chunks that never mix two levels, so
+// a wave never holds two rows where one depends on the other.  A chunk gives
+// each of its rows G lanes (G a power of two chosen per level from the
+// longest row, so that a lane reads at most one batch of entries); the lanes'
+// partial sums meet in a shuffle reduction.  Waves take chunks from a global
+// ticket counter in schedule order, so every row a wave waits for belongs to
+// a chunk that an already-running wave holds: the sweep always makes
+// progress.  A result is published with one relaxed agent-scope store
 // and doubles as its own ready flag: consumers poll with relaxed agent-scope
 // loads until the value differs from the NaN sentinel the buffer was reset to.
 // Every wait is bounded by a wall-clock limit; a timeout raises a device flag
@@ -16,6 +19,8 @@
 #include "kcommon.h"
 
 namespace gmg {
+
+constexpr int SWEEP_BATCH = 8;
 
 template <class T>
 __device__ __forceinline__ T wait_ready(const T* p, int* abort_flag, uint64_t limit) {
@@ -45,31 +50,55 @@ __device__ __forceinline__ T not_sentinel(T v) {
 }
 
 template <class T, class TR, bool DIAG>
-__global__ __launch_bounds__(256) void k_sweep(const int* __restrict__ sched, const int* __restrict__ dp,
-                                               const int* __restrict__ dcol, const T* __restrict__ dval,
-                                               const T* __restrict__ dinv, const TR* rhs,
-                                               T* out, TR* reset_rhs, unsigned nchunks,
-                                               unsigned* ticket, unsigned base, int* abort_flag,
-                                               uint64_t limit) {
+__global__ __launch_bounds__(256) void k_sweep(const int* __restrict__ chunk, const int* __restrict__ rows,
+                                               const int* __restrict__ dp, const int* __restrict__ dcol,
+                                               const T* __restrict__ dval, const T* __restrict__ dinv,
+                                               const TR* rhs, T* out, TR* reset_rhs, unsigned nchunks,
+                                               unsigned* ticket, unsigned base, int* abort_flag, uint64_t limit) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     unsigned t = 0;
     if (lane == 0) t = atomicAdd(ticket, 1u) - base;
     t = __shfl(t, 0, 64);
     if (t >= nchunks) break;
-    const int p = (int)(t * 64u) + lane;
-    const int r = sched[p];
-    if (r >= 0) {
-      // rhs and reset_rhs may be the same buffer: read before the reset
-      T acc = (T)rhs[r];
-      if (reset_rhs) reset_rhs[r] = sentinel_of<TR>(0);
-      const int q1 = dp[p + 1];
-      for (int q = dp[p]; q < q1; ++q) {
-        const T v = wait_ready(out + dcol[q], abort_flag, limit);
-        acc -= dval[q] * v;
+    // chunk: first entry, number of rows, log2 of lanes per row
+    const int c0 = chunk[3 * t], cr = chunk[3 * t + 1], lg = chunk[3 * t + 2];
+    const int G = 1 << lg;
+    const int slot = lane >> lg, sub = lane & (G - 1);
+    const bool active = slot < cr;
+    const int e = c0 + slot;
+    T acc = (T)0;
+    if (active) {
+      // this lane's share of the row: entries q0+sub, q0+sub+G, ...; up to
+      // SWEEP_BATCH of them are loaded at once (independent loads), and only
+      // values not yet published are then waited for one by one
+      const int q1 = dp[e + 1];
+      for (int q = dp[e] + sub; q < q1; q += G * SWEEP_BATCH) {
+        int c[SWEEP_BATCH];
+        T v[SWEEP_BATCH];
+        T a[SWEEP_BATCH];
+#pragma unroll
+        for (int u = 0; u < SWEEP_BATCH; ++u)
+          if (q + u * G < q1) { c[u] = dcol[q + u * G]; a[u] = dval[q + u * G]; }
+#pragma unroll
+        for (int u = 0; u < SWEEP_BATCH; ++u)
+          if (q + u * G < q1) v[u] = ld_agent(out + c[u]);
+#pragma unroll
+        for (int u = 0; u < SWEEP_BATCH; ++u)
+          if (q + u * G < q1) {
+            if (is_sentinel(v[u])) v[u] = wait_ready(out + c[u], abort_flag, limit);
+            acc += a[u] * v[u];
+          }
       }
-      if (DIAG) acc *= dinv[r];
-      st_agent(out + r, not_sentinel(acc));
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (active && sub == 0) {
+      const int r = rows[e];
+      // rhs and reset_rhs may be the same buffer: read before the reset
+      T y = (T)rhs[r] - acc;
+      if (reset_rhs) reset_rhs[r] = sentinel_of<TR>(0);
+      if (DIAG) y *= dinv[r];
+      st_agent(out + r, not_sentinel(y));
     }
   }
 }
@@ -91,33 +120,26 @@ static uint64_t wall_limit_ticks() {
 template <class T>
 void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64, T* out,
                   T* reset_rhs, int waves, int* abort_flag, hipStream_t s) {
-  const unsigned nchunks = (unsigned)(sw.nsched / 64);
+  const unsigned nchunks = (unsigned)sw.nchunks;
   if (nchunks == 0) return;
   unsigned w = waves > 0 ? (unsigned)waves : 2048u;
   if (w > nchunks) w = nchunks;
   const unsigned blocks = (w + 3) / 4;
   const unsigned used = blocks * 4;  // every wave takes exactly one ticket that ends it
   const uint64_t lim = wall_limit_ticks();
+#define GMG_SW(TR_, DG_, RHS_, RESET_)                                                                     \
+  hipLaunchKernelGGL((k_sweep<T, TR_, DG_>), dim3(blocks), dim3(256), 0, s, sw.chunk.p, sw.rows.p, sw.dp.p, \
+                     sw.dcol.p, dval, dinv, (const TR_*)RHS_, out, RESET_, nchunks, sw.ticket.p,             \
+                     sw.ticket_base, abort_flag, lim)
   if (rhs_is_f64 && sizeof(T) == 4) {
     // FP32 sweep with an FP64 right-hand side (first sweep of the FP32 cycle)
-    if (sw.has_diag)
-      hipLaunchKernelGGL((k_sweep<T, double, true>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
-                         sw.dcol.p, dval, dinv, (const double*)rhs, out, (double*)nullptr, nchunks,
-                         sw.ticket.p, sw.ticket_base, abort_flag, lim);
-    else
-      hipLaunchKernelGGL((k_sweep<T, double, false>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
-                         sw.dcol.p, dval, dinv, (const double*)rhs, out, (double*)nullptr, nchunks,
-                         sw.ticket.p, sw.ticket_base, abort_flag, lim);
+    if (sw.has_diag) GMG_SW(double, true, rhs, (double*)nullptr);
+    else GMG_SW(double, false, rhs, (double*)nullptr);
   } else {
-    if (sw.has_diag)
-      hipLaunchKernelGGL((k_sweep<T, T, true>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
-                         sw.dcol.p, dval, dinv, (const T*)rhs, out, reset_rhs, nchunks, sw.ticket.p,
-                         sw.ticket_base, abort_flag, lim);
-    else
-      hipLaunchKernelGGL((k_sweep<T, T, false>), dim3(blocks), dim3(256), 0, s, sw.sched.p, sw.dp.p,
-                         sw.dcol.p, dval, dinv, (const T*)rhs, out, reset_rhs, nchunks, sw.ticket.p,
-                         sw.ticket_base, abort_flag, lim);
+    if (sw.has_diag) GMG_SW(T, true, rhs, reset_rhs);
+    else GMG_SW(T, false, rhs, reset_rhs);
   }
+#undef GMG_SW
   HIPCK(hipGetLastError());
   sw.ticket_base += nchunks + used;
 }

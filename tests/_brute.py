@@ -161,3 +161,65 @@ def random_mmatrix(n, rng, density=0.1, sym=False, integer=False):
     S = sp.csr_matrix(A)
     S.sort_indices()
     return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64), A
+
+
+def nd_order_ref(n, adj):
+    """Nested-dissection numbering, recursive, from the definition: returns
+    the list of vertices in their new order.  adj: list of neighbour sets."""
+    import sys
+    sys.setrecursionlimit(max(10000, 4 * n))
+
+    def bfs(S, src):
+        d = {src: 0}
+        q = [src]
+        for u in q:
+            for v in adj[u]:
+                if v in S and v not in d:
+                    d[v] = d[u] + 1
+                    q.append(v)
+        return d
+
+    def nd(S):
+        S = sorted(S)
+        if len(S) <= 64:
+            return S
+        Sset = set(S)
+        d = bfs(Sset, S[0])
+        if len(d) < len(S):
+            comp = sorted(d)
+            rest = [v for v in S if v not in d]
+            return nd(comp) + nd(rest)
+        far = max(d.values())
+        r = min(v for v in S if d[v] == far)
+        d = bfs(Sset, r)
+        L = max(d.values())
+        if L < 2:
+            return S
+        m, cum = 0, 0
+        counts = [0] * (L + 1)
+        for v in S:
+            counts[d[v]] += 1
+        cum = counts[0]
+        while cum < len(S) / 2:
+            m += 1
+            cum += counts[m]
+        m = min(max(m, 1), L - 1)
+        A = [v for v in S if d[v] < m]
+        Bp = [v for v in S if d[v] > m]
+        sep = [v for v in S if d[v] == m]
+        return nd(A) + nd(Bp) + sep
+
+    return nd(list(range(n)))
+
+
+def coarse_pattern_adj(rowptr, col, agg, nc):
+    """Neighbour sets of the aggregate graph of A's stored pattern."""
+    adj = [set() for _ in range(nc)]
+    n = len(rowptr) - 1
+    for k in range(n):
+        for p in range(rowptr[k], rowptr[k + 1]):
+            I, J = int(agg[k]), int(agg[col[p]])
+            if I != J:
+                adj[I].add(J)
+                adj[J].add(I)
+    return adj

@@ -43,13 +43,18 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=list(CASES))
+# coarse numbering: nested dissection (default) and smallest fine index
+ORDERS = {"nd": dict(coarse_order=1), "natural": dict(coarse_order=0)}
+
+
+@pytest.fixture(scope="module", params=[(c, m) for c in CASES for m in ORDERS],
+                ids=lambda cm: f"{cm[0]}-{cm[1]}")
 def case(request):
-    name = request.param
-    _say(f"[case] {name}")
+    name, mode = request.param
+    _say(f"[case] {name} coarse_order={mode}")
     p = CASES[name]()
-    O = oracle.Oracle(p.rowptr, p.col, p.val)
-    S = Solver(p.rowptr, p.col, p.val)
+    O = oracle.Oracle(p.rowptr, p.col, p.val, **ORDERS[mode])
+    S = Solver(p.rowptr, p.col, p.val, **ORDERS[mode])
     A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
     return name, p, O, S, A
 
@@ -188,6 +193,18 @@ def test_deterministic(case):
 
 
 # ------------------------------------------------------------- edge cases
+def test_sweep_waves_do_not_change_results():
+    """The number of resident sweep waves changes scheduling only, not results."""
+    _say("[case] waves")
+    p = W.scaled("fv2d", 48)
+    b = torch.as_tensor(p.b[:, 0], device="cuda")
+    xs = []
+    for w in (0, 4, 64, 2048):
+        s = Solver(p.rowptr, p.col, p.val, sweep_waves=w)
+        xs.append(s.apply(b))
+    assert all(torch.equal(xs[0], x) for x in xs[1:])
+
+
 def test_tiny_and_degenerate():
     _say("[case] tiny")
     # 1x1, diagonal matrices, a 2x2 that needs no pivoting
@@ -244,7 +261,7 @@ def test_error_paths():
     x, res = s.solve(torch.as_tensor(p.b[:, 0], device="cuda"), tol=1e-14, maxit=2)
     assert res.status == G.NOT_CONVERGED and res.info["iters"] == 2
     with pytest.raises(GmgError):
-        s.solve(torch.as_tensor(p.b[:, 0], device="cuda"), restart=100)
+        s.solve(torch.as_tensor(p.b[:, 0], device="cuda"), restart=5000)
     # the handle still works after errors
     x, res = s.solve(torch.as_tensor(p.b[:, 0], device="cuda"), tol=1e-8)
     assert res.status == G.OK

@@ -108,12 +108,21 @@ def test_multipass_aggregation_matches_reference(oracle_mod, case):
         rp, ci, v, _ = B.random_mmatrix(120, rng, 0.06, integer=True)
     opts = oracle_mod.default_options()
     for cf in (2.0, 4.0, 8.0):
-        O = oracle_mod.Oracle(rp, ci, v, cf=cf)
         ref, passes = B.multipass_aggregation(rp, ci, v, cf, opts["max_passes"], opts["qbits"],
                                               opts["seed"])
+        # numbering by smallest fine index
+        O = oracle_mod.Oracle(rp, ci, v, cf=cf, coarse_order=0)
         agg = O.aggregates()
         assert np.array_equal(agg, ref)
         assert O.passes == passes
+        # nested-dissection numbering of the same aggregates
+        nc = int(ref.max()) + 1
+        perm = B.nd_order_ref(nc, B.coarse_pattern_adj(rp, ci, ref, nc))
+        rank = np.empty(nc, dtype=np.int64)
+        rank[np.array(perm)] = np.arange(nc)
+        Ond = oracle_mod.Oracle(rp, ci, v, cf=cf, coarse_order=1)
+        assert np.array_equal(Ond.aggregates(), rank[ref])
+        agg = O.aggregates()
         # P: one 1 per row (P 1 = 1), columns non-empty, ids ordered by first member
         assert agg.min() == 0 and agg.max() == O.nc - 1
         firsts = [np.flatnonzero(agg == I)[0] for I in range(O.nc)]
@@ -416,3 +425,37 @@ def test_error_codes(oracle_mod):
     O = oracle_mod.Oracle(p.rowptr, p.col, p.val)
     _, info = O.solve(p.b[:, 0], tol=1e-12, maxit=2)
     assert info.status == oracle_mod.NOT_CONVERGED and info.steps == 2
+
+
+def test_nested_dissection_numbering(oracle_mod):
+    """ND numbering of a grid-like coarse graph: equals the recursive definition;
+    the first separator (numbered last) disconnects the two halves numbered
+    before it; ILUT depth drops versus the smallest-fine-index numbering."""
+    p = W.scaled("fv2d", 96)
+    O0 = oracle_mod.Oracle(p.rowptr, p.col, p.val, coarse_order=0)
+    O1 = oracle_mod.Oracle(p.rowptr, p.col, p.val, coarse_order=1)
+    a0, a1 = O0.aggregates(), O1.aggregates()
+    nc = O0.nc
+    perm = B.nd_order_ref(nc, B.coarse_pattern_adj(p.rowptr, p.col, a0, nc))
+    rank = np.empty(nc, dtype=np.int64)
+    rank[np.array(perm)] = np.arange(nc)
+    assert np.array_equal(a1, rank[a0])
+    # same aggregates, same A_c up to the permutation
+    r0, c0, v0 = O0.coarse()
+    r1, c1, v1 = O1.coarse()
+    A0 = sp.csr_matrix((v0, c0, r0), shape=(nc, nc)).toarray()
+    A1 = sp.csr_matrix((v1, c1, r1), shape=(nc, nc)).toarray()
+    assert np.array_equal(A1, A0[np.ix_(perm, perm)])
+
+    def depth(rp, ci):
+        lev = np.zeros(len(rp) - 1, dtype=int)
+        for i in range(len(rp) - 1):
+            c = ci[rp[i]:rp[i + 1]]
+            c = c[c < i]
+            lev[i] = lev[c].max() + 1 if len(c) else 0
+        return lev.max() + 1
+    (l0, *_), _u0 = O0.ilut()
+    (l1, *_), _u1 = O1.ilut()
+    d0 = depth(l0, O0.ilut()[0][1])
+    d1 = depth(l1, O1.ilut()[0][1])
+    assert d1 < d0
