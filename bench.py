@@ -48,27 +48,35 @@ def _alg_bytes_doc():
             "ortho 8*N*(3k+6) for k basis vectors")
 
 
-def run_cpu_baseline(p, budget_s=30.0):
-    """The oracle, as it stands, on this host: setup plus a bounded number of
-    FGMRES steps, scaled to the full step count of the GPU solve."""
+def run_cpu_baseline(p, gpu_steps, budget_s=30.0):
+    """The oracle, as it stands, on this host: its setup, then two bounded runs
+    of k1 < k2 FGMRES steps; without restarts a step's cost grows linearly with
+    the basis size, so t(k) = a k + b k^2 / 2 is fitted to the two runs and
+    evaluated at the GPU's step count."""
     import oracle
-    import numpy as np
     oracle.build()
     t0 = time.perf_counter()
     O = oracle.Oracle(p.rowptr, p.col, p.val, cf=SOLVE_OPTS["cf"], ilut_tau=SOLVE_OPTS["ilut_tau"])
     t_setup = time.perf_counter() - t0
-    # time a first bounded chunk to size the sample
-    k0 = 5
-    t0 = time.perf_counter()
-    _, info = O.solve(p.b[:, 0], tol=0.0, maxit=k0, restart=SOLVE_OPTS["restart"])
-    t_k0 = time.perf_counter() - t0
-    per = t_k0 / k0
-    k = max(k0, min(SOLVE_OPTS["maxit"], int((budget_s - t_setup) / max(per, 1e-9) / 2)))
-    t0 = time.perf_counter()
-    _, info = O.solve(p.b[:, 0], tol=TOL, maxit=k, restart=SOLVE_OPTS["restart"])
-    t_k = time.perf_counter() - t0
-    return dict(t_setup=t_setup, steps=info.steps, t_steps=t_k, converged=info.status == 0,
-                relres=info.relres)
+
+    def run(k):
+        t = time.perf_counter()
+        O.solve(p.b[:, 0], tol=0.0, maxit=k, restart=SOLVE_OPTS["restart"])
+        return time.perf_counter() - t
+
+    k1 = 4
+    t1 = run(k1)
+    per = t1 / k1
+    # the step cost grows with the basis: aim the second run at about a third
+    # of the remaining budget at the initial step cost, and at most 120 steps
+    k2 = int(max(2 * k1, min(gpu_steps, 120, (budget_s - t_setup - t1) / max(per, 1e-9) / 3.0)))
+    t2 = run(k2)
+    # t = a k + b k^2 / 2 through (k1, t1), (k2, t2)
+    b = 2.0 * (t2 / k2 - t1 / k1) / (k2 - k1)
+    a = t1 / k1 - b * k1 / 2.0
+    b = max(b, 0.0)
+    est = t_setup + a * gpu_steps + b * gpu_steps ** 2 / 2.0
+    return dict(t_setup=t_setup, k1=k1, t1=t1, k2=k2, t2=t2, est=est)
 
 
 def main():
@@ -85,6 +93,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    os.environ.setdefault("GMG_LOG", "50")   # library progress lines on stderr
     import numpy as np
     import torch
 
@@ -206,14 +215,13 @@ def main():
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = run_cpu_baseline(p)
         gpu_steps = infos[-1]["iters"]
-        est = cb["t_setup"] + cb["t_steps"] * (gpu_steps / max(cb["steps"], 1))
+        cb = run_cpu_baseline(p, gpu_steps)
         out["cpu_baseline"] = dict(
-            value=round(est, 3), unit="s", cores=1, kind="oracle",
-            sample=(f"oracle setup ({cb['t_setup']:.2f}s) + {cb['steps']} FGMRES steps ({cb['t_steps']:.2f}s) "
-                    f"on the same workload, steps scaled to the GPU's {gpu_steps} "
-                    f"(per-step cost grows with the basis, so this underestimates)"))
+            value=round(cb["est"], 3), unit="s", cores=1, kind="oracle",
+            sample=(f"oracle setup ({cb['t_setup']:.2f}s) plus {cb['k1']} and {cb['k2']} FGMRES steps "
+                    f"({cb['t1']:.2f}s, {cb['t2']:.2f}s) on the same workload and settings; per-step cost "
+                    f"a + b*j fitted to the two runs and summed to the GPU's {gpu_steps} steps"))
         print(f"[bench] cpu baseline done: {json.dumps(out['cpu_baseline'])}", file=sys.stderr, flush=True)
 
     print(json.dumps(out))

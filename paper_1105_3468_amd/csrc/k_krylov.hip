@@ -41,10 +41,22 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount,
   }
   __syncthreads();
   if (last) {
+    // all threads take part: thread t adds blocks part, part + NP, ... of
+    // vector k (t = part * K + k), then thread k adds the NP parts in order
+    constexpr int NP = KB / K;
+    __shared__ double sh2[NP][K];
     __threadfence();
+    const int k = threadIdx.x % K, part = threadIdx.x / K;
+    if (part < NP) {
+      double s = 0.0;
+      if (k < kcount)
+        for (unsigned b = part; b < gridDim.x; b += NP) s += ld_agent(&partial[(size_t)b * KMAX + k]);
+      sh2[part][k] = s;
+    }
+    __syncthreads();
     if (threadIdx.x < kcount) {
       double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += ld_agent(&partial[(size_t)b * KMAX + threadIdx.x]);
+      for (int q = 0; q < NP; ++q) s += sh2[q][threadIdx.x];
       result[threadIdx.x] = s;
     }
     if (threadIdx.x == 0) *counter = 0u;
