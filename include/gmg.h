@@ -75,6 +75,9 @@ typedef struct {
   int coarse_order;     /* numbering of the aggregates, hence of A_c and its ILUT
                            factors: 0 by smallest fine index; 1 nested dissection
                            of A_c's graph (default)                                   */
+  int sweep_kernel;     /* 0: factors with narrow dependency levels use the single-CU
+                           LDS sweep, the others the multi-CU sweep; 1: multi-CU
+                           sweep for every factor                                     */
 } gmg_options;
 
 typedef struct {

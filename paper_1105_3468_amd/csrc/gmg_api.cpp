@@ -61,6 +61,9 @@ struct Solver {
   DBuf<float> y32, t32, r32, rc32, yc32, ec32;
   // adjoint V-cycle work vectors
   DBuf<double> abc, auc, aec, as, aw, at;
+  // schedule-order staging of the single-CU sweeps
+  DBuf<double> cu_rhs, cu_out;
+  DBuf<float> cu_rhs32, cu_out32;
   // Krylov workspace
   int mcap = 0;
   size_t ld = 0;
@@ -212,6 +215,83 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
     const double per_level = levels > 0 ? (double)sw.nchunks / levels : 1.0;
     sw.waves = std::min(2048, std::max(16, (int)std::ceil(4.0 * per_level)));
   }
+  // single-CU form when every level has at most 1024 rows, every row at most
+  // 4 entries, and every entry points at one of the two previous levels
+  sw.cu.reset();
+  {
+    std::vector<int> lev(n > 0 ? n : 1, 0), pos(n > 0 ? n : 1, 0), ulptr(levels + 1, 0);
+    bool ok = levels > 0 && levels <= 16000;  // level bounds are staged in LDS
+    int width = 1;
+    for (int l = 0, e = 0; l < levels && ok; ++l) {
+      int cnt = 0;
+      for (int p = lptr[l]; p < lptr[l + 1]; ++p) {
+        const int r = sched[p];
+        if (r < 0) continue;
+        lev[r] = l;
+        pos[r] = cnt++;
+        width = std::max(width, dep_rp[r + 1] - dep_rp[r]);
+        ++e;
+      }
+      ulptr[l + 1] = ulptr[l] + cnt;
+      if (cnt > 1024) ok = false;
+    }
+    if (width > 4) ok = false;
+    for (int e = 0; e < ne_rows && ok; ++e) {
+      const int r = rows[e];
+      for (int q = dep_rp[r]; q < dep_rp[r + 1]; ++q)
+        if (lev[dep_ci[q]] < lev[r] - 2) { ok = false; break; }
+    }
+    if (ok) {
+      const int W = width <= 2 ? width : 4;  // kernel instances: 1, 2, 3->4, 4
+      const int Wk = width == 3 ? 3 : W;
+      std::unique_ptr<CuSweep> cs(new CuSweep());
+      cs->n = ne_rows;
+      cs->levels = levels;
+      cs->width = Wk;
+      cs->has_diag = has_diag;
+      // one extra (dummy) entry at index n: zero operands, read by idle threads
+      std::vector<int> wslot((size_t)(ne_rows + 1) * Wk, 3 * 1024), wsrc((size_t)(ne_rows + 1) * Wk, -1);
+      for (int e = 0; e < ne_rows; ++e) {
+        const int r = rows[e];
+        int k = 0;
+        for (int q = dep_rp[r]; q < dep_rp[r + 1]; ++q, ++k) {
+          const int c = dep_ci[q];
+          wslot[(size_t)e * Wk + k] = (lev[c] % 3) * 1024 + pos[c];
+          wsrc[(size_t)e * Wk + k] = dp[e] + k;  // index into sw.dval (entry order)
+        }
+      }
+      cs->lptr.alloc(levels + 1);
+      cs->rows.alloc(ne_rows > 0 ? ne_rows : 1);
+      cs->wslot.alloc(wslot.size() > 0 ? wslot.size() : 1);
+      h2d(cs->lptr.p, ulptr.data(), levels + 1, s);
+      h2d(cs->rows.p, rows.data(), ne_rows, s);
+      h2d(cs->wslot.p, wslot.data(), wslot.size(), s);
+      // values: gather from the entry-ordered dval; padding entries get 0
+      std::vector<double> zero(1, 0.0);
+      DBuf<double> withzero;
+      withzero.alloc(ne + 1);
+      d2d(withzero.p, sw.dval.p, ne, s);
+      h2d(withzero.p + ne, zero.data(), 1, s);
+      for (auto& x : wsrc)
+        if (x < 0) x = (int)ne;
+      DBuf<int> dsrc2;
+      dsrc2.alloc(wsrc.size() > 0 ? wsrc.size() : 1);
+      h2d(dsrc2.p, wsrc.data(), wsrc.size(), s);
+      cs->wval.alloc(wsrc.size() > 0 ? wsrc.size() : 1);
+      cs->wval32.alloc(wsrc.size() > 0 ? wsrc.size() : 1);
+      launch_gather_f64(withzero.p, dsrc2.p, cs->wval.p, (int64_t)wsrc.size(), s);
+      launch_cast_f32(cs->wval.p, cs->wval32.p, wsrc.size(), s);
+      if (has_diag) {
+        cs->dinv_e.alloc(ne_rows + 1);
+        cs->dinv_e32.alloc(ne_rows + 1);
+        launch_fill_f64_bits(cs->dinv_e.p + ne_rows, 0ULL, 1, s);
+        launch_gather_f64(sw.dinv.p, cs->rows.p, cs->dinv_e.p, ne_rows, s);
+        launch_cast_f32(cs->dinv_e.p, cs->dinv_e32.p, ne_rows + 1, s);
+      }
+      HIPCK(hipStreamSynchronize(s));
+      sw.cu = std::move(cs);
+    }
+  }
   HIPCK(hipStreamSynchronize(s));  // host vectors above go out of scope
 }
 
@@ -236,10 +316,18 @@ static void check_abort(Solver& S) {
   }
 }
 
-// One triangular sweep of a factor.
+// One triangular sweep of a factor: the single-CU kernel when the factor has
+// one and it is enabled, else the synchronisation-free multi-CU kernel.
 template <class T>
 static void run_tri(Solver& S, Sweep& sw, const void* rhs, bool rhs_f64, T* out, T* reset) {
   constexpr bool F32 = sizeof(T) == 4;
+  if (sw.cu && S.opt.sweep_kernel == 0) {
+    CuSweep& c = *sw.cu;
+    launch_cu_sweep<T>(c, F32 ? (const T*)c.wval32.p : (const T*)c.wval.p,
+                       F32 ? (const T*)c.dinv_e32.p : (const T*)c.dinv_e.p, rhs, rhs_f64, out, reset,
+                       F32 ? (T*)S.cu_rhs32.p : (T*)S.cu_rhs.p, F32 ? (T*)S.cu_out32.p : (T*)S.cu_out.p, S.s);
+    return;
+  }
   const T* di = sw.has_diag ? (F32 ? (const T*)sw.dinv32.p : (const T*)sw.dinv.p) : nullptr;
   const int waves = S.opt.sweep_waves > 0 ? S.opt.sweep_waves : sw.waves;
   launch_sweep<T>(sw, F32 ? (const T*)sw.dval32.p : (const T*)sw.dval.p, di, rhs, rhs_f64, out, reset, waves,
@@ -598,7 +686,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   const gmg_options& o = S.opt;
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
       o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
-      o.coarse_order < 0 || o.coarse_order > 1)
+      o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 1)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
   auto t0 = std::chrono::steady_clock::now();
   const int n = (int)n64;
@@ -821,6 +909,11 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   S.rc32.alloc(S.nc); S.yc32.alloc(S.nc); S.ec32.alloc(S.nc);
   S.abc.alloc(S.nc); S.auc.alloc(S.nc); S.aec.alloc(S.nc);
   S.as.alloc(n); S.aw.alloc(n); S.at.alloc(n);
+  // staging of the single-CU sweeps, with the dummy entry at index n
+  S.cu_rhs.alloc(std::max(n, S.nc) + 1); S.cu_out.alloc(std::max(n, S.nc) + 1);
+  S.cu_rhs32.alloc(std::max(n, S.nc) + 1); S.cu_out32.alloc(std::max(n, S.nc) + 1);
+  launch_fill_f64_bits(S.cu_rhs.p, 0ULL, std::max(n, S.nc) + 1, s);
+  launch_fill_f32_bits(S.cu_rhs32.p, 0u, std::max(n, S.nc) + 1, s);
   red_init(S.rw, s);
   reset_cycle_buffers(S);
   HIPCK(hipStreamSynchronize(s));
@@ -890,6 +983,7 @@ void gmg_default_options(gmg_options* o) {
   o->x0_given = 0;
   o->sweep_waves = 0;
   o->coarse_order = 1;
+  o->sweep_kernel = 0;
 }
 
 gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,

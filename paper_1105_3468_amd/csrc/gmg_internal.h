@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,19 @@ struct HCsr {
   std::vector<double> v;
 };
 
+// A narrow triangular factor prepared for the single-CU sweep: entries e in
+// schedule order (level by level, lptr[l] .. lptr[l+1]), entry e is row
+// rows[e]; its `width` operands are LDS ring slots wslot[e*width + k] with
+// values wval[...] (slot CU_RING*1024 is a zero used as padding); dinv_e[e]
+// is the reciprocal diagonal of row rows[e] when the factor stores one.
+struct CuSweep {
+  int n = 0, levels = 0, width = 0;
+  bool has_diag = false;
+  DBuf<int> lptr, rows, wslot;
+  DBuf<double> wval, dinv_e;
+  DBuf<float> wval32, dinv_e32;
+};
+
 // A triangular factor prepared for the synchronisation-free sweep: row rows[e]
 // (entries e in schedule order: by dependency level, ascending row inside a
 // level) has dependency entries dcol[dp[e] .. dp[e+1]) with values dval.
@@ -103,6 +117,7 @@ struct Sweep {
   unsigned ticket_base = 0;  // host copy of the counter value at the next launch
   bool has_diag = false;
   int waves = 0;             // resident waves (a few dependency levels of look-ahead)
+  std::unique_ptr<CuSweep> cu;  // single-CU form, for narrow factors (null otherwise)
 };
 
 // Per-kernel-class profiling with events.
@@ -157,6 +172,9 @@ void launch_exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, DB
 template <class T>
 void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64,
                   T* out, T* reset_rhs, int waves, int* abort_flag, hipStream_t s);
+template <class T>
+void launch_cu_sweep(CuSweep& cs, const T* wval, const T* dinv_e, const void* rhs, bool rhs_is_f64, T* out,
+                     T* reset_rhs, T* rhs_s, T* out_s, hipStream_t s);
 void launch_ilu0_level(const int* rows, int count, const int* rp, const int* ci, const int* dpos,
                        double* a, int* bad, hipStream_t s);
 // yout[i] = (b[i] - sum_{j != i} F_ij yin[j]) * (dinv ? dinv[i] : 1)

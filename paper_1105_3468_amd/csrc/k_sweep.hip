@@ -15,6 +15,8 @@
 // loads until the value differs from the NaN sentinel the buffer was reset to.
 // Every wait is bounded by a wall-clock limit; a timeout raises a device flag
 // that makes all other waits give up, so the grid always drains.
+#include <algorithm>
+
 #include "gmg_internal.h"
 #include "kcommon.h"
 
@@ -147,6 +149,183 @@ template void launch_sweep<double>(Sweep&, const double*, const double*, const v
                                    int, int*, hipStream_t);
 template void launch_sweep<float>(Sweep&, const float*, const float*, const void*, bool, float*, float*, int,
                                   int*, hipStream_t);
+
+
+// ------------------------------------------------------- single-CU sweep
+// For factors whose dependency levels are narrow (at most CU_THREADS rows)
+// and whose rows depend only on the previous two levels, one workgroup walks
+// all levels itself: thread t computes the row at position t of each level,
+// the values of the last three levels stay in an LDS ring (a level writes the
+// slot its successor does not read), and one
+// workgroup barrier separates consecutive levels.  A level then costs a
+// barrier and a few LDS reads instead of a global-memory hop between compute
+// units.  Operands are laid out per level in schedule order (rhs gathered
+// before, result scattered after, by the two parallel kernels below), so
+// every thread prefetches its operands PF levels ahead.
+constexpr int CU_THREADS = 1024;
+constexpr int CU_RING = 3;
+constexpr int CU_MAX_LEVELS = 16400;
+
+// The operands of entry e (W slots, W values) with as few vector loads as the
+// width allows.
+template <class T, int W>
+__device__ __forceinline__ void load_ops(const int* __restrict__ wslot, const T* __restrict__ wval, int e,
+                                         int (&ps)[W], T (&pv)[W]) {
+  if constexpr (W == 2) {
+    const int2 sl = *reinterpret_cast<const int2*>(wslot + (size_t)e * 2);
+    ps[0] = sl.x;
+    ps[1] = sl.y;
+    if constexpr (sizeof(T) == 8) {
+      const double2 v = *reinterpret_cast<const double2*>(wval + (size_t)e * 2);
+      pv[0] = v.x;
+      pv[1] = v.y;
+    } else {
+      const float2 v = *reinterpret_cast<const float2*>(wval + (size_t)e * 2);
+      pv[0] = v.x;
+      pv[1] = v.y;
+    }
+  } else if constexpr (W == 4) {
+    const int4 sl = *reinterpret_cast<const int4*>(wslot + (size_t)e * 4);
+    ps[0] = sl.x;
+    ps[1] = sl.y;
+    ps[2] = sl.z;
+    ps[3] = sl.w;
+    if constexpr (sizeof(T) == 8) {
+      const double2 a = *reinterpret_cast<const double2*>(wval + (size_t)e * 4);
+      const double2 b = *reinterpret_cast<const double2*>(wval + (size_t)e * 4 + 2);
+      pv[0] = a.x;
+      pv[1] = a.y;
+      pv[2] = b.x;
+      pv[3] = b.y;
+    } else {
+      const float4 v = *reinterpret_cast<const float4*>(wval + (size_t)e * 4);
+      pv[0] = v.x;
+      pv[1] = v.y;
+      pv[2] = v.z;
+      pv[3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      ps[k] = wslot[(size_t)e * W + k];
+      pv[k] = wval[(size_t)e * W + k];
+    }
+  }
+}
+
+template <class T, int W, int PF, bool DIAG>
+__global__ __launch_bounds__(CU_THREADS) void k_cu_sweep(int levels, int dummy, const int* __restrict__ lptr,
+                                                         const int* __restrict__ wslot, const T* __restrict__ wval,
+                                                         const T* __restrict__ dinv_e, const T* __restrict__ rhs_s,
+                                                         T* __restrict__ out_s) {
+  // ring slots: 3 levels x CU_THREADS, then a zero (padding operand) and a
+  // sink (results of idle threads)
+  __shared__ T ring[CU_RING * CU_THREADS + 2];
+  __shared__ int lp[CU_MAX_LEVELS + 1];
+  const int t = threadIdx.x;
+  const int padded = (levels + PF - 1) / PF * PF;
+  if (t == 0) ring[CU_RING * CU_THREADS] = (T)0;
+  // level bounds in LDS (levels past the end are empty), so prefetches never
+  // wait on a global load
+  for (int l = t; l <= padded + PF; l += CU_THREADS) lp[l] = lptr[min(l, levels)];
+  __syncthreads();
+  // register pipeline: operands of levels l .. l+PF-1.  Every load is issued
+  // unconditionally (idle slots read the dummy entry), so the compiler can
+  // count outstanding loads exactly and waits only for the oldest level.
+  int pe[PF];
+  T pr[PF], pd[PF], pv[PF][W];
+  int ps[PF][W];
+  const int wave0 = t & ~63;
+  auto fetch = [&](int l, int u) {
+    const int s0 = lp[l], s1 = lp[l + 1];
+    const int e = s0 + t < s1 ? s0 + t : dummy;
+    pe[u] = e;
+    // waves with no row in this level load nothing (a wave-uniform branch)
+    if (s0 + wave0 < s1) {
+      pr[u] = rhs_s[e];
+      pd[u] = DIAG ? dinv_e[e] : (T)1;
+      load_ops<T, W>(wslot, wval, e, ps[u], pv[u]);
+    } else {
+      pr[u] = (T)0;
+      pd[u] = (T)0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) { ps[u][k] = CU_RING * CU_THREADS; pv[u][k] = (T)0; }
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u) fetch(u, u);
+  for (int l0 = 0; l0 < padded; l0 += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int l = l0 + u;
+      T acc = (T)0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc += pv[u][k] * ring[ps[u][k]];
+      T y = pr[u] - acc;
+      if (DIAG) y *= pd[u];
+      const int slot = pe[u] != dummy ? (l % CU_RING) * CU_THREADS + t : CU_RING * CU_THREADS + 1;
+      ring[slot] = y;
+      out_s[pe[u]] = y;
+      fetch(l + PF, u);
+      // order the LDS ring only: a full __syncthreads() would also wait for
+      // the prefetched global loads and serialise every level on memory
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+  }
+}
+
+template <class T, class TR>
+__global__ void k_cu_gather(int n, const int* __restrict__ rows, const TR* rhs, TR* reset_rhs, T* __restrict__ rhs_s) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int r = rows[e];
+    rhs_s[e] = (T)rhs[r];
+    if (reset_rhs) reset_rhs[r] = sentinel_of<TR>(0);
+  }
+}
+
+template <class T>
+__global__ void k_cu_scatter(int n, const int* __restrict__ rows, const T* __restrict__ out_s, T* out) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) out[rows[e]] = out_s[e];
+}
+
+template <class T>
+void launch_cu_sweep(CuSweep& cs, const T* wval, const T* dinv_e, const void* rhs, bool rhs_is_f64, T* out,
+                     T* reset_rhs, T* rhs_s, T* out_s, hipStream_t s) {
+  const int n = cs.n;
+  if (n <= 0) return;
+  unsigned g = (unsigned)std::min<int64_t>(8192, (n + 255) / 256);
+  if (rhs_is_f64 && sizeof(T) == 4)
+    hipLaunchKernelGGL((k_cu_gather<T, double>), dim3(g), dim3(256), 0, s, n, cs.rows.p, (const double*)rhs,
+                       (double*)nullptr, rhs_s);
+  else
+    hipLaunchKernelGGL((k_cu_gather<T, T>), dim3(g), dim3(256), 0, s, n, cs.rows.p, (const T*)rhs, reset_rhs,
+                       rhs_s);
+#define GMG_CU(W_, PF_)                                                                                       \
+  do {                                                                                                        \
+    if (cs.has_diag)                                                                                          \
+      hipLaunchKernelGGL((k_cu_sweep<T, W_, PF_, true>), dim3(1), dim3(CU_THREADS), 0, s, cs.levels, n,       \
+                         cs.lptr.p, cs.wslot.p, wval, dinv_e, rhs_s, out_s);                                  \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_cu_sweep<T, W_, PF_, false>), dim3(1), dim3(CU_THREADS), 0, s, cs.levels, n,      \
+                         cs.lptr.p, cs.wslot.p, wval, dinv_e, rhs_s, out_s);                                  \
+  } while (0)
+  // prefetch depth within the 128-register budget of 1024-thread workgroups
+  switch (cs.width) {
+    case 1: GMG_CU(1, 8); break;
+    case 2: GMG_CU(2, 8); break;
+    case 3: GMG_CU(3, 4); break;
+    default: GMG_CU(4, 4); break;
+  }
+#undef GMG_CU
+  hipLaunchKernelGGL((k_cu_scatter<T>), dim3(g), dim3(256), 0, s, n, cs.rows.p, out_s, out);
+  HIPCK(hipGetLastError());
+}
+template void launch_cu_sweep<double>(CuSweep&, const double*, const double*, const void*, bool, double*, double*,
+                                      double*, double*, hipStream_t);
+template void launch_cu_sweep<float>(CuSweep&, const float*, const float*, const void*, bool, float*, float*,
+                                     float*, float*, hipStream_t);
 
 // ------------------------------------------------------------------ ILU(0)
 // One launch per dependency level of L0: every row of the level runs the IKJ

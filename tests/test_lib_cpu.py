@@ -42,7 +42,7 @@ def test_default_options_and_struct_layout(lib):
     # same default hash seed as the oracle's reading
     import oracle
     assert o.hash_seed == oracle.default_options()["seed"]
-    assert ctypes.sizeof(gmg.Options) == 64
+    assert ctypes.sizeof(gmg.Options) == 72
     assert ctypes.sizeof(gmg.Info) == 4 * 9 + 4 + 8 * 6 + 8 * 4
 
 
