@@ -13,6 +13,11 @@ constexpr int KGRID = 512;       // blocks of the reduction kernels
 constexpr int KMAX = 32;         // vectors per fused register-resident pass
 constexpr int KLDS = 2048;       // vectors per LDS-staged pass (longest basis)
 
+// Keeps the machine scheduler from sinking the loads issued above it into the
+// arithmetic below: without it the compiler reuses one register pair for all
+// K basis loads of an element and waits for each in turn.
+#define ALL_LOADS_ISSUED() __builtin_amdgcn_sched_barrier(0)
+
 template <int K>
 __device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount, double* partial,
                                                    unsigned* counter, double* result) {
@@ -63,7 +68,8 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount,
   }
 }
 
-// result[k] = sum_i V[k][i] w[i], k < kc
+// result[k] = sum_i V[k][i] w[i], k < K.  The vector count is a compile-time
+// constant so the K loads of an element are unconditional and all in flight.
 template <int K>
 __global__ __launch_bounds__(KB) void k_multidot(const double* __restrict__ V, size_t ld, int kc,
                                                  const double* __restrict__ w, int64_t n, double* partial,
@@ -73,9 +79,12 @@ __global__ __launch_bounds__(KB) void k_multidot(const double* __restrict__ V, s
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
     const double wi = w[i];
+    double v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kc) acc[k] += V[k * ld + i] * wi;
+    for (int k = 0; k < K; ++k) v[k] = V[k * ld + i];
+    ALL_LOADS_ISSUED();
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += v[k] * wi;
   }
   block_reduce_store<K>(acc, kc, partial, counter, result);
 }
@@ -88,15 +97,15 @@ __global__ __launch_bounds__(KB) void k_update_dot(const double* __restrict__ V,
                                                    double* result) {
   double acc[K], hk[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) { acc[k] = 0.0; hk[k] = k < kc ? h[k] : 0.0; }
+  for (int k = 0; k < K; ++k) { acc[k] = 0.0; hk[k] = h[k]; }
   for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
     double v[K];
     double s = w[i];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      v[k] = k < kc ? V[k * ld + i] : 0.0;
-      s -= hk[k] * v[k];
-    }
+    for (int k = 0; k < K; ++k) v[k] = V[k * ld + i];
+    ALL_LOADS_ISSUED();
+#pragma unroll
+    for (int k = 0; k < K; ++k) s -= hk[k] * v[k];
     w[i] = s;
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += v[k] * s;
@@ -112,12 +121,15 @@ __global__ __launch_bounds__(KB) void k_update_norm(const double* __restrict__ V
                                                     double* result) {
   double acc[1] = {0.0}, hk[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) hk[k] = k < kc ? h[k] : 0.0;
+  for (int k = 0; k < K; ++k) hk[k] = h[k];
   for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
+    double v[K];
     double s = w[i];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kc) s -= hk[k] * V[k * ld + i];
+    for (int k = 0; k < K; ++k) v[k] = V[k * ld + i];
+    ALL_LOADS_ISSUED();
+#pragma unroll
+    for (int k = 0; k < K; ++k) s -= hk[k] * v[k];
     w[i] = s;
     acc[0] += s * s;
   }
@@ -139,12 +151,20 @@ static unsigned red_grid(int64_t n) {
   return (unsigned)g;
 }
 
-#define GMG_DISPATCH_K(kc, KERNEL, ...)                                                    \
-  do {                                                                                     \
-    if ((kc) <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                             \
-    else if ((kc) <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);                      \
-    else if ((kc) <= 24) hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__);                      \
-    else hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);                                      \
+// launch KERNEL<kc> for 1 <= kc <= 32
+#define GMG_K4(KERNEL, B, ...)                                           \
+  case B + 1: hipLaunchKernelGGL(KERNEL<B + 1>, __VA_ARGS__); break;    \
+  case B + 2: hipLaunchKernelGGL(KERNEL<B + 2>, __VA_ARGS__); break;    \
+  case B + 3: hipLaunchKernelGGL(KERNEL<B + 3>, __VA_ARGS__); break;    \
+  case B + 4: hipLaunchKernelGGL(KERNEL<B + 4>, __VA_ARGS__); break;
+#define GMG_DISPATCH_K(kc, KERNEL, ...)                                                                   \
+  do {                                                                                                    \
+    switch (kc) {                                                                                         \
+      GMG_K4(KERNEL, 0, __VA_ARGS__) GMG_K4(KERNEL, 4, __VA_ARGS__) GMG_K4(KERNEL, 8, __VA_ARGS__)         \
+      GMG_K4(KERNEL, 12, __VA_ARGS__) GMG_K4(KERNEL, 16, __VA_ARGS__) GMG_K4(KERNEL, 20, __VA_ARGS__)      \
+      GMG_K4(KERNEL, 24, __VA_ARGS__) GMG_K4(KERNEL, 28, __VA_ARGS__)                                     \
+      default: fail(GMG_ERR_INVALID_ARG, "vector count out of range");                                    \
+    }                                                                                                     \
   } while (0)
 
 void launch_multidot(const double* V, size_t ld, int k, const double* w, int64_t n, RedWork& rw,
@@ -200,12 +220,15 @@ __global__ void k_xupdate(double* __restrict__ x, const double* __restrict__ Z, 
                           const double* __restrict__ c, int64_t n) {
   double ck[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) ck[k] = k < kc ? c[k] : 0.0;
+  for (int k = 0; k < K; ++k) ck[k] = c[k];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v[K];
     double s = x[i];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kc) s += ck[k] * Z[k * ld + i];
+    for (int k = 0; k < K; ++k) v[k] = Z[k * ld + i];
+    ALL_LOADS_ISSUED();
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += ck[k] * v[k];
     x[i] = s;
   }
 }
@@ -226,12 +249,13 @@ __global__ __launch_bounds__(KB) void k_update_many(const double* __restrict__ V
   for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
     double s = w[i];
     int k = 0;
-    for (; k + 8 <= kc; k += 8) {
-      double v[8];
+    for (; k + 16 <= kc; k += 16) {
+      double v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(k + u) * ld + i];
+      for (int u = 0; u < 16; ++u) v[u] = V[(size_t)(k + u) * ld + i];
+      ALL_LOADS_ISSUED();
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s -= hs[k + u] * v[u];
+      for (int u = 0; u < 16; ++u) s -= hs[k + u] * v[u];
     }
     for (; k < kc; ++k) s -= hs[k] * V[(size_t)k * ld + i];
     w[i] = s;
@@ -256,12 +280,13 @@ __global__ __launch_bounds__(KB) void k_xupdate_many(double* __restrict__ x, con
   for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
     double s = x[i];
     int k = 0;
-    for (; k + 8 <= kc; k += 8) {
-      double v[8];
+    for (; k + 16 <= kc; k += 16) {
+      double v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = Z[(size_t)(k + u) * ld + i];
+      for (int u = 0; u < 16; ++u) v[u] = Z[(size_t)(k + u) * ld + i];
+      ALL_LOADS_ISSUED();
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += cs[k + u] * v[u];
+      for (int u = 0; u < 16; ++u) s += cs[k + u] * v[u];
     }
     for (; k < kc; ++k) s += cs[k] * Z[(size_t)k * ld + i];
     x[i] = s;
