@@ -76,8 +76,13 @@ typedef struct {
                            factors: 0 by smallest fine index; 1 nested dissection
                            of A_c's graph (default)                                   */
   int sweep_kernel;     /* 0: factors with narrow dependency levels use the single-CU
-                           LDS sweep, the others the multi-CU sweep; 1: multi-CU
-                           sweep for every factor                                     */
+                           LDS sweep; the others are cut into level ranges that run
+                           on one workgroup (few rows per level) or on the whole
+                           device; 1: whole-device sweep for every factor; 2:
+                           one-workgroup sweep for every factor.  All give bitwise
+                           identical results                                        */
+  int sweep_wg_chunks;  /* sweep_kernel 0: dependency levels of at most this many
+                           64-lane chunks run on one workgroup (default 8; 0: never) */
 } gmg_options;
 
 typedef struct {

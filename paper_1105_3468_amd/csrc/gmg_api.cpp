@@ -128,19 +128,77 @@ static void prof_flush(Solver& S) {
 }
 
 // ----------------------------------------------------------------- sweeps
+// Cut the levels into ranges, each one launch: runs of narrow levels (at
+// most wg_chunks chunks, or every level when all_wg) run on one workgroup,
+// the others on the whole device.  A run shorter than kMinRun levels joins
+// the run before it, so a factor gets a few launches; a one-workgroup run is
+// split where its rows would overflow kSweepLdsRows, and a single level that
+// alone overflows it runs device-wide.
+static void make_segments(Sweep& sw, const std::vector<int>& level_c0, const std::vector<int>& level_e0,
+                          int levels, int wg_chunks, bool all_wg) {
+  constexpr int kMinRun = 16;
+  sw.seg_c0.clear();
+  sw.seg_c1.clear();
+  sw.seg_e0.clear();
+  sw.seg_e1.clear();
+  sw.seg_wg.clear();
+  std::vector<int> run_l0;
+  std::vector<char> run_wg;
+  for (int l = 0; l < levels; ++l) {
+    const char wg = (all_wg || (level_c0[l + 1] - level_c0[l]) <= wg_chunks) ? 1 : 0;
+    if (run_wg.empty() || run_wg.back() != wg) { run_l0.push_back(l); run_wg.push_back(wg); }
+  }
+  std::vector<int> l0;
+  std::vector<char> kind;
+  for (size_t r = 0; r < run_l0.size(); ++r) {
+    const int len = (r + 1 < run_l0.size() ? run_l0[r + 1] : levels) - run_l0[r];
+    if (!l0.empty() && (len < kMinRun || run_wg[r] == kind.back())) continue;
+    l0.push_back(run_l0[r]);
+    kind.push_back(run_wg[r]);
+  }
+  auto emit = [&](int la, int lb, char wg) {
+    if (level_c0[lb] == level_c0[la]) return;
+    sw.seg_c0.push_back(level_c0[la]);
+    sw.seg_c1.push_back(level_c0[lb]);
+    sw.seg_e0.push_back(level_e0[la]);
+    sw.seg_e1.push_back(level_e0[lb]);
+    sw.seg_wg.push_back(wg);
+  };
+  for (size_t g = 0; g < l0.size(); ++g) {
+    const int la = l0[g], lb = g + 1 < l0.size() ? l0[g + 1] : levels;
+    if (!kind[g]) { emit(la, lb, 0); continue; }
+    int start = la;
+    for (int l = la; l < lb; ++l) {
+      const int rows_l = level_e0[l + 1] - level_e0[l];
+      if (rows_l > kSweepLdsRows) {  // too wide for LDS
+        emit(start, l, 1);
+        emit(l, l + 1, 0);
+        start = l + 1;
+      } else if (level_e0[l + 1] - level_e0[start] > kSweepLdsRows) {
+        emit(start, l, 1);
+        start = l;
+      }
+    }
+    emit(start, lb, 1);
+  }
+}
+
 // Build a sweep from host dependency lists.  dep_rp/dep_ci/dep_src list, per
 // row, the dependency columns and the index of each value in `src_vals`
 // (device) or the value itself (host_vals, when src_vals is null).
 static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const std::vector<int>& dep_ci,
                         const std::vector<int>& dep_src, const std::vector<double>* host_vals,
                         const double* src_vals_dev, bool lower, bool has_diag,
-                        const std::vector<double>* host_dinv, const double* dev_dinv, hipStream_t s) {
+                        const std::vector<double>* host_dinv, const double* dev_dinv, int wg_chunks,
+                        bool all_wg, hipStream_t s) {
   std::vector<int> sched, lptr;
   int levels = 0;
   make_schedule(dep_rp, dep_ci, lower, sched, lptr, &levels);
-  std::vector<int> rows, chunk;
+  std::vector<int> rows, chunk, level_c0(levels + 1, 0), level_e0(levels + 1, 0);
   rows.reserve(n);
   for (int l = 0; l < levels; ++l) {
+    level_c0[l] = (int)chunk.size() / 3;
+    level_e0[l] = (int)rows.size();
     const int first = (int)rows.size();
     int maxdeps = 0;
     for (int p = lptr[l]; p < lptr[l + 1]; ++p) {
@@ -160,6 +218,9 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
       chunk.push_back(lg);
     }
   }
+  level_c0[levels] = (int)chunk.size() / 3;
+  level_e0[levels] = (int)rows.size();
+  make_segments(sw, level_c0, level_e0, levels, wg_chunks, all_wg);
   const int ne_rows = (int)rows.size();
   std::vector<int> dp(ne_rows + 1, 0);
   for (int e = 0; e < ne_rows; ++e) dp[e + 1] = dp[e] + dep_rp[rows[e] + 1] - dep_rp[rows[e]];
@@ -189,6 +250,26 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
   h2d(sw.rows.p, rows.data(), ne_rows, s);
   h2d(sw.dp.p, dp.data(), ne_rows + 1, s);
   h2d(sw.dcol.p, dcol.data(), ne, s);
+  {
+    // LDS slots of the dependencies of one-workgroup ranges
+    bool any = false;
+    for (char w : sw.seg_wg) any = any || w;
+    if (any) {
+      std::vector<int> pos(n > 0 ? n : 1, -1), dslot(ne > 0 ? ne : 1, 0);
+      for (int e = 0; e < ne_rows; ++e) pos[rows[e]] = e;
+      for (size_t g = 0; g < sw.seg_wg.size(); ++g) {
+        if (!sw.seg_wg[g]) continue;
+        const int e0 = sw.seg_e0[g], e1 = sw.seg_e1[g];
+        for (int e = e0; e < e1; ++e)
+          for (int q = dp[e]; q < dp[e + 1]; ++q) {
+            const int c = dcol[q], pc = pos[c];
+            dslot[q] = (pc >= e0 && pc < e1) ? pc - e0 : -1 - c;
+          }
+      }
+      sw.dslot.alloc(ne > 0 ? ne : 1);
+      h2d(sw.dslot.p, dslot.data(), ne, s);
+    }
+  }
   if (host_vals) {
     h2d(sw.dval.p, dval_h.data(), ne, s);
   } else {
@@ -317,7 +398,8 @@ static void check_abort(Solver& S) {
 }
 
 // One triangular sweep of a factor: the single-CU kernel when the factor has
-// one and it is enabled, else the synchronisation-free multi-CU kernel.
+// one and it is enabled, else the synchronisation-free kernel over the
+// factor's level segments (one workgroup or the whole device each).
 template <class T>
 static void run_tri(Solver& S, Sweep& sw, const void* rhs, bool rhs_f64, T* out, T* reset) {
   constexpr bool F32 = sizeof(T) == 4;
@@ -331,7 +413,7 @@ static void run_tri(Solver& S, Sweep& sw, const void* rhs, bool rhs_f64, T* out,
   const T* di = sw.has_diag ? (F32 ? (const T*)sw.dinv32.p : (const T*)sw.dinv.p) : nullptr;
   const int waves = S.opt.sweep_waves > 0 ? S.opt.sweep_waves : sw.waves;
   launch_sweep<T>(sw, F32 ? (const T*)sw.dval32.p : (const T*)sw.dval.p, di, rhs, rhs_f64, out, reset, waves,
-                  S.abort_flag.p, S.s);
+                  S.opt.sweep_kernel == 1, S.abort_flag.p, S.s);
 }
 
 static void reset_cycle_buffers(Solver& S) {
@@ -686,9 +768,20 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   const gmg_options& o = S.opt;
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
       o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
-      o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 1)
+      o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 2 ||
+      o.sweep_wg_chunks < 0)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
   auto t0 = std::chrono::steady_clock::now();
+  // GMG_LOG also prints the duration of each setup phase (it then waits for
+  // the stream at every phase boundary, which normal runs never do)
+  auto tp = t0;
+  auto phase = [&](const char* what) {
+    if (S.log_every <= 0) return;
+    HIPCK(hipStreamSynchronize(s));
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[gmg] setup %-22s %9.2f ms\n", what, std::chrono::duration<double, std::milli>(now - tp).count());
+    tp = now;
+  };
   const int n = (int)n64;
   S.n = n;
   S.nnz = nnz64;
@@ -730,6 +823,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   S.AT.nnz = nnz64;
   DBuf<int> at_src;
   transpose_csr(n, n, nnz64, S.A.rp.p, S.A.ci.p, S.A.v.p, S.AT.rp, S.AT.ci, &S.AT.v, &at_src, s);
+  phase("validate+transpose");
   // ---- aggregation
   {
     DBuf<int> grp, gci;
@@ -738,8 +832,10 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     S.nc = aggregate(n, grp, gci, gw, o.cf, o.max_passes, o.match_qbits, o.hash_seed, S.agg, &S.passes,
                      &S.rounds, s);
   }
+  phase("matching");
   build_members(n, S.nc, S.agg.p, S.aptr, S.amem, s);
   galerkin(n, S.nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
+  phase("galerkin");
   if (o.coarse_order == 1 && S.nc > 1) {
     // number the aggregates in nested-dissection order of A_c's graph, then
     // rebuild P^T and A_c (same sums, permuted rows and columns)
@@ -767,6 +863,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     HIPCK(hipStreamSynchronize(s));
     build_members(n, nc, S.agg.p, S.aptr, S.amem, s);
     galerkin(n, nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
+    phase("nested dissection");
   }
   // ---- host copy of A's pattern for the analysis
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
@@ -806,6 +903,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     ut_rp[j + 1] = (int)ut_ci.size();
     lt_rp[j + 1] = (int)lt_ci.size();
   }
+  phase("fine dependency lists");
   // ---- ILU(0), one launch per level of L0
   S.ilu.alloc(nnz64);
   d2d(S.ilu.p, S.A.v.p, nnz64, s);
@@ -826,14 +924,16 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     if (hb & 1) fail(GMG_ERR_ZERO_PIVOT, "ILU(0): zero pivot");
     if (hb & 2) fail(GMG_ERR_NONFINITE, "ILU(0): non-finite pivot");
   }
+  phase("ILU(0)");
   DBuf<double> u0dinv;
   u0dinv.alloc(n);
   hipLaunchKernelGGL(k_recip_diag, dim3((n + 255) / 256), dim3(256), 0, s, n, S.ilu.p, S.dpos.p, u0dinv.p);
   HIPCK(hipGetLastError());
-  build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, s);
-  build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, u0dinv.p, s);
-  build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, u0dinv.p, s);
-  build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, s);
+  build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+  build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+  build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+  build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+  phase("fine sweeps");
   // ---- ILUT of A_c on the host
   {
     HCsr hAc;
@@ -847,6 +947,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     if (st == GMG_ERR_ZERO_PIVOT) fail(st, "ILUT: zero pivot");
     if (st != GMG_OK) fail(st, "ILUT: non-finite pivot");
   }
+  phase("coarse ILUT");
   {
     const int nc = S.nc;
     const HCsr &L = S.hLc, &U = S.hUc;
@@ -858,8 +959,9 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) { us_ci.push_back(U.ci[q]); us_src.push_back(q); }
       us_rp[i + 1] = (int)us_ci.size();
     }
-    build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, s);
-    build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, s);
+    build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    phase("coarse sweeps");
     // transposes: U~^T row j lists i < j (strict part), L~^T row j lists i > j
     std::vector<int> uct_cnt(nc + 1, 0), lct_cnt(nc + 1, 0);
     for (size_t q = 0; q < us_ci.size(); ++q) uct_cnt[us_ci[q] + 1]++;
@@ -879,8 +981,9 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
         lct_src[o2] = q;
       }
     }
-    build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, s);
-    build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, s);
+    build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    phase("coarse adjoint sweeps");
     if (o.coarse_mode == 1) {
       auto up = [&](DCsr& D, const HCsr& H) {
         D.n = D.m = nc;
@@ -917,6 +1020,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   red_init(S.rw, s);
   reset_cycle_buffers(S);
   HIPCK(hipStreamSynchronize(s));
+  phase("work vectors");
   auto t1 = std::chrono::steady_clock::now();
   gmg_info& I = S.info;
   I.passes = S.passes;
@@ -984,6 +1088,7 @@ void gmg_default_options(gmg_options* o) {
   o->sweep_waves = 0;
   o->coarse_order = 1;
   o->sweep_kernel = 0;
+  o->sweep_wg_chunks = 8;
 }
 
 gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,

@@ -117,6 +117,14 @@ struct Sweep {
   unsigned ticket_base = 0;  // host copy of the counter value at the next launch
   bool has_diag = false;
   int waves = 0;             // resident waves (a few dependency levels of look-ahead)
+  // consecutive level ranges, one launch each: chunks [seg_c0[g], seg_c1[g])
+  // (rows = entries [seg_e0[g], seg_e1[g])) on one workgroup with the
+  // range's results in LDS (seg_wg[g] != 0) or on the whole device.  For
+  // entries of one-workgroup ranges, dslot[q] is the LDS slot of dependency
+  // dcol[q] when it lies in the same range, else -1 - dcol[q].
+  std::vector<int> seg_c0, seg_c1, seg_e0, seg_e1;
+  std::vector<char> seg_wg;
+  DBuf<int> dslot;
   std::unique_ptr<CuSweep> cu;  // single-CU form, for narrow factors (null otherwise)
 };
 
@@ -171,7 +179,9 @@ void launch_exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, DB
 // Triangular sweeps (k_sweep.hip)
 template <class T>
 void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64,
-                  T* out, T* reset_rhs, int waves, int* abort_flag, hipStream_t s);
+                  T* out, T* reset_rhs, int waves, bool whole, int* abort_flag, hipStream_t s);
+// rows of a one-workgroup level range (its FP64 results fill 128 KiB of LDS)
+constexpr int kSweepLdsRows = 16384;
 template <class T>
 void launch_cu_sweep(CuSweep& cs, const T* wval, const T* dinv_e, const void* rhs, bool rhs_is_f64, T* out,
                      T* reset_rhs, T* rhs_s, T* out_s, hipStream_t s);

@@ -15,6 +15,16 @@
 // loads until the value differs from the NaN sentinel the buffer was reset to.
 // Every wait is bounded by a wall-clock limit; a timeout raises a device flag
 // that makes all other waits give up, so the grid always drains.
+//
+// Publishing through memory at agent scope costs about half a microsecond
+// per hop (the XCDs' L2 caches are not coherent with each other), and that
+// hop is the whole cost of a dependency level when levels hold only a few
+// rows.  Such level ranges run on one workgroup instead (k_sweep_lds): the
+// same chunks and the same arithmetic in the same order, tickets from an LDS
+// counter, and the range's own results published in and polled from LDS (a
+// copy also goes to global memory for later kernels).  Wide ranges keep the
+// whole device for bandwidth.  Range boundaries are kernel boundaries, so a
+// range reads the results of earlier ranges as final values.
 #include <algorithm>
 
 #include "gmg_internal.h"
@@ -23,32 +33,167 @@
 namespace gmg {
 
 constexpr int SWEEP_BATCH = 8;
-
-template <class T>
-__device__ __forceinline__ T wait_ready(const T* p, int* abort_flag, uint64_t limit) {
-  T v = ld_agent(p);
-  if (!is_sentinel(v)) return v;
-  const uint64_t t0 = wall_clock64();
-  unsigned it = 0;
-  for (;;) {
-    __builtin_amdgcn_s_sleep(1);
-    v = ld_agent(p);
-    if (!is_sentinel(v)) return v;
-    if ((++it & 31u) == 0) {
-      if (ld_agent(abort_flag)) return __builtin_nan("");
-      if (wall_clock64() - t0 > limit) {
-        st_agent(abort_flag, 1);
-        return __builtin_nan("");
-      }
-    }
-  }
-}
+constexpr int SWEEP_WG_THREADS = 1024;  // the one workgroup of k_sweep_lds
 
 template <class T>
 __device__ __forceinline__ T not_sentinel(T v) {
   // a computed value equal to the sentinel's bits would never be seen as
   // ready; replace it by the canonical NaN (only reachable from NaN inputs)
   return is_sentinel(v) ? (T)__builtin_nan("") : v;
+}
+
+// Dependency values of the device-wide sweep: out[col], published at agent
+// scope by any CU.
+template <class T>
+struct GlobalSrc {
+  const T* out;
+  static constexpr bool kSleep = true;  // polls cross the device: do not flood it
+  __device__ void fetch(const int (&c)[SWEEP_BATCH], T (&v)[SWEEP_BATCH]) const {
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u) v[u] = ld_agent(out + c[u]);
+  }
+  __device__ unsigned pending(const int (&)[SWEEP_BATCH], const T (&v)[SWEEP_BATCH], unsigned need) const {
+    unsigned p = 0;
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u)
+      if (is_sentinel(v[u])) p |= 1u << u;
+    return p & need;
+  }
+  __device__ void refetch(const int (&c)[SWEEP_BATCH], T (&v)[SWEEP_BATCH], unsigned pend) const {
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u)
+      if (pend >> u & 1u) v[u] = ld_agent(out + c[u]);
+  }
+};
+
+// Dependency values of the one-workgroup sweep: code >= 0 is the LDS slot of a
+// row of this range; code < 0 is row -1 - code of an earlier range, final in
+// global memory.  Both loads are issued for every entry (the unused one at a
+// clamped address) and the result selected, so a batch is straight-line code
+// with all its loads in flight together.
+template <class T>
+struct LdsSrc {
+  T* xs;
+  const T* out;
+  static constexpr bool kSleep = false;  // LDS polls are cheap and local
+  __device__ void fetch(const int (&c)[SWEEP_BATCH], T (&v)[SWEEP_BATCH]) const {
+    T g[SWEEP_BATCH], l[SWEEP_BATCH];
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u) g[u] = out[c[u] < 0 ? -1 - c[u] : 0];
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u)
+      l[u] = __hip_atomic_load(xs + (c[u] >= 0 ? c[u] : 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u) v[u] = c[u] >= 0 ? l[u] : g[u];
+  }
+  __device__ unsigned pending(const int (&c)[SWEEP_BATCH], const T (&v)[SWEEP_BATCH], unsigned need) const {
+    unsigned p = 0;
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u)
+      if (c[u] >= 0 && is_sentinel(v[u])) p |= 1u << u;
+    return p & need;
+  }
+  __device__ void refetch(const int (&c)[SWEEP_BATCH], T (&v)[SWEEP_BATCH], unsigned pend) const {
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u)
+      if (pend >> u & 1u) v[u] = __hip_atomic_load(xs + c[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+// acc = sum of this lane's share of row e's entries: entries q0+sub,
+// q0+sub+G, ... (q0 < q1), SWEEP_BATCH at a time.  Every batch loads its
+// entries unconditionally (past the row's end at the row's last entry, not
+// added) so all its loads are in flight together.  Values not yet published
+// are polled as a group: every round re-issues all of them together, so a
+// round costs one latency however many are pending.  Entries are added in
+// ascending order in both sweeps, so they give bitwise identical sums.
+template <class T, class Src>
+__device__ __forceinline__ T lane_partial(const Src& src, const int* __restrict__ dref,
+                                          const T* __restrict__ dval, int q0, int q1, int G, int* abort_flag,
+                                          uint64_t limit) {
+  T acc = (T)0;
+  for (int q = q0; q < q1; q += G * SWEEP_BATCH) {
+    int c[SWEEP_BATCH];
+    T v[SWEEP_BATCH];
+    T a[SWEEP_BATCH];
+    unsigned need = 0;
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u) {
+      const int qq = q + u * G < q1 ? q + u * G : q1 - 1;
+      c[u] = dref[qq];
+      a[u] = dval[qq];
+      if (q + u * G < q1) need |= 1u << u;
+    }
+    src.fetch(c, v);
+    unsigned pend = src.pending(c, v, need);
+    if (pend) {
+      const uint64_t t0 = wall_clock64();
+      unsigned it = 0;
+#pragma clang loop unroll(disable)
+      while (pend) {
+        if constexpr (Src::kSleep) __builtin_amdgcn_s_sleep(1);
+        src.refetch(c, v, pend);
+        pend = src.pending(c, v, pend);
+        if (pend && (++it & 63u) == 0) {
+          bool give_up = ld_agent(abort_flag) != 0;
+          if (!give_up && wall_clock64() - t0 > limit) {
+            st_agent(abort_flag, 1);
+            give_up = true;
+          }
+          if (give_up) {
+#pragma unroll
+            for (int u = 0; u < SWEEP_BATCH; ++u)
+              if (pend >> u & 1u) v[u] = (T)__builtin_nan("");
+            pend = 0;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u)
+      if (need >> u & 1u) acc += a[u] * v[u];
+  }
+  return acc;
+}
+
+// The rows of one chunk: lanes grouped per row, partial sums reduced by
+// shuffles, the row's owner lane stores.  The row's own operands (index,
+// right-hand side, reciprocal diagonal) do not depend on other rows and are
+// loaded before the dependencies, so only the reduction and the store follow
+// the last dependency.  Returns, for the owner lane, the row's entry and value;
+// the caller publishes the value and only then resets the right-hand side
+// (stores count against the same wait counter as loads, so a store issued
+// before the value is computed would be waited for on the critical path).
+template <class T, class TR, bool DIAG, class Src>
+__device__ __forceinline__ bool chunk_rows(const Src& src, const int* __restrict__ chunk, unsigned t,
+                                           const int* __restrict__ rows, const int* __restrict__ dp,
+                                           const int* __restrict__ dref, const T* __restrict__ dval,
+                                           const T* __restrict__ dinv, const TR* rhs, int* abort_flag,
+                                           uint64_t limit, int& e_out, int& r_out, T& y_out) {
+  const int lane = threadIdx.x & 63;
+  // chunk: first entry, number of rows, log2 of lanes per row
+  const int c0 = chunk[3 * t], cr = chunk[3 * t + 1], lg = chunk[3 * t + 2];
+  const int G = 1 << lg;
+  const int slot = lane >> lg, sub = lane & (G - 1);
+  const bool active = slot < cr;
+  const int e = c0 + slot;
+  int r = 0;
+  T rh = (T)0, di = (T)1;
+  if (active && sub == 0) {
+    r = rows[e];
+    rh = (T)rhs[r];
+    if (DIAG) di = dinv[r];
+  }
+  T acc = (T)0;
+  if (active) acc = lane_partial<T>(src, dref, dval, dp[e] + sub, dp[e + 1], G, abort_flag, limit);
+  for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (!(active && sub == 0)) return false;
+  T y = rh - acc;
+  if (DIAG) y *= di;
+  e_out = e;
+  r_out = r;
+  y_out = not_sentinel(y);
+  return true;
 }
 
 template <class T, class TR, bool DIAG>
@@ -58,49 +203,50 @@ __global__ __launch_bounds__(256) void k_sweep(const int* __restrict__ chunk, co
                                                const TR* rhs, T* out, TR* reset_rhs, unsigned nchunks,
                                                unsigned* ticket, unsigned base, int* abort_flag, uint64_t limit) {
   const int lane = threadIdx.x & 63;
+  const GlobalSrc<T> src{out};
   for (;;) {
     unsigned t = 0;
     if (lane == 0) t = atomicAdd(ticket, 1u) - base;
     t = __shfl(t, 0, 64);
     if (t >= nchunks) break;
-    // chunk: first entry, number of rows, log2 of lanes per row
-    const int c0 = chunk[3 * t], cr = chunk[3 * t + 1], lg = chunk[3 * t + 2];
-    const int G = 1 << lg;
-    const int slot = lane >> lg, sub = lane & (G - 1);
-    const bool active = slot < cr;
-    const int e = c0 + slot;
-    T acc = (T)0;
-    if (active) {
-      // this lane's share of the row: entries q0+sub, q0+sub+G, ...; up to
-      // SWEEP_BATCH of them are loaded at once (independent loads), and only
-      // values not yet published are then waited for one by one
-      const int q1 = dp[e + 1];
-      for (int q = dp[e] + sub; q < q1; q += G * SWEEP_BATCH) {
-        int c[SWEEP_BATCH];
-        T v[SWEEP_BATCH];
-        T a[SWEEP_BATCH];
-#pragma unroll
-        for (int u = 0; u < SWEEP_BATCH; ++u)
-          if (q + u * G < q1) { c[u] = dcol[q + u * G]; a[u] = dval[q + u * G]; }
-#pragma unroll
-        for (int u = 0; u < SWEEP_BATCH; ++u)
-          if (q + u * G < q1) v[u] = ld_agent(out + c[u]);
-#pragma unroll
-        for (int u = 0; u < SWEEP_BATCH; ++u)
-          if (q + u * G < q1) {
-            if (is_sentinel(v[u])) v[u] = wait_ready(out + c[u], abort_flag, limit);
-            acc += a[u] * v[u];
-          }
-      }
-    }
-    for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (active && sub == 0) {
-      const int r = rows[e];
-      // rhs and reset_rhs may be the same buffer: read before the reset
-      T y = (T)rhs[r] - acc;
+    int e, r;
+    T y;
+    if (chunk_rows<T, TR, DIAG>(src, chunk, t, rows, dp, dcol, dval, dinv, rhs, abort_flag, limit, e, r, y)) {
+      st_agent(out + r, y);
+      // rhs and reset_rhs may be the same buffer: the row read it already
       if (reset_rhs) reset_rhs[r] = sentinel_of<TR>(0);
-      if (DIAG) y *= dinv[r];
-      st_agent(out + r, not_sentinel(y));
+    }
+  }
+}
+
+// One workgroup over the chunks of a level range whose rows are entries
+// [e0, e0 + m); their results live in LDS slots e - e0 (dynamic LDS of m
+// values, reset to the sentinel at start).  dslot holds the LDS slot or the
+// -1 - row code of every dependency entry of the range.
+template <class T, class TR, bool DIAG>
+__global__ __launch_bounds__(SWEEP_WG_THREADS) void k_sweep_lds(
+    const int* __restrict__ chunk, const int* __restrict__ rows, const int* __restrict__ dp,
+    const int* __restrict__ dslot, const T* __restrict__ dval, const T* __restrict__ dinv, const TR* rhs, T* out,
+    TR* reset_rhs, unsigned nchunks, int e0, int m, int* abort_flag, uint64_t limit) {
+  extern __shared__ __align__(16) unsigned char sweep_smem[];
+  T* xs = reinterpret_cast<T*>(sweep_smem);
+  __shared__ unsigned ticket;
+  for (int i = threadIdx.x; i < m; i += SWEEP_WG_THREADS) xs[i] = sentinel_of<T>(0);
+  if (threadIdx.x == 0) ticket = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const LdsSrc<T> src{xs, out};
+  for (;;) {
+    unsigned t = 0;
+    if (lane == 0) t = atomicAdd(&ticket, 1u);
+    t = __shfl(t, 0, 64);
+    if (t >= nchunks) break;
+    int e, r;
+    T y;
+    if (chunk_rows<T, TR, DIAG>(src, chunk, t, rows, dp, dslot, dval, dinv, rhs, abort_flag, limit, e, r, y)) {
+      __hip_atomic_store(xs + (e - e0), y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      out[r] = y;
+      if (reset_rhs) reset_rhs[r] = sentinel_of<TR>(0);
     }
   }
 }
@@ -121,34 +267,67 @@ static uint64_t wall_limit_ticks() {
 
 template <class T>
 void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64, T* out,
-                  T* reset_rhs, int waves, int* abort_flag, hipStream_t s) {
-  const unsigned nchunks = (unsigned)sw.nchunks;
-  if (nchunks == 0) return;
-  unsigned w = waves > 0 ? (unsigned)waves : 2048u;
-  if (w > nchunks) w = nchunks;
-  const unsigned blocks = (w + 3) / 4;
-  const unsigned used = blocks * 4;  // every wave takes exactly one ticket that ends it
+                  T* reset_rhs, int waves, bool whole, int* abort_flag, hipStream_t s) {
+  if (sw.nchunks == 0) return;
   const uint64_t lim = wall_limit_ticks();
-#define GMG_SW(TR_, DG_, RHS_, RESET_)                                                                     \
-  hipLaunchKernelGGL((k_sweep<T, TR_, DG_>), dim3(blocks), dim3(256), 0, s, sw.chunk.p, sw.rows.p, sw.dp.p, \
-                     sw.dcol.p, dval, dinv, (const TR_*)RHS_, out, RESET_, nchunks, sw.ticket.p,             \
-                     sw.ticket_base, abort_flag, lim)
-  if (rhs_is_f64 && sizeof(T) == 4) {
-    // FP32 sweep with an FP64 right-hand side (first sweep of the FP32 cycle)
-    if (sw.has_diag) GMG_SW(double, true, rhs, (double*)nullptr);
-    else GMG_SW(double, false, rhs, (double*)nullptr);
-  } else {
-    if (sw.has_diag) GMG_SW(T, true, rhs, reset_rhs);
-    else GMG_SW(T, false, rhs, reset_rhs);
-  }
+  // whole: every level device-wide in one launch; else the level ranges
+  // chosen at setup
+  const int nseg = whole ? 1 : (int)sw.seg_c0.size();
+  for (int g = 0; g < nseg; ++g) {
+    const int c0 = whole ? 0 : sw.seg_c0[g];
+    const unsigned nchunks = (unsigned)((whole ? sw.nchunks : sw.seg_c1[g]) - c0);
+    const bool wg = !whole && sw.seg_wg[g] != 0;
+    const int* ch = sw.chunk.p + 3 * (size_t)c0;
+    if (nchunks == 0) continue;
+    if (wg) {
+      const int e0 = sw.seg_e0[g], m = sw.seg_e1[g] - e0;
+      const size_t lds = (size_t)m * sizeof(T);
+#define GMG_SWL(TR_, DG_, RHS_, RESET_)                                                                            \
+  do {                                                                                                            \
+    static bool attr = false;                                                                                     \
+    if (!attr) {                                                                                                  \
+      HIPCK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_lds<T, TR_, DG_>),                         \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kSweepLdsRows * sizeof(double)))); \
+      attr = true;                                                                                                \
+    }                                                                                                             \
+    hipLaunchKernelGGL((k_sweep_lds<T, TR_, DG_>), dim3(1), dim3(SWEEP_WG_THREADS), lds, s, ch, sw.rows.p,        \
+                       sw.dp.p, sw.dslot.p, dval, dinv, (const TR_*)RHS_, out, RESET_, nchunks, e0, m, abort_flag, lim); \
+  } while (0)
+      if (rhs_is_f64 && sizeof(T) == 4) {
+        if (sw.has_diag) GMG_SWL(double, true, rhs, (double*)nullptr);
+        else GMG_SWL(double, false, rhs, (double*)nullptr);
+      } else {
+        if (sw.has_diag) GMG_SWL(T, true, rhs, reset_rhs);
+        else GMG_SWL(T, false, rhs, reset_rhs);
+      }
+#undef GMG_SWL
+      HIPCK(hipGetLastError());
+      continue;
+    }
+    unsigned w = waves > 0 ? (unsigned)waves : 2048u;
+    if (w > nchunks) w = nchunks;
+    const unsigned blocks = (w + 3) / 4;
+    const unsigned used = blocks * 4;  // every wave takes exactly one ticket that ends it
+#define GMG_SW(TR_, DG_, RHS_, RESET_)                                                                        \
+  hipLaunchKernelGGL((k_sweep<T, TR_, DG_>), dim3(blocks), dim3(256), 0, s, ch, sw.rows.p, sw.dp.p, sw.dcol.p, \
+                     dval, dinv, (const TR_*)RHS_, out, RESET_, nchunks, sw.ticket.p, sw.ticket_base, abort_flag, lim)
+    if (rhs_is_f64 && sizeof(T) == 4) {
+      // FP32 sweep with an FP64 right-hand side (first sweep of the FP32 cycle)
+      if (sw.has_diag) GMG_SW(double, true, rhs, (double*)nullptr);
+      else GMG_SW(double, false, rhs, (double*)nullptr);
+    } else {
+      if (sw.has_diag) GMG_SW(T, true, rhs, reset_rhs);
+      else GMG_SW(T, false, rhs, reset_rhs);
+    }
 #undef GMG_SW
-  HIPCK(hipGetLastError());
-  sw.ticket_base += nchunks + used;
+    HIPCK(hipGetLastError());
+    sw.ticket_base += nchunks + used;
+  }
 }
 template void launch_sweep<double>(Sweep&, const double*, const double*, const void*, bool, double*, double*,
-                                   int, int*, hipStream_t);
+                                   int, bool, int*, hipStream_t);
 template void launch_sweep<float>(Sweep&, const float*, const float*, const void*, bool, float*, float*, int,
-                                  int*, hipStream_t);
+                                  bool, int*, hipStream_t);
 
 
 // ------------------------------------------------------- single-CU sweep

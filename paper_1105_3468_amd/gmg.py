@@ -32,7 +32,8 @@ class Options(C.Structure):
                 ("hash_seed", C.c_uint64), ("ilut_tau", C.c_double), ("coarse_mode", C.c_int),
                 ("coarse_sweeps", C.c_int), ("restart", C.c_int), ("maxit", C.c_int),
                 ("precond_fp32", C.c_int), ("x0_given", C.c_int), ("sweep_waves", C.c_int),
-                ("coarse_order", C.c_int), ("sweep_kernel", C.c_int)]
+                ("coarse_order", C.c_int), ("sweep_kernel", C.c_int),
+                ("sweep_wg_chunks", C.c_int)]
 
 
 class Info(C.Structure):

@@ -194,31 +194,36 @@ def test_deterministic(case):
 
 # ------------------------------------------------------------- edge cases
 def test_sweep_waves_do_not_change_results():
-    """The number of resident sweep waves changes scheduling only, not results."""
+    """The number of resident sweep waves changes scheduling only, not results
+    (device-wide and one-XCD multi-CU sweeps)."""
     _say("[case] waves")
     p = W.scaled("fv2d", 48)
     b = torch.as_tensor(p.b[:, 0], device="cuda")
     xs = []
-    for w in (0, 4, 64, 2048):
-        s = Solver(p.rowptr, p.col, p.val, sweep_waves=w)
-        xs.append(s.apply(b))
+    for kern in (1, 2):
+        for w in (0, 4, 64, 2048):
+            s = Solver(p.rowptr, p.col, p.val, sweep_waves=w, sweep_kernel=kern)
+            xs.append(s.apply(b))
     assert all(torch.equal(xs[0], x) for x in xs[1:])
 
 
-@pytest.mark.parametrize("kind", ["fv2d_rot_96", "fv3d_20", "fv2d_37"])
-def test_single_cu_sweep_matches_multi_cu(kind):
-    """The single-CU LDS sweep (narrow factors) and the multi-CU sweep perform
-    the same operations in the same order: bitwise-equal preconditioner
-    applications, in FP64 and FP32, forward and adjoint."""
-    _say(f"[case] cu-vs-multi {kind}")
+@pytest.mark.parametrize("kind", ["fv2d_rot_96", "fv3d_20", "fv2d_37", "rgg_3001"])
+def test_sweep_kernels_bitwise_equal(kind):
+    """The single-CU LDS sweep (narrow factors), the device-wide multi-CU
+    sweep and the one-XCD multi-CU sweep perform the same operations in the
+    same order: bitwise-equal preconditioner applications, in FP64 and FP32,
+    forward and adjoint."""
+    _say(f"[case] sweep kernels {kind}")
     p = CASES[kind]()
     z = torch.as_tensor(np.random.default_rng(9).uniform(-1, 1, p.n_rows), device="cuda")
-    s0 = Solver(p.rowptr, p.col, p.val, sweep_kernel=0)
-    s1 = Solver(p.rowptr, p.col, p.val, sweep_kernel=1)
+    configs = [dict(sweep_kernel=1), dict(sweep_kernel=0), dict(sweep_kernel=2),
+               dict(sweep_kernel=0, sweep_wg_chunks=1), dict(sweep_kernel=0, sweep_wg_chunks=64)]
+    solvers = [Solver(p.rowptr, p.col, p.val, **c) for c in configs]
     for prec, adj in ((0, False), (1, False), (0, True)):
-        a = s0.apply(z, precision=prec, adjoint=adj)
-        b = s1.apply(z, precision=prec, adjoint=adj)
-        assert torch.equal(a, b), (kind, prec, adj)
+        ref = solvers[0].apply(z, precision=prec, adjoint=adj)
+        for c, s in zip(configs[1:], solvers[1:]):
+            a = s.apply(z, precision=prec, adjoint=adj)
+            assert torch.equal(a, ref), (kind, c, prec, adj)
 
 
 def test_tiny_and_degenerate():

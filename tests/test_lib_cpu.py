@@ -42,6 +42,8 @@ def test_default_options_and_struct_layout(lib):
     # same default hash seed as the oracle's reading
     import oracle
     assert o.hash_seed == oracle.default_options()["seed"]
+    assert o.sweep_kernel == 0 and o.sweep_wg_chunks == 8
+    # C layout: 12 ints, one uint64, two doubles, no padding
     assert ctypes.sizeof(gmg.Options) == 72
     assert ctypes.sizeof(gmg.Info) == 4 * 9 + 4 + 8 * 6 + 8 * 4
 
