@@ -64,6 +64,12 @@ struct Solver {
   // schedule-order staging of the single-CU sweeps
   DBuf<double> cu_rhs, cu_out;
   DBuf<float> cu_rhs32, cu_out32;
+  // wavefront form of the fine factors (2D-grid structure)
+  bool wave = false;
+  WaveGrid wg;
+  WaveSweep wL0, wU0, wU0t, wL0t;
+  DBuf<double> wz, wy, wt;
+  DBuf<float> wz32, wy32, wt32;
   // Krylov workspace
   int mcap = 0;
   size_t ld = 0;
@@ -418,6 +424,12 @@ static void run_tri(Solver& S, Sweep& sw, const void* rhs, bool rhs_f64, T* out,
 
 static void reset_cycle_buffers(Solver& S) {
   hipStream_t s = S.s;
+  if (S.wave) {
+    launch_fill_f64_bits(S.wy.p, kSent64, S.wg.total, s);
+    launch_fill_f64_bits(S.wt.p, kSent64, S.wg.total, s);
+    launch_fill_f32_bits(S.wy32.p, kSent32, S.wg.total, s);
+    launch_fill_f32_bits(S.wt32.p, kSent32, S.wg.total, s);
+  }
   launch_fill_f64_bits(S.y.p, kSent64, S.n, s);
   launch_fill_f64_bits(S.t.p, kSent64, S.n, s);
   launch_fill_f64_bits(S.yc.p, kSent64, S.nc, s);
@@ -447,13 +459,19 @@ static void vcycle(Solver& S, const double* z, double* q) {
   T* ec = F32 ? (T*)S.ec32.p : (T*)S.ec.p;
   const T* Av = F32 ? (const T*)S.A.v32.p : (const T*)S.A.v.p;
   const size_t sz = sizeof(T);
-  {
-    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false));
-    run_tri<T>(S, S.L0, z, true, y, nullptr);
-  }
-  {
-    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0, sz, sz, true));
-    run_tri<T>(S, S.U0, y, false, t, y);
+  if (S.wave) {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false) + sweep_bytes(S.U0, sz, sz, true));
+    launch_wave_pair<T>(S.wg, S.wL0, S.wU0, z, true, F32 ? (T*)S.wz32.p : (T*)S.wz.p, F32 ? (T*)S.wy32.p : (T*)S.wy.p,
+                        F32 ? (T*)S.wt32.p : (T*)S.wt.p, t, S.abort_flag.p, s);
+  } else {
+    {
+      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false));
+      run_tri<T>(S, S.L0, z, true, y, nullptr);
+    }
+    {
+      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0, sz, sz, true));
+      run_tri<T>(S, S.U0, y, false, t, y);
+    }
   }
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 8 + 3 * sz + 4) +
@@ -518,13 +536,18 @@ static void vcycle_adjoint(Solver& S, const double* z, double* q) {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * 12 + (double)S.n * 24);
     launch_resid_adj(S.n, S.AT.rp.p, S.AT.ci.p, S.AT.v.p, S.agg.p, S.aec.p, z, S.as.p, s);
   }
-  {
-    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
-    run_tri<double>(S, S.U0t, S.as.p, false, S.aw.p, nullptr);
-  }
-  {
-    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
-    run_tri<double>(S, S.L0t, S.aw.p, false, S.at.p, S.aw.p);
+  if (S.wave) {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false) + sweep_bytes(S.L0t, 8, 8, true));
+    launch_wave_pair<double>(S.wg, S.wU0t, S.wL0t, S.as.p, true, S.wz.p, S.wy.p, S.wt.p, S.at.p, S.abort_flag.p, s);
+  } else {
+    {
+      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
+      run_tri<double>(S, S.U0t, S.as.p, false, S.aw.p, nullptr);
+    }
+    {
+      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
+      run_tri<double>(S, S.L0t, S.aw.p, false, S.at.p, S.aw.p);
+    }
   }
   {
     Prof p(S, PC_PROLONG, (double)S.n * 28 + (double)S.nc * 8);
@@ -759,6 +782,88 @@ static std::vector<int> to_host_int(const int* d, size_t n, hipStream_t s) {
   return h;
 }
 
+// 2D-grid structure of a triangular factor given by dependency lists: every
+// dependency of row k is k -/+ 1 (same grid row) or k -/+ nx, for one nx
+// dividing n (lower: minus, upper: plus).  Returns nx, or 0.
+static int grid2d_nx(int n, const std::vector<int>& dep_rp, const std::vector<int>& dep_ci, bool lower) {
+  int nx = 0;
+  bool has1 = false;
+  for (int k = 0; k < n; ++k)
+    for (int q = dep_rp[k]; q < dep_rp[k + 1]; ++q) {
+      const int d = lower ? k - dep_ci[q] : dep_ci[q] - k;
+      if (d <= 0) return 0;
+      if (d == 1) { has1 = true; continue; }
+      if (nx == 0) nx = d;
+      else if (d != nx) return 0;
+    }
+  if (nx == 0) nx = has1 ? n : 0;
+  if (nx < 2 || n % nx != 0) return 0;
+  for (int k = 0; k < n; ++k)
+    for (int q = dep_rp[k]; q < dep_rp[k + 1]; ++q) {
+      const int d = lower ? k - dep_ci[q] : dep_ci[q] - k;
+      if (d == 1 && (lower ? k % nx == 0 : k % nx == nx - 1)) return 0;  // crosses a grid row
+    }
+  return nx;
+}
+
+static int wave_cell_host(int64_t q, const WaveGrid& g) {
+  const int l = (int)(q & 63);
+  const int64_t ws = q >> 6;
+  const int w = (int)(ws / g.S), s = (int)(ws - (int64_t)w * g.S);
+  const int j = 64 * w + l, i = s - l;
+  return (i >= 0 && i < g.nx && j < g.ny) ? j * g.nx + i : -1;
+}
+
+// Lay a factor out for the wavefront sweep: values from vals_dev (entries
+// dep_src), reciprocal diagonal from dinv_dev (natural order) when given.
+static void build_wave(WaveSweep& f, const WaveGrid& g, const std::vector<int>& dep_rp,
+                       const std::vector<int>& dep_ci, const std::vector<int>& dep_src, bool lower,
+                       const double* vals_dev, int64_t nvals, const double* dinv_dev, int n, hipStream_t s) {
+  f.has_diag = dinv_dev != nullptr;
+  const int64_t T2 = 2 * g.total;
+  std::vector<int> cidx(T2), didx(f.has_diag ? g.total : 0);
+  for (int64_t p = 0; p < g.total; ++p) {
+    const int c = wave_cell_host(lower ? p : g.total - 1 - p, g);
+    int below = (int)nvals, left = (int)nvals;  // index nvals: zero
+    if (c >= 0) {
+      const int cb = lower ? c - g.nx : c + g.nx, cl = lower ? c - 1 : c + 1;
+      for (int q = dep_rp[c]; q < dep_rp[c + 1]; ++q) {
+        if (dep_ci[q] == cb) below = dep_src[q];
+        if (dep_ci[q] == cl) left = dep_src[q];
+      }
+    }
+    cidx[2 * p] = below;
+    cidx[2 * p + 1] = left;
+    if (f.has_diag) didx[p] = c >= 0 ? c : n;
+  }
+  DBuf<double> vz;
+  vz.alloc(nvals + 1);
+  d2d(vz.p, vals_dev, nvals, s);
+  launch_fill_f64_bits(vz.p + nvals, 0ULL, 1, s);
+  DBuf<int> ix;
+  ix.alloc(T2);
+  h2d(ix.p, cidx.data(), T2, s);
+  f.coef.alloc(T2);
+  f.coef32.alloc(T2);
+  launch_gather_f64(vz.p, ix.p, f.coef.p, T2, s);
+  launch_cast_f32(f.coef.p, f.coef32.p, T2, s);
+  if (f.has_diag) {
+    DBuf<double> dz;
+    dz.alloc((size_t)n + 1);
+    d2d(dz.p, dinv_dev, n, s);
+    launch_fill_f64_bits(dz.p + n, 0ULL, 1, s);
+    DBuf<int> dx;
+    dx.alloc(g.total);
+    h2d(dx.p, didx.data(), g.total, s);
+    f.dinv.alloc(g.total);
+    f.dinv32.alloc(g.total);
+    launch_gather_f64(dz.p, dx.p, f.dinv.p, g.total, s);
+    launch_cast_f32(f.dinv.p, f.dinv32.p, g.total, s);
+    HIPCK(hipStreamSynchronize(s));
+  }
+  HIPCK(hipStreamSynchronize(s));
+}
+
 static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* rowptr, const int32_t* col,
                        const double* val) {
   hipStream_t s = S.s;
@@ -934,6 +1039,28 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
   build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
   phase("fine sweeps");
+  // wavefront form when all four fine factors have 2D-grid structure
+  S.wave = false;
+  if (o.sweep_kernel == 0) {
+    const int nx = grid2d_nx(n, l_rp, l_ci, true);
+    if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx && grid2d_nx(n, ut_rp, ut_ci, true) == nx &&
+        grid2d_nx(n, lt_rp, lt_ci, false) == nx) {
+      WaveGrid& g = S.wg;
+      g.nx = nx;
+      g.ny = n / nx;
+      g.W = (g.ny + 63) / 64;
+      g.S = nx + 63;
+      g.total = (int64_t)g.W * g.S * 64;
+      build_wave(S.wL0, g, l_rp, l_ci, l_src, true, S.ilu.p, nnz64, nullptr, n, s);
+      build_wave(S.wU0, g, u_rp, u_ci, u_src, false, S.ilu.p, nnz64, u0dinv.p, n, s);
+      build_wave(S.wU0t, g, ut_rp, ut_ci, ut_src, true, S.ilu.p, nnz64, u0dinv.p, n, s);
+      build_wave(S.wL0t, g, lt_rp, lt_ci, lt_src, false, S.ilu.p, nnz64, nullptr, n, s);
+      S.wz.alloc(g.total); S.wy.alloc(g.total); S.wt.alloc(g.total);
+      S.wz32.alloc(g.total); S.wy32.alloc(g.total); S.wt32.alloc(g.total);
+      S.wave = true;
+      phase("wavefront layout");
+    }
+  }
   // ---- ILUT of A_c on the host
   {
     HCsr hAc;

@@ -128,6 +128,29 @@ struct Sweep {
   std::unique_ptr<CuSweep> cu;  // single-CU form, for narrow factors (null otherwise)
 };
 
+// Wavefront sweeps of factors with 2D-grid structure (k_wave.hip): grid of
+// nx columns and ny rows, W waves of 64 grid rows, S = nx + 63 steps per
+// wave, total = W * S * 64 positions (the lower layout; an upper factor uses
+// it backwards).
+struct WaveGrid {
+  int nx = 0, ny = 0, W = 0, S = 0;
+  int64_t total = 0;
+};
+// One factor in that layout: coef holds (neighbour below, left neighbour)
+// coefficient pairs per position, zero where absent or outside the grid;
+// dinv the reciprocal diagonal per position when the factor stores one.
+struct WaveSweep {
+  bool has_diag = false;
+  DBuf<double> coef, dinv;
+  DBuf<float> coef32, dinv32;
+};
+// z (natural order, FP64 if z_f64) -> lower sweep -> upper sweep -> t
+// (natural order); zs, ys, ts are layout-ordered work vectors, ys and ts
+// all-sentinel on entry and left so.
+template <class T>
+void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& up, const void* z, bool z_f64, T* zs,
+                      T* ys, T* ts, T* t, int* abort_flag, hipStream_t s);
+
 // Per-kernel-class profiling with events.
 enum ProfClass {
   PC_SPMV = 0, PC_SWEEP_FINE, PC_SWEEP_COARSE, PC_RESID_RESTRICT, PC_PROLONG,
