@@ -1049,7 +1049,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       g.nx = nx;
       g.ny = n / nx;
       g.W = (g.ny + 63) / 64;
-      g.S = nx + 63;
+      g.S = (nx + 63 + 7) / 8 * 8;  // whole chunks of the wavefront kernel
       g.total = (int64_t)g.W * g.S * 64;
       build_wave(S.wL0, g, l_rp, l_ci, l_src, true, S.ilu.p, nnz64, nullptr, n, s);
       build_wave(S.wU0, g, u_rp, u_ci, u_src, false, S.ilu.p, nnz64, u0dinv.p, n, s);

@@ -12,9 +12,12 @@
 // the one below in lane l - 1, moved over with a DPP lane shift; only lane 0
 // reads the previous wave's lane 63, through memory (value-as-flag, like the
 // general sweep).  A step costs a few vector instructions instead of a hop,
-// and wave w runs about 64 steps behind wave w - 1.
+// and wave w runs about 64 steps behind wave w - 1.  So that the computing
+// wave never waits on memory latency, two more waves of its workgroup stream
+// its operands into an LDS ring ahead of it.
 //
-// Positions p = (w * S + s) * 64 + l (S = nx + 63 steps per wave) hold the
+// Positions p = (w * S + s) * 64 + l (S = nx + 63 steps per wave, rounded up
+// to whole chunks of the kernel below) hold the
 // operands of step s of lane l, so every step reads and writes one contiguous
 // 64-element segment; positions outside the grid hold zero coefficients and
 // a zero right-hand side, which make their results zero.  The positions of
@@ -30,17 +33,31 @@
 
 namespace gmg {
 
-constexpr int WAVE_PF = 8;  // steps of operands in flight
+// One workgroup per 64 grid rows: wave 0 computes; waves 1 and 2 stream the
+// operands of alternate chunks of WAVE_CH steps into an LDS ring of
+// WAVE_RING steps, each keeping WAVE_D chunks of loads in flight; wave 3
+// polls the previous band's boundary values into a second ring of WAVE_XRING
+// steps.  The computing wave thus issues no global loads: its stores, which
+// share the in-order memory counter with loads, never hold it up.
+constexpr int WAVE_CH = 8;
+constexpr int WAVE_D = 2;
+constexpr int WAVE_RING = 48;
+constexpr int WAVE_PRODUCERS = 2;
+constexpr int WAVE_XRING = 256;
+constexpr int WAVE_THREADS = 64 * (2 + WAVE_PRODUCERS);
 
-// Lane l receives lane l - 1's value (lane 0 receives 0): DPP wave_shr:1.
-__device__ __forceinline__ int lane_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
-__device__ __forceinline__ float lane_shr1(float v) {
-  return __builtin_bit_cast(float, lane_shr1(__builtin_bit_cast(int, v)));
+// Lane l receives lane l - 1's value v; lane 0 keeps lane0 (DPP wave_shr:1
+// without bound control leaves the destination of a lane with no source).
+__device__ __forceinline__ int lane_shr1(int lane0, int v) {
+  return __builtin_amdgcn_update_dpp(lane0, v, 0x138, 0xF, 0xF, false);
 }
-__device__ __forceinline__ double lane_shr1(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)lane_shr1((int)(uint32_t)b);
-  const uint32_t hi = (uint32_t)lane_shr1((int)(uint32_t)(b >> 32));
+__device__ __forceinline__ float lane_shr1(float lane0, float v) {
+  return __builtin_bit_cast(float, lane_shr1(__builtin_bit_cast(int, lane0), __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_shr1(double lane0, double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v), o = __builtin_bit_cast(uint64_t, lane0);
+  const uint32_t lo = (uint32_t)lane_shr1((int)(uint32_t)o, (int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)lane_shr1((int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32));
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
@@ -51,72 +68,213 @@ struct Pair<double> { using type = double2; };
 template <>
 struct Pair<float> { using type = float2; };
 
+// Bounded wait on an LDS progress counter (relaxed loads); false when the
+// sweep is abandoned (abort flag raised, or the time limit hit here).  SLEEP:
+// back off between polls (producers ahead of the consumer must not flood the
+// LDS pipe the consumer reads its operands through).
+template <int SLEEP>
+__device__ __forceinline__ bool wait_lds_at_least(const int* ctr, int want, int* abort_flag, uint64_t limit) {
+  if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want) return true;
+  const uint64_t t0 = wall_clock64();
+  unsigned it = 0;
+#pragma clang loop unroll(disable)
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < want) {
+    __builtin_amdgcn_s_sleep(SLEEP);
+    if ((++it & 255u) == 0) {
+      if (ld_agent(abort_flag)) return false;
+      if (wall_clock64() - t0 > limit) {
+        st_agent(abort_flag, 1);
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+// LDS-only release / acquire: orders the ring's data against its counters
+// without waiting for global memory operations.
+__device__ __forceinline__ void lds_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local"); }
+__device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
+
 // coef[p] = (coefficient of the neighbour below, coefficient of the left
 // neighbour); UP_FIRST: the neighbour below has the smaller original column
-// (lower factors), else the left one (upper factors).
+// (lower factors), else the left one (upper factors).  REV: the right-hand
+// side is read at total - 1 - p.
 template <class T, bool DIAG, bool UP_FIRST, bool REV>
-__global__ __launch_bounds__(64) void k_wave(int S, int nx, int64_t total, const typename Pair<T>::type* __restrict__ coef,
-                                             const T* __restrict__ dinv, T* rhs, T* out, int* abort_flag,
-                                             uint64_t limit) {
-  const int w = blockIdx.x, l = threadIdx.x;
+__global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t total,
+                                                       const typename Pair<T>::type* __restrict__ coef,
+                                                       const T* __restrict__ dinv, const T* __restrict__ rhs, T* out,
+                                                       int* abort_flag, uint64_t limit) {
+  using P2 = typename Pair<T>::type;
+  __shared__ P2 r_coef[WAVE_RING][64];
+  __shared__ T r_b[WAVE_RING][64];
+  __shared__ T r_d[DIAG ? WAVE_RING : 1][64];
+  __shared__ T r_x[WAVE_XRING];              // previous band's boundary values
+  __shared__ int produced[WAVE_PRODUCERS];  // chunks written by each producer
+  __shared__ int xready;                    // boundary values in r_x
+  __shared__ int consumed;                  // steps finished by the consumer
+  const int w = blockIdx.x, l = threadIdx.x & 63, role = threadIdx.x >> 6;
   const int64_t p0 = (int64_t)w * S * 64 + l;
-  // previous wave, lane 63, step s + 63 (the same column as lane 0, step s)
-  const T* prev = out + ((int64_t)(w - 1) * S + 63) * 64 + 63;
-  const bool reads_prev = l == 0 && w > 0;
-  T cu[WAVE_PF], cl[WAVE_PF], b[WAVE_PF], d[WAVE_PF], x[WAVE_PF];
-  auto fetch = [&](int s, int u) {
-    const int64_t p = p0 + (int64_t)std::min(s, S - 1) * 64;
-    const typename Pair<T>::type c = coef[p];
-    cu[u] = c.x;
-    cl[u] = c.y;
-    b[u] = REV ? rhs[total - 1 - p] : rhs[p];
-    d[u] = DIAG ? dinv[p] : (T)1;
-    x[u] = (reads_prev && s < nx) ? ld_agent(prev + (int64_t)s * 64) : (T)0;
-  };
-#pragma unroll
-  for (int u = 0; u < WAVE_PF; ++u) fetch(u, u);
-  T yp = (T)0;  // this lane's result of the previous step
-  for (int s0 = 0; s0 < S; s0 += WAVE_PF) {
-#pragma unroll
-    for (int u = 0; u < WAVE_PF; ++u) {
-      const int s = s0 + u;
-      if (s >= S) break;
-      T xb = x[u];
-      if (reads_prev && s < nx && is_sentinel(xb)) {
-        const uint64_t t0 = wall_clock64();
-        unsigned it = 0;
+  const int nchunks = S / WAVE_CH;
+  if (threadIdx.x < WAVE_PRODUCERS) produced[threadIdx.x] = 0;
+  if (threadIdx.x == 0) { consumed = 0; xready = 0; }
+  // the boundary ring starts at zero: the consumer reads it for every step,
+  // and steps without a boundary value (first band, padding) have a zero
+  // coefficient for it, which a finite value times zero leaves exact
+  for (int i = threadIdx.x; i < WAVE_XRING; i += WAVE_THREADS) r_x[i] = (T)0;
+  __syncthreads();
+
+  // boundary values exist for steps s < xn (the previous band's lane 63 at
+  // step s + 63); later steps are padding
+  const int xn = S - 63;
+  if (role == 1 + WAVE_PRODUCERS) {
+    // ------------------------------------------- previous band's boundary
+    if (w == 0) return;
+    const T* prev = out + ((int64_t)(w - 1) * S + 63) * 64 + 63;
+    int next = 0;
+    const uint64_t t0 = wall_clock64();
+    unsigned it = 0;
 #pragma clang loop unroll(disable)
-        do {
-          __builtin_amdgcn_s_sleep(1);
-          xb = ld_agent(prev + (int64_t)s * 64);
-          if (is_sentinel(xb) && (++it & 63u) == 0) {
-            if (ld_agent(abort_flag)) { xb = (T)__builtin_nan(""); break; }
-            if (wall_clock64() - t0 > limit) {
-              st_agent(abort_flag, 1);
-              xb = (T)__builtin_nan("");
-              break;
-            }
-          }
-        } while (is_sentinel(xb));
-      }
-      T up = lane_shr1(yp);
-      if (l == 0) up = xb;
-      T acc = (T)0;
-      if (UP_FIRST) {
-        acc += cu[u] * up;
-        acc += cl[u] * yp;
+    while (next < xn) {
+      // ring space: slots of steps next .. next + 63 were used WAVE_XRING steps earlier
+      if (!wait_lds_at_least<4>(&consumed, next + 64 - WAVE_XRING, abort_flag, limit)) return;
+      const int s = next + l;
+      const T v = s < xn ? ld_agent(prev + (int64_t)s * 64) : (T)0;
+      const uint64_t pend = __ballot(s < xn && is_sentinel(v));
+      const int k = pend ? (int)__builtin_ctzll(pend) : 64;  // leading published steps
+      if (k > 0) {
+        if (l < k) r_x[s % WAVE_XRING] = v;
+        lds_release();
+        next = std::min(next + k, xn);
+        if (l == 0) __hip_atomic_store(&xready, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       } else {
-        acc += cl[u] * yp;
-        acc += cu[u] * up;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++it & 63u) == 0) {
+          if (ld_agent(abort_flag)) return;
+          if (wall_clock64() - t0 > limit) {
+            st_agent(abort_flag, 1);
+            return;
+          }
+        }
       }
-      T y = b[u] - acc;
-      if (DIAG) y *= d[u];
-      if (is_sentinel(y)) y = (T)__builtin_nan("");
-      const int64_t p = p0 + (int64_t)s * 64;
-      st_agent(out + p, y);
-      if (REV) rhs[total - 1 - p] = sentinel_of<T>(0);
-      yp = y;
-      fetch(s + WAVE_PF, u);
+    }
+    return;
+  }
+
+  if (role > 0) {
+    // ---------------------------------------------------------- producer
+    const int k = role - 1;
+    P2 rc[WAVE_D][WAVE_CH];
+    T rb[WAVE_D][WAVE_CH], rd[WAVE_D][WAVE_CH];
+    auto issue = [&](int c, int slot) {
+#pragma unroll
+      for (int u = 0; u < WAVE_CH; ++u) {
+        const int64_t p = p0 + (int64_t)(c * WAVE_CH + u) * 64;
+        rc[slot][u] = coef[p];
+        rb[slot][u] = REV ? rhs[total - 1 - p] : rhs[p];
+        if (DIAG) rd[slot][u] = dinv[p];
+      }
+    };
+    // chunks of this producer: c = k, k + P, k + 2P, ...; the d-th of them
+    // uses register slot d % WAVE_D
+#pragma unroll
+    for (int d = 0; d < WAVE_D; ++d) {
+      const int c = k + d * WAVE_PRODUCERS;
+      if (c < nchunks) issue(c, d);
+    }
+    int done = 0;  // chunks of this producer written to the ring
+    for (int d0 = 0;; d0 += WAVE_D) {
+#pragma unroll
+      for (int dd = 0; dd < WAVE_D; ++dd) {
+        const int c = k + (d0 + dd) * WAVE_PRODUCERS;
+        if (c >= nchunks) return;
+        // the ring slots of this chunk were last used WAVE_RING steps earlier
+        if (!wait_lds_at_least<4>(&consumed, (c + 1) * WAVE_CH - WAVE_RING, abort_flag, limit)) return;
+#pragma unroll
+        for (int u = 0; u < WAVE_CH; ++u) {
+          const int st = (c * WAVE_CH + u) % WAVE_RING;
+          r_coef[st][l] = rc[dd][u];
+          r_b[st][l] = rb[dd][u];
+          if (DIAG) r_d[st][l] = rd[dd][u];
+        }
+        lds_release();
+        ++done;
+        if (l == 0) __hip_atomic_store(&produced[k], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int cn = c + WAVE_D * WAVE_PRODUCERS;
+        if (cn < nchunks) issue(cn, dd);
+      }
+    }
+  }
+
+  // ------------------------------------------------------------ consumer
+  // Chunks of WAVE_CH steps (S is a multiple of WAVE_CH): the waits of a
+  // chunk are taken once, the operands of the next chunk are read from the
+  // ring while this one computes, and its steps run without branches.
+  const bool reads_prev = w > 0;
+  // progress of the producers as last read; the reads for the next check are
+  // issued a chunk ahead, so a check rarely waits on LDS
+  int seen_prod[WAVE_PRODUCERS], seen_x = 0;
+#pragma unroll
+  for (int k = 0; k < WAVE_PRODUCERS; ++k) seen_prod[k] = 0;
+  P2 cf[2][WAVE_CH];
+  T bb[2][WAVE_CH], dv[2][WAVE_CH], xb[2][WAVE_CH];
+  auto take = [&](int c, int h) -> bool {
+    const int k = c % WAVE_PRODUCERS;
+    if (seen_prod[k] < c / WAVE_PRODUCERS + 1) {
+      if (!wait_lds_at_least<0>(&produced[k], c / WAVE_PRODUCERS + 1, abort_flag, limit)) return false;
+      seen_prod[k] = c / WAVE_PRODUCERS + 1;
+    }
+    const int s0 = c * WAVE_CH;
+    if (reads_prev && s0 < xn) {
+      const int need = std::min(s0 + WAVE_CH, xn);
+      if (seen_x < need) {
+        if (!wait_lds_at_least<0>(&xready, need, abort_flag, limit)) return false;
+        seen_x = need;
+      }
+    }
+    lds_acquire();
+#pragma unroll
+    for (int u = 0; u < WAVE_CH; ++u) {
+      const int st = (s0 + u) % WAVE_RING;
+      cf[h][u] = r_coef[st][l];
+      bb[h][u] = r_b[st][l];
+      dv[h][u] = DIAG ? r_d[st][l] : (T)1;
+      xb[h][u] = r_x[(s0 + u) % WAVE_XRING];
+    }
+    // progress for the next checks
+#pragma unroll
+    for (int kk = 0; kk < WAVE_PRODUCERS; ++kk)
+      seen_prod[kk] = std::max(seen_prod[kk], __hip_atomic_load(&produced[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (reads_prev)
+      seen_x = std::max(seen_x, __hip_atomic_load(&xready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    return true;
+  };
+  T yp = (T)0;  // this lane's result of the previous step
+  if (!take(0, 0)) return;
+  for (int c = 0; c < nchunks; c += 2) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cc = c + h;
+      if (cc >= nchunks) break;
+      if (cc + 1 < nchunks && !take(cc + 1, h ^ 1)) return;
+#pragma unroll
+      for (int u = 0; u < WAVE_CH; ++u) {
+        const T upv = lane_shr1(xb[h][u], yp);
+        T acc = (T)0;
+        if (UP_FIRST) {
+          acc += cf[h][u].x * upv;
+          acc += cf[h][u].y * yp;
+        } else {
+          acc += cf[h][u].y * yp;
+          acc += cf[h][u].x * upv;
+        }
+        T y = bb[h][u] - acc;
+        if (DIAG) y *= dv[h][u];
+        st_agent(out + p0 + (int64_t)(cc * WAVE_CH + u) * 64, is_sentinel(y) ? (T)__builtin_nan("") : y);
+        yp = y;
+      }
+      lds_release();
+      if (l == 0) __hip_atomic_store(&consumed, (cc + 1) * WAVE_CH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
@@ -139,13 +297,16 @@ __global__ void k_wave_gather(int64_t total, int S, int nx, int ny, const TR* __
 }
 
 // out[cell] = ts[p] for the upper layout (cell of lower position total-1-p);
-// ts is reset to the sentinel for the next sweep
+// ts and the lower sweep's output ys are reset to the sentinel for the next
+// pair of sweeps
 template <class T>
-__global__ void k_wave_scatter(int64_t total, int S, int nx, int ny, T* __restrict__ ts, T* __restrict__ t) {
+__global__ void k_wave_scatter(int64_t total, int S, int nx, int ny, T* __restrict__ ts, T* __restrict__ ys,
+                               T* __restrict__ t) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
     const int c = wave_cell(total - 1 - p, S, nx, ny);
     if (c >= 0) t[c] = ts[p];
     ts[p] = sentinel_of<T>(0);
+    ys[total - 1 - p] = sentinel_of<T>(0);
   }
 }
 
@@ -179,19 +340,20 @@ void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& u
   auto di = [&](const WaveSweep& f) { return F32 ? (const T*)f.dinv32.p : (const T*)f.dinv.p; };
   // lower factor: neighbour below first; upper factor: left neighbour first,
   // right-hand side = the lower sweep's output read backwards
+  const dim3 blk(WAVE_THREADS);
   if (lo.has_diag)
-    hipLaunchKernelGGL((k_wave<T, true, true, false>), dim3(g.W), dim3(64), 0, s, g.S, g.nx, g.total, co(lo), di(lo),
-                       zs, ys, abort_flag, lim);
+    hipLaunchKernelGGL((k_wave<T, true, true, false>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
+                       ys, abort_flag, lim);
   else
-    hipLaunchKernelGGL((k_wave<T, false, true, false>), dim3(g.W), dim3(64), 0, s, g.S, g.nx, g.total, co(lo),
-                       di(lo), zs, ys, abort_flag, lim);
+    hipLaunchKernelGGL((k_wave<T, false, true, false>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
+                       ys, abort_flag, lim);
   if (up.has_diag)
-    hipLaunchKernelGGL((k_wave<T, true, false, true>), dim3(g.W), dim3(64), 0, s, g.S, g.nx, g.total, co(up), di(up),
-                       ys, ts, abort_flag, lim);
+    hipLaunchKernelGGL((k_wave<T, true, false, true>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
+                       ts, abort_flag, lim);
   else
-    hipLaunchKernelGGL((k_wave<T, false, false, true>), dim3(g.W), dim3(64), 0, s, g.S, g.nx, g.total, co(up),
-                       di(up), ys, ts, abort_flag, lim);
-  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, ts, t);
+    hipLaunchKernelGGL((k_wave<T, false, false, true>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
+                       ts, abort_flag, lim);
+  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, ts, ys, t);
   HIPCK(hipGetLastError());
 }
 template void launch_wave_pair<double>(const WaveGrid&, const WaveSweep&, const WaveSweep&, const void*, bool,
