@@ -49,8 +49,9 @@ struct Solver {
   DBuf<int> agg, aptr, amem;
   int nc = 0, passes = 0, rounds = 0;
   DCsr Ac;
-  DBuf<double> ilu;
-  DBuf<int> dpos;
+  DBuf<double> ilu, u0dinv;    // ILU(0) values (A's pattern), U0's reciprocal diagonal
+  DBuf<int> dpos, at_src;      // diagonal positions; A^T entry -> A entry
+  bool adj_ready = false;      // transposed factors built (on first adjoint use)
   HCsr hLc, hUc;
   Sweep L0, U0, Lc, Uc;        // forward factors
   Sweep U0t, L0t, Uct, Lct;    // transposed factors (adjoint)
@@ -309,7 +310,7 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
     std::vector<int> lev(n > 0 ? n : 1, 0), pos(n > 0 ? n : 1, 0), ulptr(levels + 1, 0);
     bool ok = levels > 0 && levels <= 16000;  // level bounds are staged in LDS
     int width = 1;
-    for (int l = 0, e = 0; l < levels && ok; ++l) {
+    for (int l = 0; l < levels && ok; ++l) {
       int cnt = 0;
       for (int p = lptr[l]; p < lptr[l + 1]; ++p) {
         const int r = sched[p];
@@ -317,7 +318,6 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
         lev[r] = l;
         pos[r] = cnt++;
         width = std::max(width, dep_rp[r + 1] - dep_rp[r]);
-        ++e;
       }
       ulptr[l + 1] = ulptr[l] + cnt;
       if (cnt > 1024) ok = false;
@@ -516,9 +516,87 @@ static void vcycle(Solver& S, const double* z, double* q) {
   }
 }
 
+static std::vector<int> to_host_int(const int* d, size_t n, hipStream_t s);
+static void build_wave(WaveSweep& f, const WaveGrid& g, const std::vector<int>& dep_rp,
+                       const std::vector<int>& dep_ci, const std::vector<int>& dep_src, bool lower,
+                       const double* vals_dev, int64_t nvals, const double* dinv_dev, int n, hipStream_t s);
+
+// The transposed fine and coarse factors of the adjoint cycle, built on the
+// first adjoint use (a forward-only caller never pays for them).
+static void ensure_adjoint(Solver& S) {
+  if (S.adj_ready) return;
+  hipStream_t s = S.s;
+  const int n = S.n, nc = S.nc;
+  const int64_t nnz64 = S.nnz;
+  const gmg_options& o = S.opt;
+  {
+    // row j of U0^T lists i < j with (i, j) in strict U; of L0^T lists i > j with (i, j) in strict L
+    std::vector<int> hat_rp = to_host_int(S.AT.rp.p, n + 1, s);
+    std::vector<int> hat_ci = to_host_int(S.AT.ci.p, nnz64, s);
+    std::vector<int> hat_src = to_host_int(S.at_src.p, nnz64, s);
+    HIPCK(hipStreamSynchronize(s));
+    std::vector<int> ut_rp(n + 1, 0), ut_ci, ut_src, lt_rp(n + 1, 0), lt_ci, lt_src;
+    for (int j = 0; j < n; ++j) {
+      for (int q = hat_rp[j]; q < hat_rp[j + 1]; ++q) {
+        const int i = hat_ci[q], p = hat_src[q];
+        if (i < j) { ut_ci.push_back(i); ut_src.push_back(p); }
+        else if (i > j) { lt_ci.push_back(i); lt_src.push_back(p); }
+      }
+      ut_rp[j + 1] = (int)ut_ci.size();
+      lt_rp[j + 1] = (int)lt_ci.size();
+    }
+    if (S.wave) {
+      build_wave(S.wU0t, S.wg, ut_rp, ut_ci, ut_src, true, S.ilu.p, nnz64, S.u0dinv.p, n, s);
+      build_wave(S.wL0t, S.wg, lt_rp, lt_ci, lt_src, false, S.ilu.p, nnz64, nullptr, n, s);
+      S.U0t.n = S.L0t.n = n;
+      S.U0t.nnz = (int64_t)ut_ci.size();
+      S.L0t.nnz = (int64_t)lt_ci.size();
+      S.U0t.has_diag = true;
+    } else {
+      build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+      build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    }
+  }
+  {
+    // U~^T row j lists i < j (strict part), L~^T row j lists i > j
+    const HCsr &L = S.hLc, &U = S.hUc;
+    std::vector<double> udinv(nc);
+    std::vector<int> uct_cnt(nc + 1, 0), lct_cnt(nc + 1, 0);
+    for (int i = 0; i < nc; ++i) {
+      udinv[i] = 1.0 / U.v[U.rp[i]];
+      for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) uct_cnt[U.ci[q] + 1]++;
+      for (int q = L.rp[i]; q < L.rp[i + 1]; ++q) lct_cnt[L.ci[q] + 1]++;
+    }
+    for (int j = 0; j < nc; ++j) { uct_cnt[j + 1] += uct_cnt[j]; lct_cnt[j + 1] += lct_cnt[j]; }
+    std::vector<int> uct_ci(uct_cnt[nc]), uct_src(uct_cnt[nc]), lct_ci(lct_cnt[nc]), lct_src(lct_cnt[nc]);
+    std::vector<int> fu(uct_cnt.begin(), uct_cnt.end() - 1), fl(lct_cnt.begin(), lct_cnt.end() - 1);
+    for (int i = 0; i < nc; ++i) {
+      for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) {
+        const int o2 = fu[U.ci[q]]++;
+        uct_ci[o2] = i;
+        uct_src[o2] = q;
+      }
+      for (int q = L.rp[i]; q < L.rp[i + 1]; ++q) {
+        const int o2 = fl[L.ci[q]]++;
+        lct_ci[o2] = i;
+        lct_src[o2] = q;
+      }
+    }
+    build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+  }
+  if (S.wave) {
+    launch_fill_f64_bits(S.wy.p, kSent64, S.wg.total, s);
+    launch_fill_f64_bits(S.wt.p, kSent64, S.wg.total, s);
+  }
+  HIPCK(hipStreamSynchronize(s));
+  S.adj_ready = true;
+}
+
 // q = B~^{-T} z (FP64): ec = L~^{-T} U~^{-T} P^T z; s = z - A^T P ec;
 // t = L0^{-T} U0^{-T} s; q = P ec + t
 static void vcycle_adjoint(Solver& S, const double* z, double* q) {
+  ensure_adjoint(S);
   hipStream_t s = S.s;
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.n * 12 + (double)S.nc * 16);
@@ -926,8 +1004,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   // ---- A^T (graph, adjoint)
   S.AT.n = S.AT.m = n;
   S.AT.nnz = nnz64;
-  DBuf<int> at_src;
-  transpose_csr(n, n, nnz64, S.A.rp.p, S.A.ci.p, S.A.v.p, S.AT.rp, S.AT.ci, &S.AT.v, &at_src, s);
+  transpose_csr(n, n, nnz64, S.A.rp.p, S.A.ci.p, S.A.v.p, S.AT.rp, S.AT.ci, &S.AT.v, &S.at_src, s);
   phase("validate+transpose");
   // ---- aggregation
   {
@@ -973,9 +1050,6 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   // ---- host copy of A's pattern for the analysis
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
   std::vector<int> hci = to_host_int(S.A.ci.p, nnz64, s);
-  std::vector<int> hat_rp = to_host_int(S.AT.rp.p, n + 1, s);
-  std::vector<int> hat_ci = to_host_int(S.AT.ci.p, nnz64, s);
-  std::vector<int> hat_src = to_host_int(at_src.p, nnz64, s);
   HIPCK(hipStreamSynchronize(s));
   std::vector<int> hdpos(n);
   for (int i = 0; i < n; ++i)
@@ -983,7 +1057,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       if (hci[p] == i) hdpos[i] = p;
   S.dpos.alloc(n);
   h2d(S.dpos.p, hdpos.data(), n, s);
-  // dependency lists of the four fine sweeps
+  // dependency lists of the two forward fine sweeps
   std::vector<int> l_rp(n + 1, 0), l_ci, l_src, u_rp(n + 1, 0), u_ci, u_src;
   l_ci.reserve(nnz64 / 2);
   l_src.reserve(nnz64 / 2);
@@ -996,17 +1070,6 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     }
     l_rp[i + 1] = (int)l_ci.size();
     u_rp[i + 1] = (int)u_ci.size();
-  }
-  // transposed: row j of U0^T lists i < j with (i, j) in strict U; of L0^T lists i > j with (i, j) in strict L
-  std::vector<int> ut_rp(n + 1, 0), ut_ci, ut_src, lt_rp(n + 1, 0), lt_ci, lt_src;
-  for (int j = 0; j < n; ++j) {
-    for (int q = hat_rp[j]; q < hat_rp[j + 1]; ++q) {
-      const int i = hat_ci[q], p = hat_src[q];
-      if (i < j) { ut_ci.push_back(i); ut_src.push_back(p); }
-      else if (i > j) { lt_ci.push_back(i); lt_src.push_back(p); }
-    }
-    ut_rp[j + 1] = (int)ut_ci.size();
-    lt_rp[j + 1] = (int)lt_ci.size();
   }
   phase("fine dependency lists");
   // ---- ILU(0), one launch per level of L0
@@ -1030,21 +1093,16 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     if (hb & 2) fail(GMG_ERR_NONFINITE, "ILU(0): non-finite pivot");
   }
   phase("ILU(0)");
-  DBuf<double> u0dinv;
-  u0dinv.alloc(n);
-  hipLaunchKernelGGL(k_recip_diag, dim3((n + 255) / 256), dim3(256), 0, s, n, S.ilu.p, S.dpos.p, u0dinv.p);
+  S.u0dinv.alloc(n);
+  hipLaunchKernelGGL(k_recip_diag, dim3((n + 255) / 256), dim3(256), 0, s, n, S.ilu.p, S.dpos.p, S.u0dinv.p);
   HIPCK(hipGetLastError());
-  build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-  build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-  build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-  build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-  phase("fine sweeps");
-  // wavefront form when all four fine factors have 2D-grid structure
+  // wavefront form when both fine factors have 2D-grid structure (their
+  // transposes then have it too: the same offsets, mirrored); else the
+  // level-scheduled sweeps
   S.wave = false;
   if (o.sweep_kernel == 0) {
     const int nx = grid2d_nx(n, l_rp, l_ci, true);
-    if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx && grid2d_nx(n, ut_rp, ut_ci, true) == nx &&
-        grid2d_nx(n, lt_rp, lt_ci, false) == nx) {
+    if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx) {
       WaveGrid& g = S.wg;
       g.nx = nx;
       g.ny = n / nx;
@@ -1052,14 +1110,23 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       g.S = (nx + 63 + 7) / 8 * 8;  // whole chunks of the wavefront kernel
       g.total = (int64_t)g.W * g.S * 64;
       build_wave(S.wL0, g, l_rp, l_ci, l_src, true, S.ilu.p, nnz64, nullptr, n, s);
-      build_wave(S.wU0, g, u_rp, u_ci, u_src, false, S.ilu.p, nnz64, u0dinv.p, n, s);
-      build_wave(S.wU0t, g, ut_rp, ut_ci, ut_src, true, S.ilu.p, nnz64, u0dinv.p, n, s);
-      build_wave(S.wL0t, g, lt_rp, lt_ci, lt_src, false, S.ilu.p, nnz64, nullptr, n, s);
+      build_wave(S.wU0, g, u_rp, u_ci, u_src, false, S.ilu.p, nnz64, S.u0dinv.p, n, s);
       S.wz.alloc(g.total); S.wy.alloc(g.total); S.wt.alloc(g.total);
       S.wz32.alloc(g.total); S.wy32.alloc(g.total); S.wt32.alloc(g.total);
       S.wave = true;
+      // sizes and depths of the factors (profiling byte counts, info)
+      S.L0.n = S.U0.n = n;
+      S.L0.nnz = (int64_t)l_ci.size();
+      S.U0.nnz = (int64_t)u_ci.size();
+      S.U0.has_diag = true;
+      S.L0.levels = S.U0.levels = g.nx + g.ny - 1;
       phase("wavefront layout");
     }
+  }
+  if (!S.wave) {
+    build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    phase("fine sweeps");
   }
   // ---- ILUT of A_c on the host
   {
@@ -1089,28 +1156,6 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
     build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
     phase("coarse sweeps");
-    // transposes: U~^T row j lists i < j (strict part), L~^T row j lists i > j
-    std::vector<int> uct_cnt(nc + 1, 0), lct_cnt(nc + 1, 0);
-    for (size_t q = 0; q < us_ci.size(); ++q) uct_cnt[us_ci[q] + 1]++;
-    for (size_t q = 0; q < L.ci.size(); ++q) lct_cnt[L.ci[q] + 1]++;
-    for (int j = 0; j < nc; ++j) { uct_cnt[j + 1] += uct_cnt[j]; lct_cnt[j + 1] += lct_cnt[j]; }
-    std::vector<int> uct_ci(us_ci.size()), uct_src(us_ci.size()), lct_ci(L.ci.size()), lct_src(L.ci.size());
-    std::vector<int> fu(uct_cnt.begin(), uct_cnt.end() - 1), fl(lct_cnt.begin(), lct_cnt.end() - 1);
-    for (int i = 0; i < nc; ++i) {
-      for (int q = us_rp[i]; q < us_rp[i + 1]; ++q) {
-        const int j = us_ci[q], o2 = fu[j]++;
-        uct_ci[o2] = i;
-        uct_src[o2] = us_src[q];
-      }
-      for (int q = L.rp[i]; q < L.rp[i + 1]; ++q) {
-        const int j = L.ci[q], o2 = fl[j]++;
-        lct_ci[o2] = i;
-        lct_src[o2] = q;
-      }
-    }
-    build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-    build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-    phase("coarse adjoint sweeps");
     if (o.coarse_mode == 1) {
       auto up = [&](DCsr& D, const HCsr& H) {
         D.n = D.m = nc;
