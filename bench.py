@@ -8,13 +8,22 @@ FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
 before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--profile-steps]
+                       [--no-cpu-baseline] [--no-fp32]
+       python bench.py --copy-calibration   (a plain 1 GiB device copy, run
+                       under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
+
+The roofline's `traffic` (HBM bytes per launch of the dominant kernel class)
+comes from the counter summary committed under profiles/, and only while the
+class is still the dominant one and the kernel source still hashes to the value
+recorded with the counters; otherwise it is null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -40,6 +49,51 @@ WORKLOAD_DESC = {
                  "diagonally dominant M-matrix"),
     "fv2d_64": "2D FV convection-diffusion 64x64 (4096 unknowns), small oracle-sized case",
 }
+
+
+# measured HBM traffic per launch of a kernel class (from rocprofv3 --pmc runs)
+TRAFFIC_FILES = {"sweep_coarse": "profiles/pmc_traffic_sweep_coarse_fv2d_1024.md"}
+
+
+def _source_digest(paths):
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_class: str, workload: str):
+    """HBM bytes per launch recorded for `kernel_class`, or None when no record
+    exists for this workload or the kernel sources changed since it was taken."""
+    rel = TRAFFIC_FILES.get(kernel_class)
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    with open(os.path.join(ROOT, rel)) as f:
+        m = re.search(r"```json\n(.*?)\n```", f.read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("workload") != workload or rec.get("kernel_class") != kernel_class:
+        return None
+    if _source_digest(rec["sources"]) != rec["sources_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain device copy of 1 GiB, three times (torch's copy kernel): under
+    rocprofv3 --pmc it gives the counter reading for a known byte count."""
+    import torch
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 8 * n, "copy_calibration_bytes_written": 8 * n,
+                      "launches": 3}))
 
 
 def _alg_bytes_doc():
@@ -87,7 +141,11 @@ def main():
     ap.add_argument("--workload", default="fv2d_1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -161,7 +219,7 @@ def main():
     d = agg[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=measured_traffic(dom, args.workload),
                     avg_launch_us=round(d["ms"] / d["launches"] * 1e3, 3),
                     bytes_per_launch=round(d["bytes"] / d["launches"]))
     spmv = agg.get("spmv")
