@@ -195,7 +195,7 @@ def test_deterministic(case):
 # ------------------------------------------------------------- edge cases
 def test_sweep_waves_do_not_change_results():
     """The number of resident sweep waves changes scheduling only, not results
-    (device-wide and one-XCD multi-CU sweeps)."""
+    (device-wide and one-workgroup sweeps)."""
     _say("[case] waves")
     p = W.scaled("fv2d", 48)
     b = torch.as_tensor(p.b[:, 0], device="cuda")
@@ -210,7 +210,7 @@ def test_sweep_waves_do_not_change_results():
 @pytest.mark.parametrize("kind", ["fv2d_rot_96", "fv3d_20", "fv2d_37", "rgg_3001"])
 def test_sweep_kernels_bitwise_equal(kind):
     """The single-CU LDS sweep (narrow factors), the device-wide multi-CU
-    sweep and the one-XCD multi-CU sweep perform the same operations in the
+    sweep and the one-workgroup LDS sweep perform the same operations in the
     same order: bitwise-equal preconditioner applications, in FP64 and FP32,
     forward and adjoint."""
     _say(f"[case] sweep kernels {kind}")
