@@ -3,6 +3,10 @@
 // update.  Reductions are deterministic: every block writes its partial sums
 // in a fixed order and the last block to finish adds the partials in block
 // order (no floating-point atomics), so repeated runs are bitwise identical.
+// The partials are published like the sweeps' results: relaxed agent-scope
+// stores into a buffer reset to a NaN sentinel, polled by the last block,
+// which resets them again.  No fence is needed; an agent-scope fence writes
+// the whole L2 back and cost ~40 us per launch here.
 #include "gmg_internal.h"
 #include "kcommon.h"
 
@@ -36,9 +40,9 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount,
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < KB / 64; ++w) s += sh[w][threadIdx.x];
-    partial[(size_t)blockIdx.x * KMAX + threadIdx.x] = s;
+    if (is_sentinel(s)) s = __builtin_nan("");
+    st_agent(&partial[(size_t)blockIdx.x * KMAX + threadIdx.x], s);
   }
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned t = atomicAdd(counter, 1u);
@@ -50,12 +54,37 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount,
     // vector k (t = part * K + k), then thread k adds the NP parts in order
     constexpr int NP = KB / K;
     __shared__ double sh2[NP][K];
-    __threadfence();
     const int k = threadIdx.x % K, part = threadIdx.x / K;
     if (part < NP) {
       double s = 0.0;
-      if (k < kcount)
-        for (unsigned b = part; b < gridDim.x; b += NP) s += ld_agent(&partial[(size_t)b * KMAX + k]);
+      if (k < kcount) {
+        // 16 partials in flight at a time, added in block order; a partial
+        // not yet visible is polled (its block stored it before counting)
+        double* pp = partial + k;
+        for (unsigned b0 = part; b0 < gridDim.x; b0 += 16 * NP) {
+          double v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const unsigned b = b0 + u * NP;
+            v[u] = b < gridDim.x ? ld_agent(pp + (size_t)b * KMAX) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const unsigned b = b0 + u * NP;
+            if (b < gridDim.x) {
+              unsigned spins = 0;
+#pragma clang loop unroll(disable)
+              while (is_sentinel(v[u])) {
+                if (++spins > (1u << 22)) { v[u] = __builtin_nan(""); break; }  // bounded
+                __builtin_amdgcn_s_sleep(1);
+                v[u] = ld_agent(pp + (size_t)b * KMAX);
+              }
+              s += v[u];
+              st_agent(pp + (size_t)b * KMAX, sentinel_of<double>(0));
+            }
+          }
+        }
+      }
       sh2[part][k] = s;
     }
     __syncthreads();
@@ -142,6 +171,7 @@ void red_init(RedWork& rw, hipStream_t s) {
   rw.counter.alloc(1);
   rw.result.alloc(2 * KLDS + 8);
   launch_fill_u32(rw.counter.p, 0u, 1, s);
+  launch_fill_f64_bits(rw.partial.p, SENT64, (size_t)KGRID * KMAX, s);
 }
 
 static unsigned red_grid(int64_t n) {
