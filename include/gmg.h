@@ -75,13 +75,17 @@ typedef struct {
   int coarse_order;     /* numbering of the aggregates, hence of A_c and its ILUT
                            factors: 0 by smallest fine index; 1 nested dissection
                            of A_c's graph (default)                                   */
-  int sweep_kernel;     /* 0: factors with narrow dependency levels use the single-CU
-                           LDS sweep; the others are cut into level ranges that run
-                           on one workgroup (few rows per level) or on the whole
-                           device; 1: whole-device sweep for every factor; 2:
-                           one-workgroup sweep for every factor.  All give bitwise
-                           identical results                                        */
-  int sweep_wg_chunks;  /* sweep_kernel 0: dependency levels of at most this many
+  int sweep_kernel;     /* 0 (default): fine factors with 2D-grid structure use the
+                           wavefront sweep, coarse factors in nested-dissection
+                           order the tree solve, other factors the level sweeps
+                           (single-CU ring for narrow factors, else level ranges
+                           on one workgroup or the whole device); 3: as 0 but
+                           with level sweeps for the coarse factors; 1: the
+                           whole-device level sweep for every factor; 2: the
+                           one-workgroup level sweep for every factor.  1, 2
+                           and 3 give bitwise identical results; 0 differs from
+                           them only in the coarse solves' summation order      */
+  int sweep_wg_chunks;  /* level sweeps under sweep_kernel 0 or 3: dependency levels of at most this many
                            64-lane chunks run on one workgroup (default 8; 0: never) */
 } gmg_options;
 

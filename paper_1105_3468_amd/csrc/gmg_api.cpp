@@ -65,6 +65,12 @@ struct Solver {
   // schedule-order staging of the single-CU sweeps
   DBuf<double> cu_rhs, cu_out;
   DBuf<float> cu_rhs32, cu_out32;
+  // coarse factors solved over the nested-dissection tree
+  std::vector<NdNode> nd_tree;
+  bool tree = false, tree_adj = false;
+  TreeSolve tLc, tUc, tUct, tLct;
+  DBuf<double> text;
+  DBuf<float> text32;
   // wavefront form of the fine factors (2D-grid structure)
   bool wave = false;
   WaveGrid wg;
@@ -188,6 +194,138 @@ static void make_segments(Sweep& sw, const std::vector<int>& level_c0, const std
     }
     emit(start, lb, 1);
   }
+}
+
+// Lay a triangular factor out for the tree solve (k_tree.hip).  Returns false
+// (and leaves ts empty) when the factor does not follow the tree: an entry
+// outside its row's node must point into a descendant node (lower) or an
+// ancestor node (upper), and every node must fit kTreeMaxRows rows.
+static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, const std::vector<int>& dep_rp,
+                       const std::vector<int>& dep_ci, const std::vector<int>& dep_src,
+                       const std::vector<double>& vals, bool lower, const std::vector<double>* dinv,
+                       hipStream_t s) {
+  constexpr int kHelperEntries = 2048, kHelperRows = 256;
+  const int nn = (int)tree.size();
+  if (nn == 0 || n <= 0) return false;
+  std::vector<int> node_of(n, -1);
+  int max_rows = 0, max_h = 0;
+  for (int k = 0; k < nn; ++k) {
+    const NdNode& d = tree[k];
+    if (d.hi - d.lo > kTreeMaxRows) return false;
+    max_rows = std::max(max_rows, d.hi - d.lo);
+    max_h = std::max(max_h, d.height);
+    for (int r = d.lo; r < d.hi; ++r) node_of[r] = k;
+  }
+  for (int r = 0; r < n; ++r)
+    if (node_of[r] < 0) return false;
+  // Euler-tour intervals: x is a descendant of y iff tin[y] <= tin[x] < tout[y]
+  std::vector<std::vector<int>> kids(nn);
+  for (int k = 1; k < nn; ++k) kids[tree[k].parent].push_back(k);
+  std::vector<int> tin(nn), tout(nn), st{0}, it(nn, 0);
+  int clock = 0;
+  tin[0] = clock++;
+  while (!st.empty()) {
+    const int k = st.back();
+    if (it[k] < (int)kids[k].size()) {
+      const int c = kids[k][it[k]++];
+      tin[c] = clock++;
+      st.push_back(c);
+    } else {
+      tout[k] = clock;
+      st.pop_back();
+    }
+  }
+  auto desc = [&](int x, int y) { return tin[y] <= tin[x] && tin[x] < tout[y]; };
+  // entries outside the row's node (CSR over rows) and the diagonal blocks
+  std::vector<int> erp(n + 1, 0), ecol;
+  std::vector<double> eval;
+  std::vector<int64_t> boff(nn, 0);
+  int64_t total = 0;
+  for (int k = 0; k < nn; ++k) {
+    boff[k] = total;
+    const int64_t sz = tree[k].hi - tree[k].lo;
+    total += sz * sz;
+  }
+  std::vector<double> blk(total > 0 ? total : 1, 0.0);
+  std::vector<int64_t> node_ext(nn, 0);
+  for (int r = 0; r < n; ++r) {
+    const int a = node_of[r];
+    const NdNode& d = tree[a];
+    const int sz = d.hi - d.lo;
+    for (int q = dep_rp[r]; q < dep_rp[r + 1]; ++q) {
+      const int c = dep_ci[q], b = node_of[c];
+      const double v = vals[dep_src[q]];
+      if (b == a) {
+        blk[boff[a] + (int64_t)(c - d.lo) * sz + (r - d.lo)] = v;
+      } else {
+        if (!(lower ? desc(b, a) : desc(a, b))) return false;
+        ecol.push_back(c);
+        eval.push_back(v);
+        node_ext[a]++;
+      }
+    }
+    erp[r + 1] = (int)ecol.size();
+  }
+  // tasks: nodes by height (lower: ascending, upper: descending), each node's
+  // helpers (slices of about kHelperEntries outside entries) before it
+  std::vector<int> order;
+  for (int k = 0; k < nn; ++k)
+    if (tree[k].hi > tree[k].lo) order.push_back(k);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return lower ? tree[x].height < tree[y].height : tree[x].height > tree[y].height;
+  });
+  std::vector<int> task;
+  for (int k : order) {
+    const NdNode& d = tree[k];
+    const bool has_ext = node_ext[k] > 0;
+    if (has_ext) {
+      int r = d.lo;
+      while (r < d.hi) {
+        int r1 = r, ents = 0, longest = 0;
+        while (r1 < d.hi && r1 - r < kHelperRows && (ents < kHelperEntries || r1 == r)) {
+          const int e = erp[r1 + 1] - erp[r1];
+          ents += e;
+          longest = std::max(longest, e);
+          ++r1;
+        }
+        int lg = 0;
+        while ((1 << lg) * 8 < longest && lg < 6) ++lg;
+        task.insert(task.end(), {0, d.lo, d.hi - d.lo, r, r1, k, 1, lg});
+        r = r1;
+      }
+    }
+    task.insert(task.end(), {1, d.lo, d.hi - d.lo, 0, 0, k, has_ext ? 1 : 0, 0});
+  }
+  ts.lower = lower;
+  ts.has_diag = dinv != nullptr;
+  ts.ntasks = (int)task.size() / 8;
+  ts.max_rows = max_rows;
+  ts.heights = max_h + 1;
+  const size_t ne = ecol.size();
+  ts.task.alloc(task.size());
+  ts.erp.alloc(n + 1);
+  ts.ecol.alloc(ne > 0 ? ne : 1);
+  ts.eval.alloc(ne > 0 ? ne : 1);
+  ts.eval32.alloc(ne > 0 ? ne : 1);
+  ts.boff.alloc(nn);
+  ts.blk.alloc(blk.size());
+  ts.blk32.alloc(blk.size());
+  h2d(ts.task.p, task.data(), task.size(), s);
+  h2d(ts.erp.p, erp.data(), n + 1, s);
+  h2d(ts.ecol.p, ecol.data(), ne, s);
+  h2d(ts.eval.p, eval.data(), ne, s);
+  h2d(ts.boff.p, boff.data(), nn, s);
+  h2d(ts.blk.p, blk.data(), blk.size(), s);
+  launch_cast_f32(ts.eval.p, ts.eval32.p, ne, s);
+  launch_cast_f32(ts.blk.p, ts.blk32.p, blk.size(), s);
+  if (dinv) {
+    ts.dinv.alloc(n);
+    ts.dinv32.alloc(n);
+    h2d(ts.dinv.p, dinv->data(), n, s);
+    launch_cast_f32(ts.dinv.p, ts.dinv32.p, n, s);
+  }
+  HIPCK(hipStreamSynchronize(s));  // host vectors go out of scope
+  return true;
 }
 
 // Build a sweep from host dependency lists.  dep_rp/dep_ci/dep_src list, per
@@ -409,7 +547,7 @@ static void check_abort(Solver& S) {
 template <class T>
 static void run_tri(Solver& S, Sweep& sw, const void* rhs, bool rhs_f64, T* out, T* reset) {
   constexpr bool F32 = sizeof(T) == 4;
-  if (sw.cu && S.opt.sweep_kernel == 0) {
+  if (sw.cu && (S.opt.sweep_kernel == 0 || S.opt.sweep_kernel == 3)) {
     CuSweep& c = *sw.cu;
     launch_cu_sweep<T>(c, F32 ? (const T*)c.wval32.p : (const T*)c.wval.p,
                        F32 ? (const T*)c.dinv_e32.p : (const T*)c.dinv_e.p, rhs, rhs_f64, out, reset,
@@ -429,6 +567,10 @@ static void reset_cycle_buffers(Solver& S) {
     launch_fill_f64_bits(S.wt.p, kSent64, S.wg.total, s);
     launch_fill_f32_bits(S.wy32.p, kSent32, S.wg.total, s);
     launch_fill_f32_bits(S.wt32.p, kSent32, S.wg.total, s);
+  }
+  if (S.tree) {
+    launch_fill_f64_bits(S.text.p, kSent64, S.nc, s);
+    launch_fill_f32_bits(S.text32.p, kSent32, S.nc, s);
   }
   launch_fill_f64_bits(S.y.p, kSent64, S.n, s);
   launch_fill_f64_bits(S.t.p, kSent64, S.n, s);
@@ -479,7 +621,17 @@ static void vcycle(Solver& S, const double* z, double* q) {
     launch_resid_fine<T>(S.n, S.A.rp.p, S.A.ci.p, Av, t, z, r, s);
     launch_restrict<T>(S.nc, S.aptr.p, S.amem.p, r, rc, ec, 0, s);
   }
-  if (S.opt.coarse_mode == 0) {
+  if (S.opt.coarse_mode == 0 && S.tree) {
+    T* ext = F32 ? (T*)S.text32.p : (T*)S.text.p;
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lc, sz, sz, false));
+      launch_tree<T>(S.tLc, rc, false, yc, nullptr, ext, S.abort_flag.p, s);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uc, sz, sz, true));
+      launch_tree<T>(S.tUc, yc, false, ec, yc, ext, S.abort_flag.p, s);
+    }
+  } else if (S.opt.coarse_mode == 0) {
     {
       Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lc, sz, sz, false));
       run_tri<T>(S, S.Lc, rc, false, yc, nullptr);
@@ -582,8 +734,21 @@ static void ensure_adjoint(Solver& S) {
         lct_src[o2] = q;
       }
     }
-    build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-    build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    // the transposes of tree-following factors follow the tree too (an entry
+    // into a descendant becomes one into an ancestor); checked all the same
+    S.tree_adj = S.tree && build_tree(S.tUct, S.nd_tree, nc, uct_cnt, uct_ci, uct_src, U.v, true, &udinv, s) &&
+                 build_tree(S.tLct, S.nd_tree, nc, lct_cnt, lct_ci, lct_src, L.v, false, nullptr, s);
+    if (S.tree_adj) {
+      S.Uct.n = S.Lct.n = nc;
+      S.Uct.nnz = (int64_t)uct_ci.size();
+      S.Lct.nnz = (int64_t)lct_ci.size();
+      S.Uct.has_diag = true;
+    } else {
+      S.tUct = TreeSolve();
+      S.tLct = TreeSolve();
+      build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+      build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    }
   }
   if (S.wave) {
     launch_fill_f64_bits(S.wy.p, kSent64, S.wg.total, s);
@@ -602,13 +767,24 @@ static void vcycle_adjoint(Solver& S, const double* z, double* q) {
     Prof p(S, PC_RESID_RESTRICT, (double)S.n * 12 + (double)S.nc * 16);
     launch_restrict_plain(S.nc, S.aptr.p, S.amem.p, z, S.abc.p, S.aec.p, 0, s);
   }
-  {
-    Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
-    run_tri<double>(S, S.Uct, S.abc.p, false, S.auc.p, nullptr);
-  }
-  {
-    Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
-    run_tri<double>(S, S.Lct, S.auc.p, false, S.aec.p, S.auc.p);
+  if (S.tree_adj) {
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
+      launch_tree<double>(S.tUct, S.abc.p, false, S.auc.p, nullptr, S.text.p, S.abort_flag.p, s);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
+      launch_tree<double>(S.tLct, S.auc.p, false, S.aec.p, S.auc.p, S.text.p, S.abort_flag.p, s);
+    }
+  } else {
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
+      run_tri<double>(S, S.Uct, S.abc.p, false, S.auc.p, nullptr);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
+      run_tri<double>(S, S.Lct, S.auc.p, false, S.aec.p, S.auc.p);
+    }
   }
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * 12 + (double)S.n * 24);
@@ -951,7 +1127,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   const gmg_options& o = S.opt;
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
       o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
-      o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 2 ||
+      o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 3 ||
       o.sweep_wg_chunks < 0)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
   auto t0 = std::chrono::steady_clock::now();
@@ -1035,7 +1211,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       for (int p = crp[i]; p < crp[i + 1]; ++p)
         if (cci[p] != i) { gci[fillp[i]++] = cci[p]; gci[fillp[cci[p]]++] = i; }
     // duplicates (both (i,j) and (j,i) stored) are harmless for the traversal
-    std::vector<int> perm = nd_numbering(nc, cnt, gci);
+    std::vector<int> perm = nd_numbering(nc, cnt, gci, &S.nd_tree);
     std::vector<int> rank(nc);
     for (int k = 0; k < nc; ++k) rank[perm[k]] = k;
     DBuf<int> drank;
@@ -1100,7 +1276,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   // transposes then have it too: the same offsets, mirrored); else the
   // level-scheduled sweeps
   S.wave = false;
-  if (o.sweep_kernel == 0) {
+  if (o.sweep_kernel == 0 || o.sweep_kernel == 3) {
     const int nx = grid2d_nx(n, l_rp, l_ci, true);
     if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx) {
       WaveGrid& g = S.wg;
@@ -1137,8 +1313,9 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     hAc.v.resize(S.Ac.nnz);
     d2h(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
     HIPCK(hipStreamSynchronize(s));
-    gmg_status st = host_ilut(hAc, o.ilut_tau, S.hLc, S.hUc);
+    gmg_status st = host_ilut(hAc, o.ilut_tau, S.hLc, S.hUc, &S.nd_tree);
     if (st == GMG_ERR_ZERO_PIVOT) fail(st, "ILUT: zero pivot");
+    if (st == GMG_ERR_OOM) fail(st, "ILUT: factor exceeds int32 indexing");
     if (st != GMG_OK) fail(st, "ILUT: non-finite pivot");
   }
   phase("coarse ILUT");
@@ -1153,9 +1330,29 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) { us_ci.push_back(U.ci[q]); us_src.push_back(q); }
       us_rp[i + 1] = (int)us_ci.size();
     }
-    build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-    build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-    phase("coarse sweeps");
+    // tree solves when the coarse unknowns are in nested-dissection order and
+    // both factors follow the tree; else the level-scheduled sweeps
+    S.tree = false;
+    if (o.sweep_kernel == 0 && o.coarse_order == 1 && !S.nd_tree.empty() &&
+        build_tree(S.tLc, S.nd_tree, nc, L.rp, L.ci, lsrc, L.v, true, nullptr, s) &&
+        build_tree(S.tUc, S.nd_tree, nc, us_rp, us_ci, us_src, U.v, false, &udinv, s)) {
+      S.tree = true;
+      S.text.alloc(nc);
+      S.text32.alloc(nc);
+      // sizes and depths (profiling byte counts, info)
+      S.Lc.n = S.Uc.n = nc;
+      S.Lc.nnz = (int64_t)L.ci.size();
+      S.Uc.nnz = (int64_t)us_ci.size();
+      S.Uc.has_diag = true;
+      S.Lc.levels = S.Uc.levels = S.tLc.heights;
+      phase("coarse tree solves");
+    } else {
+      S.tLc = TreeSolve();
+      S.tUc = TreeSolve();
+      build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+      build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+      phase("coarse sweeps");
+    }
     if (o.coarse_mode == 1) {
       auto up = [&](DCsr& D, const HCsr& H) {
         D.n = D.m = nc;

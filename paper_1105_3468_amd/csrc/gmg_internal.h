@@ -151,6 +151,26 @@ template <class T>
 void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& up, const void* z, bool z_f64, T* zs,
                       T* ys, T* ts, T* t, int* abort_flag, hipStream_t s);
 
+// A triangular factor solved over the nested-dissection tree (k_tree.hip):
+// tasks in tree order, 8 ints each (kind 0: helper for rows [r0, r1) of a
+// node, kind 1: the node's own solve; lo, s = the node's rows; node index
+// into boff; has_ext; log2 lanes per row for helpers); erp/ecol/eval: per row,
+// the entries outside the row's node; blk: each node's diagonal block, dense
+// s x s column-major at boff[node] (zeros where the factor has none); dinv:
+// reciprocal diagonal per row (factors with a stored diagonal).
+constexpr int kTreeMaxRows = 2048;  // rows of one node (its values are staged in LDS)
+struct TreeSolve {
+  bool lower = true, has_diag = false;
+  int ntasks = 0, max_rows = 0, heights = 0;
+  DBuf<int> task, erp, ecol;
+  DBuf<int64_t> boff;
+  DBuf<double> eval, blk, dinv;
+  DBuf<float> eval32, blk32, dinv32;
+};
+template <class T>
+void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, T* reset_rhs, T* ext,
+                 int* abort_flag, hipStream_t s);
+
 // Per-kernel-class profiling with events.
 enum ProfClass {
   PC_SPMV = 0, PC_SWEEP_FINE, PC_SWEEP_COARSE, PC_RESID_RESTRICT, PC_PROLONG,
@@ -268,10 +288,22 @@ void galerkin(int n, int nc, const int* rp, const int* ci, const double* v, cons
 // level_ptr[l] is the first schedule position of level l (levels padded to 64).
 void make_schedule(const std::vector<int>& dep_rp, const std::vector<int>& dep_ci, bool lower,
                    std::vector<int>& sched, std::vector<int>& level_ptr, int* levels);
-// Nested-dissection numbering (position -> vertex) of a symmetric graph.
-std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci);
+// Nested-dissection numbering (position -> vertex) of a symmetric graph.  A
+// node of the dissection tree owns the positions [lo, hi) (a leaf's subgraph,
+// or the separator of its two children; empty for a split into components)
+// and is numbered after all of its descendants; height 0 for leaves.
+struct NdNode {
+  int lo, hi, parent, height;
+};
+std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci,
+                              std::vector<NdNode>* tree = nullptr);
 // Row-wise ILUT(tau) without pivoting on a host CSR; L strictly lower,
 // U with the diagonal first.  Returns GMG_OK / GMG_ERR_ZERO_PIVOT / NONFINITE.
-gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U);
+// With the nested-dissection tree of A's numbering, the tree's nodes are
+// factored in parallel (same result).
+gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vector<NdNode>* tree = nullptr);
+// host worker threads: GMG_THREADS, else OMP_NUM_THREADS, else the hardware's
+// (at most 64)
+int host_threads();
 
 }  // namespace gmg

@@ -1,9 +1,15 @@
 // Host-side analysis steps of the setup: dependency-level schedules of the
 // triangular factors, and the row-wise ILUT factorisation of the coarse matrix.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <memory>
+#include <condition_variable>
+#include <cstdlib>
 #include <functional>
+#include <mutex>
 #include <queue>
+#include <thread>
 #include <vector>
 
 #include "gmg_internal.h"
@@ -53,67 +59,240 @@ void make_schedule(const std::vector<int>& dep_rp, const std::vector<int>& dep_c
 // otherwise it becomes the multiplier l_ik = w_k / u_kk and row k of U is
 // subtracted.  U entries j > i below the threshold are dropped; the diagonal
 // is always kept and stored first in its row.
-gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U) {
-  const int n = A.n;
-  L.n = U.n = n;
-  L.rp.assign(n + 1, 0);
-  U.rp.assign(n + 1, 0);
-  L.ci.clear(); L.v.clear(); U.ci.clear(); U.v.clear();
-  L.ci.reserve(A.ci.size()); L.v.reserve(A.ci.size());
-  U.ci.reserve(A.ci.size()); U.v.reserve(A.ci.size());
-  std::vector<double> w(n > 0 ? n : 1, 0.0);
-  std::vector<signed char> state(n > 0 ? n : 1, 0);  // 0 absent, 1 present, 2 dropped
+//
+// Row i reads only A's row i and the finished U rows of the k it eliminates.
+// Under a nested-dissection numbering those rows lie in i's own tree node
+// (earlier rows) or in its descendants, fill included: eliminating k adds
+// columns of U's row k, which lie in k's node or its ancestors, all on the
+// path through i's node.  So the nodes of the tree are factored as tasks, a
+// node once all of its children are done, on a pool of threads.  Every row
+// performs the same operations in the same order as in a row-by-row pass, so
+// the factors are bit-identical to the sequential ones.
+namespace {
+
+struct IlutNodeRows {  // the factor rows [lo, hi) of one tree node
+  int lo = 0;
+  std::vector<int> lrp{0}, lci, urp{0}, uci;
+  std::vector<double> lv, uv;
+};
+
+struct IlutWork {
+  std::vector<double> w;
+  std::vector<signed char> state;  // 0 absent, 1 present, 2 dropped
   std::vector<int> touched;
-  touched.reserve(256);
   std::priority_queue<int, std::vector<int>, std::greater<int>> pending;
-  for (int i = 0; i < n; ++i) {
+  explicit IlutWork(int n) : w(n > 0 ? n : 1, 0.0), state(n > 0 ? n : 1, 0) { touched.reserve(256); }
+};
+
+// factor rows lo .. hi-1 into R; returns the first failing row (or -1) and
+// its status
+int ilut_rows(const HCsr& A, double tau, int lo, int hi, const std::vector<int>& node_of,
+              std::vector<IlutNodeRows>& rows, int self, IlutWork& W, gmg_status* st) {
+  IlutNodeRows& R = rows[self];
+  for (int i = lo; i < hi; ++i) {
     double ss = 0.0;
-    touched.clear();
+    W.touched.clear();
     for (int p = A.rp[i]; p < A.rp[i + 1]; ++p) {
       const int j = A.ci[p];
       ss = ss + A.v[p] * A.v[p];
-      w[j] = A.v[p];
-      state[j] = 1;
-      touched.push_back(j);
-      if (j < i) pending.push(j);
+      W.w[j] = A.v[p];
+      W.state[j] = 1;
+      W.touched.push_back(j);
+      if (j < i) W.pending.push(j);
     }
     const double thr = tau * std::sqrt(ss);
-    if (state[i] == 0) { state[i] = 1; w[i] = 0.0; touched.push_back(i); }
-    while (!pending.empty()) {
-      const int k = pending.top();
-      pending.pop();
-      if (std::fabs(w[k]) < thr) { w[k] = 0.0; state[k] = 2; continue; }
-      const int uk = U.rp[k];
-      const double lik = w[k] / U.v[uk];
-      w[k] = lik;
-      for (int r = uk + 1; r < U.rp[k + 1]; ++r) {
-        const int j = U.ci[r];
-        if (state[j] == 0) {
-          state[j] = 1;
-          w[j] = 0.0;
-          touched.push_back(j);
-          if (j < i) pending.push(j);
+    if (W.state[i] == 0) { W.state[i] = 1; W.w[i] = 0.0; W.touched.push_back(i); }
+    while (!W.pending.empty()) {
+      const int k = W.pending.top();
+      W.pending.pop();
+      if (std::fabs(W.w[k]) < thr) { W.w[k] = 0.0; W.state[k] = 2; continue; }
+      const IlutNodeRows& K = rows[node_of[k]];
+      const int uk = K.urp[k - K.lo], ue = K.urp[k - K.lo + 1];
+      const int* uci = K.uci.data();
+      const double* uv = K.uv.data();
+      const double lik = W.w[k] / uv[uk];
+      W.w[k] = lik;
+      for (int r = uk + 1; r < ue; ++r) {
+        const int j = uci[r];
+        if (W.state[j] == 0) {
+          W.state[j] = 1;
+          W.w[j] = 0.0;
+          W.touched.push_back(j);
+          if (j < i) W.pending.push(j);
         }
-        w[j] = w[j] - lik * U.v[r];
+        W.w[j] = W.w[j] - lik * uv[r];
       }
     }
-    std::sort(touched.begin(), touched.end());
-    const double d = w[i];
-    U.ci.push_back(i);
-    U.v.push_back(d);
-    for (int j : touched) {
+    std::sort(W.touched.begin(), W.touched.end());
+    const double d = W.w[i];
+    R.uci.push_back(i);
+    R.uv.push_back(d);
+    for (int j : W.touched) {
       if (j < i) {
-        if (state[j] == 1) { L.ci.push_back(j); L.v.push_back(w[j]); }
+        if (W.state[j] == 1) { R.lci.push_back(j); R.lv.push_back(W.w[j]); }
       } else if (j > i) {
-        if (!(std::fabs(w[j]) < thr)) { U.ci.push_back(j); U.v.push_back(w[j]); }
+        if (!(std::fabs(W.w[j]) < thr)) { R.uci.push_back(j); R.uv.push_back(W.w[j]); }
       }
-      state[j] = 0;
-      w[j] = 0.0;
+      W.state[j] = 0;
+      W.w[j] = 0.0;
     }
-    L.rp[i + 1] = (int)L.ci.size();
-    U.rp[i + 1] = (int)U.ci.size();
-    if (d == 0.0) return GMG_ERR_ZERO_PIVOT;
-    if (!std::isfinite(d)) return GMG_ERR_NONFINITE;
+    R.lrp.push_back((int)R.lci.size());
+    R.urp.push_back((int)R.uci.size());
+    if (d == 0.0) { *st = GMG_ERR_ZERO_PIVOT; return i; }
+    if (!std::isfinite(d)) { *st = GMG_ERR_NONFINITE; return i; }
+  }
+  return -1;
+}
+
+}  // namespace
+
+int host_threads() {
+  static int t = 0;
+  if (!t) {
+    const char* e = std::getenv("GMG_THREADS");
+    if (!e || !*e) e = std::getenv("OMP_NUM_THREADS");
+    int v = e ? std::atoi(e) : 0;
+    if (v <= 0) v = (int)std::thread::hardware_concurrency();
+    t = std::max(1, std::min(v, 64));
+  }
+  return t;
+}
+
+gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vector<NdNode>* tree) {
+  const int n = A.n;
+  L.n = U.n = n;
+  // tasks: the tree's nonempty nodes, or one task over all rows
+  std::vector<int> lo, hi, parent;
+  std::vector<int> node_of(n > 0 ? n : 1, -1);
+  bool use_tree = tree && !tree->empty() && host_threads() > 1;
+  if (use_tree) {
+    const int nn = (int)tree->size();
+    std::vector<int> task_of(nn, -1);
+    for (int k = 0; k < nn; ++k) {
+      const NdNode& d = (*tree)[k];
+      if (d.lo < 0 || d.hi > n || d.lo > d.hi) { use_tree = false; break; }
+      task_of[k] = (int)lo.size();
+      lo.push_back(d.lo);
+      hi.push_back(d.hi);
+      for (int r = d.lo; r < d.hi; ++r) {
+        if (node_of[r] >= 0) use_tree = false;
+        node_of[r] = task_of[k];
+      }
+    }
+    for (int r = 0; r < n && use_tree; ++r)
+      if (node_of[r] < 0) use_tree = false;
+    if (use_tree) {
+      // a node's parent is the task of its tree parent (empty nodes included:
+      // they are trivial tasks and keep the dependency chain intact)
+      parent.assign(lo.size(), -1);
+      for (int k = 0; k < nn; ++k) parent[task_of[k]] = (*tree)[k].parent >= 0 ? task_of[(*tree)[k].parent] : -1;
+    }
+  }
+  if (!use_tree) {
+    lo.assign(1, 0);
+    hi.assign(1, n);
+    parent.assign(1, -1);
+    std::fill(node_of.begin(), node_of.end(), 0);
+  }
+  const int nt = (int)lo.size();
+  std::vector<IlutNodeRows> rows(nt);
+  for (int k = 0; k < nt; ++k) {
+    rows[k].lo = lo[k];
+    rows[k].lrp.reserve(hi[k] - lo[k] + 1);
+    rows[k].urp.reserve(hi[k] - lo[k] + 1);
+  }
+  std::vector<int> fail_row(nt, -1);
+  std::vector<gmg_status> fail_st(nt, GMG_OK);
+  if (nt == 1) {
+    IlutWork W(n);
+    fail_row[0] = ilut_rows(A, tau, 0, n, node_of, rows, 0, W, &fail_st[0]);
+  } else {
+    std::vector<int> waiting(nt, 0);
+    for (int k = 0; k < nt; ++k)
+      if (parent[k] >= 0) waiting[parent[k]]++;
+    std::vector<char> poisoned(nt, 0);
+    std::vector<int> ready;
+    for (int k = 0; k < nt; ++k)
+      if (waiting[k] == 0) ready.push_back(k);
+    int remaining = nt;
+    std::mutex mu;
+    std::condition_variable cv;
+    auto worker = [&]() {
+      IlutWork W(n);
+      std::unique_lock<std::mutex> lk(mu);
+      for (;;) {
+        cv.wait(lk, [&] { return !ready.empty() || remaining == 0; });
+        if (ready.empty()) return;
+        const int k = ready.back();
+        ready.pop_back();
+        const bool skip = poisoned[k] != 0;
+        lk.unlock();
+        int fr = -1;
+        gmg_status fs = GMG_OK;
+        if (!skip) fr = ilut_rows(A, tau, lo[k], hi[k], node_of, rows, k, W, &fs);
+        lk.lock();
+        fail_row[k] = fr;
+        fail_st[k] = fs;
+        const int p = parent[k];
+        if (p >= 0) {
+          // a failed row leaves its ancestors unfactored (they would read it)
+          if (skip || fr >= 0) poisoned[p] = 1;
+          if (--waiting[p] == 0) ready.push_back(p);
+        }
+        --remaining;
+        cv.notify_all();
+      }
+    };
+    const int nthreads = std::min(host_threads(), nt);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+  }
+  // the first failing row in row order (rows before it do not depend on any
+  // failing row, so it is the row a sequential pass stops at)
+  int first = -1;
+  gmg_status st = GMG_OK;
+  for (int k = 0; k < nt; ++k)
+    if (fail_row[k] >= 0 && (first < 0 || fail_row[k] < first)) { first = fail_row[k]; st = fail_st[k]; }
+  if (first >= 0) return st;
+  // concatenate the nodes' rows in row order
+  std::vector<int> order(nt);
+  for (int k = 0; k < nt; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return lo[x] < lo[y]; });
+  std::vector<int64_t> loff(nt + 1, 0), uoff(nt + 1, 0);
+  for (int q = 0; q < nt; ++q) {
+    loff[q + 1] = loff[q] + (int64_t)rows[order[q]].lci.size();
+    uoff[q + 1] = uoff[q] + (int64_t)rows[order[q]].uci.size();
+  }
+  if (loff[nt] > INT32_MAX || uoff[nt] > INT32_MAX) return GMG_ERR_OOM;  // int32 row pointers
+  L.rp.assign(n + 1, 0);
+  U.rp.assign(n + 1, 0);
+  L.ci.resize(loff[nt]);
+  L.v.resize(loff[nt]);
+  U.ci.resize(uoff[nt]);
+  U.v.resize(uoff[nt]);
+  auto copy_nodes = [&](int q0, int q1) {
+    for (int q = q0; q < q1; ++q) {
+      const IlutNodeRows& R = rows[order[q]];
+      const int nr = (int)R.lrp.size() - 1;
+      for (int r = 0; r < nr; ++r) {
+        L.rp[R.lo + r + 1] = (int)loff[q] + R.lrp[r + 1];
+        U.rp[R.lo + r + 1] = (int)uoff[q] + R.urp[r + 1];
+      }
+      std::copy(R.lci.begin(), R.lci.end(), L.ci.begin() + loff[q]);
+      std::copy(R.lv.begin(), R.lv.end(), L.v.begin() + loff[q]);
+      std::copy(R.uci.begin(), R.uci.end(), U.ci.begin() + uoff[q]);
+      std::copy(R.uv.begin(), R.uv.end(), U.v.begin() + uoff[q]);
+    }
+  };
+  const int nthreads = std::min(host_threads(), nt);
+  if (nthreads <= 1) {
+    copy_nodes(0, nt);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t)
+      pool.emplace_back(copy_nodes, (int)((int64_t)nt * t / nthreads), (int)((int64_t)nt * (t + 1) / nthreads));
+    for (auto& t : pool) t.join();
   }
   return GMG_OK;
 }
@@ -127,49 +306,81 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U) {
 // at least half of S cumulatively, clamped to [1, L-1]; then ND(d < m),
 // ND(d > m), and the separator d == m ascending.  Returns perm (position ->
 // vertex).
-std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci) {
-  struct Task { int kind, start, len; };  // kind 0: dissect, 1: emit as is
-  std::vector<int> seq(n), perm;
-  perm.reserve(n);
+std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci,
+                              std::vector<NdNode>* tree) {
+  // A task owns a segment of seq (the vertices of one subgraph, ascending);
+  // dissecting it stable-partitions the segment into [part a | part b |
+  // separator] and hands the parts on as child tasks.  Taken depth first
+  // (part a's subtree, then part b's, then the separator), the emitted order
+  // is the final segment order itself, so disjoint segments can be dissected
+  // concurrently and the numbering is seq once all tasks are done.  Tree
+  // nodes are created under a lock and renumbered afterwards in the order a
+  // depth-first pass creates them (both children of a node on its visit).
+  struct Task { int kind, start, len, node; };  // kind 0: dissect, 1: emit as is
+  struct Node { int lo = 0, hi = 0, parent = -1, a = -1, b = -1; };
+  std::vector<int> seq(n);
   for (int i = 0; i < n; ++i) seq[i] = i;
-  std::vector<int> mark(n, -1), dist(n, -1), queue;
-  queue.reserve(n);
-  std::vector<Task> stack{{0, 0, n}};
-  int tag = 0;
-  auto bfs = [&](int src) {
-    queue.clear();
-    dist[src] = 0;
-    queue.push_back(src);
-    for (size_t h = 0; h < queue.size(); ++h) {
-      const int u = queue[h];
-      for (int p = rp[u]; p < rp[u + 1]; ++p) {
-        const int v = ci[p];
-        if (mark[v] == tag && dist[v] < 0) {
-          dist[v] = dist[u] + 1;
-          queue.push_back(v);
-        }
-      }
-    }
+  std::unique_ptr<std::atomic<int>[]> mark(new std::atomic<int>[n > 0 ? n : 1]);
+  for (int i = 0; i < n; ++i) mark[i].store(-1, std::memory_order_relaxed);
+  std::vector<int> dist(n > 0 ? n : 1, -1);
+  std::atomic<int> next_tag{0};
+  std::vector<Node> nodes(1);
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<Task> ready{{0, 0, n, 0}};
+  int active = 0;
+
+  // under mu: two children of node x
+  auto children = [&](int x, int* na, int* nb) {
+    *na = (int)nodes.size();
+    *nb = *na + 1;
+    nodes.resize(nodes.size() + 2);
+    nodes[*na].parent = nodes[*nb].parent = x;
+    nodes[x].a = *na;
+    nodes[x].b = *nb;
   };
-  while (!stack.empty()) {
-    const Task t = stack.back();
-    stack.pop_back();
-    if (t.len == 0) continue;
+
+  // process one task; appends its child tasks to out (under no lock)
+  auto run = [&](const Task& t, std::vector<int>& queue, std::vector<Task>& out, std::vector<int>& ids) {
+    if (t.len == 0) return;
     int* b = seq.data() + t.start;
     int* e = b + t.len;
     if (t.kind == 1 || t.len <= 64) {
-      perm.insert(perm.end(), b, e);
-      continue;
+      // the node's own rows: numbered after all of its descendants'
+      std::lock_guard<std::mutex> g(mu);
+      nodes[t.node].lo = t.start;
+      nodes[t.node].hi = t.start + t.len;
+      return;
     }
-    ++tag;
-    for (int* q = b; q != e; ++q) { mark[*q] = tag; dist[*q] = -1; }
+    const int tag = next_tag.fetch_add(1, std::memory_order_relaxed);
+    for (int* q = b; q != e; ++q) { mark[*q].store(tag, std::memory_order_relaxed); dist[*q] = -1; }
+    auto bfs = [&](int src) {
+      queue.clear();
+      dist[src] = 0;
+      queue.push_back(src);
+      for (size_t h = 0; h < queue.size(); ++h) {
+        const int u = queue[h];
+        for (int p = rp[u]; p < rp[u + 1]; ++p) {
+          const int v = ci[p];
+          if (mark[v].load(std::memory_order_relaxed) == tag && dist[v] < 0) {
+            dist[v] = dist[u] + 1;
+            queue.push_back(v);
+          }
+        }
+      }
+    };
     bfs(*b);  // segments are kept ascending, so *b is the smallest vertex
     if ((int)queue.size() < t.len) {
+      // disconnected: the component of *b, then the rest
       int* mid = std::stable_partition(b, e, [&](int v) { return dist[v] >= 0; });
       const int c0 = (int)(mid - b);
-      stack.push_back({0, t.start + c0, t.len - c0});
-      stack.push_back({0, t.start, c0});
-      continue;
+      {
+        std::lock_guard<std::mutex> g(mu);
+        children(t.node, &ids[0], &ids[1]);
+      }
+      out.push_back({0, t.start, c0, ids[0]});
+      out.push_back({0, t.start + c0, t.len - c0, ids[1]});
+      return;
     }
     int r = *b, far = 0;
     for (int* q = b; q != e; ++q)
@@ -179,8 +390,8 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
     int L = 0;
     for (int* q = b; q != e; ++q) L = std::max(L, dist[*q]);
     if (L < 2) {
-      stack.push_back({1, t.start, t.len});
-      continue;
+      out.push_back({1, t.start, t.len, t.node});
+      return;
     }
     std::vector<int> cnt(L + 1, 0);
     for (int* q = b; q != e; ++q) cnt[dist[*q]]++;
@@ -190,11 +401,70 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
     int* m1 = std::stable_partition(b, e, [&](int v) { return dist[v] < m; });
     int* m2 = std::stable_partition(m1, e, [&](int v) { return dist[v] > m; });
     const int c0 = (int)(m1 - b), c1 = (int)(m2 - m1);
-    stack.push_back({1, t.start + c0 + c1, t.len - c0 - c1});
-    stack.push_back({0, t.start + c0, c1});
-    stack.push_back({0, t.start, c0});
+    {
+      std::lock_guard<std::mutex> g(mu);
+      children(t.node, &ids[0], &ids[1]);
+    }
+    out.push_back({0, t.start, c0, ids[0]});
+    out.push_back({0, t.start + c0, c1, ids[1]});
+    out.push_back({1, t.start + c0 + c1, t.len - c0 - c1, t.node});
+  };
+
+  auto worker = [&]() {
+    std::vector<int> queue;
+    std::vector<Task> out;
+    std::vector<int> ids(2);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv.wait(lk, [&] { return !ready.empty() || active == 0; });
+      if (ready.empty()) return;
+      const Task t = ready.back();
+      ready.pop_back();
+      ++active;
+      lk.unlock();
+      out.clear();
+      run(t, queue, out, ids);
+      lk.lock();
+      ready.insert(ready.end(), out.begin(), out.end());
+      --active;
+      cv.notify_all();
+    }
+  };
+  // small graphs are not worth the threads
+  const int nthreads = n >= 4096 ? host_threads() : 1;
+  if (nthreads <= 1) {
+    worker();
+  } else {
+    std::vector<std::thread> pool;
+    for (int k = 0; k < nthreads; ++k) pool.emplace_back(worker);
+    for (auto& th : pool) th.join();
   }
-  return perm;
+  if (tree) {
+    // ids in depth-first creation order, then heights (children come after
+    // their parent)
+    const int nn = (int)nodes.size();
+    std::vector<int> id(nn, -1), stack{0};
+    id[0] = 0;
+    int next = 1;
+    while (!stack.empty()) {
+      const int x = stack.back();
+      stack.pop_back();
+      if (nodes[x].a < 0) continue;
+      id[nodes[x].a] = next++;
+      id[nodes[x].b] = next++;
+      stack.push_back(nodes[x].b);
+      stack.push_back(nodes[x].a);
+    }
+    std::vector<NdNode> out(nn);
+    for (int x = 0; x < nn; ++x)
+      out[id[x]] = NdNode{nodes[x].lo, nodes[x].hi, nodes[x].parent >= 0 ? id[nodes[x].parent] : -1, 0};
+    for (int k = nn - 1; k > 0; --k) {
+      NdNode& p = out[out[k].parent];
+      p.height = std::max(p.height, out[k].height + 1);
+    }
+    *tree = std::move(out);
+  }
+  return seq;
 }
 
 }  // namespace gmg

@@ -209,21 +209,26 @@ def test_sweep_waves_do_not_change_results():
 
 @pytest.mark.parametrize("kind", ["fv2d_rot_96", "fv3d_20", "fv2d_37", "rgg_3001"])
 def test_sweep_kernels_bitwise_equal(kind):
-    """The single-CU LDS sweep (narrow factors), the device-wide multi-CU
-    sweep and the one-workgroup LDS sweep perform the same operations in the
-    same order: bitwise-equal preconditioner applications, in FP64 and FP32,
-    forward and adjoint."""
+    """The level sweeps (single-CU ring, device-wide, one-workgroup LDS, in any
+    mix of level ranges) and the wavefront sweep perform the same operations in
+    the same order: bitwise-equal preconditioner applications, in FP64 and
+    FP32, forward and adjoint.  The tree solve of the coarse factors (the
+    default) adds the same terms in another order: within FP64 rounding."""
     _say(f"[case] sweep kernels {kind}")
     p = CASES[kind]()
     z = torch.as_tensor(np.random.default_rng(9).uniform(-1, 1, p.n_rows), device="cuda")
-    configs = [dict(sweep_kernel=1), dict(sweep_kernel=0), dict(sweep_kernel=2),
-               dict(sweep_kernel=0, sweep_wg_chunks=1), dict(sweep_kernel=0, sweep_wg_chunks=64)]
+    configs = [dict(sweep_kernel=1), dict(sweep_kernel=3), dict(sweep_kernel=2),
+               dict(sweep_kernel=3, sweep_wg_chunks=1), dict(sweep_kernel=3, sweep_wg_chunks=64)]
     solvers = [Solver(p.rowptr, p.col, p.val, **c) for c in configs]
+    tree = Solver(p.rowptr, p.col, p.val, sweep_kernel=0)
     for prec, adj in ((0, False), (1, False), (0, True)):
         ref = solvers[0].apply(z, precision=prec, adjoint=adj)
         for c, s in zip(configs[1:], solvers[1:]):
             a = s.apply(z, precision=prec, adjoint=adj)
             assert torch.equal(a, ref), (kind, c, prec, adj)
+        t = tree.apply(z, precision=prec, adjoint=adj)
+        tol = 1e-12 if prec == 0 else 1e-5
+        assert float(torch.linalg.norm(t - ref) / torch.linalg.norm(ref)) <= tol, (kind, prec, adj)
 
 
 def test_tiny_and_degenerate():
