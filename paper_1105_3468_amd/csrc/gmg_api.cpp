@@ -205,6 +205,8 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
                        const std::vector<double>& vals, bool lower, const std::vector<double>* dinv,
                        hipStream_t s) {
   constexpr int kHelperEntries = 2048, kHelperRows = 256;
+  constexpr int kSliceLgRows = 4;             // rows per slice of a node above 64 rows: 16
+  constexpr size_t kSmallInvLds = 40 * 1024;  // inversion chunks launched with this much LDS or less first
   const int nn = (int)tree.size();
   if (nn == 0 || n <= 0) return false;
   std::vector<int> node_of(n, -1);
@@ -294,7 +296,24 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
         r = r1;
       }
     }
-    task.insert(task.end(), {1, d.lo, d.hi - d.lo, 0, 0, k, has_ext ? 1 : 0, 0});
+    // the node's slices: one for a leaf-sized block, else kSliceRows rows each
+    const int sz = d.hi - d.lo;
+    const int lgR = sz <= 64 ? 6 : kSliceLgRows, R = 1 << lgR;
+    const int nsl = (sz + R - 1) / R;
+    for (int q = 0; q < nsl; ++q)
+      task.insert(task.end(), {1, d.lo, sz, q * R, std::min(sz, (q + 1) * R), k, (has_ext ? 1 : 0) | lgR << 1, nsl});
+  }
+  // inversion tasks: W-column chunks of every node, small-LDS ones first
+  std::vector<int> itask[2];
+  size_t ilds[2] = {0, 0};
+  for (int k = 0; k < nn; ++k) {
+    const int sz = tree[k].hi - tree[k].lo;
+    if (sz == 0) continue;
+    const int lgW = tree_inv_width(sz);
+    const size_t need = tree_inv_lds(sz, lgW);
+    const int cls = need <= kSmallInvLds ? 0 : 1;
+    ilds[cls] = std::max(ilds[cls], need);
+    for (int c0 = 0; c0 < sz; c0 += 1 << lgW) itask[cls].insert(itask[cls].end(), {tree[k].lo, sz, c0, k, lgW, 0, 0, 0});
   }
   ts.lower = lower;
   ts.has_diag = dinv != nullptr;
@@ -308,23 +327,36 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
   ts.eval.alloc(ne > 0 ? ne : 1);
   ts.eval32.alloc(ne > 0 ? ne : 1);
   ts.boff.alloc(nn);
-  ts.blk.alloc(blk.size());
-  ts.blk32.alloc(blk.size());
+  ts.ncount.alloc(nn);
+  ts.inv.alloc(blk.size());
+  ts.inv32.alloc(blk.size());
   h2d(ts.task.p, task.data(), task.size(), s);
   h2d(ts.erp.p, erp.data(), n + 1, s);
   h2d(ts.ecol.p, ecol.data(), ne, s);
   h2d(ts.eval.p, eval.data(), ne, s);
   h2d(ts.boff.p, boff.data(), nn, s);
-  h2d(ts.blk.p, blk.data(), blk.size(), s);
+  HIPCK(hipMemsetAsync(ts.ncount.p, 0, sizeof(int) * nn, s));
   launch_cast_f32(ts.eval.p, ts.eval32.p, ne, s);
-  launch_cast_f32(ts.blk.p, ts.blk32.p, blk.size(), s);
-  if (dinv) {
-    ts.dinv.alloc(n);
-    ts.dinv32.alloc(n);
-    h2d(ts.dinv.p, dinv->data(), n, s);
-    launch_cast_f32(ts.dinv.p, ts.dinv32.p, n, s);
+  {
+    DBuf<double> dblk, ddinv;
+    DBuf<int> dit[2];
+    dblk.alloc(blk.size());
+    h2d(dblk.p, blk.data(), blk.size(), s);
+    if (dinv) {
+      ddinv.alloc(n);
+      h2d(ddinv.p, dinv->data(), n, s);
+    }
+    HIPCK(hipMemsetAsync(ts.inv.p, 0, sizeof(double) * blk.size(), s));
+    for (int c = 0; c < 2; ++c) {
+      if (itask[c].empty()) continue;
+      dit[c].alloc(itask[c].size());
+      h2d(dit[c].p, itask[c].data(), itask[c].size(), s);
+      launch_tree_invert(ts, dit[c].p, (int)itask[c].size() / 8, ilds[c], dblk.p, dinv ? ddinv.p : nullptr,
+                         ts.inv.p, s);
+    }
+    launch_cast_f32(ts.inv.p, ts.inv32.p, blk.size(), s);
+    HIPCK(hipStreamSynchronize(s));  // host vectors and staging buffers go out of scope
   }
-  HIPCK(hipStreamSynchronize(s));  // host vectors go out of scope
   return true;
 }
 
@@ -571,6 +603,8 @@ static void reset_cycle_buffers(Solver& S) {
   if (S.tree) {
     launch_fill_f64_bits(S.text.p, kSent64, S.nc, s);
     launch_fill_f32_bits(S.text32.p, kSent32, S.nc, s);
+    for (TreeSolve* t : {&S.tLc, &S.tUc, &S.tUct, &S.tLct})
+      if (t->ncount.p) launch_fill_f32_bits(reinterpret_cast<float*>(t->ncount.p), 0u, t->ncount.n, s);
   }
   launch_fill_f64_bits(S.y.p, kSent64, S.n, s);
   launch_fill_f64_bits(S.t.p, kSent64, S.n, s);
@@ -908,6 +942,12 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
         launch_multidot(V, ld, kc, w, n, S.rw, h1, s);
         launch_update_dot(V, ld, kc, h1, w, n, S.rw, h2, s);
         launch_update_norm(V, ld, kc, h2, w, n, S.rw, nrm, s);
+      } else if (kc <= many_max()) {
+        // the first update and the second dot product share one read of V
+        Prof p(S, PC_ORTHO, 8.0 * n * (3 * kc + 6));
+        launch_multidot_many(V, ld, kc, w, n, S.rw, h1, s);
+        launch_update_dot_many(V, ld, kc, h1, w, n, S.rw, h2, s);
+        launch_update_many(V, ld, kc, h2, w, n, true, S.rw, nrm, s);
       } else {
         Prof p(S, PC_ORTHO, 8.0 * n * (4 * kc + 4 * ((kc + kFused - 1) / kFused) + 4));
         for (int c0 = 0; c0 < kc; c0 += kFused)

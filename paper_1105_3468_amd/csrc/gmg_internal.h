@@ -159,17 +159,31 @@ void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& u
 // s x s column-major at boff[node] (zeros where the factor has none); dinv:
 // reciprocal diagonal per row (factors with a stored diagonal).
 constexpr int kTreeMaxRows = 2048;  // rows of one node (its values are staged in LDS)
+// A triangular factor laid out for the tree solve: per task 8 ints (helper
+// or node slice), outside entries as CSR over rows (erp, ecol, eval), and per
+// node the inverse of its diagonal block, dense column-major at boff[node]
+// (zeros in the other triangle); ncount[node] counts the node's slices
+// arriving in a solve (zero between solves).
 struct TreeSolve {
   bool lower = true, has_diag = false;
   int ntasks = 0, max_rows = 0, heights = 0;
-  DBuf<int> task, erp, ecol;
+  DBuf<int> task, erp, ecol, ncount;
   DBuf<int64_t> boff;
-  DBuf<double> eval, blk, dinv;
-  DBuf<float> eval32, blk32, dinv32;
+  DBuf<double> eval, inv;
+  DBuf<float> eval32, inv32;
 };
 template <class T>
 void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, T* reset_rhs, T* ext,
                  int* abort_flag, hipStream_t s);
+// Setup: inverses of the diagonal blocks blk (same layout as inv) into inv,
+// one workgroup per task (8 ints: lo, s, c0, node, log2 W; a chunk of W
+// columns of one node), with `lds` bytes of LDS (tree_inv_lds of each task,
+// at most kTreeInvLds).
+constexpr size_t kTreeInvLds = 128 * 1024;
+size_t tree_inv_lds(int rows, int lgW);
+int tree_inv_width(int rows);
+void launch_tree_invert(const TreeSolve& ts, const int* itask, int ntask, size_t lds, const double* blk,
+                        const double* dinv, double* inv, hipStream_t s);
 
 // Per-kernel-class profiling with events.
 enum ProfClass {
@@ -237,6 +251,7 @@ void launch_jacobi(int n, const int* rp, const int* ci, const double* v, const d
 // Krylov kernels (k_krylov.hip)
 struct RedWork {  // scratch for deterministic two-level reductions
   DBuf<double> partial;
+  DBuf<double> mpart;    // block partials of the many-vector passes
   DBuf<unsigned> counter;
   DBuf<double> result;   // two coefficient blocks of up to 2048 values + norms
   int blocks = 0;
@@ -252,6 +267,13 @@ void launch_update_dot(const double* V, size_t ld, int k, const double* h, doubl
 void launch_update_norm(const double* V, size_t ld, int k, const double* h, double* w, int64_t n,
                         RedWork& rw, double* result, hipStream_t s);
 // any k (<= 2048): w -= V^T h (h device); if want_norm, result[0] = ||w_new||^2
+// Many-vector passes (up to many_max() vectors): result[0..k) = V^T w, and
+// w <- w - V h with result[0..k) = V^T w_new, each reading V once.
+int many_max();
+void launch_multidot_many(const double* V, size_t ld, int k, const double* w, int64_t n, RedWork& rw, double* result,
+                          hipStream_t s);
+void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
+                            double* result, hipStream_t s);
 void launch_update_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
                         RedWork& rw, double* result, hipStream_t s);
 // result[0] = ||x||^2

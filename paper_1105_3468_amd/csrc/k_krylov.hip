@@ -16,6 +16,12 @@ constexpr int KB = 256;          // threads per block
 constexpr int KGRID = 512;       // blocks of the reduction kernels
 constexpr int KMAX = 32;         // vectors per fused register-resident pass
 constexpr int KLDS = 2048;       // vectors per LDS-staged pass (longest basis)
+// many-vector passes (a basis longer than KMAX)
+constexpr int MROWS = 16;         // rows per chunk
+constexpr int MG = KB / MROWS;    // vector groups per block
+constexpr int MGRID = 512;        // blocks
+constexpr int MMAX = 640;         // longest basis they take
+constexpr int MPARTS = 32;        // thread groups adding the block partials of one vector
 
 // Keeps the machine scheduler from sinking the loads issued above it into the
 // arithmetic below: without it the compiler reuses one register pair for all
@@ -170,6 +176,7 @@ void red_init(RedWork& rw, hipStream_t s) {
   rw.partial.alloc((size_t)KGRID * KMAX);
   rw.counter.alloc(1);
   rw.result.alloc(2 * KLDS + 8);
+  rw.mpart.alloc((size_t)MGRID * MMAX);
   launch_fill_u32(rw.counter.p, 0u, 1, s);
   launch_fill_f64_bits(rw.partial.p, SENT64, (size_t)KGRID * KMAX, s);
 }
@@ -301,6 +308,174 @@ void launch_update_many(const double* V, size_t ld, int k, const double* h, doub
                      rw.partial.p, rw.counter.p, result);
   HIPCK(hipGetLastError());
 }
+
+// ----------------------------------------------------- many-vector passes
+// For a basis longer than one register-resident pass: rows are taken in
+// chunks of MROWS; thread (r, g) of a block holds row r of the chunk for the
+// basis vectors g, g + MG, g + 2 MG, ... (PER of them, loads all in flight)
+// and keeps their running dot products in registers across chunks.  The
+// block's per-vector sums (over r, in order) go to mpart[block][k]; a second
+// kernel adds the blocks in order.
+
+template <int PER>
+__device__ __forceinline__ void many_block_sums(const double (&acc)[PER], int kc, double* mpart) {
+  // acc[u] of thread (r, g) belongs to vector g + MG u; sum over r in order
+  __shared__ double red[MROWS][MG + 1];
+  const int r = threadIdx.x % MROWS, g = threadIdx.x / MROWS;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (MG * u >= kc) break;  // the same for every thread of the block
+    red[r][g] = acc[u];
+    __syncthreads();
+    if (threadIdx.x < MG) {
+      double t = 0.0;
+      for (int q = 0; q < MROWS; ++q) t += red[q][threadIdx.x];
+      const int k = threadIdx.x + MG * u;
+      if (k < kc) mpart[(size_t)blockIdx.x * MMAX + k] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// h[k] = V[k] . w for k < kc (block partials)
+template <int PER>
+__global__ __launch_bounds__(KB) void k_multidot_many(const double* __restrict__ V, size_t ld, int kc,
+                                                      const double* __restrict__ w, int64_t n,
+                                                      double* __restrict__ mpart) {
+  const int r = threadIdx.x % MROWS, g = threadIdx.x / MROWS;
+  double acc[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) acc[u] = 0.0;
+  const int64_t nch = (n + MROWS - 1) / MROWS;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const int64_t i = ch * MROWS + r;
+    if (i >= n) continue;
+    const double wi = w[i];
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] = g + MG * u < kc ? V[(size_t)(g + MG * u) * ld + i] : 0.0;
+    ALL_LOADS_ISSUED();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc[u] += v[u] * wi;
+  }
+  many_block_sums<PER>(acc, kc, mpart);
+}
+
+// w <- w - sum_k h[k] V[k]; block partials of V[k] . w_new
+template <int PER>
+__global__ __launch_bounds__(KB) void k_update_dot_many(const double* __restrict__ V, size_t ld, int kc,
+                                                        const double* __restrict__ h, double* __restrict__ w,
+                                                        int64_t n, double* __restrict__ mpart) {
+  __shared__ double pr[MROWS][MG + 1];
+  __shared__ double wn[MROWS];
+  __shared__ double hs[MMAX];
+  const int r = threadIdx.x % MROWS, g = threadIdx.x / MROWS;
+  for (int k = threadIdx.x; k < MG * PER; k += KB) hs[k] = k < kc ? h[k] : 0.0;
+  __syncthreads();
+  double acc[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) acc[u] = 0.0;
+  const int64_t nch = (n + MROWS - 1) / MROWS;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const int64_t i = ch * MROWS + r;
+    const bool ok = i < n;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] = (ok && g + MG * u < kc) ? V[(size_t)(g + MG * u) * ld + i] : 0.0;
+    ALL_LOADS_ISSUED();
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) p += hs[g + MG * u] * v[u];
+    pr[r][g] = p;
+    __syncthreads();
+    if (threadIdx.x < MROWS) {
+      const int64_t ii = ch * MROWS + threadIdx.x;
+      double t = 0.0;
+      if (ii < n) {
+        t = w[ii];
+        for (int q = 0; q < MG; ++q) t -= pr[threadIdx.x][q];
+        w[ii] = t;
+      }
+      wn[threadIdx.x] = t;
+    }
+    __syncthreads();
+    const double wi = wn[r];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc[u] += v[u] * wi;
+  }
+  many_block_sums<PER>(acc, kc, mpart);
+}
+
+// result[k] = sum over blocks b (in order) of mpart[b][k]; 8 vectors per
+// block, MPARTS thread groups each adding every MPARTS-th block, then the
+// groups in order
+__global__ __launch_bounds__(KB) void k_colsum(const double* __restrict__ mpart, int nb, int kc,
+                                               double* __restrict__ result) {
+  constexpr int NC = KB / MPARTS;
+  __shared__ double sh[MPARTS][NC];
+  const int c = threadIdx.x % NC, part = threadIdx.x / NC;
+  const int k = blockIdx.x * NC + c;
+  double s = 0.0;
+  if (k < kc) {
+    constexpr int IN = MGRID / MPARTS;
+    double v[IN];
+#pragma unroll
+    for (int u = 0; u < IN; ++u) {
+      const int b = part + u * MPARTS;
+      v[u] = b < nb ? mpart[(size_t)b * MMAX + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < IN; ++u) s += v[u];
+  }
+  sh[part][c] = s;
+  __syncthreads();
+  if (threadIdx.x < NC && k < kc) {
+    double t = 0.0;
+    for (int q = 0; q < MPARTS; ++q) t += sh[q][threadIdx.x];
+    result[k] = t;
+  }
+}
+
+static unsigned many_grid(int64_t n) {
+  int64_t g = (n + MROWS - 1) / MROWS;
+  if (g > MGRID) g = MGRID;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+#define GMG_MANY(KERNEL, kc, ...)                                                  \
+  do {                                                                             \
+    const int per_ = (kc + MG - 1) / MG;                                           \
+    if (per_ <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                     \
+    else if (per_ <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);              \
+    else if (per_ <= 24) hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__);              \
+    else if (per_ <= 32) hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);              \
+    else hipLaunchKernelGGL(KERNEL<40>, __VA_ARGS__);                              \
+  } while (0)
+
+int many_max() { return MMAX; }
+
+void launch_multidot_many(const double* V, size_t ld, int k, const double* w, int64_t n, RedWork& rw, double* result,
+                          hipStream_t s) {
+  if (k < 1 || k > MMAX) fail(GMG_ERR_INVALID_ARG, "multidot_many: bad vector count");
+  const unsigned nb = many_grid(n);
+  GMG_MANY(k_multidot_many, k, dim3(nb), dim3(KB), 0, s, V, ld, k, w, n, rw.mpart.p);
+  hipLaunchKernelGGL(k_colsum, dim3((k + KB / MPARTS - 1) / (KB / MPARTS)), dim3(KB), 0, s, rw.mpart.p, (int)nb, k,
+                     result);
+  HIPCK(hipGetLastError());
+}
+
+void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
+                            double* result, hipStream_t s) {
+  if (k < 1 || k > MMAX) fail(GMG_ERR_INVALID_ARG, "update_dot_many: bad vector count");
+  const unsigned nb = many_grid(n);
+  GMG_MANY(k_update_dot_many, k, dim3(nb), dim3(KB), 0, s, V, ld, k, h, w, n, rw.mpart.p);
+  hipLaunchKernelGGL(k_colsum, dim3((k + KB / MPARTS - 1) / (KB / MPARTS)), dim3(KB), 0, s, rw.mpart.p, (int)nb, k,
+                     result);
+  HIPCK(hipGetLastError());
+}
+#undef GMG_MANY
+
 
 __global__ __launch_bounds__(KB) void k_xupdate_many(double* __restrict__ x, const double* __restrict__ Z, size_t ld,
                                                      int kc, const double* __restrict__ c, int64_t n) {

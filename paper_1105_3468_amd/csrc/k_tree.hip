@@ -4,24 +4,22 @@
 // creates entries between a row and the rows of its own tree node or of the
 // node's descendants (strictly lower part) or ancestors (strictly upper
 // part).  So a lower solve can run bottom-up over the tree and an upper solve
-// top-down, one node at a time along a root-leaf path, every node solving
-// with its own diagonal block after subtracting the terms of rows outside it,
-// which are final by then.  The diagonal blocks of separators are nearly dense
-// after fill; they are stored dense (column-major, zeros where the factor
-// has no entry) and solved in panels of 64 rows: one wave walks the panel's
-// columns, broadcasting each finished value with readlane (zeros of the
-// other triangle leave finished rows unchanged), and the workgroup then
-// applies the panel to the node's remaining rows.  A level sweep would pay
-// one dependency hop per row of a separator chain instead.
+// top-down: a node's rows are x = T^{-1} (rhs - E x_outside), where T is the
+// node's diagonal block and the rows outside it that E refers to are final by
+// then.  The diagonal blocks of separators are nearly dense after fill, and a
+// substitution through one costs a dependent step per row; instead T^{-1} is
+// formed once at setup (dense, column-major, zeros in the other triangle) and
+// the solve applies it as a matrix-vector product, whose rows are independent
+// and are split over several workgroups.
 //
 // One launch runs a whole solve as a list of tasks in tree order (lower:
 // heights ascending; upper: descending).  For a node with terms outside it,
 // helper tasks first compute rhs - (those terms) for slices of its rows,
 // polling the published results of other nodes (value-as-flag, as in the
 // sweeps), and publish them to a staging vector that doubles as its own
-// ready flag; the node's own task polls them, solves, and publishes its rows.
-// Every task waits only on earlier tasks and workgroups start in order, so
-// the solve always makes progress; every wait is bounded.
+// ready flag; the node's slice tasks poll them, multiply, and publish their
+// rows.  Every task waits only on earlier tasks and workgroups start in
+// order, so the solve always makes progress; every wait is bounded.
 #include <algorithm>
 
 #include "gmg_internal.h"
@@ -30,7 +28,8 @@
 namespace gmg {
 
 constexpr int TREE_THREADS = 256;
-constexpr int TREE_BATCH = 8;
+constexpr int TREE_BATCH = 8;   // helper loads in flight per lane
+constexpr int TREE_MBATCH = 24; // inverse-block loads in flight per lane
 
 template <class T>
 __device__ __forceinline__ T tree_poll(const T* p, int* abort_flag, uint64_t limit) {
@@ -53,34 +52,25 @@ __device__ __forceinline__ T tree_poll(const T* p, int* abort_flag, uint64_t lim
   return v;
 }
 
-__device__ __forceinline__ double bcast_lane(double v, int j) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, j);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), j);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ float bcast_lane(float v, int j) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
-}
-
-// task[8t ..]: kind (0 helper, 1 node), lo, s, r0, r1, node, has_ext, log2 G
-template <class T, class TR, bool LOWER, bool DIAG>
+// task[8t ..]: helper: 0, lo, s, r0, r1, node, 1, log2 G
+//               slice:  1, lo, s, a, b, node, has_ext | log2 R << 1, slices
+template <class T, class TR, bool LOWER>
 __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ task, const int64_t* __restrict__ boff,
                                                        const int* __restrict__ erp, const int* __restrict__ ecol,
-                                                       const T* __restrict__ eval, const T* __restrict__ blk,
-                                                       const T* __restrict__ dinv, const TR* rhs, T* out, T* ext,
-                                                       TR* reset_rhs, int* abort_flag, uint64_t limit) {
+                                                       const T* __restrict__ eval, const T* __restrict__ inv,
+                                                       int* ncount, const TR* rhs, T* out, T* ext, TR* reset_rhs,
+                                                       int* abort_flag, uint64_t limit) {
   extern __shared__ __align__(16) unsigned char tree_smem[];
   T* y = reinterpret_cast<T*>(tree_smem);
   const int* tk = task + 8 * (size_t)blockIdx.x;
   const int kind = tk[0], lo = tk[1], s = tk[2];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   if (kind == 0) {
     // ------------------------------------------------------------ helper
     // rows [r0, r1) of the node: ext[r] = rhs[r] - sum over entries outside
     // the node, G lanes per row, TREE_BATCH loads in flight per lane, pending
     // values polled as a group
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r0 = tk[3], r1 = tk[4], lg = tk[7];
     const int G = 1 << lg, per_wave = 64 >> lg;
     const int slot = lane >> lg, sub = lane & (G - 1);
@@ -124,86 +114,79 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
     return;
   }
 
-  // -------------------------------------------------------------- node
-  const int has_ext = tk[6];
-  const T* B = blk + boff[tk[5]];
-  // the node's right-hand side: all loads issued first, pending ones polled
+  // ------------------------------------------------------- node slice
+  // rows [a, b) of the node: x = Tinv[a:b, cols] y[cols], cols = [0, b)
+  // (lower) or [a, s) (upper); R rows per slice, G = 256 / R column groups,
+  // each thread one row and one group's columns, then a fixed-order sum of the
+  // groups' partial sums
+  const int a = tk[3], b = tk[4], node = tk[5];
+  const int has_ext = tk[6] & 1, lgR = tk[6] >> 1, nsl = tk[7];
+  const int j0 = LOWER ? 0 : a, j1 = LOWER ? b : s;
+  __shared__ T part[TREE_THREADS];
+  __shared__ int last_slice;
+  const int R = 1 << lgR, G = TREE_THREADS >> lgR;
+  const int rl = threadIdx.x & (R - 1), cg = threadIdx.x >> lgR;
+  const int i = a + rl < b ? a + rl : a;
+  const int ncol = j1 - j0, cw = (ncol + G - 1) / G;
+  const int jb = j0 + cg * cw, je = jb + cw < j1 ? jb + cw : j1;
+  const T* col = inv + boff[node] + i;  // column-major: Tinv[j][i] at j * s + i
+  // the first batch of the block's entries does not depend on the
+  // right-hand side: in flight while the inputs are awaited
+  T m[TREE_MBATCH];
+#pragma unroll
+  for (int u = 0; u < TREE_MBATCH; ++u) m[u] = jb + u < je ? col[(int64_t)(jb + u) * s] : (T)0;
+  // the slice's right-hand side: all loads issued first, pending ones polled
   // (s <= kTreeMaxRows, checked on the host)
   constexpr int YK = kTreeMaxRows / TREE_THREADS;
   {
     T v[YK];
 #pragma unroll
     for (int k = 0; k < YK; ++k) {
-      const int i = threadIdx.x + k * TREE_THREADS;
-      if (i < s) v[k] = has_ext ? ld_agent(ext + lo + i) : (T)rhs[lo + i];
+      const int r = j0 + threadIdx.x + k * TREE_THREADS;
+      if (r < j1) v[k] = has_ext ? ld_agent(ext + lo + r) : (T)rhs[lo + r];
     }
 #pragma unroll
     for (int k = 0; k < YK; ++k) {
-      const int i = threadIdx.x + k * TREE_THREADS;
-      if (i < s) {
-        if (has_ext) {
-          if (is_sentinel(v[k])) v[k] = tree_poll(ext + lo + i, abort_flag, limit);
-          st_agent(ext + lo + i, sentinel_of<T>(0));
-        } else if (reset_rhs) {
-          reset_rhs[lo + i] = sentinel_of<TR>(0);
-        }
-        y[i] = v[k];
+      const int r = j0 + threadIdx.x + k * TREE_THREADS;
+      if (r < j1) {
+        if (has_ext && is_sentinel(v[k])) v[k] = tree_poll(ext + lo + r, abort_flag, limit);
+        y[r - j0] = v[k];
       }
     }
   }
   __syncthreads();
-  const int np = (s + 63) / 64;
-  for (int pi = 0; pi < np; ++pi) {
-    // lower: panels top-down, columns left to right; upper: bottom-up,
-    // columns right to left
-    const int p0 = LOWER ? pi * 64 : std::max(0, s - (pi + 1) * 64);
-    const int pw = LOWER ? std::min(64, s - p0) : (s - pi * 64) - p0;
-    if (wave == 0) {
-      const bool in = lane < pw;
-      T yl = in ? y[p0 + lane] : (T)0;
-      const T dl = DIAG ? (in ? dinv[lo + p0 + lane] : (T)0) : (T)1;
-      // row p0 + lane of the panel: columns p0 .. p0 + pw - 1
-      T b[64];
-#pragma unroll
-      for (int j = 0; j < 64; ++j) {
-        const int jj = j < pw ? j : pw - 1;
-        b[j] = B[(int64_t)(p0 + jj) * s + p0 + (in ? lane : 0)];
-      }
-      // columns in solve order; fully unrolled so that b[] stays in registers
-      // (the bound pw is the same for the whole wave)
-#pragma unroll
-      for (int jr = 0; jr < 64; ++jr) {
-        const int j = LOWER ? jr : 63 - jr;
-        if (j < pw) {
-          const T xj = bcast_lane(DIAG ? yl * dl : yl, j);
-          yl -= b[j] * xj;  // zero in the other triangle: finished rows keep their value
-        }
-      }
-      if (in) {
-        T x = DIAG ? yl * dl : yl;
-        if (is_sentinel(x)) x = (T)__builtin_nan("");
-        y[p0 + lane] = x;
-        st_agent(out + lo + p0 + lane, x);
-      }
+  // the last slice of the node to get here resets what the slices read (the
+  // counter is left at zero for the next solve)
+  if (threadIdx.x == 0) {
+    const int t = atomicAdd(ncount + node, 1);
+    last_slice = t == nsl - 1;
+    if (last_slice) st_agent(ncount + node, 0);
+  }
+  __syncthreads();
+  if (last_slice) {
+    for (int r = threadIdx.x; r < s; r += TREE_THREADS) {
+      if (has_ext) st_agent(ext + lo + r, sentinel_of<T>(0));
+      else if (reset_rhs) reset_rhs[lo + r] = sentinel_of<TR>(0);
     }
-    __syncthreads();
-    // apply the panel to the rows still to be solved: one row per thread, the
-    // panel's 64 entries of the row loaded together (a chain of dependent
-    // loads would cost one memory round trip per column), then subtracted in
-    // column order
-    const int ra = LOWER ? p0 + pw : 0, rz = LOWER ? s : p0;
-    for (int r = ra + threadIdx.x; r < rz; r += TREE_THREADS) {
-      const T* col = B + (int64_t)p0 * s + r;
-      T bb[64];
+  }
+  T acc = (T)0;
 #pragma unroll
-      for (int j = 0; j < 64; ++j) bb[j] = col[(int64_t)(j < pw ? j : pw - 1) * s];
-      T acc = y[r];
+  for (int u = 0; u < TREE_MBATCH; ++u)
+    if (jb + u < je) acc += m[u] * y[jb + u - j0];
+  for (int j = jb + TREE_MBATCH; j < je; j += TREE_MBATCH) {
 #pragma unroll
-      for (int j = 0; j < 64; ++j)
-        if (j < pw) acc -= bb[j] * y[p0 + j];
-      y[r] = acc;
-    }
-    __syncthreads();
+    for (int u = 0; u < TREE_MBATCH; ++u) m[u] = col[(int64_t)(j + u < je ? j + u : je - 1) * s];
+#pragma unroll
+    for (int u = 0; u < TREE_MBATCH; ++u)
+      if (j + u < je) acc += m[u] * y[j + u - j0];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < R && a + (int)threadIdx.x < b) {
+    T x = (T)0;
+    for (int g = 0; g < G; ++g) x += part[g * R + threadIdx.x];
+    if (is_sentinel(x)) x = (T)__builtin_nan("");
+    st_agent(out + lo + a + threadIdx.x, x);
   }
 }
 
@@ -227,31 +210,25 @@ void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, 
   if (ts.ntasks == 0) return;
   constexpr bool F32 = sizeof(T) == 4;
   const T* ev = F32 ? (const T*)ts.eval32.p : (const T*)ts.eval.p;
-  const T* bk = F32 ? (const T*)ts.blk32.p : (const T*)ts.blk.p;
-  const T* di = F32 ? (const T*)ts.dinv32.p : (const T*)ts.dinv.p;
+  const T* iv = F32 ? (const T*)ts.inv32.p : (const T*)ts.inv.p;
   const size_t lds = (size_t)ts.max_rows * sizeof(T);
   const uint64_t lim = tree_limit_ticks();
-#define GMG_TREE(TR_, LO_, DG_, RHS_, RESET_)                                                                       \
+#define GMG_TREE(TR_, LO_, RHS_, RESET_)                                                                           \
   do {                                                                                                             \
     static bool attr = false;                                                                                      \
     if (!attr) {                                                                                                   \
-      HIPCK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tree<T, TR_, LO_, DG_>),                          \
+      HIPCK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tree<T, TR_, LO_>),                               \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kTreeMaxRows * sizeof(double)))); \
       attr = true;                                                                                                 \
     }                                                                                                              \
-    hipLaunchKernelGGL((k_tree<T, TR_, LO_, DG_>), dim3(ts.ntasks), dim3(TREE_THREADS), lds, s, ts.task.p,        \
-                       ts.boff.p, ts.erp.p, ts.ecol.p, ev, bk, di, (const TR_*)RHS_, out, ext, RESET_, abort_flag,  \
+    hipLaunchKernelGGL((k_tree<T, TR_, LO_>), dim3(ts.ntasks), dim3(TREE_THREADS), lds, s, ts.task.p, ts.boff.p,   \
+                       ts.erp.p, ts.ecol.p, ev, iv, ts.ncount.p, (const TR_*)RHS_, out, ext, RESET_, abort_flag,    \
                        lim);                                                                                       \
   } while (0)
-#define GMG_TREE_RHS(TR_, RHS_, RESET_)                                        \
-  do {                                                                         \
-    if (ts.lower) {                                                            \
-      if (ts.has_diag) GMG_TREE(TR_, true, true, RHS_, RESET_);                \
-      else GMG_TREE(TR_, true, false, RHS_, RESET_);                           \
-    } else {                                                                   \
-      if (ts.has_diag) GMG_TREE(TR_, false, true, RHS_, RESET_);               \
-      else GMG_TREE(TR_, false, false, RHS_, RESET_);                          \
-    }                                                                          \
+#define GMG_TREE_RHS(TR_, RHS_, RESET_)                \
+  do {                                                 \
+    if (ts.lower) GMG_TREE(TR_, true, RHS_, RESET_);   \
+    else GMG_TREE(TR_, false, RHS_, RESET_);           \
   } while (0)
   if (rhs_is_f64 && F32) GMG_TREE_RHS(double, rhs, (double*)nullptr);
   else GMG_TREE_RHS(T, rhs, reset_rhs);
@@ -261,5 +238,109 @@ void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, 
 }
 template void launch_tree<double>(const TreeSolve&, const void*, bool, double*, double*, double*, int*, hipStream_t);
 template void launch_tree<float>(const TreeSolve&, const void*, bool, float*, float*, float*, int*, hipStream_t);
+
+// ---------------------------------------------------------------- setup
+// Inverse of a node's diagonal block T (unit diagonal, or diagonal 1/dinv):
+// Tinv = T^{-1} by substitution on W columns of the identity at once (one
+// workgroup per W-column chunk).  The chunk's unknowns X (rows x W) live in
+// LDS; step k takes row k in elimination order (lower: ascending, upper:
+// descending), finishes it, x_k = d_k X[k], stores it, and subtracts
+// T[i][k] x_k from the rows i still to come.  The column of T that the next
+// step needs is loaded during the current one and staged in LDS.
+// itask[8t ..]: lo, s, c0, node, log2 W
+template <bool LOWER, bool DIAG>
+__global__ __launch_bounds__(TREE_THREADS) void k_tree_inv(const int* __restrict__ itask,
+                                                           const int64_t* __restrict__ boff,
+                                                           const double* __restrict__ blk,
+                                                           const double* __restrict__ dinv, double* __restrict__ inv) {
+  extern __shared__ __align__(16) unsigned char inv_smem[];
+  const int* t = itask + 8 * (size_t)blockIdx.x;
+  const int lo = t[0], s = t[1], c0 = t[2], node = t[3], lgW = t[4];
+  const int W = 1 << lgW, RG = TREE_THREADS >> lgW;
+  const int w = W < s - c0 ? W : s - c0;
+  const int rbeg = LOWER ? c0 : 0, rend = LOWER ? s : c0 + w;
+  const int nr = rend - rbeg;
+  double* X = reinterpret_cast<double*>(inv_smem);  // X[(i - rbeg) * W + c]
+  double* Tc = X + (size_t)nr * W;                   // two staged columns of T
+  const double* Tb = blk + boff[node];
+  double* M = inv + boff[node];
+  const int c = threadIdx.x & (W - 1), g = threadIdx.x >> lgW;
+  for (int q = threadIdx.x; q < nr * W; q += TREE_THREADS) X[q] = (rbeg + (q >> lgW) == c0 + (q & (W - 1))) ? 1.0 : 0.0;
+  // rows of column k still to come: lower (k, rend), upper [rbeg, k)
+  constexpr int PK = kTreeMaxRows / TREE_THREADS;
+  auto row_at = [&](int k, int u) { return (LOWER ? k + 1 : rbeg) + (int)threadIdx.x + u * TREE_THREADS; };
+  auto in_col = [&](int k, int i) { return LOWER ? i < rend : i < k; };
+  {
+    const int k = LOWER ? rbeg : rend - 1;
+#pragma unroll
+    for (int u = 0; u < PK; ++u) {
+      const int i = row_at(k, u);
+      if (in_col(k, i)) Tc[i - rbeg] = Tb[(int64_t)k * s + i];
+    }
+  }
+  __syncthreads();
+  for (int step = 0; step < nr; ++step) {
+    const int k = LOWER ? rbeg + step : rend - 1 - step;
+    const double* cur = Tc + (size_t)(step & 1) * nr;
+    double* nxt = Tc + (size_t)((step + 1) & 1) * nr;
+    // next column's loads in flight during this step's update
+    const int kn = LOWER ? k + 1 : k - 1;
+    const bool more = step + 1 < nr;
+    double pre[PK];
+#pragma unroll
+    for (int u = 0; u < PK; ++u) {
+      const int i = row_at(kn, u);
+      pre[u] = (more && in_col(kn, i)) ? Tb[(int64_t)kn * s + i] : 0.0;
+    }
+    const double xk = (DIAG ? dinv[lo + k] : 1.0) * X[(k - rbeg) * W + c];
+    if (g == 0 && c < w) M[(int64_t)(c0 + c) * s + k] = xk;
+    if (LOWER) {
+      for (int i = k + 1 + g; i < rend; i += RG) X[(i - rbeg) * W + c] -= cur[i - rbeg] * xk;
+    } else {
+      for (int i = rbeg + g; i < k; i += RG) X[(i - rbeg) * W + c] -= cur[i - rbeg] * xk;
+    }
+#pragma unroll
+    for (int u = 0; u < PK; ++u) {
+      const int i = row_at(kn, u);
+      if (more && in_col(kn, i)) nxt[i - rbeg] = pre[u];
+    }
+    __syncthreads();
+  }
+}
+
+size_t tree_inv_lds(int rows, int lgW) { return (size_t)rows * ((1 << lgW) + 2) * sizeof(double); }
+
+int tree_inv_width(int rows) {
+  // the widest chunk (at most 64 columns) whose LDS fits kTreeInvLds
+  for (int lg = 6; lg > 0; --lg)
+    if (tree_inv_lds(rows, lg) <= kTreeInvLds) return lg;
+  return 0;
+}
+
+void launch_tree_invert(const TreeSolve& ts, const int* itask, int ntask, size_t lds, const double* blk,
+                        const double* dinv, double* inv, hipStream_t s) {
+  if (ntask == 0) return;
+  if (lds > kTreeInvLds) fail(GMG_ERR_INVALID_ARG, "tree inverse: LDS request too large");
+#define GMG_INV(LO_, DG_)                                                                                     \
+  do {                                                                                                        \
+    static bool attr = false;                                                                                 \
+    if (!attr) {                                                                                              \
+      HIPCK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tree_inv<LO_, DG_>),                         \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTreeInvLds));               \
+      attr = true;                                                                                            \
+    }                                                                                                         \
+    hipLaunchKernelGGL((k_tree_inv<LO_, DG_>), dim3(ntask), dim3(TREE_THREADS), lds, s, itask, ts.boff.p, blk, \
+                       dinv, inv);                                                                            \
+  } while (0)
+  if (ts.lower) {
+    if (dinv) GMG_INV(true, true);
+    else GMG_INV(true, false);
+  } else {
+    if (dinv) GMG_INV(false, true);
+    else GMG_INV(false, false);
+  }
+#undef GMG_INV
+  HIPCK(hipGetLastError());
+}
 
 }  // namespace gmg
