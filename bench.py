@@ -52,7 +52,8 @@ WORKLOAD_DESC = {
 
 
 # measured HBM traffic per launch of a kernel class (from rocprofv3 --pmc runs)
-TRAFFIC_FILES = {"sweep_coarse": "profiles/pmc_traffic_sweep_coarse_fv2d_1024.md"}
+TRAFFIC_FILES = {"ortho": "profiles/pmc_traffic_ortho_fv2d_1024.md",
+                 "sweep_coarse": "profiles/pmc_traffic_sweep_coarse_fv2d_1024.md"}
 
 
 def _source_digest(paths):
