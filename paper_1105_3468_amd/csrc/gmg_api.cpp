@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gmg_internal.h"
@@ -196,12 +197,31 @@ static void make_segments(Sweep& sw, const std::vector<int>& level_c0, const std
   }
 }
 
-// Lay a triangular factor out for the tree solve (k_tree.hip).  Returns false
-// (and leaves ts empty) when the factor does not follow the tree: an entry
-// outside its row's node must point into a descendant node (lower) or an
-// ancestor node (upper), and every node must fit kTreeMaxRows rows.
-static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, const std::vector<int>& dep_rp,
-                       const std::vector<int>& dep_ci, const std::vector<int>& dep_src,
+// Runs f(begin, end, thread) over [0, n) split into one contiguous range per
+// host thread (one range when n is small).
+template <class F>
+static void parallel_ranges(int n, F&& f) {
+  const int nt = std::max(1, std::min(host_threads(), n / 4096));
+  if (nt == 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&f, n, nt, t] { f((int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt), t); });
+  for (auto& th : pool) th.join();
+}
+
+// Lay a triangular factor out for the tree solve (k_tree.hip).  Row r's
+// entries are q in [rp[r] + skip, rp[r+1]) with column ci[q] and value
+// vals[src ? src[q] : q].  Returns false (and leaves ts empty) when the factor
+// does not follow the tree: an entry outside its row's node must point into a
+// descendant node (lower) or an ancestor node (upper), and every node must fit
+// kTreeMaxRows rows.  The host checks the structure and counts the outside
+// entries per row; the dense diagonal blocks and the outside-entry lists are
+// scattered on the GPU, then the blocks are inverted there.
+static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, const std::vector<int>& rp,
+                       const std::vector<int>& ci, const std::vector<int>* src, int skip,
                        const std::vector<double>& vals, bool lower, const std::vector<double>* dinv,
                        hipStream_t s) {
   constexpr int kHelperEntries = 2048, kHelperRows = 256;
@@ -209,11 +229,13 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
   constexpr size_t kSmallInvLds = 40 * 1024;  // inversion chunks launched with this much LDS or less first
   const int nn = (int)tree.size();
   if (nn == 0 || n <= 0) return false;
-  std::vector<int> node_of(n, -1);
+  std::vector<int> node_of(n, -1), nlo(nn), nsz(nn);
   int max_rows = 0, max_h = 0;
   for (int k = 0; k < nn; ++k) {
     const NdNode& d = tree[k];
     if (d.hi - d.lo > kTreeMaxRows) return false;
+    nlo[k] = d.lo;
+    nsz[k] = d.hi - d.lo;
     max_rows = std::max(max_rows, d.hi - d.lo);
     max_h = std::max(max_h, d.height);
     for (int r = d.lo; r < d.hi; ++r) node_of[r] = k;
@@ -238,35 +260,31 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
     }
   }
   auto desc = [&](int x, int y) { return tin[y] <= tin[x] && tin[x] < tout[y]; };
-  // entries outside the row's node (CSR over rows) and the diagonal blocks
-  std::vector<int> erp(n + 1, 0), ecol;
-  std::vector<double> eval;
-  std::vector<int64_t> boff(nn, 0);
+  // outside entries per row, and the structure check
+  std::vector<int> erp(n + 1, 0);
+  std::vector<char> bad(std::max(1, std::min(host_threads(), n / 4096)), 0);
+  parallel_ranges(n, [&](int r0, int r1, int t) {
+    for (int r = r0; r < r1; ++r) {
+      const int a = node_of[r];
+      int cnt = 0;
+      for (int q = rp[r] + skip; q < rp[r + 1]; ++q) {
+        const int b = node_of[ci[q]];
+        if (b == a) continue;
+        if (!(lower ? desc(b, a) : desc(a, b))) bad[t] = 1;
+        ++cnt;
+      }
+      erp[r + 1] = cnt;
+    }
+  });
+  for (char b : bad)
+    if (b) return false;
+  for (int r = 0; r < n; ++r) erp[r + 1] += erp[r];
+  std::vector<int64_t> boff(nn, 0), node_ext(nn, 0);
   int64_t total = 0;
   for (int k = 0; k < nn; ++k) {
     boff[k] = total;
-    const int64_t sz = tree[k].hi - tree[k].lo;
-    total += sz * sz;
-  }
-  std::vector<double> blk(total > 0 ? total : 1, 0.0);
-  std::vector<int64_t> node_ext(nn, 0);
-  for (int r = 0; r < n; ++r) {
-    const int a = node_of[r];
-    const NdNode& d = tree[a];
-    const int sz = d.hi - d.lo;
-    for (int q = dep_rp[r]; q < dep_rp[r + 1]; ++q) {
-      const int c = dep_ci[q], b = node_of[c];
-      const double v = vals[dep_src[q]];
-      if (b == a) {
-        blk[boff[a] + (int64_t)(c - d.lo) * sz + (r - d.lo)] = v;
-      } else {
-        if (!(lower ? desc(b, a) : desc(a, b))) return false;
-        ecol.push_back(c);
-        eval.push_back(v);
-        node_ext[a]++;
-      }
-    }
-    erp[r + 1] = (int)ecol.size();
+    total += (int64_t)nsz[k] * nsz[k];
+    node_ext[k] = erp[tree[k].hi] - erp[tree[k].lo];
   }
   // tasks: nodes by height (lower: ascending, upper: descending), each node's
   // helpers (slices of about kHelperEntries outside entries) before it
@@ -320,7 +338,8 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
   ts.ntasks = (int)task.size() / 8;
   ts.max_rows = max_rows;
   ts.heights = max_h + 1;
-  const size_t ne = ecol.size();
+  const size_t ne = (size_t)erp[n];
+  const size_t nent = (size_t)rp[n];
   ts.task.alloc(task.size());
   ts.erp.alloc(n + 1);
   ts.ecol.alloc(ne > 0 ? ne : 1);
@@ -328,25 +347,47 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
   ts.eval32.alloc(ne > 0 ? ne : 1);
   ts.boff.alloc(nn);
   ts.ncount.alloc(nn);
-  ts.inv.alloc(blk.size());
-  ts.inv32.alloc(blk.size());
+  ts.inv.alloc(total > 0 ? total : 1);
+  ts.inv32.alloc(total > 0 ? total : 1);
   h2d(ts.task.p, task.data(), task.size(), s);
   h2d(ts.erp.p, erp.data(), n + 1, s);
-  h2d(ts.ecol.p, ecol.data(), ne, s);
-  h2d(ts.eval.p, eval.data(), ne, s);
   h2d(ts.boff.p, boff.data(), nn, s);
   HIPCK(hipMemsetAsync(ts.ncount.p, 0, sizeof(int) * nn, s));
-  launch_cast_f32(ts.eval.p, ts.eval32.p, ne, s);
   {
-    DBuf<double> dblk, ddinv;
+    // the factor's rows on the device, values in entry order
+    DBuf<int> drp, dci, dnode, dlo, dsz;
+    DBuf<double> dv, dblk, ddinv;
     DBuf<int> dit[2];
-    dblk.alloc(blk.size());
-    h2d(dblk.p, blk.data(), blk.size(), s);
+    drp.alloc(n + 1);
+    dci.alloc(nent > 0 ? nent : 1);
+    dv.alloc(nent > 0 ? nent : 1);
+    dnode.alloc(n);
+    dlo.alloc(nn);
+    dsz.alloc(nn);
+    h2d(drp.p, rp.data(), n + 1, s);
+    h2d(dci.p, ci.data(), nent, s);
+    std::vector<double> vq;
+    if (src) {
+      vq.resize(nent);
+      parallel_ranges((int)nent, [&](int q0, int q1, int) {
+        for (int q = q0; q < q1; ++q) vq[q] = vals[(*src)[q]];
+      });
+      h2d(dv.p, vq.data(), nent, s);
+    } else {
+      h2d(dv.p, vals.data(), nent, s);
+    }
+    h2d(dnode.p, node_of.data(), n, s);
+    h2d(dlo.p, nlo.data(), nn, s);
+    h2d(dsz.p, nsz.data(), nn, s);
+    dblk.alloc(total > 0 ? total : 1);
+    HIPCK(hipMemsetAsync(dblk.p, 0, sizeof(double) * (total > 0 ? total : 1), s));
+    launch_tree_fill(n, drp.p, dci.p, dv.p, skip, dnode.p, dlo.p, dsz.p, ts.boff.p, ts.erp.p, dblk.p, ts.ecol.p,
+                     ts.eval.p, s);
     if (dinv) {
       ddinv.alloc(n);
       h2d(ddinv.p, dinv->data(), n, s);
     }
-    HIPCK(hipMemsetAsync(ts.inv.p, 0, sizeof(double) * blk.size(), s));
+    HIPCK(hipMemsetAsync(ts.inv.p, 0, sizeof(double) * (total > 0 ? total : 1), s));
     for (int c = 0; c < 2; ++c) {
       if (itask[c].empty()) continue;
       dit[c].alloc(itask[c].size());
@@ -354,7 +395,8 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
       launch_tree_invert(ts, dit[c].p, (int)itask[c].size() / 8, ilds[c], dblk.p, dinv ? ddinv.p : nullptr,
                          ts.inv.p, s);
     }
-    launch_cast_f32(ts.inv.p, ts.inv32.p, blk.size(), s);
+    launch_cast_f32(ts.eval.p, ts.eval32.p, ne, s);
+    launch_cast_f32(ts.inv.p, ts.inv32.p, total, s);
     HIPCK(hipStreamSynchronize(s));  // host vectors and staging buffers go out of scope
   }
   return true;
@@ -770,8 +812,8 @@ static void ensure_adjoint(Solver& S) {
     }
     // the transposes of tree-following factors follow the tree too (an entry
     // into a descendant becomes one into an ancestor); checked all the same
-    S.tree_adj = S.tree && build_tree(S.tUct, S.nd_tree, nc, uct_cnt, uct_ci, uct_src, U.v, true, &udinv, s) &&
-                 build_tree(S.tLct, S.nd_tree, nc, lct_cnt, lct_ci, lct_src, L.v, false, nullptr, s);
+    S.tree_adj = S.tree && build_tree(S.tUct, S.nd_tree, nc, uct_cnt, uct_ci, &uct_src, 0, U.v, true, &udinv, s) &&
+                 build_tree(S.tLct, S.nd_tree, nc, lct_cnt, lct_ci, &lct_src, 0, L.v, false, nullptr, s);
     if (S.tree_adj) {
       S.Uct.n = S.Lct.n = nc;
       S.Uct.nnz = (int64_t)uct_ci.size();
@@ -1362,33 +1404,34 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   {
     const int nc = S.nc;
     const HCsr &L = S.hLc, &U = S.hUc;
-    std::vector<int> lsrc(L.ci.size()), us_rp(nc + 1, 0), us_ci, us_src;
-    for (size_t q = 0; q < L.ci.size(); ++q) lsrc[q] = (int)q;
     std::vector<double> udinv(nc);
-    for (int i = 0; i < nc; ++i) {
-      udinv[i] = 1.0 / U.v[U.rp[i]];
-      for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) { us_ci.push_back(U.ci[q]); us_src.push_back(q); }
-      us_rp[i + 1] = (int)us_ci.size();
-    }
+    for (int i = 0; i < nc; ++i) udinv[i] = 1.0 / U.v[U.rp[i]];
     // tree solves when the coarse unknowns are in nested-dissection order and
-    // both factors follow the tree; else the level-scheduled sweeps
+    // both factors follow the tree (U without its leading diagonal entries);
+    // else the level-scheduled sweeps
     S.tree = false;
     if (o.sweep_kernel == 0 && o.coarse_order == 1 && !S.nd_tree.empty() &&
-        build_tree(S.tLc, S.nd_tree, nc, L.rp, L.ci, lsrc, L.v, true, nullptr, s) &&
-        build_tree(S.tUc, S.nd_tree, nc, us_rp, us_ci, us_src, U.v, false, &udinv, s)) {
+        build_tree(S.tLc, S.nd_tree, nc, L.rp, L.ci, nullptr, 0, L.v, true, nullptr, s) &&
+        build_tree(S.tUc, S.nd_tree, nc, U.rp, U.ci, nullptr, 1, U.v, false, &udinv, s)) {
       S.tree = true;
       S.text.alloc(nc);
       S.text32.alloc(nc);
       // sizes and depths (profiling byte counts, info)
       S.Lc.n = S.Uc.n = nc;
       S.Lc.nnz = (int64_t)L.ci.size();
-      S.Uc.nnz = (int64_t)us_ci.size();
+      S.Uc.nnz = (int64_t)U.ci.size() - nc;
       S.Uc.has_diag = true;
       S.Lc.levels = S.Uc.levels = S.tLc.heights;
       phase("coarse tree solves");
     } else {
       S.tLc = TreeSolve();
       S.tUc = TreeSolve();
+      std::vector<int> lsrc(L.ci.size()), us_rp(nc + 1, 0), us_ci, us_src;
+      for (size_t q = 0; q < L.ci.size(); ++q) lsrc[q] = (int)q;
+      for (int i = 0; i < nc; ++i) {
+        for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) { us_ci.push_back(U.ci[q]); us_src.push_back(q); }
+        us_rp[i + 1] = (int)us_ci.size();
+      }
       build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
       build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
       phase("coarse sweeps");

@@ -180,6 +180,11 @@ void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, 
 // columns of one node), with `lds` bytes of LDS (tree_inv_lds of each task,
 // at most kTreeInvLds).
 constexpr size_t kTreeInvLds = 128 * 1024;
+// Setup: dense diagonal blocks (zeroed beforehand) and outside-entry lists of
+// a factor whose row r holds entries [rp[r] + skip, rp[r+1]).
+void launch_tree_fill(int n, const int* rp, const int* ci, const double* v, int skip, const int* node_of,
+                      const int* nlo, const int* nsz, const int64_t* boff, const int* erp, double* blk, int* ecol,
+                      double* eval, hipStream_t s);
 size_t tree_inv_lds(int rows, int lgW);
 int tree_inv_width(int rows);
 void launch_tree_invert(const TreeSolve& ts, const int* itask, int ntask, size_t lds, const double* blk,

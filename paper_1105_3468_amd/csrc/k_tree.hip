@@ -343,4 +343,39 @@ void launch_tree_invert(const TreeSolve& ts, const int* itask, int ntask, size_t
   HIPCK(hipGetLastError());
 }
 
+// Setup: scatter a factor's rows (entries q in [rp[r] + skip, rp[r+1])) into
+// the dense column-major diagonal blocks (entries inside the row's node) and
+// the outside-entry lists (erp from the host's count of the same test), one
+// thread per row.
+__global__ void k_tree_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const double* __restrict__ v, int skip, const int* __restrict__ node_of,
+                            const int* __restrict__ nlo, const int* __restrict__ nsz,
+                            const int64_t* __restrict__ boff, const int* __restrict__ erp,
+                            double* __restrict__ blk, int* __restrict__ ecol, double* __restrict__ eval) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int a = node_of[r], lo = nlo[a], sz = nsz[a];
+  double* B = blk + boff[a];
+  int e = erp[r];
+  for (int q = rp[r] + skip; q < rp[r + 1]; ++q) {
+    const int c = ci[q];
+    if (node_of[c] == a) {
+      B[(int64_t)(c - lo) * sz + (r - lo)] = v[q];
+    } else {
+      ecol[e] = c;
+      eval[e] = v[q];
+      ++e;
+    }
+  }
+}
+
+void launch_tree_fill(int n, const int* rp, const int* ci, const double* v, int skip, const int* node_of,
+                      const int* nlo, const int* nsz, const int64_t* boff, const int* erp, double* blk, int* ecol,
+                      double* eval, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_tree_fill, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, ci, v, skip, node_of, nlo, nsz, boff,
+                     erp, blk, ecol, eval);
+  HIPCK(hipGetLastError());
+}
+
 }  // namespace gmg
