@@ -17,11 +17,13 @@ constexpr int KGRID = 512;       // blocks of the reduction kernels
 constexpr int KMAX = 32;         // vectors per fused register-resident pass
 constexpr int KLDS = 2048;       // vectors per LDS-staged pass (longest basis)
 // many-vector passes (a basis longer than KMAX)
-constexpr int MROWS = 16;         // rows per chunk
-constexpr int MG = KB / MROWS;    // vector groups per block
-constexpr int MGRID = 512;        // blocks
-constexpr int MMAX = 640;         // longest basis they take
+constexpr int MKB = 512;          // threads per block
+constexpr int MROWS = 64;         // rows per chunk (two per thread)
+constexpr int MG = MKB / (MROWS / 2);  // vector groups per block
+constexpr int MGRID = 256;        // blocks (one per CU)
+constexpr int MMAX = 384;         // longest basis they take (24 vectors per thread group)
 constexpr int MPARTS = 32;        // thread groups adding the block partials of one vector
+constexpr int MPIPE = 16;         // up to this many vectors per thread, the next chunk is loaded early
 
 // Keeps the machine scheduler from sinking the loads issued above it into the
 // arithmetic below: without it the compiler reuses one register pair for all
@@ -311,17 +313,21 @@ void launch_update_many(const double* V, size_t ld, int k, const double* h, doub
 
 // ----------------------------------------------------- many-vector passes
 // For a basis longer than one register-resident pass: rows are taken in
-// chunks of MROWS; thread (r, g) of a block holds row r of the chunk for the
-// basis vectors g, g + MG, g + 2 MG, ... (PER of them, loads all in flight)
-// and keeps their running dot products in registers across chunks.  The
-// block's per-vector sums (over r, in order) go to mpart[block][k]; a second
-// kernel adds the blocks in order.
+// chunks of MROWS; thread (r, g) of a block holds rows 2r and 2r + 1 of the
+// chunk (one 16-byte load) for the basis vectors g, g + MG, g + 2 MG, ...
+// (PER of them, loads all in flight) and keeps their running dot products in
+// registers across chunks.  A chunk reads 512 contiguous bytes of each
+// vector: shorter segments of many vectors 8 MB apart cost HBM efficiency.
+// The block's per-vector sums (over r, in order) go to mpart[block][k]; a
+// second kernel adds the blocks in order.  Rows at or past n (the padding up
+// to ld, which is a multiple of 64) are loaded but count as zero.
+constexpr int MRT = MROWS / 2;    // threads along a chunk's rows
 
 template <int PER>
 __device__ __forceinline__ void many_block_sums(const double (&acc)[PER], int kc, double* mpart) {
   // acc[u] of thread (r, g) belongs to vector g + MG u; sum over r in order
-  __shared__ double red[MROWS][MG + 1];
-  const int r = threadIdx.x % MROWS, g = threadIdx.x / MROWS;
+  __shared__ double red[MRT][MG + 1];
+  const int r = threadIdx.x % MRT, g = threadIdx.x / MRT;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     if (MG * u >= kc) break;  // the same for every thread of the block
@@ -329,7 +335,7 @@ __device__ __forceinline__ void many_block_sums(const double (&acc)[PER], int kc
     __syncthreads();
     if (threadIdx.x < MG) {
       double t = 0.0;
-      for (int q = 0; q < MROWS; ++q) t += red[q][threadIdx.x];
+      for (int q = 0; q < MRT; ++q) t += red[q][threadIdx.x];
       const int k = threadIdx.x + MG * u;
       if (k < kc) mpart[(size_t)blockIdx.x * MMAX + k] = t;
     }
@@ -337,72 +343,133 @@ __device__ __forceinline__ void many_block_sums(const double (&acc)[PER], int kc
   }
 }
 
-// h[k] = V[k] . w for k < kc (block partials)
+// the two rows of thread r in chunk c of V's vector k (zero past n)
+__device__ __forceinline__ double2 many_load(const double* __restrict__ V, size_t ld, int k, int64_t i, int64_t n,
+                                             bool ok) {
+  double2 x = ok ? *reinterpret_cast<const double2*>(V + (size_t)k * ld + i) : make_double2(0.0, 0.0);
+  if (i >= n) x.x = 0.0;
+  if (i + 1 >= n) x.y = 0.0;
+  return x;
+}
+
+// h[k] = V[k] . w for k < kc (block partials); the next chunk's loads are
+// issued before the current chunk's products
 template <int PER>
-__global__ __launch_bounds__(KB) void k_multidot_many(const double* __restrict__ V, size_t ld, int kc,
-                                                      const double* __restrict__ w, int64_t n,
-                                                      double* __restrict__ mpart) {
-  const int r = threadIdx.x % MROWS, g = threadIdx.x / MROWS;
+__global__ __launch_bounds__(MKB) void k_multidot_many(const double* __restrict__ V, size_t ld, int kc,
+                                                       const double* __restrict__ w, int64_t n,
+                                                       double* __restrict__ mpart) {
+  const int r = threadIdx.x % MRT, g = threadIdx.x / MRT;
   double acc[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) acc[u] = 0.0;
   const int64_t nch = (n + MROWS - 1) / MROWS;
-  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    const int64_t i = ch * MROWS + r;
-    if (i >= n) continue;
-    const double wi = w[i];
-    double v[PER];
+  double2 v[PER], wi;
+  auto load = [&](double2 (&x)[PER], double2& xw, int64_t c) {
+    const int64_t i = c * MROWS + 2 * r;
+    const bool ok = c < nch;
+    xw = many_load(w, 0, 0, i, n, ok);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) v[u] = g + MG * u < kc ? V[(size_t)(g + MG * u) * ld + i] : 0.0;
-    ALL_LOADS_ISSUED();
+    for (int u = 0; u < PER; ++u) x[u] = many_load(V, ld, g + MG * u, i, n, ok && g + MG * u < kc);
+  };
+  if constexpr (PER <= MPIPE) {
+    load(v, wi, blockIdx.x);
+    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+      double2 vn[PER], wn;
+      load(vn, wn, ch + gridDim.x);
+      ALL_LOADS_ISSUED();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) acc[u] += v[u] * wi;
+      for (int u = 0; u < PER; ++u) {
+        acc[u] += v[u].x * wi.x + v[u].y * wi.y;
+        v[u] = vn[u];
+      }
+      wi = wn;
+    }
+  } else {
+    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+      load(v, wi, ch);
+      ALL_LOADS_ISSUED();
+#pragma unroll
+      for (int u = 0; u < PER; ++u) acc[u] += v[u].x * wi.x + v[u].y * wi.y;
+    }
   }
   many_block_sums<PER>(acc, kc, mpart);
 }
 
-// w <- w - sum_k h[k] V[k]; block partials of V[k] . w_new
+// A barrier that orders LDS accesses only: global loads issued before it stay
+// in flight (__syncthreads would also wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// w <- w - sum_k h[k] V[k]; block partials of V[k] . w_new.  A chunk's new w
+// needs every vector group's partial sum (two barriers per chunk), so the
+// next chunk's basis values (and w) are loaded before them.
 template <int PER>
-__global__ __launch_bounds__(KB) void k_update_dot_many(const double* __restrict__ V, size_t ld, int kc,
-                                                        const double* __restrict__ h, double* __restrict__ w,
-                                                        int64_t n, double* __restrict__ mpart) {
+__global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restrict__ V, size_t ld, int kc,
+                                                         const double* __restrict__ h, double* __restrict__ w,
+                                                         int64_t n, double* __restrict__ mpart) {
   __shared__ double pr[MROWS][MG + 1];
   __shared__ double wn[MROWS];
   __shared__ double hs[MMAX];
-  const int r = threadIdx.x % MROWS, g = threadIdx.x / MROWS;
-  for (int k = threadIdx.x; k < MG * PER; k += KB) hs[k] = k < kc ? h[k] : 0.0;
+  const int r = threadIdx.x % MRT, g = threadIdx.x / MRT;
+  for (int k = threadIdx.x; k < MG * PER; k += MKB) hs[k] = k < kc ? h[k] : 0.0;
   __syncthreads();
   double acc[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) acc[u] = 0.0;
   const int64_t nch = (n + MROWS - 1) / MROWS;
+  double2 v[PER];
+  auto load = [&](double2 (&x)[PER], int64_t c) {
+    const int64_t i = c * MROWS + 2 * r;
+    const bool ok = c < nch;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) x[u] = many_load(V, ld, g + MG * u, i, n, ok && g + MG * u < kc);
+  };
+  // threads 0..MROWS-1 also hold w of their row of the chunk (loaded one
+  // chunk ahead, like the basis values)
+  auto load_w = [&](int64_t c) {
+    const int64_t ii = c * MROWS + threadIdx.x;
+    return (threadIdx.x < MROWS && c < nch && ii < n) ? w[ii] : 0.0;
+  };
+  double wc = load_w(blockIdx.x);
+  if constexpr (PER <= MPIPE) load(v, blockIdx.x);
   for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    const int64_t i = ch * MROWS + r;
-    const bool ok = i < n;
-    double v[PER];
+    double2 vn[PER];
+    const double wnext = load_w(ch + gridDim.x);
+    if constexpr (PER <= MPIPE) load(vn, ch + gridDim.x);
+    else load(v, ch);
+    double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) v[u] = (ok && g + MG * u < kc) ? V[(size_t)(g + MG * u) * ld + i] : 0.0;
-    ALL_LOADS_ISSUED();
-    double p = 0.0;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) p += hs[g + MG * u] * v[u];
-    pr[r][g] = p;
-    __syncthreads();
+    for (int u = 0; u < PER; ++u) {
+      const double hk = hs[g + MG * u];
+      p0 += hk * v[u].x;
+      p1 += hk * v[u].y;
+    }
+    pr[2 * r][g] = p0;
+    pr[2 * r + 1][g] = p1;
+    lds_barrier();
     if (threadIdx.x < MROWS) {
       const int64_t ii = ch * MROWS + threadIdx.x;
       double t = 0.0;
       if (ii < n) {
-        t = w[ii];
+        t = wc;
         for (int q = 0; q < MG; ++q) t -= pr[threadIdx.x][q];
         w[ii] = t;
       }
       wn[threadIdx.x] = t;
     }
-    __syncthreads();
-    const double wi = wn[r];
+    wc = wnext;
+    lds_barrier();
+    const double w0 = wn[2 * r], w1 = wn[2 * r + 1];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) acc[u] += v[u] * wi;
+    for (int u = 0; u < PER; ++u) {
+      acc[u] += v[u].x * w0 + v[u].y * w1;
+      if constexpr (PER <= MPIPE) v[u] = vn[u];
+    }
   }
+  __syncthreads();
   many_block_sums<PER>(acc, kc, mpart);
 }
 
@@ -448,18 +515,17 @@ static unsigned many_grid(int64_t n) {
     const int per_ = (kc + MG - 1) / MG;                                           \
     if (per_ <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                     \
     else if (per_ <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);              \
-    else if (per_ <= 24) hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__);              \
-    else if (per_ <= 32) hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);              \
-    else hipLaunchKernelGGL(KERNEL<40>, __VA_ARGS__);                              \
+    else hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__);                              \
   } while (0)
 
+static_assert(MMAX <= 24 * MG, "the widest many-vector instance holds 24 vectors per group");
 int many_max() { return MMAX; }
 
 void launch_multidot_many(const double* V, size_t ld, int k, const double* w, int64_t n, RedWork& rw, double* result,
                           hipStream_t s) {
   if (k < 1 || k > MMAX) fail(GMG_ERR_INVALID_ARG, "multidot_many: bad vector count");
   const unsigned nb = many_grid(n);
-  GMG_MANY(k_multidot_many, k, dim3(nb), dim3(KB), 0, s, V, ld, k, w, n, rw.mpart.p);
+  GMG_MANY(k_multidot_many, k, dim3(nb), dim3(MKB), 0, s, V, ld, k, w, n, rw.mpart.p);
   hipLaunchKernelGGL(k_colsum, dim3((k + KB / MPARTS - 1) / (KB / MPARTS)), dim3(KB), 0, s, rw.mpart.p, (int)nb, k,
                      result);
   HIPCK(hipGetLastError());
@@ -469,7 +535,7 @@ void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, 
                             double* result, hipStream_t s) {
   if (k < 1 || k > MMAX) fail(GMG_ERR_INVALID_ARG, "update_dot_many: bad vector count");
   const unsigned nb = many_grid(n);
-  GMG_MANY(k_update_dot_many, k, dim3(nb), dim3(KB), 0, s, V, ld, k, h, w, n, rw.mpart.p);
+  GMG_MANY(k_update_dot_many, k, dim3(nb), dim3(MKB), 0, s, V, ld, k, h, w, n, rw.mpart.p);
   hipLaunchKernelGGL(k_colsum, dim3((k + KB / MPARTS - 1) / (KB / MPARTS)), dim3(KB), 0, s, rw.mpart.p, (int)nb, k,
                      result);
   HIPCK(hipGetLastError());
