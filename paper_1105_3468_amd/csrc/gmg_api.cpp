@@ -1305,6 +1305,24 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     galerkin(n, nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
     phase("nested dissection");
   }
+  // ---- ILUT of A_c on host threads, while the fine level is set up below
+  HCsr hAc;
+  hAc.n = S.nc;
+  hAc.rp = to_host_int(S.Ac.rp.p, S.nc + 1, s);
+  hAc.ci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
+  hAc.v.resize(S.Ac.nnz);
+  d2h(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
+  HIPCK(hipStreamSynchronize(s));
+  gmg_status ilut_st = GMG_OK;
+  struct Joiner {  // joins on every path out of the setup, failures included
+    std::thread t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } ilut_job;
+  ilut_job.t = std::thread([&S, &hAc, &ilut_st, tau = o.ilut_tau] {
+    ilut_st = host_ilut(hAc, tau, S.hLc, S.hUc, &S.nd_tree);
+  });
   // ---- host copy of A's pattern for the analysis
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
   std::vector<int> hci = to_host_int(S.A.ci.p, nnz64, s);
@@ -1365,7 +1383,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       g.nx = nx;
       g.ny = n / nx;
       g.W = (g.ny + 63) / 64;
-      g.S = (nx + 63 + 7) / 8 * 8;  // whole chunks of the wavefront kernel
+      g.S = (nx + 63 + 15) / 16 * 16;  // whole pairs of chunks of the wavefront kernel
       g.total = (int64_t)g.W * g.S * 64;
       build_wave(S.wL0, g, l_rp, l_ci, l_src, true, S.ilu.p, nnz64, nullptr, n, s);
       build_wave(S.wU0, g, u_rp, u_ci, u_src, false, S.ilu.p, nnz64, S.u0dinv.p, n, s);
@@ -1386,21 +1404,15 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
     phase("fine sweeps");
   }
-  // ---- ILUT of A_c on the host
+  // ---- the ILUT started above
+  ilut_job.t.join();
   {
-    HCsr hAc;
-    hAc.n = S.nc;
-    hAc.rp = to_host_int(S.Ac.rp.p, S.nc + 1, s);
-    hAc.ci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
-    hAc.v.resize(S.Ac.nnz);
-    d2h(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
-    HIPCK(hipStreamSynchronize(s));
-    gmg_status st = host_ilut(hAc, o.ilut_tau, S.hLc, S.hUc, &S.nd_tree);
+    const gmg_status st = ilut_st;
     if (st == GMG_ERR_ZERO_PIVOT) fail(st, "ILUT: zero pivot");
     if (st == GMG_ERR_OOM) fail(st, "ILUT: factor exceeds int32 indexing");
     if (st != GMG_OK) fail(st, "ILUT: non-finite pivot");
   }
-  phase("coarse ILUT");
+  phase("coarse ILUT (rest after the fine level)");
   {
     const int nc = S.nc;
     const HCsr &L = S.hLc, &U = S.hUc;

@@ -147,14 +147,13 @@ int ilut_rows(const HCsr& A, double tau, int lo, int hi, const std::vector<int>&
 }  // namespace
 
 int host_threads() {
-  static int t = 0;
-  if (!t) {
+  static const int t = [] {
     const char* e = std::getenv("GMG_THREADS");
     if (!e || !*e) e = std::getenv("OMP_NUM_THREADS");
     int v = e ? std::atoi(e) : 0;
     if (v <= 0) v = (int)std::thread::hardware_concurrency();
-    t = std::max(1, std::min(v, 64));
-  }
+    return std::max(1, std::min(v, 64));
+  }();
   return t;
 }
 
@@ -211,9 +210,17 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
     for (int k = 0; k < nt; ++k)
       if (parent[k] >= 0) waiting[parent[k]]++;
     std::vector<char> poisoned(nt, 0);
-    std::vector<int> ready;
+    // ready nodes by the estimated length of their path to the root (a node
+    // costs about rows^1.5 here), longest first; a parent precedes its
+    // children in the task order
+    std::vector<double> prio(nt, 0.0);
+    for (int k = 0; k < nt; ++k) {
+      const double rows = (double)(hi[k] - lo[k]);
+      prio[k] = rows * std::sqrt(rows) + (parent[k] >= 0 && parent[k] < k ? prio[parent[k]] : 0.0);
+    }
+    std::priority_queue<std::pair<double, int>> ready;
     for (int k = 0; k < nt; ++k)
-      if (waiting[k] == 0) ready.push_back(k);
+      if (waiting[k] == 0) ready.push({prio[k], k});
     int remaining = nt;
     std::mutex mu;
     std::condition_variable cv;
@@ -223,8 +230,8 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
       for (;;) {
         cv.wait(lk, [&] { return !ready.empty() || remaining == 0; });
         if (ready.empty()) return;
-        const int k = ready.back();
-        ready.pop_back();
+        const int k = ready.top().second;
+        ready.pop();
         const bool skip = poisoned[k] != 0;
         lk.unlock();
         int fr = -1;
@@ -237,7 +244,7 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
         if (p >= 0) {
           // a failed row leaves its ancestors unfactored (they would read it)
           if (skip || fr >= 0) poisoned[p] = 1;
-          if (--waiting[p] == 0) ready.push_back(p);
+          if (--waiting[p] == 0) ready.push({prio[p], p});
         }
         --remaining;
         cv.notify_all();

@@ -17,7 +17,7 @@
 // its operands into an LDS ring ahead of it.
 //
 // Positions p = (w * S + s) * 64 + l (S = nx + 63 steps per wave, rounded up
-// to whole chunks of the kernel below) hold the
+// to whole pairs of chunks of the kernel below) hold the
 // operands of step s of lane l, so every step reads and writes one contiguous
 // 64-element segment; positions outside the grid hold zero coefficients and
 // a zero right-hand side, which make their results zero.  The positions of
@@ -27,6 +27,7 @@
 // order with the same fused multiply-adds as the general sweep, so the
 // results are bitwise identical to it.
 #include <algorithm>
+#include <type_traits>
 
 #include "gmg_internal.h"
 #include "kcommon.h"
@@ -45,6 +46,7 @@ constexpr int WAVE_RING = 48;
 constexpr int WAVE_PRODUCERS = 2;
 constexpr int WAVE_XRING = 256;
 constexpr int WAVE_THREADS = 64 * (2 + WAVE_PRODUCERS);
+static_assert(WAVE_PRODUCERS == 2, "the consumer takes even chunks from producer 0, odd ones from producer 1");
 
 // Lane l receives lane l - 1's value v; lane 0 keeps lane0 (DPP wave_shr:1
 // without bound control leaves the destination of a lane with no source).
@@ -68,11 +70,21 @@ struct Pair<double> { using type = double2; };
 template <>
 struct Pair<float> { using type = float2; };
 
+// one step's operands of one lane in the LDS ring: the two coefficients, the
+// right-hand side and the reciprocal diagonal (two 16-byte LDS reads for FP64)
+template <class T>
+struct alignas(4 * sizeof(T)) WaveOp {
+  T cb, cl, b, d;  // coefficient of the neighbour below, of the left one
+};
+
 // Bounded wait on an LDS progress counter (relaxed loads); false when the
 // sweep is abandoned (abort flag raised, or the time limit hit here).  SLEEP:
 // back off between polls (producers ahead of the consumer must not flood the
-// LDS pipe the consumer reads its operands through).
-template <int SLEEP>
+// LDS pipe the consumer reads its operands through).  READ_ABORT: also poll
+// the abort flag; the computing wave does not (a global load on its path
+// makes the compiler wait for all of its outstanding stores where the load's
+// register is reused), so it gives up on its own time limit only.
+template <int SLEEP, bool READ_ABORT = true>
 __device__ __forceinline__ bool wait_lds_at_least(const int* ctr, int want, int* abort_flag, uint64_t limit) {
   if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want) return true;
   const uint64_t t0 = wall_clock64();
@@ -81,7 +93,7 @@ __device__ __forceinline__ bool wait_lds_at_least(const int* ctr, int want, int*
   while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < want) {
     __builtin_amdgcn_s_sleep(SLEEP);
     if ((++it & 255u) == 0) {
-      if (ld_agent(abort_flag)) return false;
+      if (READ_ABORT && ld_agent(abort_flag)) return false;
       if (wall_clock64() - t0 > limit) {
         st_agent(abort_flag, 1);
         return false;
@@ -106,14 +118,14 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
                                                        const T* __restrict__ dinv, const T* __restrict__ rhs, T* out,
                                                        int* abort_flag, uint64_t limit) {
   using P2 = typename Pair<T>::type;
-  __shared__ P2 r_coef[WAVE_RING][64];
-  __shared__ T r_b[WAVE_RING][64];
-  __shared__ T r_d[DIAG ? WAVE_RING : 1][64];
+  __shared__ WaveOp<T> r_op[WAVE_RING][64];
   __shared__ T r_x[WAVE_XRING];              // previous band's boundary values
   __shared__ int produced[WAVE_PRODUCERS];  // chunks written by each producer
   __shared__ int xready;                    // boundary values in r_x
   __shared__ int consumed;                  // steps finished by the consumer
-  const int w = blockIdx.x, l = threadIdx.x & 63, role = threadIdx.x >> 6;
+  // the role is the same for the whole wave: taken from lane 0 so the role
+  // branches are scalar and no role's pending loads reach another's code
+  const int w = blockIdx.x, l = threadIdx.x & 63, role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t p0 = (int64_t)w * S * 64 + l;
   const int nchunks = S / WAVE_CH;
   if (threadIdx.x < WAVE_PRODUCERS) produced[threadIdx.x] = 0;
@@ -193,9 +205,12 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
 #pragma unroll
         for (int u = 0; u < WAVE_CH; ++u) {
           const int st = (c * WAVE_CH + u) % WAVE_RING;
-          r_coef[st][l] = rc[dd][u];
-          r_b[st][l] = rb[dd][u];
-          if (DIAG) r_d[st][l] = rd[dd][u];
+          WaveOp<T> op;
+          op.cb = rc[dd][u].x;
+          op.cl = rc[dd][u].y;
+          op.b = rb[dd][u];
+          op.d = DIAG ? rd[dd][u] : (T)1;
+          r_op[st][l] = op;
         }
         lds_release();
         ++done;
@@ -207,75 +222,85 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
   }
 
   // ------------------------------------------------------------ consumer
-  // Chunks of WAVE_CH steps (S is a multiple of WAVE_CH): the waits of a
-  // chunk are taken once, the operands of the next chunk are read from the
-  // ring while this one computes, and its steps run without branches.
+  // Chunks of WAVE_CH steps, two at a time (S is a multiple of 2 WAVE_CH):
+  // set A holds the operands of the even chunk, set B of the odd one, each
+  // read from the ring while the other set computes, so no values are moved
+  // between registers; even chunks come from producer 0, odd ones from
+  // producer 1.  A wait that is abandoned (abort flag, time limit) only marks
+  // the sweep dead: the rest runs without waiting and its results are
+  // discarded by the host, so the loop has no early exit.
   const bool reads_prev = w > 0;
-  // progress of the producers as last read; the reads for the next check are
-  // issued a chunk ahead, so a check rarely waits on LDS
+  bool live = true;
   int seen_prod[WAVE_PRODUCERS], seen_x = 0;
 #pragma unroll
   for (int k = 0; k < WAVE_PRODUCERS; ++k) seen_prod[k] = 0;
-  P2 cf[2][WAVE_CH];
-  T bb[2][WAVE_CH], dv[2][WAVE_CH], xb[2][WAVE_CH];
-  auto take = [&](int c, int h) -> bool {
-    const int k = c % WAVE_PRODUCERS;
-    if (seen_prod[k] < c / WAVE_PRODUCERS + 1) {
-      if (!wait_lds_at_least<0>(&produced[k], c / WAVE_PRODUCERS + 1, abort_flag, limit)) return false;
-      seen_prod[k] = c / WAVE_PRODUCERS + 1;
+  WaveOp<T> opA[WAVE_CH], opB[WAVE_CH];
+  T xA[WAVE_CH], xB[WAVE_CH];
+  // wait until chunk c (of producer K) and its boundary values are in LDS,
+  // then read its operands
+  auto take = [&](auto kc, int c, WaveOp<T>(&op)[WAVE_CH], T(&xv)[WAVE_CH]) {
+    constexpr int K = decltype(kc)::value;
+    const int need_p = c / WAVE_PRODUCERS + 1;
+    if (live && seen_prod[K] < need_p) {
+      seen_prod[K] = __hip_atomic_load(&produced[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (seen_prod[K] < need_p) {
+        live = wait_lds_at_least<0, false>(&produced[K], need_p, abort_flag, limit);
+        seen_prod[K] = need_p;
+      }
     }
     const int s0 = c * WAVE_CH;
     if (reads_prev && s0 < xn) {
       const int need = std::min(s0 + WAVE_CH, xn);
-      if (seen_x < need) {
-        if (!wait_lds_at_least<0>(&xready, need, abort_flag, limit)) return false;
-        seen_x = need;
+      if (live && seen_x < need) {
+        seen_x = __hip_atomic_load(&xready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (seen_x < need) {
+          live = wait_lds_at_least<0, false>(&xready, need, abort_flag, limit);
+          seen_x = need;
+        }
       }
     }
     lds_acquire();
 #pragma unroll
     for (int u = 0; u < WAVE_CH; ++u) {
-      const int st = (s0 + u) % WAVE_RING;
-      cf[h][u] = r_coef[st][l];
-      bb[h][u] = r_b[st][l];
-      dv[h][u] = DIAG ? r_d[st][l] : (T)1;
-      xb[h][u] = r_x[(s0 + u) % WAVE_XRING];
+      op[u] = r_op[(s0 + u) % WAVE_RING][l];
+      xv[u] = r_x[(s0 + u) % WAVE_XRING];
     }
-    // progress for the next checks
-#pragma unroll
-    for (int kk = 0; kk < WAVE_PRODUCERS; ++kk)
-      seen_prod[kk] = std::max(seen_prod[kk], __hip_atomic_load(&produced[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-    if (reads_prev)
-      seen_x = std::max(seen_x, __hip_atomic_load(&xready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-    return true;
   };
   T yp = (T)0;  // this lane's result of the previous step
-  if (!take(0, 0)) return;
-  for (int c = 0; c < nchunks; c += 2) {
+  // the steps of chunk c; results stored with immediate offsets from one
+  // base, each one step later in program order so that its check and store
+  // fill the latency of the next step's chain instead of lengthening it
+  auto run = [&](int c, const WaveOp<T>(&op)[WAVE_CH], const T(&xv)[WAVE_CH]) {
+    T* ob = out + p0 + (int64_t)c * WAVE_CH * 64;
+    auto publish = [&](int u, T y) { st_agent(ob + u * 64, is_sentinel(y) ? (T)__builtin_nan("") : y); };
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int cc = c + h;
-      if (cc >= nchunks) break;
-      if (cc + 1 < nchunks && !take(cc + 1, h ^ 1)) return;
-#pragma unroll
-      for (int u = 0; u < WAVE_CH; ++u) {
-        const T upv = lane_shr1(xb[h][u], yp);
-        T acc = (T)0;
-        if (UP_FIRST) {
-          acc += cf[h][u].x * upv;
-          acc += cf[h][u].y * yp;
-        } else {
-          acc += cf[h][u].y * yp;
-          acc += cf[h][u].x * upv;
-        }
-        T y = bb[h][u] - acc;
-        if (DIAG) y *= dv[h][u];
-        st_agent(out + p0 + (int64_t)(cc * WAVE_CH + u) * 64, is_sentinel(y) ? (T)__builtin_nan("") : y);
-        yp = y;
+    for (int u = 0; u < WAVE_CH; ++u) {
+      const T upv = lane_shr1(xv[u], yp);
+      T acc = (T)0;
+      if (UP_FIRST) {
+        acc += op[u].cb * upv;
+        acc += op[u].cl * yp;
+      } else {
+        acc += op[u].cl * yp;
+        acc += op[u].cb * upv;
       }
-      lds_release();
-      if (l == 0) __hip_atomic_store(&consumed, (cc + 1) * WAVE_CH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      T y = op[u].b - acc;
+      if (DIAG) y *= op[u].d;
+      if (u > 0) publish(u - 1, yp);
+      yp = y;
     }
+    publish(WAVE_CH - 1, yp);
+    lds_release();
+    if (l == 0) __hip_atomic_store(&consumed, (c + 1) * WAVE_CH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  using K0 = std::integral_constant<int, 0>;
+  using K1 = std::integral_constant<int, 1>;
+  take(K0{}, 0, opA, xA);
+  for (int c = 0; c < nchunks; c += 2) {
+    take(K1{}, c + 1, opB, xB);
+    run(c, opA, xA);
+    if (c + 2 < nchunks) take(K0{}, c + 2, opA, xA);
+    run(c + 1, opB, xB);
   }
 }
 
@@ -329,6 +354,7 @@ void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& u
                       T* ys, T* ts, T* t, int* abort_flag, hipStream_t s) {
   constexpr bool F32 = sizeof(T) == 4;
   using P2 = typename Pair<T>::type;
+  if (g.S % (2 * WAVE_CH) != 0) fail(GMG_ERR_INVALID_ARG, "wavefront layout: steps not a multiple of two chunks");
   const unsigned gb = (unsigned)std::min<int64_t>(4096, (g.total + 255) / 256);
   if (z_f64)
     hipLaunchKernelGGL((k_wave_gather<T, double>), dim3(gb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny,
