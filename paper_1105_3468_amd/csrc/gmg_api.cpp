@@ -224,7 +224,7 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, co
                        const std::vector<int>& ci, const std::vector<int>* src, int skip,
                        const std::vector<double>& vals, bool lower, const std::vector<double>* dinv,
                        hipStream_t s) {
-  constexpr int kHelperEntries = 2048, kHelperRows = 256;
+  constexpr int kHelperEntries = 512, kHelperRows = 64;
   constexpr int kSliceLgRows = 4;             // rows per slice of a node above 64 rows: 16
   constexpr size_t kSmallInvLds = 40 * 1024;  // inversion chunks launched with this much LDS or less first
   const int nn = (int)tree.size();
