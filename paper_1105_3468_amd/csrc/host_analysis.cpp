@@ -84,64 +84,105 @@ struct IlutWork {
   explicit IlutWork(int n) : w(n > 0 ? n : 1, 0.0), state(n > 0 ? n : 1, 0) { touched.reserve(256); }
 };
 
-// factor rows lo .. hi-1 into R; returns the first failing row (or -1) and
-// its status
-int ilut_rows(const HCsr& A, double tau, int lo, int hi, const std::vector<int>& node_of,
-              std::vector<IlutNodeRows>& rows, int self, IlutWork& W, gmg_status* st) {
-  IlutNodeRows& R = rows[self];
-  for (int i = lo; i < hi; ++i) {
-    double ss = 0.0;
-    W.touched.clear();
-    for (int p = A.rp[i]; p < A.rp[i + 1]; ++p) {
-      const int j = A.ci[p];
-      ss = ss + A.v[p] * A.v[p];
-      W.w[j] = A.v[p];
-      W.state[j] = 1;
-      W.touched.push_back(j);
-      if (j < i) W.pending.push(j);
-    }
-    const double thr = tau * std::sqrt(ss);
-    if (W.state[i] == 0) { W.state[i] = 1; W.w[i] = 0.0; W.touched.push_back(i); }
-    while (!W.pending.empty()) {
-      const int k = W.pending.top();
-      W.pending.pop();
-      if (std::fabs(W.w[k]) < thr) { W.w[k] = 0.0; W.state[k] = 2; continue; }
-      const IlutNodeRows& K = rows[node_of[k]];
-      const int uk = K.urp[k - K.lo], ue = K.urp[k - K.lo + 1];
-      const int* uci = K.uci.data();
-      const double* uv = K.uv.data();
-      const double lik = W.w[k] / uv[uk];
-      W.w[k] = lik;
-      for (int r = uk + 1; r < ue; ++r) {
-        const int j = uci[r];
-        if (W.state[j] == 0) {
-          W.state[j] = 1;
-          W.w[j] = 0.0;
-          W.touched.push_back(j);
-          if (j < i) W.pending.push(j);
-        }
-        W.w[j] = W.w[j] - lik * uv[r];
-      }
-    }
-    std::sort(W.touched.begin(), W.touched.end());
-    const double d = W.w[i];
-    R.uci.push_back(i);
-    R.uv.push_back(d);
-    for (int j : W.touched) {
-      if (j < i) {
-        if (W.state[j] == 1) { R.lci.push_back(j); R.lv.push_back(W.w[j]); }
-      } else if (j > i) {
-        if (!(std::fabs(W.w[j]) < thr)) { R.uci.push_back(j); R.uv.push_back(W.w[j]); }
-      }
-      W.state[j] = 0;
-      W.w[j] = 0.0;
-    }
-    R.lrp.push_back((int)R.lci.size());
-    R.urp.push_back((int)R.uci.size());
-    if (d == 0.0) { *st = GMG_ERR_ZERO_PIVOT; return i; }
-    if (!std::isfinite(d)) { *st = GMG_ERR_NONFINITE; return i; }
+// A row's working state after the eliminations of the rows below its node.
+struct IlutRowState {
+  double thr = 0.0;
+  std::vector<int> col;
+  std::vector<double> val;
+  std::vector<signed char> st;
+};
+
+// Row i's start: A's row i in the work vector, its drop threshold, the
+// candidates k < i pending.
+double ilut_row_begin(const HCsr& A, double tau, int i, IlutWork& W) {
+  double ss = 0.0;
+  W.touched.clear();
+  for (int p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+    const int j = A.ci[p];
+    ss = ss + A.v[p] * A.v[p];
+    W.w[j] = A.v[p];
+    W.state[j] = 1;
+    W.touched.push_back(j);
+    if (j < i) W.pending.push(j);
   }
-  return -1;
+  if (W.state[i] == 0) { W.state[i] = 1; W.w[i] = 0.0; W.touched.push_back(i); }
+  return tau * std::sqrt(ss);
+}
+
+// Eliminations of the pending candidates k < until, in ascending order.
+void ilut_row_eliminate(int i, double thr, int until, const std::vector<int>& node_of,
+                        const std::vector<IlutNodeRows>& rows, IlutWork& W) {
+  while (!W.pending.empty() && W.pending.top() < until) {
+    const int k = W.pending.top();
+    W.pending.pop();
+    if (std::fabs(W.w[k]) < thr) { W.w[k] = 0.0; W.state[k] = 2; continue; }
+    const IlutNodeRows& K = rows[node_of[k]];
+    const int uk = K.urp[k - K.lo], ue = K.urp[k - K.lo + 1];
+    const int* uci = K.uci.data();
+    const double* uv = K.uv.data();
+    const double lik = W.w[k] / uv[uk];
+    W.w[k] = lik;
+    for (int r = uk + 1; r < ue; ++r) {
+      const int j = uci[r];
+      if (W.state[j] == 0) {
+        W.state[j] = 1;
+        W.w[j] = 0.0;
+        W.touched.push_back(j);
+        if (j < i) W.pending.push(j);
+      }
+      W.w[j] = W.w[j] - lik * uv[r];
+    }
+  }
+}
+
+// Save a row's state (the pending candidates are exactly its present columns
+// in [until, i)) and clear the work vector; restore it for the rest.
+void ilut_row_save(double thr, IlutWork& W, IlutRowState& R) {
+  R.thr = thr;
+  R.col.assign(W.touched.begin(), W.touched.end());
+  R.val.resize(R.col.size());
+  R.st.resize(R.col.size());
+  for (size_t q = 0; q < R.col.size(); ++q) {
+    const int j = R.col[q];
+    R.val[q] = W.w[j];
+    R.st[q] = W.state[j];
+    W.w[j] = 0.0;
+    W.state[j] = 0;
+  }
+  while (!W.pending.empty()) W.pending.pop();
+}
+double ilut_row_restore(int i, int from, const IlutRowState& R, IlutWork& W) {
+  W.touched.assign(R.col.begin(), R.col.end());
+  for (size_t q = 0; q < R.col.size(); ++q) {
+    const int j = R.col[q];
+    W.w[j] = R.val[q];
+    W.state[j] = R.st[q];
+    if (R.st[q] == 1 && j >= from && j < i) W.pending.push(j);
+  }
+  return R.thr;
+}
+
+// Row i's end: drops, the split into L and U, the work vector cleared.
+// Returns false (status in *st) on a zero or non-finite pivot.
+bool ilut_row_finish(int i, double thr, IlutWork& W, IlutNodeRows& R, gmg_status* st) {
+  std::sort(W.touched.begin(), W.touched.end());
+  const double d = W.w[i];
+  R.uci.push_back(i);
+  R.uv.push_back(d);
+  for (int j : W.touched) {
+    if (j < i) {
+      if (W.state[j] == 1) { R.lci.push_back(j); R.lv.push_back(W.w[j]); }
+    } else if (j > i) {
+      if (!(std::fabs(W.w[j]) < thr)) { R.uci.push_back(j); R.uv.push_back(W.w[j]); }
+    }
+    W.state[j] = 0;
+    W.w[j] = 0.0;
+  }
+  R.lrp.push_back((int)R.lci.size());
+  R.urp.push_back((int)R.uci.size());
+  if (d == 0.0) { *st = GMG_ERR_ZERO_PIVOT; return false; }
+  if (!std::isfinite(d)) { *st = GMG_ERR_NONFINITE; return false; }
+  return true;
 }
 
 }  // namespace
@@ -202,26 +243,67 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
   }
   std::vector<int> fail_row(nt, -1);
   std::vector<gmg_status> fail_st(nt, GMG_OK);
+  // whole rows of a node, stopping at the first failing one
+  auto full_rows = [&](int k, IlutWork& W) {
+    for (int i = lo[k]; i < hi[k]; ++i) {
+      const double thr = ilut_row_begin(A, tau, i, W);
+      ilut_row_eliminate(i, thr, i, node_of, rows, W);
+      if (!ilut_row_finish(i, thr, W, rows[k], &fail_st[k])) {
+        fail_row[k] = i;
+        return;
+      }
+    }
+  };
   if (nt == 1) {
     IlutWork W(n);
-    fail_row[0] = ilut_rows(A, tau, 0, n, node_of, rows, 0, W, &fail_st[0]);
+    full_rows(0, W);
   } else {
-    std::vector<int> waiting(nt, 0);
+    // Jobs: a node's rows in one go; or, for a large node with descendants,
+    // phase 1 (the eliminations of rows below the node, whose U rows are all
+    // final once the children are done: independent across the node's rows,
+    // so cut into chunks) and phase 2 (the node's own eliminations, row by
+    // row, from the saved states).  Each row runs the same operations in the
+    // same order either way.
+    constexpr int kSplitRows = 48, kChunkRows = 16;
+    struct Job { int kind, node, r0, r1; };  // kind 0: whole node, 1: phase 1 of rows [r0, r1), 2: phase 2
+    std::vector<Job> jobs;
+    std::vector<int> first_job(nt), n_first(nt), phase2(nt, -1), p1_left(nt, 0);
+    std::vector<std::vector<IlutRowState>> saved(nt);
+    std::vector<int> nkids(nt, 0);
     for (int k = 0; k < nt; ++k)
-      if (parent[k] >= 0) waiting[parent[k]]++;
+      if (parent[k] >= 0) nkids[parent[k]]++;
+    for (int k = 0; k < nt; ++k) {
+      first_job[k] = (int)jobs.size();
+      const int nr = hi[k] - lo[k];
+      if (nr >= kSplitRows && nkids[k] > 0) {
+        for (int r = lo[k]; r < hi[k]; r += kChunkRows) jobs.push_back({1, k, r, std::min(hi[k], r + kChunkRows)});
+        n_first[k] = (int)jobs.size() - first_job[k];
+        p1_left[k] = n_first[k];
+        phase2[k] = (int)jobs.size();
+        jobs.push_back({2, k, lo[k], hi[k]});
+        saved[k].resize(nr);
+      } else {
+        jobs.push_back({0, k, lo[k], hi[k]});
+        n_first[k] = 1;
+      }
+    }
+    std::vector<int> waiting(nkids);
     std::vector<char> poisoned(nt, 0);
-    // ready nodes by the estimated length of their path to the root (a node
-    // costs about rows^1.5 here), longest first; a parent precedes its
+    // ready jobs by the estimated length of their node's path to the root (a
+    // node costs about rows^1.5 here), longest first; a parent precedes its
     // children in the task order
     std::vector<double> prio(nt, 0.0);
     for (int k = 0; k < nt; ++k) {
-      const double rows = (double)(hi[k] - lo[k]);
-      prio[k] = rows * std::sqrt(rows) + (parent[k] >= 0 && parent[k] < k ? prio[parent[k]] : 0.0);
+      const double nr = (double)(hi[k] - lo[k]);
+      prio[k] = nr * std::sqrt(nr) + (parent[k] >= 0 && parent[k] < k ? prio[parent[k]] : 0.0);
     }
     std::priority_queue<std::pair<double, int>> ready;
+    auto node_ready = [&](int k) {
+      for (int q = 0; q < n_first[k]; ++q) ready.push({prio[k], first_job[k] + q});
+    };
     for (int k = 0; k < nt; ++k)
-      if (waiting[k] == 0) ready.push({prio[k], k});
-    int remaining = nt;
+      if (waiting[k] == 0) node_ready(k);
+    int remaining = nt;  // nodes not finished
     std::mutex mu;
     std::condition_variable cv;
     auto worker = [&]() {
@@ -230,23 +312,45 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
       for (;;) {
         cv.wait(lk, [&] { return !ready.empty() || remaining == 0; });
         if (ready.empty()) return;
-        const int k = ready.top().second;
+        const Job jb = jobs[ready.top().second];
         ready.pop();
+        const int k = jb.node;
         const bool skip = poisoned[k] != 0;
         lk.unlock();
-        int fr = -1;
-        gmg_status fs = GMG_OK;
-        if (!skip) fr = ilut_rows(A, tau, lo[k], hi[k], node_of, rows, k, W, &fs);
-        lk.lock();
-        fail_row[k] = fr;
-        fail_st[k] = fs;
-        const int p = parent[k];
-        if (p >= 0) {
-          // a failed row leaves its ancestors unfactored (they would read it)
-          if (skip || fr >= 0) poisoned[p] = 1;
-          if (--waiting[p] == 0) ready.push({prio[p], p});
+        if (!skip) {
+          if (jb.kind == 0) {
+            full_rows(k, W);
+          } else if (jb.kind == 1) {
+            for (int i = jb.r0; i < jb.r1; ++i) {
+              const double thr = ilut_row_begin(A, tau, i, W);
+              ilut_row_eliminate(i, thr, lo[k], node_of, rows, W);
+              ilut_row_save(thr, W, saved[k][i - lo[k]]);
+            }
+          } else {
+            for (int i = lo[k]; i < hi[k]; ++i) {
+              IlutRowState& R = saved[k][i - lo[k]];
+              const double thr = ilut_row_restore(i, lo[k], R, W);
+              R = IlutRowState();
+              ilut_row_eliminate(i, thr, i, node_of, rows, W);
+              if (!ilut_row_finish(i, thr, W, rows[k], &fail_st[k])) {
+                fail_row[k] = i;
+                break;
+              }
+            }
+          }
         }
-        --remaining;
+        lk.lock();
+        bool node_done = jb.kind != 1;
+        if (jb.kind == 1 && --p1_left[k] == 0) ready.push({prio[k], phase2[k]});
+        if (node_done) {
+          const int p = parent[k];
+          if (p >= 0) {
+            // a failed row leaves its ancestors unfactored (they would read it)
+            if (skip || fail_row[k] >= 0) poisoned[p] = 1;
+            if (--waiting[p] == 0) node_ready(p);
+          }
+          --remaining;
+        }
         cv.notify_all();
       }
     };
