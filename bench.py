@@ -8,7 +8,7 @@ FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
 before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-fp32]
+                       [--no-cpu-baseline] [--no-fp32] [--egmg]
        python bench.py --copy-calibration   (a plain 1 GiB device copy, run
                        under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
 
@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--workload", default="fv2d_1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--egmg", action="store_true",
+                    help="also time the exact coarse solve (ILUT tau = 0: complete LU of A_c), reported beside")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -271,6 +273,27 @@ def main():
                      if v["launches"]})
         print(f"[bench] fp32-preconditioned step: {t32:.3f}s its={r32.info['iters']}", file=sys.stderr,
               flush=True)
+
+    if args.egmg:
+        # the paper's EGMG variant: the same two-grid method with an exact
+        # coarse solve (complete LU of A_c without pivoting), one warm and one
+        # timed setup + solve in FP64
+        def egmg_step():
+            Se = Solver(rp, ci, va, cf=SOLVE_OPTS["cf"], ilut_tau=0.0)
+            xe, re = Se.solve(b, tol=TOL, restart=SOLVE_OPTS["restart"], maxit=SOLVE_OPTS["maxit"])
+            return Se, xe, re
+        egmg_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Se, xe, re = egmg_step()
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t0
+        xeh = xe.cpu().numpy()
+        out["egmg"] = dict(
+            time_s=round(te, 6), setup_ms=round(Se.setup_info["setup_ms"], 2), solve_ms=round(re.info["solve_ms"], 2),
+            iters=re.info["iters"], nnz_ilut=int(Se.setup_info["nnz_lc"] + Se.setup_info["nnz_uc"]),
+            relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xeh) / np.linalg.norm(p.b[:, 0])))
+        print(f"[bench] exact coarse solve (EGMG) step: {te:.3f}s its={re.info['iters']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -15,6 +15,7 @@ import sys
 import numpy as np
 import pytest
 import scipy.sparse as sp
+import scipy.sparse.linalg  # noqa: F401  (sp.linalg)
 
 import workloads as W
 
@@ -229,6 +230,41 @@ def test_sweep_kernels_bitwise_equal(kind):
         t = tree.apply(z, precision=prec, adjoint=adj)
         tol = 1e-12 if prec == 0 else 1e-5
         assert float(torch.linalg.norm(t - ref) / torch.linalg.norm(ref)) <= tol, (kind, prec, adj)
+
+
+@pytest.mark.parametrize("kind", ["fv2d_64", "rgg_3001"])
+def test_exact_coarse_solve(kind):
+    """Exact coarse solve (the paper's EGMG variant): ILUT with tau = 0 is the
+    complete LU of A_c without pivoting, so the preconditioner must equal the
+    two-grid operator with A_c^{-1} itself.  Reference built without the
+    oracle's ILUT: the oracle's ILU(0) smoother applied by scipy triangular
+    solves, and A_c^{-1} by numpy's pivoted dense solve."""
+    _say(f"[case] exact coarse solve {kind}")
+    p = CASES[kind]()
+    S = Solver(p.rowptr, p.col, p.val, ilut_tau=0.0)
+    O = oracle.Oracle(p.rowptr, p.col, p.val, ilut_tau=0.0)
+    (lrp, lci, lv), (urp, uci, uv) = S.ilut()
+    (olrp, olci, olv), (ourp, ouci, ouv) = O.ilut()
+    assert np.array_equal(lv.cpu().numpy(), olv) and np.array_equal(uv.cpu().numpy(), ouv)
+    n = p.n_rows
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(n, n))
+    f = sp.csr_matrix((O.ilu0(), p.col, p.rowptr), shape=(n, n))
+    L0 = sp.tril(f, -1, format="csr") + sp.identity(n, format="csr")
+    U0 = sp.triu(f, 0, format="csr")
+    agg = O.aggregates()
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, O.nc))
+    crp, cci, cv = O.coarse()
+    Ac = sp.csr_matrix((cv, cci, crp), shape=(O.nc, O.nc)).toarray()
+    z = np.random.default_rng(11).uniform(-1, 1, n)
+    t = sp.linalg.spsolve_triangular(U0, sp.linalg.spsolve_triangular(L0, z, lower=True), lower=False)
+    ref = t + P @ np.linalg.solve(Ac, P.T @ (z - A @ t))
+    q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
+    assert np.linalg.norm(q - ref) <= 1e-10 * np.linalg.norm(ref), (kind, np.linalg.norm(q - ref) / np.linalg.norm(ref))
+    # and the solve converges to tol
+    b = p.b[:, 0]
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8)
+    assert res.status == G.OK
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
 
 
 def test_tiny_and_degenerate():

@@ -305,6 +305,25 @@ def test_preconditioner_matches_dense_twogrid(oracle_mod, case):
     assert np.abs((I - P @ np.linalg.inv(Ac) @ P.T @ A) @ P).max() < 1e-9
 
 
+@pytest.mark.parametrize("case", ["fv2d", "rgg"])
+def test_exact_coarse_solve_is_twogrid_with_inverse(oracle_mod, case):
+    """ILUT with tau = 0 (the exact coarse solve of the paper's EGMG) makes the
+    preconditioner the two-grid operator with M~^{-1} = P A_c^{-1} P^T itself,
+    A_c^{-1} taken by numpy's pivoted dense inverse; tau > 0 does not."""
+    p = W.scaled("fv2d", 20) if case == "fv2d" else W.scaled("rgg", 400)
+    rp, ci, v = p.rowptr, p.col, p.val
+    O = oracle_mod.Oracle(rp, ci, v, ilut_tau=0.0)
+    A, S, Si, _, P = _dense_parts(O, rp, ci, v)
+    crp, cci, cv = O.coarse()
+    Mi = P @ np.linalg.inv(B.dense(crp, cci, cv, O.nc)) @ P.T
+    Binv = Si + Mi - Mi @ A @ Si
+    z = np.random.default_rng(7).standard_normal(O.n)
+    ref = Binv @ z
+    assert np.abs(O.apply(z) - ref).max() <= 1e-11 * np.abs(ref).max()
+    inexact = oracle_mod.Oracle(rp, ci, v, ilut_tau=1e-2).apply(z)
+    assert np.abs(inexact - ref).max() > 1e-6 * np.abs(ref).max()
+
+
 def test_preconditioner_fp32_close_to_fp64(oracle_mod):
     p = W.scaled("fv2d", 32)
     O = oracle_mod.Oracle(p.rowptr, p.col, p.val)
