@@ -8,7 +8,7 @@ FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
 before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-fp32] [--egmg]
+                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K]
        python bench.py --copy-calibration   (a plain 1 GiB device copy, run
                        under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
 
@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--egmg", action="store_true",
                     help="also time the exact coarse solve (ILUT tau = 0: complete LU of A_c), reported beside")
+    ap.add_argument("--jacobi", type=int, default=0,
+                    help="also time the coarse solve by K Jacobi sweeps per ILUT factor, reported beside")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -294,6 +296,26 @@ def main():
             iters=re.info["iters"], nnz_ilut=int(Se.setup_info["nnz_lc"] + Se.setup_info["nnz_uc"]),
             relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xeh) / np.linalg.norm(p.b[:, 0])))
         print(f"[bench] exact coarse solve (EGMG) step: {te:.3f}s its={re.info['iters']}", file=sys.stderr, flush=True)
+
+    if args.jacobi > 0:
+        # the parallel inexact coarse solve: K Jacobi sweeps on each ILUT factor
+        def jacobi_step():
+            Sj = Solver(rp, ci, va, cf=SOLVE_OPTS["cf"], ilut_tau=SOLVE_OPTS["ilut_tau"], coarse_mode=1,
+                        coarse_sweeps=args.jacobi)
+            xj, rj = Sj.solve(b, tol=TOL, restart=SOLVE_OPTS["restart"], maxit=SOLVE_OPTS["maxit"])
+            return Sj, xj, rj
+        jacobi_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sj, xj, rj = jacobi_step()
+        torch.cuda.synchronize()
+        tj = time.perf_counter() - t0
+        out["coarse_jacobi"] = dict(
+            sweeps=args.jacobi, time_s=round(tj, 6), solve_ms=round(rj.info["solve_ms"], 2), iters=rj.info["iters"],
+            status=int(rj.status),
+            relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xj.cpu().numpy()) / np.linalg.norm(p.b[:, 0])))
+        print(f"[bench] Jacobi coarse step ({args.jacobi} sweeps): {tj:.3f}s its={rj.info['iters']}", file=sys.stderr,
+              flush=True)
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

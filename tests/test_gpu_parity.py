@@ -267,6 +267,33 @@ def test_exact_coarse_solve(kind):
     assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
 
 
+@pytest.mark.parametrize("kind", ["fv2d_64", "fv3d_20", "rgg_3001"])
+def test_jacobi_coarse_solve(kind):
+    """Coarse solve by k Jacobi sweeps on each ILUT factor (the parallel
+    inexact variant): one application against the oracle's same mode, with
+    k = 3 and with k = N_c (then exact, equal to the triangular solves), and a
+    converged solve."""
+    _say(f"[case] jacobi coarse {kind}")
+    p = CASES[kind]()
+    z = np.random.default_rng(12).uniform(-1, 1, p.n_rows)
+    zt = torch.as_tensor(z, device="cuda")
+    S0 = Solver(p.rowptr, p.col, p.val)
+    nc = S0.info()["n_coarse"]
+    for k in (3, nc):
+        S = Solver(p.rowptr, p.col, p.val, coarse_mode=1, coarse_sweeps=k)
+        O = oracle.Oracle(p.rowptr, p.col, p.val, coarse_mode=1, coarse_sweeps=k)
+        q = S.apply(zt, precision=0).cpu().numpy()
+        ref = O.apply(z, 0)
+        assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref), (kind, k)
+    exact = S0.apply(zt, precision=0).cpu().numpy()
+    assert np.linalg.norm(q - exact) <= 1e-10 * np.linalg.norm(exact), kind
+    S = Solver(p.rowptr, p.col, p.val, coarse_mode=1, coarse_sweeps=3)
+    b = p.b[:, 0]
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, restart=600)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    assert res.status == G.OK and np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+
+
 def test_tiny_and_degenerate():
     _say("[case] tiny")
     # 1x1, diagonal matrices, a 2x2 that needs no pivoting
