@@ -30,6 +30,7 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 constexpr uint64_t kSent64 = 0x7FF8DEADBEEFF00DULL;
 constexpr uint32_t kSent32 = 0x7FC0FEEDu;
 constexpr int kMaxRestart = 2048;   // longest Krylov basis (vectors)
+constexpr int kPinCol = 2 * kMaxRestart + 8;  // doubles per pinned block (scalars, or h1, h2, ||w||^2)
 constexpr int kFused = 32;          // basis size handled by the fused CGS2 kernels
 
 static const char* kProfNames[PC_COUNT] = {"spmv", "sweep_fine", "sweep_coarse", "resid_restrict",
@@ -84,7 +85,8 @@ struct Solver {
   DBuf<double> V, Z, w, xcol, bcol, coef;
   RedWork rw;
   DBuf<int> abort_flag;
-  double* hpin = nullptr;      // pinned host scalars
+  double* hpin = nullptr;      // pinned host scalars, then two Hessenberg columns (kPinCol each)
+  hipEvent_t colev[2] = {nullptr, nullptr};  // a column's copy into hpin finished
   gmg_info info{};
   int log_every = 0;           // GMG_LOG=k prints the residual estimate every k steps
   // profiling
@@ -98,6 +100,8 @@ struct Solver {
     for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
     for (auto e : pool) (void)hipEventDestroy(e);
     if (hpin) (void)hipHostFree(hpin);
+    for (auto e : colev)
+      if (e) (void)hipEventDestroy(e);
   }
 
   hipEvent_t ev() {
@@ -967,9 +971,15 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
     }
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
+    // Steps run one deep in a pipeline: the host reads step j's Hessenberg
+    // column (Givens rotation, convergence test) while the GPU already runs
+    // step j + 1, whose basis vector the GPU normalises itself.  A step
+    // enqueued after the last one needed is left unused: the update below
+    // takes only Z's first k columns, so iterates and step counts are those
+    // of the plain loop.
     int k = 0;
     bool breakdown = false;
-    for (int j = 0; j < m; ++j) {
+    auto enqueue_step = [&](int j) {
       double* vj = V + (size_t)j * ld;
       double* zj = Z + (size_t)j * ld;
       if (adjoint) vcycle_adjoint(S, vj, zj);
@@ -1001,15 +1011,21 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
           launch_multidot(V + (size_t)c0 * ld, ld, std::min(kFused, kc - c0), w, n, S.rw, h2 + c0, s);
         launch_update_many(V, ld, kc, h2, w, n, true, S.rw, nrm, s);
       }
-      d2h(hp, res, 2 * kc + 1, s);
-      HIPCK(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) HH(i, j) = hp[i] + hp[kc + i];
-      const double hn = std::sqrt(hp[2 * kc]);
-      HH(j + 1, j) = hn;
-      if (hn != 0.0) {
+      {
         Prof p(S, PC_VECTOR, (double)n * 16);
-        launch_scale(w, 1.0 / hn, V + (size_t)(j + 1) * ld, n, s);
+        launch_normalize(w, nrm, V + (size_t)(j + 1) * ld, n, s);
       }
+      d2h(hp + (size_t)kPinCol * (1 + (j & 1)), res, 2 * kc + 1, s);
+      HIPCK(hipEventRecord(S.colev[j & 1], s));
+    };
+    // true when the cycle ends with step j
+    auto process_step = [&](int j) -> bool {
+      HIPCK(hipEventSynchronize(S.colev[j & 1]));
+      const double* col = hp + (size_t)kPinCol * (1 + (j & 1));
+      const int kc = j + 1;
+      for (int i = 0; i <= j; ++i) HH(i, j) = col[i] + col[kc + i];
+      const double hn = std::sqrt(col[2 * kc]);
+      HH(j + 1, j) = hn;
       for (int i = 0; i < j; ++i) {
         const double a = HH(i, j), c = HH(i + 1, j);
         HH(i, j) = cs[i] * a + sn[i] * c;
@@ -1019,7 +1035,7 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       if (rho == 0.0 || !std::isfinite(rho)) {
         out.st = std::isfinite(rho) ? GMG_ERR_BREAKDOWN : GMG_ERR_NONFINITE;
         breakdown = true;
-        break;
+        return true;
       }
       cs[j] = HH(j, j) / rho;
       sn[j] = HH(j + 1, j) / rho;
@@ -1034,8 +1050,14 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
         std::fprintf(stderr, "[gmg] step %d  estimated relres %.3e\n", total, out.est);
         std::fflush(stderr);
       }
-      if (out.est < tol || hn == 0.0 || total >= maxit) break;
+      return out.est < tol || hn == 0.0 || total >= maxit;
+    };
+    bool ended = false;
+    for (int j = 0; j < m && !ended; ++j) {
+      enqueue_step(j);
+      if (j > 0) ended = process_step(j - 1);
     }
+    if (!ended) process_step(m - 1);
     check_abort(S);
     if (breakdown) break;
     for (int i = k - 1; i >= 0; --i) {
@@ -1228,7 +1250,8 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   const int n = (int)n64;
   S.n = n;
   S.nnz = nnz64;
-  HIPCK(hipHostMalloc(&S.hpin, sizeof(double) * (2 * kMaxRestart + 8), hipHostMallocDefault));
+  HIPCK(hipHostMalloc(&S.hpin, sizeof(double) * 3 * kPinCol, hipHostMallocDefault));
+  for (auto& e : S.colev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   S.abort_flag.alloc(1);
   launch_fill_u32(reinterpret_cast<unsigned*>(S.abort_flag.p), 0u, 1, s);
   // ---- validate and copy A

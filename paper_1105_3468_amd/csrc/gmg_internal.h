@@ -285,6 +285,8 @@ void launch_update_many(const double* V, size_t ld, int k, const double* h, doub
 void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s);
 // y = alpha * x
 void launch_scale(const double* x, double alpha, double* y, int64_t n, hipStream_t s);
+// y = x / sqrt(*nrm2) (zero when *nrm2 is zero); nrm2 on the device
+void launch_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
 // x += sum_i c[i] Z[i]  (c device)
 void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n,
                     hipStream_t s);

@@ -254,6 +254,23 @@ void launch_scale(const double* x, double a, double* y, int64_t n, hipStream_t s
   HIPCK(hipGetLastError());
 }
 
+// y = x / sqrt(*nrm2), or zero when the norm is zero (the squared norm is
+// read on the device, so the host need not wait for it)
+__global__ void k_normalize(const double* __restrict__ x, const double* __restrict__ nrm2, double* __restrict__ y,
+                            int64_t n) {
+  const double hn = sqrt(*nrm2);
+  const double a = hn != 0.0 ? 1.0 / hn : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+void launch_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_normalize, dim3((unsigned)g), dim3(256), 0, s, x, nrm2, y, n);
+  HIPCK(hipGetLastError());
+}
+
 template <int K>
 __global__ void k_xupdate(double* __restrict__ x, const double* __restrict__ Z, size_t ld, int kc,
                           const double* __restrict__ c, int64_t n) {
