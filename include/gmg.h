@@ -159,7 +159,10 @@ gmg_status gmg_get_ilut(gmg_handle h, int32_t* lrowptr, int32_t* lcol, double* l
 gmg_status gmg_set_stream(gmg_handle h, void* stream);
 
 /* Per-kernel-class timing with HIP events on the handle's stream.
- * gmg_profile_enable(h, 1) starts recording (resets the counters);
+ * gmg_profile_enable(h, 1) starts recording every class (resets the
+ * counters); enable > 1 records only the classes c whose bit c + 1 is set
+ * (each recorded class boundary costs the stream a few microseconds); 0 stops;
+ * negative values are GMG_ERR_INVALID_ARG.
  * gmg_profile_read fills up to `cap` records (host arrays) with the class
  * name index, launch count, total milliseconds and algorithmic bytes moved,
  * and returns the number of classes in *count.  Names: gmg_profile_name. */

@@ -91,6 +91,7 @@ struct Solver {
   int log_every = 0;           // GMG_LOG=k prints the residual estimate every k steps
   // profiling
   bool prof = false;
+  unsigned prof_mask = 0;      // classes that record events (bit c: class c)
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   int64_t pc_launch[PC_COUNT] = {};
@@ -121,7 +122,7 @@ struct Prof {
   double bytes;
   hipEvent_t a = nullptr;
   Prof(Solver& s_, int c, double b) : S(s_), cls(c), bytes(b) {
-    if (S.prof) { a = S.ev(); HIPCK(hipEventRecord(a, S.s)); }
+    if (S.prof && (S.prof_mask >> cls & 1u)) { a = S.ev(); HIPCK(hipEventRecord(a, S.s)); }
   }
   ~Prof() noexcept(false) {
     if (S.prof && a) {
@@ -1716,7 +1717,9 @@ gmg_status gmg_profile_enable(gmg_handle h, int enable) {
     Solver& S = h->S;
     gmg::prof_flush(S);
     for (int c = 0; c < gmg::PC_COUNT; ++c) { S.pc_launch[c] = 0; S.pc_ms[c] = 0; S.pc_bytes[c] = 0; }
+    if (enable < 0) gmg::fail(GMG_ERR_INVALID_ARG, "profile: negative class mask");
     S.prof = enable != 0;
+    S.prof_mask = enable == 1 ? ~0u : (unsigned)enable >> 1;
     return GMG_OK;
   });
 }

@@ -273,8 +273,17 @@ class Solver:
         return y
 
     # ----------------------------------------------------------- profiling
-    def profile(self, enable: bool):
-        _check(load().gmg_profile_enable(self._h, int(enable)), "profile")
+    def profile(self, enable: bool, classes=None):
+        """Start (or stop) per-class event timing; `classes`: names from
+        profile_read's keys to record only those (fewer events on the stream)."""
+        code = int(bool(enable))
+        if enable and classes is not None:
+            lib = load()
+            names = [lib.gmg_profile_name(c).decode() for c in range(16)]
+            code = 0
+            for nm in classes:
+                code |= 1 << (names.index(nm) + 1)
+        _check(load().gmg_profile_enable(self._h, code), "profile")
 
     def profile_read(self) -> dict:
         cap = 16

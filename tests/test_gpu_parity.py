@@ -294,6 +294,26 @@ def test_jacobi_coarse_solve(kind):
     assert res.status == G.OK and np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
 
 
+def test_profile_class_selection():
+    """Event timing of selected kernel classes only, of all classes, and a
+    rejected negative mask."""
+    _say("[case] profile classes")
+    p = W.make("fv2d_64")
+    S = Solver(p.rowptr, p.col, p.val)
+    b = torch.as_tensor(p.b[:, 0], device="cuda")
+    S.profile(True, classes=["ortho"])
+    S.solve(b, tol=1e-8)
+    pr = S.profile_read()
+    assert pr["ortho"]["launches"] > 0 and pr["ortho"]["ms"] > 0
+    assert all(v["launches"] == 0 for k, v in pr.items() if k != "ortho")
+    S.profile(True)
+    S.solve(b, tol=1e-8)
+    pr = S.profile_read()
+    assert all(pr[k]["launches"] > 0 for k in ("spmv", "sweep_fine", "sweep_coarse", "ortho"))
+    assert G.load().gmg_profile_enable(S._h, -1) == G.ERR_INVALID_ARG
+    S.profile(False)
+
+
 def test_tiny_and_degenerate():
     _say("[case] tiny")
     # 1x1, diagonal matrices, a 2x2 that needs no pivoting
