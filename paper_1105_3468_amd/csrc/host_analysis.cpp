@@ -79,15 +79,38 @@ struct IlutNodeRows {  // the factor rows [lo, hi) of one tree node
 struct IlutWork {
   std::vector<double> w;
   std::vector<signed char> state;  // 0 absent, 1 present, 2 dropped
-  std::vector<int> touched;
-  std::priority_queue<int, std::vector<int>, std::greater<int>> pending;
-  explicit IlutWork(int n) : w(n > 0 ? n : 1, 0.0), state(n > 0 ? n : 1, 0) { touched.reserve(256); }
+  std::vector<int> touched;        // every column set in this row (for the reset)
+  std::vector<int> ucols;          // columns above the diagonal
+  std::vector<int> kept;           // L columns, ascending (the eliminated, undropped candidates)
+  std::vector<uint64_t> bits;      // pending candidates k < i (a set of column indices)
+  int pos = 0;                     // no pending candidate below this column
+  explicit IlutWork(int n)
+      : w(n > 0 ? n : 1, 0.0), state(n > 0 ? n : 1, 0), bits((size_t)(n > 0 ? n : 1) / 64 + 1, 0) {
+    touched.reserve(256);
+    ucols.reserve(256);
+    kept.reserve(256);
+  }
+  void add_pending(int j) { bits[(size_t)j >> 6] |= 1ull << (j & 63); }
+  // the smallest pending candidate, or i when there is none (candidates are
+  // all below i; an elimination only adds candidates above the one taken, so
+  // the scan only moves forward)
+  int next_pending(int i) {
+    size_t wd = (size_t)pos >> 6;
+    uint64_t m = bits[wd] & (~0ull << (pos & 63));
+    const size_t last = (size_t)(i - 1) >> 6;
+    while (m == 0) {
+      if (i <= 0 || wd >= last) return i;
+      m = bits[++wd];
+    }
+    const int k = (int)(wd * 64) + __builtin_ctzll(m);
+    return k < i ? k : i;
+  }
 };
 
 // A row's working state after the eliminations of the rows below its node.
 struct IlutRowState {
   double thr = 0.0;
-  std::vector<int> col;
+  std::vector<int> col, kept;
   std::vector<double> val;
   std::vector<signed char> st;
 };
@@ -97,13 +120,21 @@ struct IlutRowState {
 double ilut_row_begin(const HCsr& A, double tau, int i, IlutWork& W) {
   double ss = 0.0;
   W.touched.clear();
+  W.ucols.clear();
+  W.kept.clear();
+  W.pos = i;
   for (int p = A.rp[i]; p < A.rp[i + 1]; ++p) {
     const int j = A.ci[p];
     ss = ss + A.v[p] * A.v[p];
     W.w[j] = A.v[p];
     W.state[j] = 1;
     W.touched.push_back(j);
-    if (j < i) W.pending.push(j);
+    if (j < i) {
+      W.add_pending(j);
+      W.pos = std::min(W.pos, j);
+    } else if (j > i) {
+      W.ucols.push_back(j);
+    }
   }
   if (W.state[i] == 0) { W.state[i] = 1; W.w[i] = 0.0; W.touched.push_back(i); }
   return tau * std::sqrt(ss);
@@ -112,9 +143,11 @@ double ilut_row_begin(const HCsr& A, double tau, int i, IlutWork& W) {
 // Eliminations of the pending candidates k < until, in ascending order.
 void ilut_row_eliminate(int i, double thr, int until, const std::vector<int>& node_of,
                         const std::vector<IlutNodeRows>& rows, IlutWork& W) {
-  while (!W.pending.empty() && W.pending.top() < until) {
-    const int k = W.pending.top();
-    W.pending.pop();
+  for (;;) {
+    const int k = W.next_pending(i);
+    if (k >= until) break;
+    W.bits[(size_t)k >> 6] &= ~(1ull << (k & 63));
+    W.pos = k + 1;
     if (std::fabs(W.w[k]) < thr) { W.w[k] = 0.0; W.state[k] = 2; continue; }
     const IlutNodeRows& K = rows[node_of[k]];
     const int uk = K.urp[k - K.lo], ue = K.urp[k - K.lo + 1];
@@ -122,59 +155,72 @@ void ilut_row_eliminate(int i, double thr, int until, const std::vector<int>& no
     const double* uv = K.uv.data();
     const double lik = W.w[k] / uv[uk];
     W.w[k] = lik;
+    W.kept.push_back(k);
     for (int r = uk + 1; r < ue; ++r) {
       const int j = uci[r];
       if (W.state[j] == 0) {
         W.state[j] = 1;
         W.w[j] = 0.0;
         W.touched.push_back(j);
-        if (j < i) W.pending.push(j);
+        if (j < i) W.add_pending(j);
+        else if (j > i) W.ucols.push_back(j);
       }
       W.w[j] = W.w[j] - lik * uv[r];
     }
   }
 }
 
-// Save a row's state (the pending candidates are exactly its present columns
-// in [until, i)) and clear the work vector; restore it for the rest.
-void ilut_row_save(double thr, IlutWork& W, IlutRowState& R) {
+// Save a row's state (its pending candidates are exactly its present
+// columns in [until, i)) and clear the work vector; restore it for the rest.
+void ilut_row_save(int i, int until, double thr, IlutWork& W, IlutRowState& R) {
   R.thr = thr;
   R.col.assign(W.touched.begin(), W.touched.end());
+  R.kept.assign(W.kept.begin(), W.kept.end());
   R.val.resize(R.col.size());
   R.st.resize(R.col.size());
   for (size_t q = 0; q < R.col.size(); ++q) {
     const int j = R.col[q];
     R.val[q] = W.w[j];
     R.st[q] = W.state[j];
+    if (W.state[j] == 1 && j >= until && j < i) W.bits[(size_t)j >> 6] &= ~(1ull << (j & 63));
     W.w[j] = 0.0;
     W.state[j] = 0;
   }
-  while (!W.pending.empty()) W.pending.pop();
 }
 double ilut_row_restore(int i, int from, const IlutRowState& R, IlutWork& W) {
   W.touched.assign(R.col.begin(), R.col.end());
+  W.kept.assign(R.kept.begin(), R.kept.end());
+  W.ucols.clear();
+  W.pos = i;
   for (size_t q = 0; q < R.col.size(); ++q) {
     const int j = R.col[q];
     W.w[j] = R.val[q];
     W.state[j] = R.st[q];
-    if (R.st[q] == 1 && j >= from && j < i) W.pending.push(j);
+    if (R.st[q] == 1 && j >= from && j < i) {
+      W.add_pending(j);
+      W.pos = std::min(W.pos, j);
+    } else if (j > i) {
+      W.ucols.push_back(j);
+    }
   }
   return R.thr;
 }
 
-// Row i's end: drops, the split into L and U, the work vector cleared.
-// Returns false (status in *st) on a zero or non-finite pivot.
+// Row i's end: drops, the split into L (the kept candidates, ascending) and U
+// (diagonal first, then ascending columns), the work vector cleared.  Returns
+// false (status in *st) on a zero or non-finite pivot.
 bool ilut_row_finish(int i, double thr, IlutWork& W, IlutNodeRows& R, gmg_status* st) {
-  std::sort(W.touched.begin(), W.touched.end());
+  for (int j : W.kept) {
+    R.lci.push_back(j);
+    R.lv.push_back(W.w[j]);
+  }
   const double d = W.w[i];
   R.uci.push_back(i);
   R.uv.push_back(d);
+  std::sort(W.ucols.begin(), W.ucols.end());
+  for (int j : W.ucols)
+    if (!(std::fabs(W.w[j]) < thr)) { R.uci.push_back(j); R.uv.push_back(W.w[j]); }
   for (int j : W.touched) {
-    if (j < i) {
-      if (W.state[j] == 1) { R.lci.push_back(j); R.lv.push_back(W.w[j]); }
-    } else if (j > i) {
-      if (!(std::fabs(W.w[j]) < thr)) { R.uci.push_back(j); R.uv.push_back(W.w[j]); }
-    }
     W.state[j] = 0;
     W.w[j] = 0.0;
   }
@@ -324,7 +370,7 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
             for (int i = jb.r0; i < jb.r1; ++i) {
               const double thr = ilut_row_begin(A, tau, i, W);
               ilut_row_eliminate(i, thr, lo[k], node_of, rows, W);
-              ilut_row_save(thr, W, saved[k][i - lo[k]]);
+              ilut_row_save(i, lo[k], thr, W, saved[k][i - lo[k]]);
             }
           } else {
             for (int i = lo[k]; i < hi[k]; ++i) {
