@@ -139,6 +139,15 @@ gmg_status gmg_spmv(gmg_handle h, int transposed, const double* x, double* y);
 /* Setup statistics (sizes, passes, levels, setup time) into *info (host). */
 gmg_status gmg_get_info(gmg_handle h, gmg_info* info);
 
+/* Cheap condition estimates of Section 3 (the lemma on diagonal entries and
+ * the estimate for an incomplete factorization that follows it), computed on
+ * demand on the host: *est_coarse = max_i |(A_c)_ii| / min_i |(A_c)_ii|, a
+ * lower bound of cond(A_c) when A_c is SPD; *est_ilut = max_i |(L~U~)_ii| /
+ * min_i |(L~U~)_ii|, the unsymmetric form of the factorization's estimate,
+ * (L~U~)_ii = u_ii + sum_{j<i} l_ij u_ji.  Both are host doubles; a zero
+ * denominator gives +inf. */
+gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut);
+
 /* Aggregate of every fine unknown: agg device int32[N]; ids 0..N_c-1 ordered
  * by each aggregate's smallest fine index. */
 gmg_status gmg_get_aggregates(gmg_handle h, int32_t* agg);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <thread>
@@ -1648,6 +1649,47 @@ gmg_status gmg_get_info(gmg_handle h, gmg_info* info) {
     REQUIRE_HANDLE(h);
     if (!info) gmg::fail(GMG_ERR_INVALID_ARG, "null info");
     *info = h->S.info;
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!est_coarse || !est_ilut) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    gmg::Solver& S = h->S;
+    const int nc = S.nc;
+    auto ratio = [](const std::vector<double>& d) {
+      double mx = 0.0, mn = std::numeric_limits<double>::infinity();
+      for (double v : d) { mx = std::max(mx, std::fabs(v)); mn = std::min(mn, std::fabs(v)); }
+      return mn > 0.0 ? mx / mn : std::numeric_limits<double>::infinity();
+    };
+    // diagonal of A_c
+    std::vector<int> rp = gmg::to_host_int(S.Ac.rp.p, nc + 1, S.s);
+    std::vector<int> ci = gmg::to_host_int(S.Ac.ci.p, S.Ac.nnz, S.s);
+    std::vector<double> v(S.Ac.nnz), dac(nc, 0.0);
+    gmg::d2h(v.data(), S.Ac.v.p, S.Ac.nnz, S.s);
+    HIPCK(hipStreamSynchronize(S.s));
+    for (int i = 0; i < nc; ++i)
+      for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) dac[i] = v[p];
+    // diagonal of L~U~: u_ii + sum_{j<i} l_ij u_ji (U~'s rows: diagonal, then
+    // ascending columns)
+    const gmg::HCsr &L = S.hLc, &U = S.hUc;
+    std::vector<double> dlu(nc, 0.0);
+    for (int i = 0; i < nc; ++i) {
+      double sum = U.v[U.rp[i]];
+      for (int q = L.rp[i]; q < L.rp[i + 1]; ++q) {
+        const int j = L.ci[q];
+        const int* b = U.ci.data() + U.rp[j] + 1;
+        const int* e = U.ci.data() + U.rp[j + 1];
+        const int* f = std::lower_bound(b, e, i);
+        if (f != e && *f == i) sum += L.v[q] * U.v[f - U.ci.data()];
+      }
+      dlu[i] = sum;
+    }
+    *est_coarse = ratio(dac);
+    *est_ilut = ratio(dlu);
     return GMG_OK;
   });
 }

@@ -567,6 +567,7 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
     out.push_back({1, t.start + c0 + c1, t.len - c0 - c1, t.node});
   };
 
+  constexpr int kLocalSubtree = 4096;
   auto worker = [&]() {
     std::vector<int> queue;
     std::vector<Task> out;
@@ -580,7 +581,20 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
       ++active;
       lk.unlock();
       out.clear();
-      run(t, queue, out, ids);
+      if (t.len <= kLocalSubtree) {
+        // a small subtree: finished here, without the shared list
+        std::vector<Task> local{t};
+        while (!local.empty()) {
+          const Task u = local.back();
+          local.pop_back();
+          const size_t o0 = out.size();
+          run(u, queue, out, ids);
+          local.insert(local.end(), out.begin() + o0, out.end());
+          out.resize(o0);
+        }
+      } else {
+        run(t, queue, out, ids);
+      }
       lk.lock();
       ready.insert(ready.end(), out.begin(), out.end());
       --active;

@@ -20,7 +20,7 @@ ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOT_SETUP, ERR_STALLED = -5, -6, -7, -8
 
 EXPORTED = [
     "gmg_default_options", "gmg_setup", "gmg_solve", "gmg_solve_adjoint", "gmg_apply_precond",
-    "gmg_spmv", "gmg_get_info", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
+    "gmg_spmv", "gmg_get_info", "gmg_cond_estimate", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
     "gmg_get_ilut", "gmg_set_stream", "gmg_profile_enable", "gmg_profile_read",
     "gmg_profile_name", "gmg_destroy", "gmg_last_error", "gmg_fv_nnz", "gmg_fv_assemble",
     "gmg_fv_kappa_grad", "gmg_pattern_grad",
@@ -75,6 +75,7 @@ def load():
         "gmg_apply_precond": (I, [P, P, P, I, I]),
         "gmg_spmv": (I, [P, I, P, P]),
         "gmg_get_info": (I, [P, C.POINTER(Info)]),
+        "gmg_cond_estimate": (I, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "gmg_get_aggregates": (I, [P, P]),
         "gmg_get_coarse": (I, [P, P, P, P]),
         "gmg_get_ilu0": (I, [P, P]),
@@ -271,6 +272,13 @@ class Solver:
         y = t.empty_like(x)
         _check(load().gmg_spmv(self._h, int(transposed), _ptr(x), _ptr(y)), "spmv")
         return y
+
+    def cond_estimate(self):
+        """(max/min |diag A_c|, max/min |diag L~U~|): the cheap condition
+        estimates of the coarse matrix and of its incomplete factorization."""
+        ec, el = C.c_double(0.0), C.c_double(0.0)
+        _check(load().gmg_cond_estimate(self._h, C.byref(ec), C.byref(el)), "cond_estimate")
+        return ec.value, el.value
 
     # ----------------------------------------------------------- profiling
     def profile(self, enable: bool, classes=None):

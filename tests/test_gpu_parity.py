@@ -314,6 +314,63 @@ def test_profile_class_selection():
     S.profile(False)
 
 
+@pytest.mark.parametrize("case,n", [("dcc1_2d", 128), ("dcc2_3d", 30), ("dc1_2d", 128), ("dc1_3d", 30)])
+def test_paper_problems_exact_vs_inexact(case, n):
+    """The paper's analytic problems (Section 3.1) with GMRES(30), cf = 4:
+    exact (tau = 0) and inexact (tau = 1e-4) coarse solves, each converged and
+    within one step of the oracle's count.  With convection (DCC1, DCC2) the
+    two converge in nearly the same number of steps while the inexact factor
+    is several times smaller, as the paper reports; for pure diffusion (DC1)
+    the inexact solve needs more steps under this drop rule (recorded, not a
+    pass condition beyond exact <= inexact)."""
+    _say(f"[case] paper problem {case} n={n}")
+    p = W.paper_problem(case, n)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    b = p.b[:, 0]
+    steps, nnz = {}, {}
+    for tau in (0.0, 1e-4):
+        S = Solver(p.rowptr, p.col, p.val, cf=4.0, ilut_tau=tau)
+        x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, restart=30, maxit=600)
+        assert res.status == G.OK, (case, tau, res.info)
+        assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+        O = oracle.Oracle(p.rowptr, p.col, p.val, cf=4.0, ilut_tau=tau)
+        xo, info = O.solve(b, tol=1e-8, restart=30, maxit=600)
+        assert abs(res.info["iters"] - info.steps) <= 1, (case, tau, res.info["iters"], info.steps)
+        steps[tau] = res.info["iters"]
+        inf = S.info()
+        nnz[tau] = inf["nnz_lc"] + inf["nnz_uc"]
+    _say(f"[case] {case}: steps exact {steps[0.0]} inexact {steps[1e-4]}, factor storage ratio "
+         f"{nnz[0.0] / nnz[1e-4]:.2f}")
+    assert nnz[0.0] >= 1.5 * nnz[1e-4]
+    assert steps[0.0] <= steps[1e-4]
+    if case.startswith("dcc"):
+        assert steps[1e-4] - steps[0.0] <= 2
+
+
+def test_condition_estimates():
+    """The cheap estimates of Section 3: max/min of |diag A_c| and of
+    |diag L~U~|, against scipy on the oracle's A_c and ILUT factors; larger
+    coefficient jumps give larger estimates (the paper's qualitative use)."""
+    _say("[case] condition estimates")
+    ests = []
+    for lo, hi in ((-1, 1), (-4, 4)):
+        p = W.fv_problem(48, 2, 8, lo, hi, W.velocity_const((1.0, 0.5)), 3)
+        S = Solver(p.rowptr, p.col, p.val)
+        O = oracle.Oracle(p.rowptr, p.col, p.val)
+        ec, el = S.cond_estimate()
+        crp, cci, cv = O.coarse()
+        Ac = sp.csr_matrix((cv, cci, crp), shape=(O.nc, O.nc))
+        (lrp, lci, lv), (urp, uci, uv) = O.ilut()
+        L = sp.csr_matrix((lv, lci, lrp), shape=(O.nc, O.nc)) + sp.identity(O.nc, format="csr")
+        U = sp.csr_matrix((uv, uci, urp), shape=(O.nc, O.nc))
+        d = np.abs(Ac.diagonal())
+        dlu = np.abs((L @ U).diagonal())
+        assert np.isclose(ec, d.max() / d.min(), rtol=1e-12, atol=0)
+        assert np.isclose(el, dlu.max() / dlu.min(), rtol=1e-10, atol=0)
+        ests.append((ec, el))
+    assert ests[1][0] > 100 * ests[0][0] and ests[1][1] > 100 * ests[0][1]
+
+
 def test_tiny_and_degenerate():
     _say("[case] tiny")
     # 1x1, diagonal matrices, a 2x2 that needs no pivoting

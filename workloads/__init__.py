@@ -70,6 +70,24 @@ def rgg_problem(N=500_000, seed=0, nrhs=1, name=None):
     return Problem(name or f"rgg_{N}", N, rp, ci, va, b, meta=dict(seed=seed))
 
 
+def paper_problem(case: str, n: int, seed: int = 0, nrhs: int = 1) -> Problem:
+    """The paper's analytic test problems (Section 3.1) on an n^dim cell grid:
+    ``dc1_2d`` / ``dc1_3d`` (discontinuous kappa of dc1_kappa, zero velocity),
+    ``dcc1_2d`` (velocity (1000, 1000)) and ``dcc2_3d`` (velocity
+    (1000, 1000, 1000)); right-hand side U(-1, 1) from the seed."""
+    dims = {"dc1_2d": 2, "dc1_3d": 3, "dcc1_2d": 2, "dcc2_3d": 3}
+    if case not in dims:
+        raise KeyError(case)
+    dim = dims[case]
+    kap = dc1_kappa(n, dim)
+    vel = velocity_const((1000.0,) * dim) if case.startswith("dcc") else None
+    rp, ci, va = fv_matrix(n, dim, kap, vel)
+    N = n ** dim
+    b = _rhs(np.random.default_rng(seed), N, nrhs)
+    return Problem(f"{case}_{n}", N, rp, ci, va, b, kappa=kap, grid=(n, dim), velocity=vel,
+                   meta=dict(n=n, dim=dim, case=case, seed=seed))
+
+
 def make(name: str, seed: int = 0, **kw) -> Problem:
     """Build one of the named workloads (see module docstring)."""
     if name == "fv2d_64":
@@ -111,4 +129,4 @@ def scaled(kind: str, n: int, seed: int = 0, nrhs: int = 1) -> Problem:
 
 
 __all__ = ["Problem", "make", "scaled", "fv_matrix", "fv_problem", "rgg_problem",
-           "block_kappa", "dc1_kappa", "velocity_const", "velocity_rotating", "rgg_matrix"]
+           "paper_problem", "block_kappa", "dc1_kappa", "velocity_const", "velocity_rotating", "rgg_matrix"]
