@@ -40,7 +40,7 @@ def build(force: bool = False) -> str:
 class _Opts(C.Structure):
     _fields_ = [("cf", C.c_double), ("max_passes", C.c_int), ("qbits", C.c_int),
                 ("seed", C.c_uint64), ("ilut_tau", C.c_double), ("coarse_mode", C.c_int),
-                ("coarse_sweeps", C.c_int), ("coarse_order", C.c_int)]
+                ("coarse_sweeps", C.c_int), ("coarse_order", C.c_int), ("fine_order", C.c_int)]
 
 
 _lib = None
@@ -62,6 +62,7 @@ def _L():
         _lib.or_get_coarse.argtypes = [P, P, P, P]
         _lib.or_get_ilut.argtypes = [P, P, P, P, P, P, P]
         _lib.or_get_ilu0.argtypes = [P, P]
+        _lib.or_get_fine.argtypes = [P, P, P, P, P]
         _lib.or_precond_apply.argtypes = [P, C.c_int, P, P]
         _lib.or_precond_apply_twosolve.argtypes = [P, P, P]
         _lib.or_precond_apply_adjoint.argtypes = [P, P, P]
@@ -157,8 +158,19 @@ class Oracle:
         _L().or_get_coarse(self._h, _p(rp), _p(ci), _p(v))
         return rp, ci, v
 
+    def fine(self):
+        """The smoother's numbering perm (position -> fine unknown; identity
+        unless fine_order = 1) and its matrix F = Q A Q^T as (rowptr, col, val)."""
+        perm = np.empty(self.n, dtype=np.int32)
+        rp = np.empty(self.n + 1, dtype=np.int32)
+        ci = np.empty(self.nnz, dtype=np.int32)
+        v = np.empty(self.nnz, dtype=np.float64)
+        _L().or_get_fine(self._h, _p(perm), _p(rp), _p(ci), _p(v))
+        return perm, (rp, ci, v)
+
     def ilu0(self):
-        """ILU(0) values on A's pattern (strict lower part = L0, rest = U0)."""
+        """ILU(0) values on the pattern of the smoother's matrix F (A itself
+        unless fine_order = 1; strict lower part = L0, rest = U0)."""
         v = np.empty(self.nnz, dtype=np.float64)
         _L().or_get_ilu0(self._h, _p(v))
         return v

@@ -10,6 +10,8 @@
  *   coarse operator A_c = P^T A P ................ Section 2, Eq. (E:galerkin) and the
  *                                                  double-sum formula after Eq. (aggr)
  *   smoother S = L0 U0 = ILU(0)(A) ............... Section 2 (choice of S), Algorithm 1 setup
+ *   ... or ILU(0) of A in nested-dissection order  the GMG-ND variant (Section 3.1 variant
+ *       (S = Q^T L0 U0 Q) .......................  list and the comments on ND ordering)
  *   inexact coarse factors ILUT(A_c) ............. Section 2 (ILU(t) paragraph), Algorithm 1 setup
  *   two-grid preconditioner B~ ................... Eq. (twogrid) and Algorithm 1 "SOLVE B~q=z",
  *                                                  "SOLVE M~g=h"
@@ -46,6 +48,8 @@ typedef struct {
     int coarse_mode;     /* 0: exact triangular sweeps, 1: Jacobi sweeps          */
     int coarse_sweeps;   /* Jacobi sweeps per factor when coarse_mode == 1        */
     int coarse_order;    /* 0: aggregates by smallest fine index; 1: nested dissection */
+    int fine_order;      /* 0: ILU(0) smoother on A's numbering; 1: on A renumbered by
+                            nested dissection (the GMG-ND variant)                   */
 } or_opts;
 
 typedef struct {
@@ -62,8 +66,11 @@ typedef struct {
     int *aptr, *amem;    /* aggregate member lists, ascending           */
     int passes, rounds;
     csr_t Ac;            /* coarse matrix                               */
-    double *ilu;         /* ILU(0) values on A's pattern                */
-    int *dpos;           /* position of the diagonal in each row of A   */
+    csr_t F;             /* the smoother's matrix: A (fine_order 0) or  */
+                         /* Q A Q^T with (Q x)_k = x_{fperm[k]}          */
+    int *fperm;          /* position -> fine unknown (fine_order 1)     */
+    double *ilu;         /* ILU(0) values on F's pattern                */
+    int *dpos;           /* position of the diagonal in each row of F   */
     csr_t Lc, Uc;        /* ILUT factors: Lc strictly lower (unit diag implied),
                             Uc upper with the diagonal stored first    */
     or_opts o;
@@ -494,10 +501,59 @@ static int renumber_coarse(or_solver *S) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* ILU(0): incomplete LU restricted to the pattern of A (IKJ form).          */
+/* The smoother's matrix F.  GMG-ND (the variant list of Section 3.1 and its */
+/* comments) reorders the unknowns by nested dissection before ILU(0) so that */
+/* the smoother can be built and applied in parallel: F = Q A Q^T, row k of  */
+/* F being row fperm[k] of A with columns renumbered and sorted, fperm the   */
+/* same dissection rule as the coarse numbering applied to A's graph.        */
+/* ------------------------------------------------------------------------ */
+static int pair_cmp(const void *a, const void *b) {
+    const int *x = a, *y = b;
+    return (x[0] > y[0]) - (x[0] < y[0]);
+}
+
+static int smoother_matrix(or_solver *S) {
+    const csr_t *A = &S->A;
+    int n = A->n, nnz = A->rp[n];
+    S->F.n = n;
+    S->F.rp = malloc(sizeof(int) * ((size_t)n + 1));
+    S->F.ci = malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+    S->F.v = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    S->fperm = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    if (!S->F.rp || !S->F.ci || !S->F.v || !S->fperm) return OR_ERR_OOM;
+    if (S->o.fine_order == 0) {
+        for (int k = 0; k < n; ++k) S->fperm[k] = k;
+        memcpy(S->F.rp, A->rp, sizeof(int) * ((size_t)n + 1));
+        memcpy(S->F.ci, A->ci, sizeof(int) * (size_t)nnz);
+        memcpy(S->F.v, A->v, sizeof(double) * (size_t)nnz);
+        return OR_OK;
+    }
+    int st = nd_order(A, S->fperm);
+    if (st) return st;
+    int *rank = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *pr = malloc(sizeof(int) * 2 * (size_t)(n > 0 ? n : 1));
+    if (!rank || !pr) { free(rank); free(pr); return OR_ERR_OOM; }
+    for (int k = 0; k < n; ++k) rank[S->fperm[k]] = k;
+    S->F.rp[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        int i = S->fperm[k], len = A->rp[i + 1] - A->rp[i];
+        for (int q = 0; q < len; ++q) { pr[2 * q] = rank[A->ci[A->rp[i] + q]]; pr[2 * q + 1] = A->rp[i] + q; }
+        qsort(pr, (size_t)len, 2 * sizeof(int), pair_cmp);
+        for (int q = 0; q < len; ++q) {
+            S->F.ci[S->F.rp[k] + q] = pr[2 * q];
+            S->F.v[S->F.rp[k] + q] = A->v[pr[2 * q + 1]];
+        }
+        S->F.rp[k + 1] = S->F.rp[k] + len;
+    }
+    free(rank); free(pr);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ILU(0): incomplete LU restricted to the pattern of F (IKJ form).          */
 /* ------------------------------------------------------------------------ */
 static int ilu0(or_solver *S) {
-    const csr_t *A = &S->A;
+    const csr_t *A = &S->F;
     int n = A->n;
     S->ilu = malloc(sizeof(double) * (size_t)(A->rp[n] > 0 ? A->rp[n] : 1));
     S->dpos = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
@@ -650,11 +706,13 @@ void or_default_opts(or_opts *o) {
     o->coarse_mode = 0;
     o->coarse_sweeps = 3;
     o->coarse_order = 1;
+    o->fine_order = 0;
 }
 
 void or_destroy(or_solver *S) {
     if (!S) return;
     csr_free(&S->A); csr_free(&S->G); csr_free(&S->Ac); csr_free(&S->Lc); csr_free(&S->Uc);
+    csr_free(&S->F); free(S->fperm);
     free(S->agg); free(S->aptr); free(S->amem); free(S->ilu); free(S->dpos);
     free(S->v32); free(S->ilu32); free(S->lc32); free(S->uc32);
     free(S);
@@ -669,7 +727,8 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, const or_opts
     or_solver *S = calloc(1, sizeof(or_solver));
     if (!S) return OR_ERR_OOM;
     S->o = *opts;
-    if (S->o.qbits < 0 || S->o.qbits > 52 || !(S->o.cf >= 1.0) || S->o.coarse_order < 0 || S->o.coarse_order > 1) {
+    if (S->o.qbits < 0 || S->o.qbits > 52 || !(S->o.cf >= 1.0) || S->o.coarse_order < 0 || S->o.coarse_order > 1 ||
+        S->o.fine_order < 0 || S->o.fine_order > 1) {
         or_destroy(S);
         return OR_ERR_INVALID;
     }
@@ -705,6 +764,7 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, const or_opts
     if (!st) st = members(S);
     if (!st) st = galerkin(S);
     if (!st && !agg_given && S->o.coarse_order == 1) st = renumber_coarse(S);
+    if (!st) st = smoother_matrix(S);
     if (!st) st = ilu0(S);
     if (!st) st = ilut(&S->Ac, S->o.ilut_tau, &S->Lc, &S->Uc);
     if (!st) {
@@ -751,6 +811,11 @@ void or_get_ilut(const or_solver *S, int *lrp, int *lci, double *lv, int *urp, i
 void or_get_ilu0(const or_solver *S, double *vals) {
     memcpy(vals, S->ilu, sizeof(double) * (size_t)S->A.rp[S->A.n]);
 }
+/* the smoother's numbering (position -> fine unknown) and matrix F */
+void or_get_fine(const or_solver *S, int *perm, int *rp, int *ci, double *v) {
+    memcpy(perm, S->fperm, sizeof(int) * (size_t)S->A.n);
+    get_csr(&S->F, rp, ci, v);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Preconditioner application (the one-coarse-solve form of SOLVE B~q = z):  */
@@ -760,19 +825,22 @@ void or_get_ilu0(const or_solver *S, double *vals) {
 /* the second coarse solve applied to A t.                                   */
 /* ------------------------------------------------------------------------ */
 #define DEFINE_APPLY(T, SUF, AV, ILU, LCV, UCV)                                            \
-static void fine_smooth_##SUF(const or_solver *S, const T *z, T *y, T *t) {               \
-    const csr_t *A = &S->A;                                                                \
-    int n = A->n;                                                                          \
+/* t = S^{-1} z, S = Q^T L0 U0 Q: u = Q z, y = L0^{-1} u, u = U0^{-1} y, t = Q^T u */  \
+static void fine_smooth_##SUF(const or_solver *S, const T *z, T *y, T *t, T *u) {         \
+    const csr_t *F = &S->F;                                                                \
+    int n = F->n;                                                                          \
+    for (int k = 0; k < n; ++k) u[k] = z[S->fperm[k]];                                     \
     for (int i = 0; i < n; ++i) {                                                          \
-        T s = z[i];                                                                        \
-        for (int p = A->rp[i]; p < S->dpos[i]; ++p) s = s - (T)(ILU)[p] * y[A->ci[p]];     \
+        T s = u[i];                                                                        \
+        for (int p = F->rp[i]; p < S->dpos[i]; ++p) s = s - (T)(ILU)[p] * y[F->ci[p]];     \
         y[i] = s;                                                                          \
     }                                                                                      \
     for (int i = n - 1; i >= 0; --i) {                                                     \
         T s = y[i];                                                                        \
-        for (int p = S->dpos[i] + 1; p < A->rp[i + 1]; ++p) s = s - (T)(ILU)[p] * t[A->ci[p]]; \
-        t[i] = s / (T)(ILU)[S->dpos[i]];                                                   \
+        for (int p = S->dpos[i] + 1; p < F->rp[i + 1]; ++p) s = s - (T)(ILU)[p] * u[F->ci[p]]; \
+        u[i] = s / (T)(ILU)[S->dpos[i]];                                                   \
     }                                                                                      \
+    for (int k = 0; k < n; ++k) t[S->fperm[k]] = u[k];                                     \
 }                                                                                          \
 static void coarse_solve_##SUF(const or_solver *S, const T *rc, T *yc, T *ec, T *tmp) {   \
     int nc = S->nc;                                                                        \
@@ -813,8 +881,9 @@ static void coarse_solve_##SUF(const or_solver *S, const T *rc, T *yc, T *ec, T 
 static void apply_##SUF(const or_solver *S, const T *z, T *q, T *w) {                      \
     const csr_t *A = &S->A;                                                                \
     int n = A->n, nc = S->nc;                                                              \
-    T *y = w, *t = w + n, *rc = w + 2 * n, *yc = rc + nc, *ec = yc + nc, *tmp = ec + nc;   \
-    fine_smooth_##SUF(S, z, y, t);                                                         \
+    T *y = w, *t = w + n, *u = w + 2 * n, *rc = w + 3 * n, *yc = rc + nc, *ec = yc + nc;   \
+    T *tmp = ec + nc;                                                                      \
+    fine_smooth_##SUF(S, z, y, t, u);                                                      \
     for (int I = 0; I < nc; ++I) rc[I] = (T)0;                                             \
     for (int I = 0; I < nc; ++I)                                                           \
         for (int m = S->aptr[I]; m < S->aptr[I + 1]; ++m) {                                \
@@ -831,7 +900,7 @@ DEFINE_APPLY(double, f64, S->A.v, S->ilu, S->Lc.v, S->Uc.v)
 DEFINE_APPLY(float, f32, S->v32, S->ilu32, S->lc32, S->uc32)
 
 /* workspace doubles needed by or_precond_apply */
-long or_work_size(const or_solver *S) { return 2L * S->A.n + 4L * S->nc + 8; }
+long or_work_size(const or_solver *S) { return 3L * S->A.n + 4L * S->nc + 8; }
 
 /* precision 0: FP64; 1: FP32 (z rounded to nearest float on entry, every
    operation in float on float copies of A and the factors, q widened on exit) */
@@ -876,7 +945,7 @@ void or_precond_apply_twosolve(const or_solver *S, const double *z, double *q) {
     double *hc = malloc(sizeof(double) * (size_t)nc * 4 + 8);
     double *yc = hc + nc, *fc = yc + nc, *tmp = fc + nc;
     double *gc = malloc(sizeof(double) * (size_t)nc + 8);
-    fine_smooth_f64(S, z, y, t);
+    fine_smooth_f64(S, z, y, t, at);
     for (int I = 0; I < nc; ++I) hc[I] = 0.0;
     for (int k = 0; k < n; ++k) hc[S->agg[k]] += z[k];
     coarse_solve_f64(S, hc, yc, fc, tmp);
@@ -891,7 +960,7 @@ void or_precond_apply_twosolve(const or_solver *S, const double *z, double *q) {
 /* Transposed preconditioner.  From Eq. (twogrid),
    B~^{-1} = S^{-1} + M~^{-1} (I - A S^{-1}), hence
    B~^{-T} = M~^{-T} + S^{-T} (I - A^T M~^{-T}) with M~^{-T} = P (L~ U~)^{-T} P^T
-   and S^{-T} = (L0 U0)^{-T}:
+   and S^{-T} = Q^T (L0 U0)^{-T} Q:
      e_c = L~^{-T} U~^{-T} P^T z,  f = P e_c,  s = z - A^T f,
      t = L0^{-T} U0^{-T} s,  q = f + t.
    Only the exact coarse solve has a transpose here. */
@@ -902,6 +971,8 @@ void or_precond_apply_adjoint(const or_solver *S, const double *z, double *q) {
     double *b = malloc(sizeof(double) * (size_t)nc + 8), *e = malloc(sizeof(double) * (size_t)nc + 8);
     double *f = malloc(sizeof(double) * (size_t)n + 8), *s = malloc(sizeof(double) * (size_t)n + 8);
     double *t = malloc(sizeof(double) * (size_t)n + 8);
+    double *u = malloc(sizeof(double) * (size_t)n + 8), *tt = malloc(sizeof(double) * (size_t)n + 8);
+    const csr_t *F = &S->F;
     for (int I = 0; I < nc; ++I) b[I] = 0.0;
     for (int k = 0; k < n; ++k) b[S->agg[k]] += z[k];
     /* U~^T e = b: U~^T is lower triangular, column-oriented substitution */
@@ -915,15 +986,18 @@ void or_precond_apply_adjoint(const or_solver *S, const double *z, double *q) {
     for (int k = 0; k < n; ++k) f[k] = e[S->agg[k]];
     spmv_t(A, f, s);
     for (int k = 0; k < n; ++k) s[k] = z[k] - s[k];
-    /* U0^T w = s (lower, with diagonal), then L0^T t = w (unit upper) */
+    /* u = Q s; U0^T w = u (lower, with diagonal), then L0^T tt = w (unit
+       upper); t = Q^T tt */
+    for (int k = 0; k < n; ++k) u[k] = s[S->fperm[k]];
     for (int i = 0; i < n; ++i) {
-        t[i] = s[i] / S->ilu[S->dpos[i]];
-        for (int p = S->dpos[i] + 1; p < A->rp[i + 1]; ++p) s[A->ci[p]] -= S->ilu[p] * t[i];
+        tt[i] = u[i] / S->ilu[S->dpos[i]];
+        for (int p = S->dpos[i] + 1; p < F->rp[i + 1]; ++p) u[F->ci[p]] -= S->ilu[p] * tt[i];
     }
     for (int i = n - 1; i >= 0; --i)
-        for (int p = A->rp[i]; p < S->dpos[i]; ++p) t[A->ci[p]] -= S->ilu[p] * t[i];
+        for (int p = F->rp[i]; p < S->dpos[i]; ++p) tt[F->ci[p]] -= S->ilu[p] * tt[i];
+    for (int k = 0; k < n; ++k) t[S->fperm[k]] = tt[k];
     for (int k = 0; k < n; ++k) q[k] = f[k] + t[k];
-    free(b); free(e); free(f); free(s); free(t);
+    free(b); free(e); free(f); free(s); free(t); free(u); free(tt);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -478,3 +478,84 @@ def test_nested_dissection_numbering(oracle_mod):
     d0 = depth(l0, O0.ilut()[0][1])
     d1 = depth(l1, O1.ilut()[0][1])
     assert d1 < d0
+
+
+# ------------------------------------------------------ GMG-ND fine smoother
+def _nd_case(name):
+    if name == "fv2d_24":
+        p = W.scaled("fv2d", 24)
+    elif name == "fv3d_8":
+        p = W.scaled("fv3d", 8)
+    else:
+        p = W.scaled("rgg", 500)
+    return p.rowptr, p.col, p.val, p.n_rows
+
+
+@pytest.mark.parametrize("case", ["fv2d_24", "fv3d_8", "rgg_500"])
+def test_fine_nd_smoother(oracle_mod, case):
+    """GMG-ND (Section 3.1 variants): the smoother is ILU(0) of A renumbered by
+    nested dissection.  The numbering equals the recursive definition on A's
+    graph; F = A[perm][:, perm]; its factors satisfy the ILU(0) definition
+    (L U = F on F's pattern); the preconditioner and its adjoint equal the
+    dense Eq. (twogrid) operator built with S = Q^T L U Q."""
+    rp, ci, v, n = _nd_case(case)
+    O = oracle_mod.Oracle(rp, ci, v, fine_order=1)
+    perm, (frp, fci, fv) = O.fine()
+    ref = B.nd_order_ref(n, B.coarse_pattern_adj(rp, ci, np.arange(n), n))
+    assert np.array_equal(perm, np.array(ref))
+    assert not np.array_equal(perm, np.arange(n))
+    A = B.dense(rp, ci, v)
+    F = B.dense(frp, fci, fv)
+    assert np.array_equal(F, A[np.ix_(perm, perm)])
+    Fi = B.dense(frp, fci, O.ilu0())
+    L = np.tril(Fi, -1) + np.eye(n)
+    U = np.triu(Fi)
+    pat = F != 0
+    assert np.allclose((L @ U)[pat], F[pat], rtol=1e-12, atol=1e-12 * np.abs(F).max())
+    # dense two-grid operator
+    LU = L @ U
+    Q = np.zeros((n, n))
+    Q[np.arange(n), perm] = 1.0                        # (Q x)_k = x[perm[k]]
+    Sinv = Q.T @ np.linalg.inv(LU) @ Q
+    (lrp, lci, lv), (urp, uci, uv) = O.ilut()
+    Lc = B.dense(lrp, lci, lv, O.nc) + np.eye(O.nc)
+    Uc = B.dense(urp, uci, uv, O.nc)
+    P = B.prolongation(O.aggregates(), O.nc)
+    Minv = P @ np.linalg.inv(Lc @ Uc) @ P.T
+    Binv = Sinv + Minv @ (np.eye(n) - A @ Sinv)
+    z = np.random.default_rng(5).uniform(-1, 1, n)
+    q = O.apply(z)
+    assert np.allclose(q, Binv @ z, rtol=1e-9, atol=1e-9 * np.abs(Binv @ z).max())
+    qa = O.apply_adjoint(z)
+    assert np.allclose(qa, Binv.T @ z, rtol=1e-9, atol=1e-9 * np.abs(Binv.T @ z).max())
+    # the natural numbering is the same operator with Q = I
+    O0 = oracle_mod.Oracle(rp, ci, v, fine_order=0)
+    p0, (r0, c0, v0) = O0.fine()
+    assert np.array_equal(p0, np.arange(n)) and np.array_equal(r0, rp) and np.array_equal(v0, v)
+
+
+def test_fine_nd_exact_on_dense_blocks(oracle_mod):
+    """Block-diagonal A with dense, diagonally dominant blocks of at most 40
+    rows under a shuffled numbering: ILU(0) keeps every entry of each block, so
+    the smoother is exact in either numbering and the preconditioner is A^{-1}
+    (any mix-up of the permutation's two directions breaks this)."""
+    rng = np.random.default_rng(11)
+    sizes = [int(s) for s in rng.integers(5, 41, size=12)]
+    n = sum(sizes)
+    A = np.zeros((n, n))
+    o = 0
+    for s in sizes:
+        Bk = rng.uniform(-1, 1, (s, s))
+        Bk[np.arange(s), np.arange(s)] = np.abs(Bk).sum(axis=1) + 1.0
+        A[o:o + s, o:o + s] = Bk
+        o += s
+    sh = rng.permutation(n)
+    A = A[np.ix_(sh, sh)]
+    z = rng.uniform(-1, 1, n)
+    x = np.linalg.solve(A, z)
+    for fo in (0, 1):
+        O = _mk(oracle_mod, A, fine_order=fo)
+        q = O.apply(z)
+        assert np.allclose(q, x, rtol=1e-10, atol=1e-10 * np.abs(x).max()), fo
+    perm, _ = _mk(oracle_mod, A, fine_order=1).fine()
+    assert not np.array_equal(perm, np.arange(n))
