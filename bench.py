@@ -8,7 +8,7 @@ FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
 before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K]
+                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K] [--fine-nd]
        python bench.py --copy-calibration   (a plain 1 GiB device copy, run
                        under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
 
@@ -146,6 +146,8 @@ def main():
                     help="also time the exact coarse solve (ILUT tau = 0: complete LU of A_c), reported beside")
     ap.add_argument("--jacobi", type=int, default=0,
                     help="also time the coarse solve by K Jacobi sweeps per ILUT factor, reported beside")
+    ap.add_argument("--fine-nd", action="store_true",
+                    help="also time GMG-ND (ILU(0) smoother in nested-dissection order), reported beside")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -329,6 +331,31 @@ def main():
             relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xj.cpu().numpy()) / np.linalg.norm(p.b[:, 0])))
         print(f"[bench] Jacobi coarse step ({args.jacobi} sweeps): {tj:.3f}s its={rj.info['iters']}", file=sys.stderr,
               flush=True)
+
+    if args.fine_nd:
+        # the paper's GMG-ND variant: ILU(0) of A renumbered by nested
+        # dissection, applied over the dissection tree; one warm and one timed
+        # setup + solve in FP64, then one profiled solve for the fine sweeps
+        def nd_step(profile=False):
+            Sn = Solver(rp, ci, va, cf=SOLVE_OPTS["cf"], ilut_tau=SOLVE_OPTS["ilut_tau"], fine_order=1)
+            if profile:
+                Sn.profile(True)
+            xn, rn = Sn.solve(b, tol=TOL, restart=SOLVE_OPTS["restart"], maxit=SOLVE_OPTS["maxit"])
+            return Sn, xn, rn, (Sn.profile_read() if profile else None)
+        nd_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sn, xn, rn, _ = nd_step()
+        torch.cuda.synchronize()
+        tn = time.perf_counter() - t0
+        _, _, _, prn = nd_step(True)
+        out["gmg_nd"] = dict(
+            time_s=round(tn, 6), setup_ms=round(Sn.setup_info["setup_ms"], 2), solve_ms=round(rn.info["solve_ms"], 2),
+            iters=rn.info["iters"], status=int(rn.status), levels_L0=Sn.setup_info["levels_L0"],
+            relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xn.cpu().numpy()) / np.linalg.norm(p.b[:, 0])),
+            kernels={k: dict(launches=v["launches"], total_ms=round(v["ms"], 4)) for k, v in prn.items()
+                     if v["launches"]})
+        print(f"[bench] GMG-ND step: {tn:.3f}s its={rn.info['iters']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

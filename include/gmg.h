@@ -87,6 +87,13 @@ typedef struct {
                            them only in the coarse solves' summation order      */
   int sweep_wg_chunks;  /* level sweeps under sweep_kernel 0 or 3: dependency levels of at most this many
                            64-lane chunks run on one workgroup (default 8; 0: never) */
+  int fine_order;       /* numbering of the ILU(0) smoother: 0 (default) A's own;
+                           1 nested dissection of A's graph (the GMG-ND variant of
+                           Section 3.1): S = Q^T L0 U0 Q with L0 U0 = ILU(0) of
+                           Q A Q^T, applied over the dissection tree under
+                           sweep_kernel 0 (level sweeps otherwise, or when a
+                           separator exceeds 2048 rows).  Aggregates, A_c and
+                           its ILUT do not depend on it.  No adjoint.           */
 } gmg_options;
 
 typedef struct {
@@ -155,9 +162,16 @@ gmg_status gmg_get_aggregates(gmg_handle h, int32_t* agg);
 /* A_c as CSR into device arrays rowptr[N_c+1], col[nnz_coarse], val[nnz_coarse]. */
 gmg_status gmg_get_coarse(gmg_handle h, int32_t* rowptr, int32_t* col, double* val);
 
-/* ILU(0) factors as values on A's pattern (device double[nnz]): the strictly
- * lower part is L0 (unit diagonal implied), the rest is U0. */
+/* ILU(0) factors as values on the pattern of the smoother's matrix (device
+ * double[nnz]): A's pattern, or under fine_order 1 that of Q A Q^T (row k is
+ * row perm[k] of A, columns renumbered and ascending).  The strictly lower
+ * part is L0 (unit diagonal implied), the rest is U0. */
 gmg_status gmg_get_ilu0(gmg_handle h, double* val);
+
+/* The smoother's numbering: perm (device int32[N]) with position k holding
+ * fine unknown perm[k]; the identity under fine_order 0.  Section 3.1
+ * (GMG-ND) and the dissection rule of the coarse numbering. */
+gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm);
 
 /* ILUT factors of A_c: L~ strictly lower (unit diagonal implied) and U~ with
  * its diagonal first in each row; device arrays sized by gmg_get_info. */

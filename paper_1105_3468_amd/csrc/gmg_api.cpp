@@ -80,6 +80,15 @@ struct Solver {
   WaveSweep wL0, wU0, wU0t, wL0t;
   DBuf<double> wz, wy, wt;
   DBuf<float> wz32, wy32, wt32;
+  // smoother in nested-dissection numbering (fine_order 1): the smoother's
+  // matrix F = Q A Q^T (pattern), position -> unknown, and its factors over
+  // the dissection tree (or level sweeps in S.L0/S.U0)
+  bool fine_nd = false, ftree = false;
+  DBuf<int> fperm, frp, fci;
+  std::vector<NdNode> fnd_tree;
+  TreeSolve tL0, tU0;
+  DBuf<double> fext, fzp, ftp;
+  DBuf<float> fext32, fzp32, ftp32;
   // Krylov workspace
   int mcap = 0;
   size_t ld = 0;
@@ -656,6 +665,16 @@ static void reset_cycle_buffers(Solver& S) {
     for (TreeSolve* t : {&S.tLc, &S.tUc, &S.tUct, &S.tLct})
       if (t->ncount.p) launch_fill_f32_bits(reinterpret_cast<float*>(t->ncount.p), 0u, t->ncount.n, s);
   }
+  if (S.ftree) {
+    launch_fill_f64_bits(S.fext.p, kSent64, S.n, s);
+    launch_fill_f32_bits(S.fext32.p, kSent32, S.n, s);
+    for (TreeSolve* t : {&S.tL0, &S.tU0})
+      if (t->ncount.p) launch_fill_f32_bits(reinterpret_cast<float*>(t->ncount.p), 0u, t->ncount.n, s);
+  }
+  if (S.fine_nd) {
+    launch_fill_f64_bits(S.ftp.p, kSent64, S.n, s);
+    launch_fill_f32_bits(S.ftp32.p, kSent32, S.n, s);
+  }
   launch_fill_f64_bits(S.y.p, kSent64, S.n, s);
   launch_fill_f64_bits(S.t.p, kSent64, S.n, s);
   launch_fill_f64_bits(S.yc.p, kSent64, S.nc, s);
@@ -689,6 +708,22 @@ static void vcycle(Solver& S, const double* z, double* q) {
     Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false) + sweep_bytes(S.U0, sz, sz, true));
     launch_wave_pair<T>(S.wg, S.wL0, S.wU0, z, true, F32 ? (T*)S.wz32.p : (T*)S.wz.p, F32 ? (T*)S.wy32.p : (T*)S.wy.p,
                         F32 ? (T*)S.wt32.p : (T*)S.wt.p, t, S.abort_flag.p, s);
+  } else if (S.fine_nd) {
+    // t = Q^T U0^{-1} L0^{-1} Q z
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, sz, false) + sweep_bytes(S.U0, sz, sz, true) +
+                                 (double)S.n * (2 * 4 + 8 + 3 * sz));
+    T* zp = F32 ? (T*)S.fzp32.p : (T*)S.fzp.p;
+    T* tp = F32 ? (T*)S.ftp32.p : (T*)S.ftp.p;
+    launch_perm_gather<T>(S.n, S.fperm.p, z, zp, s);
+    if (S.ftree) {
+      T* ext = F32 ? (T*)S.fext32.p : (T*)S.fext.p;
+      launch_tree<T>(S.tL0, zp, false, y, nullptr, ext, S.abort_flag.p, s);
+      launch_tree<T>(S.tU0, y, false, tp, y, ext, S.abort_flag.p, s);
+    } else {
+      run_tri<T>(S, S.L0, zp, false, y, nullptr);
+      run_tri<T>(S, S.U0, y, false, tp, y);
+    }
+    launch_perm_scatter<T>(S.n, S.fperm.p, tp, t, s);
   } else {
     {
       Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false));
@@ -1091,8 +1126,8 @@ static gmg_status solve_impl(Solver& S, bool adjoint, const double* b, double* x
   }
   if (opt.restart < 1 || opt.restart > kMaxRestart) fail(GMG_ERR_INVALID_ARG, "restart must be in [1, 2048]");
   if (opt.maxit < 0) fail(GMG_ERR_INVALID_ARG, "maxit must be >= 0");
-  if (adjoint && (opt.precond_fp32 || S.opt.coarse_mode != 0))
-    fail(GMG_ERR_INVALID_ARG, "the adjoint solve needs coarse_mode 0 and FP64");
+  if (adjoint && (opt.precond_fp32 || S.opt.coarse_mode != 0 || S.fine_nd))
+    fail(GMG_ERR_INVALID_ARG, "the adjoint solve needs coarse_mode 0, fine_order 0 and FP64");
   auto t0 = std::chrono::steady_clock::now();
   reset_cycle_buffers(S);
   gmg_status worst = GMG_OK;
@@ -1236,7 +1271,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
       o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
       o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 3 ||
-      o.sweep_wg_chunks < 0)
+      o.sweep_wg_chunks < 0 || o.fine_order < 0 || o.fine_order > 1)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
   auto t0 = std::chrono::steady_clock::now();
   // GMG_LOG also prints the duration of each setup phase (it then waits for
@@ -1354,6 +1389,62 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
   std::vector<int> hci = to_host_int(S.A.ci.p, nnz64, s);
   HIPCK(hipStreamSynchronize(s));
+  // ---- GMG-ND: the smoother works on F = Q A Q^T, Q the nested-dissection
+  // numbering of A's graph (the coarse numbering's rule); from here on
+  // hrp/hci hold F's pattern
+  const int* frp_dev = S.A.rp.p;
+  const int* fci_dev = S.A.ci.p;
+  const double* fval_dev = S.A.v.p;
+  DBuf<double> fval;
+  if (o.fine_order == 1) {
+    std::vector<int> cnt(n + 1, 0);
+    for (int i = 0; i < n; ++i)
+      for (int p = hrp[i]; p < hrp[i + 1]; ++p)
+        if (hci[p] != i) { cnt[i + 1]++; cnt[hci[p] + 1]++; }
+    for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int> gci(cnt[n]), fillp(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int p = hrp[i]; p < hrp[i + 1]; ++p)
+        if (hci[p] != i) { gci[fillp[i]++] = hci[p]; gci[fillp[hci[p]]++] = i; }
+    std::vector<int> perm = nd_numbering(n, cnt, gci, &S.fnd_tree);
+    std::vector<int> rank(n), brp(n + 1, 0), bci(nnz64), bsrc(nnz64);
+    for (int k = 0; k < n; ++k) rank[perm[k]] = k;
+    for (int k = 0; k < n; ++k) brp[k + 1] = brp[k] + hrp[perm[k] + 1] - hrp[perm[k]];
+    parallel_ranges(n, [&](int k0, int k1, int) {
+      std::vector<std::pair<int, int>> row;
+      for (int k = k0; k < k1; ++k) {
+        const int i = perm[k];
+        row.clear();
+        for (int p = hrp[i]; p < hrp[i + 1]; ++p) row.emplace_back(rank[hci[p]], p);
+        std::sort(row.begin(), row.end());
+        for (size_t q = 0; q < row.size(); ++q) {
+          bci[brp[k] + q] = row[q].first;
+          bsrc[brp[k] + q] = row[q].second;
+        }
+      }
+    });
+    S.fperm.alloc(n);
+    S.frp.alloc(n + 1);
+    S.fci.alloc(nnz64);
+    fval.alloc(nnz64);
+    h2d(S.fperm.p, perm.data(), n, s);
+    h2d(S.frp.p, brp.data(), n + 1, s);
+    h2d(S.fci.p, bci.data(), nnz64, s);
+    {
+      DBuf<int> dsrc;
+      dsrc.alloc(nnz64);
+      h2d(dsrc.p, bsrc.data(), nnz64, s);
+      launch_gather_f64(S.A.v.p, dsrc.p, fval.p, nnz64, s);
+      HIPCK(hipStreamSynchronize(s));
+    }
+    hrp.swap(brp);
+    hci.swap(bci);
+    frp_dev = S.frp.p;
+    fci_dev = S.fci.p;
+    fval_dev = fval.p;
+    S.fine_nd = true;
+    phase("fine nested dissection");
+  }
   std::vector<int> hdpos(n);
   for (int i = 0; i < n; ++i)
     for (int p = hrp[i]; p < hrp[i + 1]; ++p)
@@ -1377,7 +1468,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   phase("fine dependency lists");
   // ---- ILU(0), one launch per level of L0
   S.ilu.alloc(nnz64);
-  d2d(S.ilu.p, S.A.v.p, nnz64, s);
+  d2d(S.ilu.p, fval_dev, nnz64, s);
   {
     std::vector<int> sched, lptr;
     int levels = 0;
@@ -1388,7 +1479,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     h2d(dsched.p, sched.data(), sched.size(), s);
     launch_fill_u32(reinterpret_cast<unsigned*>(bad.p), 0u, 1, s);
     for (int l = 0; l < levels; ++l)
-      launch_ilu0_level(dsched.p + lptr[l], lptr[l + 1] - lptr[l], S.A.rp.p, S.A.ci.p, S.dpos.p, S.ilu.p, bad.p, s);
+      launch_ilu0_level(dsched.p + lptr[l], lptr[l + 1] - lptr[l], frp_dev, fci_dev, S.dpos.p, S.ilu.p, bad.p, s);
     int hb = 0;
     d2h(&hb, bad.p, 1, s);
     HIPCK(hipStreamSynchronize(s));
@@ -1403,7 +1494,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   // transposes then have it too: the same offsets, mirrored); else the
   // level-scheduled sweeps
   S.wave = false;
-  if (o.sweep_kernel == 0 || o.sweep_kernel == 3) {
+  if ((o.sweep_kernel == 0 || o.sweep_kernel == 3) && !S.fine_nd) {
     const int nx = grid2d_nx(n, l_rp, l_ci, true);
     if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx) {
       WaveGrid& g = S.wg;
@@ -1426,10 +1517,39 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       phase("wavefront layout");
     }
   }
-  if (!S.wave) {
+  if (S.fine_nd && o.sweep_kernel == 0) {
+    // ILU(0) of F follows the dissection tree as the coarse ILUT does: the
+    // tree solves apply it when every node fits
+    std::vector<double> hilu(nnz64), hud(n);
+    d2h(hilu.data(), S.ilu.p, nnz64, s);
+    d2h(hud.data(), S.u0dinv.p, n, s);
+    HIPCK(hipStreamSynchronize(s));
+    if (build_tree(S.tL0, S.fnd_tree, n, l_rp, l_ci, &l_src, 0, hilu, true, nullptr, s) &&
+        build_tree(S.tU0, S.fnd_tree, n, u_rp, u_ci, &u_src, 0, hilu, false, &hud, s)) {
+      S.ftree = true;
+      S.fext.alloc(n);
+      S.fext32.alloc(n);
+      S.L0.n = S.U0.n = n;
+      S.L0.nnz = (int64_t)l_ci.size();
+      S.U0.nnz = (int64_t)u_ci.size();
+      S.U0.has_diag = true;
+      S.L0.levels = S.U0.levels = S.tL0.heights;
+      phase("fine tree solves");
+    } else {
+      S.tL0 = TreeSolve();
+      S.tU0 = TreeSolve();
+    }
+  }
+  if (!S.wave && !S.ftree) {
     build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
     build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
     phase("fine sweeps");
+  }
+  if (S.fine_nd) {
+    S.fzp.alloc(n);
+    S.ftp.alloc(n);
+    S.fzp32.alloc(n);
+    S.ftp32.alloc(n);
   }
   // ---- the ILUT started above
   ilut_job.t.join();
@@ -1580,6 +1700,7 @@ void gmg_default_options(gmg_options* o) {
   o->coarse_order = 1;
   o->sweep_kernel = 0;
   o->sweep_wg_chunks = 8;
+  o->fine_order = 0;
 }
 
 gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
@@ -1621,7 +1742,8 @@ gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int preci
     Solver& S = h->S;
     gmg::reset_cycle_buffers(S);
     if (adjoint) {
-      if (precision != 0 || S.opt.coarse_mode != 0) gmg::fail(GMG_ERR_INVALID_ARG, "adjoint apply is FP64, coarse_mode 0");
+      if (precision != 0 || S.opt.coarse_mode != 0 || S.fine_nd)
+        gmg::fail(GMG_ERR_INVALID_ARG, "adjoint apply is FP64, coarse_mode 0, fine_order 0");
       gmg::vcycle_adjoint(S, z, q);
     } else if (precision == 1) {
       gmg::vcycle<float>(S, z, q);
@@ -1723,6 +1845,23 @@ gmg_status gmg_get_ilu0(gmg_handle h, double* val) {
     if (!val) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     gmg::d2d(val, h->S.ilu.p, h->S.nnz, h->S.s);
     HIPCK(hipStreamSynchronize(h->S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    if (!perm) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    gmg::Solver& S = h->S;
+    if (S.fine_nd) {
+      gmg::d2d(perm, S.fperm.p, S.n, S.s);
+    } else {
+      std::vector<int> id(S.n);
+      for (int k = 0; k < S.n; ++k) id[k] = k;
+      gmg::h2d(perm, id.data(), S.n, S.s);
+    }
+    HIPCK(hipStreamSynchronize(S.s));
     return GMG_OK;
   });
 }

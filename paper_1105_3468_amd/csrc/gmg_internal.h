@@ -236,6 +236,11 @@ void transpose_csr(int n, int m, int64_t nnz, const int* rp, const int* ci, cons
                    DBuf<int>& trp, DBuf<int>& tci, DBuf<double>* tv, DBuf<int>* tsrc,
                    hipStream_t s);
 void launch_gather_f64(const double* src, const int* idx, double* dst, int64_t n, hipStream_t s);
+// zp[k] = z[perm[k]]; and t[perm[k]] = tp[k] with tp reset to the sentinel
+template <class T>
+void launch_perm_gather(int n, const int* perm, const double* z, T* zp, hipStream_t s);
+template <class T>
+void launch_perm_scatter(int n, const int* perm, T* tp, T* t, hipStream_t s);
 void launch_exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, DBuf<int>& tmp);
 
 // Triangular sweeps (k_sweep.hip)

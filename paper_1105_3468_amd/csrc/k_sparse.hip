@@ -87,6 +87,37 @@ void launch_gather_f64(const double* src, const int* idx, double* dst, int64_t n
   HIPCK(hipGetLastError());
 }
 
+// Smoother in nested-dissection numbering: zp[k] = z[perm[k]] on the way in;
+// t[perm[k]] = tp[k] on the way out, tp[k] <- sentinel (the next cycle's
+// upper solve publishes into it again).
+template <class T>
+__global__ void k_perm_gather(int n, const int* __restrict__ perm, const double* __restrict__ z, T* __restrict__ zp) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) zp[k] = (T)z[perm[k]];
+}
+template <class T>
+__global__ void k_perm_scatter(int n, const int* __restrict__ perm, T* __restrict__ tp, T* __restrict__ t) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    t[perm[k]] = tp[k];
+    tp[k] = sentinel_of<T>(0);
+  }
+}
+template <class T>
+void launch_perm_gather(int n, const int* perm, const double* z, T* zp, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_perm_gather<T>, dim3(grid_for(n)), dim3(256), 0, s, n, perm, z, zp);
+  HIPCK(hipGetLastError());
+}
+template <class T>
+void launch_perm_scatter(int n, const int* perm, T* tp, T* t, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_perm_scatter<T>, dim3(grid_for(n)), dim3(256), 0, s, n, perm, tp, t);
+  HIPCK(hipGetLastError());
+}
+template void launch_perm_gather<double>(int, const int*, const double*, double*, hipStream_t);
+template void launch_perm_gather<float>(int, const int*, const double*, float*, hipStream_t);
+template void launch_perm_scatter<double>(int, const int*, double*, double*, hipStream_t);
+template void launch_perm_scatter<float>(int, const int*, float*, float*, hipStream_t);
+
 // ------------------------------------------------------------------ SpMV
 // One workgroup of 256 lanes owns 256 consecutive rows.  When the tile's
 // entries fit in LDS, the lanes first stream the tile's (col, val) pairs with

@@ -21,6 +21,7 @@ ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOT_SETUP, ERR_STALLED = -5, -6, -7, -8
 EXPORTED = [
     "gmg_default_options", "gmg_setup", "gmg_solve", "gmg_solve_adjoint", "gmg_apply_precond",
     "gmg_spmv", "gmg_get_info", "gmg_cond_estimate", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
+    "gmg_get_fine_perm",
     "gmg_get_ilut", "gmg_set_stream", "gmg_profile_enable", "gmg_profile_read",
     "gmg_profile_name", "gmg_destroy", "gmg_last_error", "gmg_fv_nnz", "gmg_fv_assemble",
     "gmg_fv_kappa_grad", "gmg_pattern_grad",
@@ -33,7 +34,7 @@ class Options(C.Structure):
                 ("coarse_sweeps", C.c_int), ("restart", C.c_int), ("maxit", C.c_int),
                 ("precond_fp32", C.c_int), ("x0_given", C.c_int), ("sweep_waves", C.c_int),
                 ("coarse_order", C.c_int), ("sweep_kernel", C.c_int),
-                ("sweep_wg_chunks", C.c_int)]
+                ("sweep_wg_chunks", C.c_int), ("fine_order", C.c_int)]
 
 
 class Info(C.Structure):
@@ -79,6 +80,7 @@ def load():
         "gmg_get_aggregates": (I, [P, P]),
         "gmg_get_coarse": (I, [P, P, P, P]),
         "gmg_get_ilu0": (I, [P, P]),
+        "gmg_get_fine_perm": (I, [P, P]),
         "gmg_get_ilut": (I, [P, P, P, P, P, P, P]),
         "gmg_set_stream": (I, [P, P]),
         "gmg_profile_enable": (I, [P, I]),
@@ -209,6 +211,12 @@ class Solver:
         v = self._torch.empty(self.nnz, dtype=self._torch.float64, device="cuda")
         _check(load().gmg_get_ilu0(self._h, _ptr(v)), "ilu0")
         return v
+
+    def fine_perm(self):
+        """The smoother's numbering: position k holds fine unknown perm[k]."""
+        v = self._torch.empty(max(self.n, 1), dtype=self._torch.int32, device="cuda")
+        _check(load().gmg_get_fine_perm(self._h, _ptr(v)), "fine_perm")
+        return v[:self.n]
 
     def ilut(self):
         inf = self.info()

@@ -371,6 +371,69 @@ def test_condition_estimates():
     assert ests[1][0] > 100 * ests[0][0] and ests[1][1] > 100 * ests[0][1]
 
 
+ND_CASES = {
+    "fv2d_64": lambda: W.make("fv2d_64"),
+    "fv3d_20": lambda: W.scaled("fv3d", 20),
+    "rgg_3001": lambda: W.scaled("rgg", 3001),
+}
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("name", list(ND_CASES))
+def test_fine_nd_smoother(name, kernel):
+    """GMG-ND (Section 3.1 variants): the smoother's nested-dissection
+    numbering and its ILU(0) factors bit-exact vs the oracle; one application
+    in FP64 within 1e-12, in FP32 within the FP32 bar; a converged solve
+    within one step of the oracle's; the adjoint refused.  kernel 0: tree
+    solves over the dissection tree; 1: whole-device level sweeps."""
+    _say(f"[case] fine_order=1 {name} sweep_kernel={kernel}")
+    p = ND_CASES[name]()
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    O = oracle.Oracle(p.rowptr, p.col, p.val, fine_order=1)
+    S = Solver(p.rowptr, p.col, p.val, fine_order=1, sweep_kernel=kernel)
+    perm, _ = O.fine()
+    assert np.array_equal(S.fine_perm().cpu().numpy(), perm)
+    assert np.array_equal(S.ilu0().cpu().numpy().view(np.uint64), O.ilu0().view(np.uint64))
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        z = rng.uniform(-1, 1, p.n_rows)
+        q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
+        ref = O.apply(z, 0)
+        assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref), name
+    q32 = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
+    ref32 = O.apply(z, 1)
+    e32 = np.linalg.norm(q32 - ref32) / np.linalg.norm(ref32)
+    e64 = np.linalg.norm(ref32 - ref) / np.linalg.norm(ref)
+    assert e32 <= max(1e-4, 10 * e64), (e32, e64)
+    b = p.b[:, 0]
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8)
+    xh = x.cpu().numpy()
+    assert res.status == G.OK and np.linalg.norm(b - A @ xh) / np.linalg.norm(b) < 1e-8, res.info
+    _, info = O.solve(b, tol=1e-8)
+    assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
+    with pytest.raises(GmgError):
+        S.apply(torch.as_tensor(z, device="cuda"), precision=0, adjoint=True)
+    if kernel == 0:
+        S0 = Solver(p.rowptr, p.col, p.val)
+        assert np.array_equal(S0.fine_perm().cpu().numpy(), np.arange(p.n_rows))
+
+
+def test_fine_nd_large_separator():
+    """GMG-ND on 64^3 cells: the first separator has more rows than one tree
+    node may hold, so the level sweeps apply the factors; same bars."""
+    _say("[case] fine_order=1 fv3d_64 (level sweeps)")
+    p = W.scaled("fv3d", 64)
+    O = oracle.Oracle(p.rowptr, p.col, p.val, fine_order=1)
+    S = Solver(p.rowptr, p.col, p.val, fine_order=1)
+    perm, _ = O.fine()
+    assert np.array_equal(S.fine_perm().cpu().numpy(), perm)
+    assert np.array_equal(S.ilu0().cpu().numpy().view(np.uint64), O.ilu0().view(np.uint64))
+    z = np.random.default_rng(6).uniform(-1, 1, p.n_rows)
+    q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
+    ref = O.apply(z, 0)
+    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_tiny_and_degenerate():
     _say("[case] tiny")
     # 1x1, diagonal matrices, a 2x2 that needs no pivoting

@@ -42,9 +42,9 @@ def test_default_options_and_struct_layout(lib):
     # same default hash seed as the oracle's reading
     import oracle
     assert o.hash_seed == oracle.default_options()["seed"]
-    assert o.sweep_kernel == 0 and o.sweep_wg_chunks == 8
-    # C layout: 12 ints, one uint64, two doubles, no padding
-    assert ctypes.sizeof(gmg.Options) == 72
+    assert o.sweep_kernel == 0 and o.sweep_wg_chunks == 8 and o.fine_order == 0
+    # C layout: 13 ints, one uint64, two doubles, 4 bytes of tail padding
+    assert ctypes.sizeof(gmg.Options) == 80
     assert ctypes.sizeof(gmg.Info) == 4 * 9 + 4 + 8 * 6 + 8 * 4
 
 
@@ -69,3 +69,30 @@ def test_no_gpu_raises_cleanly():
     p = W.scaled("fv2d", 8)
     with pytest.raises(RuntimeError):
         Solver(p.rowptr, p.col, p.val)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """Every field of the binding's Options and Info sits at the offset the C
+    header gives it (compiled with gcc against include/gmg.h)."""
+    import shutil
+    import subprocess
+    from paper_1105_3468_amd import gmg
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "gmg.h"', "int main(void) {"]
+    for cname, py in (("gmg_options", gmg.Options), ("gmg_info", gmg.Info)):
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", inc, str(src), "-o", str(exe)])
+    got = [int(t) for t in subprocess.check_output([str(exe)]).split()]
+    want = []
+    for py in (gmg.Options, gmg.Info):
+        want.append(ctypes.sizeof(py))
+        want += [getattr(py, f).offset for f, _ in py._fields_]
+    assert got == want
