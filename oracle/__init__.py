@@ -63,6 +63,7 @@ def _L():
         _lib.or_get_ilut.argtypes = [P, P, P, P, P, P, P]
         _lib.or_get_ilu0.argtypes = [P, P]
         _lib.or_get_fine.argtypes = [P, P, P, P, P]
+        _lib.or_get_spai.argtypes = [P, P, P, P]
         _lib.or_precond_apply.argtypes = [P, C.c_int, P, P]
         _lib.or_precond_apply_twosolve.argtypes = [P, P, P]
         _lib.or_precond_apply_adjoint.argtypes = [P, P, P]
@@ -156,6 +157,17 @@ class Oracle:
         ci = np.empty(self.nnz_c, dtype=np.int32)
         v = np.empty(self.nnz_c, dtype=np.float64)
         _L().or_get_coarse(self._h, _p(rp), _p(ci), _p(v))
+        return rp, ci, v
+
+    def spai(self):
+        """(rowptr, col, val) of the sparse approximate inverse of A_c
+        (coarse_mode = 2; the pattern of A_c)."""
+        if self.opts.coarse_mode != 2:
+            raise ValueError("spai needs coarse_mode = 2")
+        rp = np.empty(self.nc + 1, dtype=np.int32)
+        ci = np.empty(self.nnz_c, dtype=np.int32)
+        v = np.empty(self.nnz_c, dtype=np.float64)
+        _L().or_get_spai(self._h, _p(rp), _p(ci), _p(v))
         return rp, ci, v
 
     def fine(self):

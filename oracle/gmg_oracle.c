@@ -45,7 +45,8 @@ typedef struct {
     int qbits;           /* mantissa bits of the weight kept in the edge key      */
     uint64_t seed;       /* hash seed of the edge key                             */
     double ilut_tau;     /* ILUT drop tolerance (relative to the row 2-norm)      */
-    int coarse_mode;     /* 0: exact triangular sweeps, 1: Jacobi sweeps          */
+    int coarse_mode;     /* 0: exact triangular sweeps, 1: Jacobi sweeps,
+                            2: sparse approximate inverse of A_c                 */
     int coarse_sweeps;   /* Jacobi sweeps per factor when coarse_mode == 1        */
     int coarse_order;    /* 0: aggregates by smallest fine index; 1: nested dissection */
     int fine_order;      /* 0: ILU(0) smoother on A's numbering; 1: on A renumbered by
@@ -71,11 +72,12 @@ typedef struct {
     int *fperm;          /* position -> fine unknown (fine_order 1)     */
     double *ilu;         /* ILU(0) values on F's pattern                */
     int *dpos;           /* position of the diagonal in each row of F   */
+    csr_t Mc;            /* sparse approximate inverse of A_c (coarse_mode 2)    */
     csr_t Lc, Uc;        /* ILUT factors: Lc strictly lower (unit diag implied),
                             Uc upper with the diagonal stored first    */
     or_opts o;
     /* FP32 copies for the single-precision preconditioner */
-    float *v32, *ilu32, *lc32, *uc32;
+    float *v32, *ilu32, *lc32, *uc32, *mc32;
 } or_solver;
 
 static void csr_free(csr_t *m) {
@@ -695,6 +697,91 @@ static int ilut(const csr_t *M, double tau, csr_t *L, csr_t *U) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Sparse approximate inverse of A_c (coarse_mode 2): a coarse solve that is  */
+/* one sparse product, for the parallel inexact coarse solves Section 2 asks */
+/* for once the coarse grid is large.  M has A_c's pattern; its column j     */
+/* minimises ||A_c m - e_j||_2 over m supported on J = {i : (A_c)_ij stored} */
+/* (a static-pattern SPAI).  Only the rows I where some column k in J of A_c */
+/* is stored enter, so the problem is the dense least squares                 */
+/* min ||A_c(I, J) m - e_j(I)||, solved by Householder QR and back           */
+/* substitution; I and J ascending.  The coarse solve is e_c = M r_c.        */
+/* ------------------------------------------------------------------------ */
+static int spai(or_solver *S) {
+    const csr_t *Ac = &S->Ac;
+    int nc = S->nc;
+    csr_t T = {0}, Mt = {0};
+    int st = transpose(Ac, &T);           /* row j of T = column j of A_c */
+    if (st) { csr_free(&T); return st; }
+    int nt = T.rp[nc];
+    Mt.n = nc;
+    Mt.rp = malloc(sizeof(int) * ((size_t)nc + 1));
+    Mt.ci = malloc(sizeof(int) * (size_t)(nt > 0 ? nt : 1));
+    Mt.v = malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
+    int *pos = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    int *I = malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+    if (!Mt.rp || !Mt.ci || !Mt.v || !pos || !I) { st = OR_ERR_OOM; goto out; }
+    memcpy(Mt.rp, T.rp, sizeof(int) * ((size_t)nc + 1));
+    memcpy(Mt.ci, T.ci, sizeof(int) * (size_t)nt);
+    for (int i = 0; i < nc; ++i) pos[i] = -1;
+    for (int j = 0; j < nc && !st; ++j) {
+        const int *J = T.ci + T.rp[j];
+        int nj = T.rp[j + 1] - T.rp[j], ni = 0;
+        for (int c = 0; c < nj; ++c)
+            for (int q = T.rp[J[c]]; q < T.rp[J[c] + 1]; ++q)
+                if (pos[T.ci[q]] < 0) { pos[T.ci[q]] = 0; I[ni++] = T.ci[q]; }
+        qsort(I, (size_t)ni, sizeof(int), int_cmp);
+        for (int r = 0; r < ni; ++r) pos[I[r]] = r;
+        /* dense A_c(I, J), row-major ni x nj, and e_j(I) */
+        double *H = calloc((size_t)ni * nj + 1, sizeof(double)), *b = calloc((size_t)ni + 1, sizeof(double));
+        if (!H || !b) { free(H); free(b); st = OR_ERR_OOM; break; }
+        for (int c = 0; c < nj; ++c)
+            for (int q = T.rp[J[c]]; q < T.rp[J[c] + 1]; ++q) H[(size_t)pos[T.ci[q]] * nj + c] = T.v[q];
+        if (pos[j] >= 0) b[pos[j]] = 1.0;
+        /* Householder QR: column c is reflected onto -sign(x_c) ||x|| e_c */
+        for (int c = 0; c < nj && c < ni; ++c) {
+            double nrm = 0.0;
+            for (int r = c; r < ni; ++r) nrm = nrm + H[(size_t)r * nj + c] * H[(size_t)r * nj + c];
+            nrm = sqrt(nrm);
+            if (nrm == 0.0) continue;
+            double x0 = H[(size_t)c * nj + c];
+            double alpha = x0 >= 0.0 ? -nrm : nrm;
+            /* v = x - alpha e_c (stored in place below the diagonal, v_c apart) */
+            double vc = x0 - alpha, vtv = vc * vc;
+            for (int r = c + 1; r < ni; ++r) vtv = vtv + H[(size_t)r * nj + c] * H[(size_t)r * nj + c];
+            for (int k = c + 1; k < nj; ++k) {
+                double d = vc * H[(size_t)c * nj + k];
+                for (int r = c + 1; r < ni; ++r) d = d + H[(size_t)r * nj + c] * H[(size_t)r * nj + k];
+                double f = 2.0 * d / vtv;
+                H[(size_t)c * nj + k] = H[(size_t)c * nj + k] - f * vc;
+                for (int r = c + 1; r < ni; ++r) H[(size_t)r * nj + k] = H[(size_t)r * nj + k] - f * H[(size_t)r * nj + c];
+            }
+            double d = vc * b[c];
+            for (int r = c + 1; r < ni; ++r) d = d + H[(size_t)r * nj + c] * b[r];
+            double f = 2.0 * d / vtv;
+            b[c] = b[c] - f * vc;
+            for (int r = c + 1; r < ni; ++r) b[r] = b[r] - f * H[(size_t)r * nj + c];
+            H[(size_t)c * nj + c] = alpha;
+        }
+        /* R m = (Q^T e_j)[0..nj) */
+        double *m = Mt.v + T.rp[j];
+        for (int c = nj - 1; c >= 0; --c) {
+            double t = b[c];
+            for (int k = c + 1; k < nj; ++k) t = t - H[(size_t)c * nj + k] * m[k];
+            double rcc = H[(size_t)c * nj + c];
+            if (rcc == 0.0) { st = OR_ERR_ZERO_PIVOT; break; }
+            m[c] = t / rcc;
+            if (!isfinite(m[c])) { st = OR_ERR_NONFINITE; break; }
+        }
+        for (int r = 0; r < ni; ++r) pos[I[r]] = -1;
+        free(H); free(b);
+    }
+    if (!st) st = transpose(&Mt, &S->Mc);
+out:
+    csr_free(&T); csr_free(&Mt); free(pos); free(I);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Setup                                                                      */
 /* ------------------------------------------------------------------------ */
 void or_default_opts(or_opts *o) {
@@ -712,7 +799,7 @@ void or_default_opts(or_opts *o) {
 void or_destroy(or_solver *S) {
     if (!S) return;
     csr_free(&S->A); csr_free(&S->G); csr_free(&S->Ac); csr_free(&S->Lc); csr_free(&S->Uc);
-    csr_free(&S->F); free(S->fperm);
+    csr_free(&S->F); free(S->fperm); csr_free(&S->Mc); free(S->mc32);
     free(S->agg); free(S->aptr); free(S->amem); free(S->ilu); free(S->dpos);
     free(S->v32); free(S->ilu32); free(S->lc32); free(S->uc32);
     free(S);
@@ -728,7 +815,7 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, const or_opts
     if (!S) return OR_ERR_OOM;
     S->o = *opts;
     if (S->o.qbits < 0 || S->o.qbits > 52 || !(S->o.cf >= 1.0) || S->o.coarse_order < 0 || S->o.coarse_order > 1 ||
-        S->o.fine_order < 0 || S->o.fine_order > 1) {
+        S->o.fine_order < 0 || S->o.fine_order > 1 || S->o.coarse_mode < 0 || S->o.coarse_mode > 2) {
         or_destroy(S);
         return OR_ERR_INVALID;
     }
@@ -767,16 +854,20 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, const or_opts
     if (!st) st = smoother_matrix(S);
     if (!st) st = ilu0(S);
     if (!st) st = ilut(&S->Ac, S->o.ilut_tau, &S->Lc, &S->Uc);
+    if (!st && S->o.coarse_mode == 2) st = spai(S);
     if (!st) {
         S->v32 = malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
         S->ilu32 = malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
         int nl = S->Lc.rp[S->nc], nu = S->Uc.rp[S->nc];
         S->lc32 = malloc(sizeof(float) * (size_t)(nl > 0 ? nl : 1));
         S->uc32 = malloc(sizeof(float) * (size_t)(nu > 0 ? nu : 1));
-        if (!S->v32 || !S->ilu32 || !S->lc32 || !S->uc32) st = OR_ERR_OOM;
+        int nm = S->o.coarse_mode == 2 ? S->Mc.rp[S->nc] : 0;
+        S->mc32 = malloc(sizeof(float) * (size_t)(nm > 0 ? nm : 1));
+        if (!S->v32 || !S->ilu32 || !S->lc32 || !S->uc32 || !S->mc32) st = OR_ERR_OOM;
         else {
             for (int p = 0; p < nnz; ++p) { S->v32[p] = (float)S->A.v[p]; S->ilu32[p] = (float)S->ilu[p]; }
             for (int p = 0; p < nl; ++p) S->lc32[p] = (float)S->Lc.v[p];
+            for (int p = 0; p < nm; ++p) S->mc32[p] = (float)S->Mc.v[p];
             for (int p = 0; p < nu; ++p) S->uc32[p] = (float)S->Uc.v[p];
         }
     }
@@ -811,6 +902,8 @@ void or_get_ilut(const or_solver *S, int *lrp, int *lci, double *lv, int *urp, i
 void or_get_ilu0(const or_solver *S, double *vals) {
     memcpy(vals, S->ilu, sizeof(double) * (size_t)S->A.rp[S->A.n]);
 }
+/* the sparse approximate inverse of A_c (coarse_mode 2; A_c's pattern) */
+void or_get_spai(const or_solver *S, int *rp, int *ci, double *v) { get_csr(&S->Mc, rp, ci, v); }
 /* the smoother's numbering (position -> fine unknown) and matrix F */
 void or_get_fine(const or_solver *S, int *perm, int *rp, int *ci, double *v) {
     memcpy(perm, S->fperm, sizeof(int) * (size_t)S->A.n);
@@ -824,7 +917,7 @@ void or_get_fine(const or_solver *S, int *perm, int *rp, int *ci, double *v) {
 /* By linearity this equals Algorithm 1's t + f - q with f = M~^{-1} z and   */
 /* the second coarse solve applied to A t.                                   */
 /* ------------------------------------------------------------------------ */
-#define DEFINE_APPLY(T, SUF, AV, ILU, LCV, UCV)                                            \
+#define DEFINE_APPLY(T, SUF, AV, ILU, LCV, UCV, MCV)                                            \
 /* t = S^{-1} z, S = Q^T L0 U0 Q: u = Q z, y = L0^{-1} u, u = U0^{-1} y, t = Q^T u */  \
 static void fine_smooth_##SUF(const or_solver *S, const T *z, T *y, T *t, T *u) {         \
     const csr_t *F = &S->F;                                                                \
@@ -855,6 +948,15 @@ static void coarse_solve_##SUF(const or_solver *S, const T *rc, T *yc, T *ec, T 
             T s = yc[i];                                                                   \
             for (int p = U->rp[i] + 1; p < U->rp[i + 1]; ++p) s = s - (T)(UCV)[p] * ec[U->ci[p]]; \
             ec[i] = s / (T)(UCV)[U->rp[i]];                                                \
+        }                                                                                  \
+        return;                                                                            \
+    }                                                                                      \
+    if (S->o.coarse_mode == 2) {                                                           \
+        const csr_t *M = &S->Mc;                                                           \
+        for (int i = 0; i < nc; ++i) {                                                     \
+            T s = (T)0;                                                                    \
+            for (int p = M->rp[i]; p < M->rp[i + 1]; ++p) s = s + (T)(MCV)[p] * rc[M->ci[p]]; \
+            ec[i] = s;                                                                     \
         }                                                                                  \
         return;                                                                            \
     }                                                                                      \
@@ -896,8 +998,8 @@ static void apply_##SUF(const or_solver *S, const T *z, T *q, T *w) {           
     for (int k = 0; k < n; ++k) q[k] = t[k] + ec[S->agg[k]];                               \
 }
 
-DEFINE_APPLY(double, f64, S->A.v, S->ilu, S->Lc.v, S->Uc.v)
-DEFINE_APPLY(float, f32, S->v32, S->ilu32, S->lc32, S->uc32)
+DEFINE_APPLY(double, f64, S->A.v, S->ilu, S->Lc.v, S->Uc.v, S->Mc.v)
+DEFINE_APPLY(float, f32, S->v32, S->ilu32, S->lc32, S->uc32, S->mc32)
 
 /* workspace doubles needed by or_precond_apply */
 long or_work_size(const or_solver *S) { return 3L * S->A.n + 4L * S->nc + 8; }

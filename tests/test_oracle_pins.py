@@ -559,3 +559,53 @@ def test_fine_nd_exact_on_dense_blocks(oracle_mod):
         assert np.allclose(q, x, rtol=1e-10, atol=1e-10 * np.abs(x).max()), fo
     perm, _ = _mk(oracle_mod, A, fine_order=1).fine()
     assert not np.array_equal(perm, np.arange(n))
+
+
+# ------------------------------------------------- SPAI coarse solve (mode 2)
+@pytest.mark.parametrize("case", ["fv2d_24", "rgg_500"])
+def test_spai_columns_minimise_the_residual(oracle_mod, case):
+    """Each column of the sparse approximate inverse is the least-squares
+    minimiser of ||A_c m - e_j|| over A_c's column pattern: equal to an SVD
+    least-squares solve of the same problem, and its residual is orthogonal
+    to the columns it may use (normal equations)."""
+    rp, ci, v, n = _nd_case(case)
+    O = oracle_mod.Oracle(rp, ci, v, coarse_mode=2)
+    crp, cci, cv = O.coarse()
+    Ac = B.dense(crp, cci, cv, O.nc)
+    mrp, mci, mv = O.spai()
+    assert np.array_equal(mrp, crp) and np.array_equal(mci, cci)   # A_c's pattern
+    M = B.dense(mrp, mci, mv, O.nc)
+    pat = B.dense(crp, cci, np.ones_like(cv), O.nc) != 0          # stored entries, zeros included
+    for j in range(O.nc):
+        J = np.flatnonzero(pat[:, j])
+        e = np.zeros(O.nc)
+        e[j] = 1.0
+        ref = np.linalg.lstsq(Ac[:, J], e, rcond=None)[0]
+        m = M[J, j]
+        assert np.allclose(m, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max()), j
+        res = Ac[:, J] @ m - e
+        assert np.abs(Ac[:, J].T @ res).max() <= 1e-10 * np.abs(Ac[:, J]).max()
+        assert np.count_nonzero(M[:, j][np.setdiff1d(np.arange(O.nc), J)]) == 0
+
+
+def test_spai_special_cases(oracle_mod):
+    """A diagonal A_c gives M = D^{-1}; a dense A_c gives M = A_c^{-1}, so the
+    SPAI preconditioner equals the exact-coarse-solve one (ILUT tau = 0)."""
+    rng = np.random.default_rng(7)
+    d = rng.uniform(0.5, 3.0, 40)
+    O = _mk(oracle_mod, np.diag(d), coarse_mode=2)
+    mrp, mci, mv = O.spai()
+    assert np.array_equal(mci, np.arange(40)) and np.allclose(mv, 1.0 / d, rtol=1e-15, atol=0)
+    n = 12
+    A = rng.uniform(-1, 1, (n, n))
+    A[np.arange(n), np.arange(n)] = np.abs(A).sum(axis=1) + 1.0
+    agg = np.repeat(np.arange(n // 2), 2).astype(np.int32)
+    O2 = _mk(oracle_mod, A, agg=agg, coarse_mode=2)
+    crp, cci, cv = O2.coarse()
+    Ac = B.dense(crp, cci, cv, O2.nc)
+    assert np.all(Ac != 0)
+    M = B.dense(*O2.spai(), O2.nc)
+    assert np.allclose(M, np.linalg.inv(Ac), rtol=1e-12, atol=1e-13)
+    O0 = _mk(oracle_mod, A, agg=agg, coarse_mode=0, ilut_tau=0.0)
+    z = rng.uniform(-1, 1, n)
+    assert np.allclose(O2.apply(z), O0.apply(z), rtol=1e-12, atol=1e-13)
