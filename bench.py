@@ -8,7 +8,7 @@ FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
 before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K] [--fine-nd]
+                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K] [--fine-nd] [--spai]
        python bench.py --copy-calibration   (a plain 1 GiB device copy, run
                        under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
 
@@ -146,6 +146,8 @@ def main():
                     help="also time the exact coarse solve (ILUT tau = 0: complete LU of A_c), reported beside")
     ap.add_argument("--jacobi", type=int, default=0,
                     help="also time the coarse solve by K Jacobi sweeps per ILUT factor, reported beside")
+    ap.add_argument("--spai", action="store_true",
+                    help="also time the coarse solve by a sparse approximate inverse of A_c, reported beside")
     ap.add_argument("--fine-nd", action="store_true",
                     help="also time GMG-ND (ILU(0) smoother in nested-dissection order), reported beside")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -331,6 +333,25 @@ def main():
             relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xj.cpu().numpy()) / np.linalg.norm(p.b[:, 0])))
         print(f"[bench] Jacobi coarse step ({args.jacobi} sweeps): {tj:.3f}s its={rj.info['iters']}", file=sys.stderr,
               flush=True)
+
+    if args.spai:
+        # the parallel inexact coarse solve by a sparse approximate inverse of
+        # A_c (one sparse product per application); setup + solve in FP64
+        def spai_step():
+            Sa = Solver(rp, ci, va, cf=SOLVE_OPTS["cf"], coarse_mode=2)
+            xa, ra = Sa.solve(b, tol=TOL, restart=SOLVE_OPTS["restart"], maxit=SOLVE_OPTS["maxit"])
+            return Sa, xa, ra
+        spai_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sa, xa, ra = spai_step()
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        out["coarse_spai"] = dict(
+            time_s=round(ta, 6), setup_ms=round(Sa.setup_info["setup_ms"], 2), solve_ms=round(ra.info["solve_ms"], 2),
+            iters=ra.info["iters"], status=int(ra.status),
+            relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xa.cpu().numpy()) / np.linalg.norm(p.b[:, 0])))
+        print(f"[bench] SPAI coarse step: {ta:.3f}s its={ra.info['iters']}", file=sys.stderr, flush=True)
 
     if args.fine_nd:
         # the paper's GMG-ND variant: ILU(0) of A renumbered by nested

@@ -64,7 +64,9 @@ typedef struct {
   uint64_t hash_seed;   /* seed of that hash                                         */
   double ilut_tau;      /* ILUT drop tolerance relative to the row 2-norm (1e-4)     */
   int coarse_mode;      /* 0: exact triangular sweeps with the ILUT factors;
-                           1: coarse_sweeps Jacobi sweeps per factor                 */
+                           1: coarse_sweeps Jacobi sweeps per factor (FP64);
+                           2: e_c = M r_c with a sparse approximate inverse M of
+                           A_c on A_c's pattern (no ILUT is computed)           */
   int coarse_sweeps;    /* (default 3)                                               */
   int restart;          /* FGMRES restart length m (default 30, at most 2048)        */
   int maxit;            /* total FGMRES steps at most (default 600)                  */
@@ -152,7 +154,7 @@ gmg_status gmg_get_info(gmg_handle h, gmg_info* info);
  * lower bound of cond(A_c) when A_c is SPD; *est_ilut = max_i |(L~U~)_ii| /
  * min_i |(L~U~)_ii|, the unsymmetric form of the factorization's estimate,
  * (L~U~)_ii = u_ii + sum_{j<i} l_ij u_ji.  Both are host doubles; a zero
- * denominator gives +inf. */
+ * denominator gives +inf.  GMG_ERR_INVALID_ARG under coarse_mode 2. */
 gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut);
 
 /* Aggregate of every fine unknown: agg device int32[N]; ids 0..N_c-1 ordered
@@ -172,6 +174,14 @@ gmg_status gmg_get_ilu0(gmg_handle h, double* val);
  * fine unknown perm[k]; the identity under fine_order 0.  Section 3.1
  * (GMG-ND) and the dissection rule of the coarse numbering. */
 gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm);
+
+/* The sparse approximate inverse of A_c (coarse_mode 2), a parallel inexact
+ * coarse solve (Section 2 leaves parallel inexact coarse solves for large
+ * coarse grids to future work): A_c's pattern, column j the least-squares
+ * minimiser of ||A_c m - e_j||_2 over that column's pattern.  Device arrays
+ * rowptr[N_c+1], col[nnz_coarse], val[nnz_coarse]; GMG_ERR_INVALID_ARG under
+ * another coarse_mode. */
+gmg_status gmg_get_spai(gmg_handle h, int32_t* rowptr, int32_t* col, double* val);
 
 /* ILUT factors of A_c: L~ strictly lower (unit diagonal implied) and U~ with
  * its diagonal first in each row; device arrays sized by gmg_get_info. */

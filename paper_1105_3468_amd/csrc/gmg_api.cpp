@@ -59,6 +59,8 @@ struct Solver {
   Sweep L0, U0, Lc, Uc;        // forward factors
   Sweep U0t, L0t, Uct, Lct;    // transposed factors (adjoint)
   DCsr dLc, dUc;               // coarse factors as CSR (Jacobi mode)
+  HCsr hMc;                    // sparse approximate inverse of A_c (coarse_mode 2)
+  DCsr dMc;
   DBuf<double> ucdinv, jzero, jtmp;
   // forward V-cycle work vectors
   DBuf<double> y, t, r, rc, yc, ec;
@@ -759,6 +761,10 @@ static void vcycle(Solver& S, const double* z, double* q) {
       Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uc, sz, sz, true));
       run_tri<T>(S, S.Uc, yc, false, ec, yc);
     }
+  } else if (S.opt.coarse_mode == 2) {
+    // e_c = M r_c with the sparse approximate inverse
+    Prof p(S, PC_SWEEP_COARSE, (double)S.dMc.nnz * (4 + sz) + (double)S.nc * (4 + 2 * sz));
+    launch_spmv<T>(S.nc, S.dMc.rp.p, S.dMc.ci.p, F32 ? (const T*)S.dMc.v32.p : (const T*)S.dMc.v.p, rc, ec, s);
   } else {
     if (F32) fail(GMG_ERR_INVALID_ARG, "coarse_mode 1 runs in FP64 only");
     // Jacobi sweeps on each factor: y <- rc - (L~ - I) y from y = rc, then
@@ -1269,7 +1275,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   if (!rowptr || !col || !val) fail(GMG_ERR_INVALID_ARG, "setup: null matrix pointer");
   const gmg_options& o = S.opt;
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
-      o.coarse_mode < 0 || o.coarse_mode > 1 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
+      o.coarse_mode < 0 || o.coarse_mode > 2 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
       o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 3 ||
       o.sweep_wg_chunks < 0 || o.fine_order < 0 || o.fine_order > 1)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
@@ -1382,8 +1388,8 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       if (t.joinable()) t.join();
     }
   } ilut_job;
-  ilut_job.t = std::thread([&S, &hAc, &ilut_st, tau = o.ilut_tau] {
-    ilut_st = host_ilut(hAc, tau, S.hLc, S.hUc, &S.nd_tree);
+  ilut_job.t = std::thread([&S, &hAc, &ilut_st, tau = o.ilut_tau, spai = o.coarse_mode == 2] {
+    ilut_st = spai ? host_spai(hAc, S.hMc) : host_ilut(hAc, tau, S.hLc, S.hUc, &S.nd_tree);
   });
   // ---- host copy of A's pattern for the analysis
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
@@ -1553,67 +1559,87 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   }
   // ---- the ILUT started above
   ilut_job.t.join();
-  {
+  if (o.coarse_mode == 2) {
     const gmg_status st = ilut_st;
-    if (st == GMG_ERR_ZERO_PIVOT) fail(st, "ILUT: zero pivot");
-    if (st == GMG_ERR_OOM) fail(st, "ILUT: factor exceeds int32 indexing");
-    if (st != GMG_OK) fail(st, "ILUT: non-finite pivot");
-  }
-  phase("coarse ILUT (rest after the fine level)");
-  {
-    const int nc = S.nc;
-    const HCsr &L = S.hLc, &U = S.hUc;
-    std::vector<double> udinv(nc);
-    for (int i = 0; i < nc; ++i) udinv[i] = 1.0 / U.v[U.rp[i]];
-    // tree solves when the coarse unknowns are in nested-dissection order and
-    // both factors follow the tree (U without its leading diagonal entries);
-    // else the level-scheduled sweeps
-    S.tree = false;
-    if (o.sweep_kernel == 0 && o.coarse_order == 1 && !S.nd_tree.empty() &&
-        build_tree(S.tLc, S.nd_tree, nc, L.rp, L.ci, nullptr, 0, L.v, true, nullptr, s) &&
-        build_tree(S.tUc, S.nd_tree, nc, U.rp, U.ci, nullptr, 1, U.v, false, &udinv, s)) {
-      S.tree = true;
-      S.text.alloc(nc);
-      S.text32.alloc(nc);
-      // sizes and depths (profiling byte counts, info)
-      S.Lc.n = S.Uc.n = nc;
-      S.Lc.nnz = (int64_t)L.ci.size();
-      S.Uc.nnz = (int64_t)U.ci.size() - nc;
-      S.Uc.has_diag = true;
-      S.Lc.levels = S.Uc.levels = S.tLc.heights;
-      phase("coarse tree solves");
-    } else {
-      S.tLc = TreeSolve();
-      S.tUc = TreeSolve();
-      std::vector<int> lsrc(L.ci.size()), us_rp(nc + 1, 0), us_ci, us_src;
-      for (size_t q = 0; q < L.ci.size(); ++q) lsrc[q] = (int)q;
-      for (int i = 0; i < nc; ++i) {
-        for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) { us_ci.push_back(U.ci[q]); us_src.push_back(q); }
-        us_rp[i + 1] = (int)us_ci.size();
-      }
-      build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-      build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-      phase("coarse sweeps");
+    if (st == GMG_ERR_ZERO_PIVOT) fail(st, "SPAI: a column's least-squares problem is rank deficient");
+    if (st != GMG_OK) fail(st, "SPAI: non-finite entry");
+    const HCsr& M = S.hMc;
+    DCsr& D = S.dMc;
+    D.n = D.m = S.nc;
+    D.nnz = (int64_t)M.ci.size();
+    D.rp.alloc(S.nc + 1);
+    D.ci.alloc(D.nnz > 0 ? D.nnz : 1);
+    D.v.alloc(D.nnz > 0 ? D.nnz : 1);
+    D.v32.alloc(D.nnz > 0 ? D.nnz : 1);
+    h2d(D.rp.p, M.rp.data(), S.nc + 1, s);
+    h2d(D.ci.p, M.ci.data(), D.nnz, s);
+    h2d(D.v.p, M.v.data(), D.nnz, s);
+    launch_cast_f32(D.v.p, D.v32.p, D.nnz, s);
+    HIPCK(hipStreamSynchronize(s));
+    phase("coarse SPAI (rest after the fine level)");
+  } else {
+    {
+      const gmg_status st = ilut_st;
+      if (st == GMG_ERR_ZERO_PIVOT) fail(st, "ILUT: zero pivot");
+      if (st == GMG_ERR_OOM) fail(st, "ILUT: factor exceeds int32 indexing");
+      if (st != GMG_OK) fail(st, "ILUT: non-finite pivot");
     }
-    if (o.coarse_mode == 1) {
-      auto up = [&](DCsr& D, const HCsr& H) {
-        D.n = D.m = nc;
-        D.nnz = (int64_t)H.ci.size();
-        D.rp.alloc(nc + 1);
-        D.ci.alloc(D.nnz > 0 ? D.nnz : 1);
-        D.v.alloc(D.nnz > 0 ? D.nnz : 1);
-        h2d(D.rp.p, H.rp.data(), nc + 1, s);
-        h2d(D.ci.p, H.ci.data(), D.nnz, s);
-        h2d(D.v.p, H.v.data(), D.nnz, s);
-      };
-      up(S.dLc, L);
-      up(S.dUc, U);
-      S.ucdinv.alloc(nc);
-      h2d(S.ucdinv.p, udinv.data(), nc, s);
-      S.jzero.alloc(nc);
-      S.jtmp.alloc(nc);
-      HIPCK(hipMemsetAsync(S.jzero.p, 0, sizeof(double) * nc, s));
-      HIPCK(hipStreamSynchronize(s));
+    phase("coarse ILUT (rest after the fine level)");
+    {
+      const int nc = S.nc;
+      const HCsr &L = S.hLc, &U = S.hUc;
+      std::vector<double> udinv(nc);
+      for (int i = 0; i < nc; ++i) udinv[i] = 1.0 / U.v[U.rp[i]];
+      // tree solves when the coarse unknowns are in nested-dissection order and
+      // both factors follow the tree (U without its leading diagonal entries);
+      // else the level-scheduled sweeps
+      S.tree = false;
+      if (o.sweep_kernel == 0 && o.coarse_order == 1 && !S.nd_tree.empty() &&
+          build_tree(S.tLc, S.nd_tree, nc, L.rp, L.ci, nullptr, 0, L.v, true, nullptr, s) &&
+          build_tree(S.tUc, S.nd_tree, nc, U.rp, U.ci, nullptr, 1, U.v, false, &udinv, s)) {
+        S.tree = true;
+        S.text.alloc(nc);
+        S.text32.alloc(nc);
+        // sizes and depths (profiling byte counts, info)
+        S.Lc.n = S.Uc.n = nc;
+        S.Lc.nnz = (int64_t)L.ci.size();
+        S.Uc.nnz = (int64_t)U.ci.size() - nc;
+        S.Uc.has_diag = true;
+        S.Lc.levels = S.Uc.levels = S.tLc.heights;
+        phase("coarse tree solves");
+      } else {
+        S.tLc = TreeSolve();
+        S.tUc = TreeSolve();
+        std::vector<int> lsrc(L.ci.size()), us_rp(nc + 1, 0), us_ci, us_src;
+        for (size_t q = 0; q < L.ci.size(); ++q) lsrc[q] = (int)q;
+        for (int i = 0; i < nc; ++i) {
+          for (int q = U.rp[i] + 1; q < U.rp[i + 1]; ++q) { us_ci.push_back(U.ci[q]); us_src.push_back(q); }
+          us_rp[i + 1] = (int)us_ci.size();
+        }
+        build_sweep(S.Lc, nc, L.rp, L.ci, lsrc, &L.v, nullptr, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+        build_sweep(S.Uc, nc, us_rp, us_ci, us_src, &U.v, nullptr, false, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+        phase("coarse sweeps");
+      }
+      if (o.coarse_mode == 1) {
+        auto up = [&](DCsr& D, const HCsr& H) {
+          D.n = D.m = nc;
+          D.nnz = (int64_t)H.ci.size();
+          D.rp.alloc(nc + 1);
+          D.ci.alloc(D.nnz > 0 ? D.nnz : 1);
+          D.v.alloc(D.nnz > 0 ? D.nnz : 1);
+          h2d(D.rp.p, H.rp.data(), nc + 1, s);
+          h2d(D.ci.p, H.ci.data(), D.nnz, s);
+          h2d(D.v.p, H.v.data(), D.nnz, s);
+        };
+        up(S.dLc, L);
+        up(S.dUc, U);
+        S.ucdinv.alloc(nc);
+        h2d(S.ucdinv.p, udinv.data(), nc, s);
+        S.jzero.alloc(nc);
+        S.jtmp.alloc(nc);
+        HIPCK(hipMemsetAsync(S.jzero.p, 0, sizeof(double) * nc, s));
+        HIPCK(hipStreamSynchronize(s));
+      }
     }
   }
   // ---- work vectors
@@ -1780,6 +1806,7 @@ gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut)
     REQUIRE_HANDLE(h);
     if (!est_coarse || !est_ilut) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     gmg::Solver& S = h->S;
+    if (S.opt.coarse_mode == 2) gmg::fail(GMG_ERR_INVALID_ARG, "no ILUT factors under coarse_mode 2");
     const int nc = S.nc;
     auto ratio = [](const std::vector<double>& d) {
       double mx = 0.0, mn = std::numeric_limits<double>::infinity();
@@ -1861,6 +1888,20 @@ gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm) {
       for (int k = 0; k < S.n; ++k) id[k] = k;
       gmg::h2d(perm, id.data(), S.n, S.s);
     }
+    HIPCK(hipStreamSynchronize(S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_spai(gmg_handle h, int32_t* rowptr, int32_t* col, double* val) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    gmg::Solver& S = h->S;
+    if (S.opt.coarse_mode != 2) gmg::fail(GMG_ERR_INVALID_ARG, "no sparse approximate inverse (coarse_mode != 2)");
+    if (!rowptr || !col || !val) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    gmg::d2d(rowptr, S.dMc.rp.p, S.nc + 1, S.s);
+    gmg::d2d(col, S.dMc.ci.p, S.dMc.nnz, S.s);
+    gmg::d2d(val, S.dMc.v.p, S.dMc.nnz, S.s);
     HIPCK(hipStreamSynchronize(S.s));
     return GMG_OK;
   });

@@ -336,6 +336,11 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
 // With the nested-dissection tree of A's numbering, the tree's nodes are
 // factored in parallel (same result).
 gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vector<NdNode>* tree = nullptr);
+// Sparse approximate inverse of A with A's pattern (each column the
+// least-squares minimiser of ||A m - e_j|| over its column's pattern), on
+// host threads.  GMG_OK / GMG_ERR_ZERO_PIVOT (rank-deficient column block) /
+// GMG_ERR_NONFINITE.
+gmg_status host_spai(const HCsr& A, HCsr& M);
 // host worker threads: GMG_THREADS, else OMP_NUM_THREADS, else the hardware's
 // (at most 64)
 int host_threads();

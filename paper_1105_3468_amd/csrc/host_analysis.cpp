@@ -638,4 +638,104 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
   return seq;
 }
 
+// Sparse approximate inverse of A (square host CSR) with A's pattern: column
+// j of M minimises ||A m - e_j||_2 over m supported on column j's pattern J.
+// The rows that those columns reach form a small dense least-squares
+// problem, solved by Householder QR (column-major, the reflector kept in the
+// column it annihilates) and back substitution.  Columns are independent and
+// spread over the host threads in blocks.
+gmg_status host_spai(const HCsr& A, HCsr& M) {
+  const int n = A.n;
+  const size_t nnz = A.ci.size();
+  // column access: cp/cr/cv list column j's rows ascending, csrc the entry in A
+  std::vector<int> cp(n + 1, 0), cr(nnz), csrc(nnz);
+  std::vector<double> cv(nnz);
+  for (size_t q = 0; q < nnz; ++q) cp[A.ci[q] + 1]++;
+  for (int j = 0; j < n; ++j) cp[j + 1] += cp[j];
+  {
+    std::vector<int> at(cp.begin(), cp.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int q = A.rp[i]; q < A.rp[i + 1]; ++q) {
+        const int k = at[A.ci[q]]++;
+        cr[k] = i;
+        cv[k] = A.v[q];
+        csrc[k] = q;
+      }
+  }
+  M.n = n;
+  M.rp = A.rp;
+  M.ci = A.ci;
+  M.v.assign(nnz, 0.0);
+  constexpr int kBlock = 256;
+  std::atomic<int> next{0};
+  std::atomic<int> status{GMG_OK};
+  auto work = [&]() {
+    std::vector<int> slot(n, -1), rows;
+    std::vector<double> H, b, m;
+    for (;;) {
+      const int j0 = next.fetch_add(kBlock);
+      if (j0 >= n || status.load(std::memory_order_relaxed) != GMG_OK) return;
+      for (int j = j0; j < std::min(n, j0 + kBlock); ++j) {
+        const int nj = cp[j + 1] - cp[j];
+        const int* J = cr.data() + cp[j];
+        rows.clear();
+        for (int c = 0; c < nj; ++c)
+          for (int q = cp[J[c]]; q < cp[J[c] + 1]; ++q)
+            if (slot[cr[q]] < 0) { slot[cr[q]] = 0; rows.push_back(cr[q]); }
+        std::sort(rows.begin(), rows.end());
+        const int ni = (int)rows.size();
+        for (int r = 0; r < ni; ++r) slot[rows[r]] = r;
+        H.assign((size_t)ni * nj, 0.0);
+        for (int c = 0; c < nj; ++c)
+          for (int q = cp[J[c]]; q < cp[J[c] + 1]; ++q) H[(size_t)c * ni + slot[cr[q]]] = cv[q];
+        b.assign(ni, 0.0);
+        if (slot[j] >= 0) b[slot[j]] = 1.0;
+        gmg_status st = GMG_OK;
+        for (int c = 0; c < nj && c < ni && st == GMG_OK; ++c) {
+          double* x = &H[(size_t)c * ni];
+          double ss = 0.0;
+          for (int r = c; r < ni; ++r) ss += x[r] * x[r];
+          const double nrm = std::sqrt(ss);
+          if (nrm == 0.0) { st = GMG_ERR_ZERO_PIVOT; break; }
+          const double alpha = x[c] >= 0.0 ? -nrm : nrm;
+          x[c] -= alpha;
+          double vv = 0.0;
+          for (int r = c; r < ni; ++r) vv += x[r] * x[r];
+          auto reflect = [&](double* y) {
+            double d = 0.0;
+            for (int r = c; r < ni; ++r) d += x[r] * y[r];
+            const double f = 2.0 * d / vv;
+            for (int r = c; r < ni; ++r) y[r] -= f * x[r];
+          };
+          for (int k = c + 1; k < nj; ++k) reflect(&H[(size_t)k * ni]);
+          reflect(b.data());
+          x[c] = alpha;
+        }
+        if (st == GMG_OK && ni < nj) st = GMG_ERR_ZERO_PIVOT;
+        m.assign(nj, 0.0);
+        for (int c = nj - 1; c >= 0 && st == GMG_OK; --c) {
+          double t = b[c];
+          for (int k = c + 1; k < nj; ++k) t -= H[(size_t)k * ni + c] * m[k];
+          m[c] = t / H[(size_t)c * ni + c];
+          if (!std::isfinite(m[c])) st = GMG_ERR_NONFINITE;
+        }
+        for (int r = 0; r < ni; ++r) slot[rows[r]] = -1;
+        if (st != GMG_OK) {
+          int expect = GMG_OK;
+          status.compare_exchange_strong(expect, st);
+          return;
+        }
+        // M(J[c], j) sits where A(J[c], j) does
+        for (int c = 0; c < nj; ++c) M.v[csrc[cp[j] + c]] = m[c];
+      }
+    }
+  };
+  const int nt = std::max(1, std::min(host_threads(), (n + kBlock - 1) / kBlock));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  return (gmg_status)status.load();
+}
+
 }  // namespace gmg

@@ -21,7 +21,7 @@ ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOT_SETUP, ERR_STALLED = -5, -6, -7, -8
 EXPORTED = [
     "gmg_default_options", "gmg_setup", "gmg_solve", "gmg_solve_adjoint", "gmg_apply_precond",
     "gmg_spmv", "gmg_get_info", "gmg_cond_estimate", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
-    "gmg_get_fine_perm",
+    "gmg_get_fine_perm", "gmg_get_spai",
     "gmg_get_ilut", "gmg_set_stream", "gmg_profile_enable", "gmg_profile_read",
     "gmg_profile_name", "gmg_destroy", "gmg_last_error", "gmg_fv_nnz", "gmg_fv_assemble",
     "gmg_fv_kappa_grad", "gmg_pattern_grad",
@@ -81,6 +81,7 @@ def load():
         "gmg_get_coarse": (I, [P, P, P, P]),
         "gmg_get_ilu0": (I, [P, P]),
         "gmg_get_fine_perm": (I, [P, P]),
+        "gmg_get_spai": (I, [P, P, P, P]),
         "gmg_get_ilut": (I, [P, P, P, P, P, P, P]),
         "gmg_set_stream": (I, [P, P]),
         "gmg_profile_enable": (I, [P, I]),
@@ -211,6 +212,18 @@ class Solver:
         v = self._torch.empty(self.nnz, dtype=self._torch.float64, device="cuda")
         _check(load().gmg_get_ilu0(self._h, _ptr(v)), "ilu0")
         return v
+
+    def spai(self):
+        """(rowptr, col, val) of the sparse approximate inverse of A_c
+        (coarse_mode = 2)."""
+        inf = self.info()
+        nc, nz = inf["n_coarse"], inf["nnz_coarse"]
+        t = self._torch
+        rp = t.empty(nc + 1, dtype=t.int32, device="cuda")
+        ci = t.empty(max(nz, 1), dtype=t.int32, device="cuda")
+        v = t.empty(max(nz, 1), dtype=t.float64, device="cuda")
+        _check(load().gmg_get_spai(self._h, _ptr(rp), _ptr(ci), _ptr(v)), "spai")
+        return rp, ci[:nz], v[:nz]
 
     def fine_perm(self):
         """The smoother's numbering: position k holds fine unknown perm[k]."""

@@ -434,6 +434,41 @@ def test_fine_nd_large_separator():
     assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("name", list(ND_CASES))
+def test_spai_coarse_solve(name):
+    """coarse_mode 2: the sparse approximate inverse of A_c bit-exact vs the
+    oracle's (the same least-squares steps in the same order on the host);
+    one application in FP64 within 1e-12 and in FP32 within the FP32 bar; an
+    unrestarted solve converged within one step of the oracle's."""
+    _say(f"[case] coarse_mode=2 {name}")
+    p = ND_CASES[name]()
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    O = oracle.Oracle(p.rowptr, p.col, p.val, coarse_mode=2)
+    S = Solver(p.rowptr, p.col, p.val, coarse_mode=2)
+    rp, ci, v = (t.cpu().numpy() for t in S.spai())
+    orp, oci, ov = O.spai()
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    assert np.array_equal(v.view(np.uint64), ov.view(np.uint64))
+    z = np.random.default_rng(8).uniform(-1, 1, p.n_rows)
+    q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
+    ref = O.apply(z, 0)
+    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
+    q32 = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
+    ref32 = O.apply(z, 1)
+    e32 = np.linalg.norm(q32 - ref32) / np.linalg.norm(ref32)
+    e64 = np.linalg.norm(ref32 - ref) / np.linalg.norm(ref)
+    assert e32 <= max(1e-4, 10 * e64), (e32, e64)
+    b = p.b[:, 0]
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, restart=600, maxit=600)
+    assert res.status == G.OK, res.info
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+    _, info = O.solve(b, tol=1e-8, restart=600, maxit=600)
+    assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
+    assert S.info()["nnz_lc"] == 0
+    with pytest.raises(GmgError):
+        S.cond_estimate()
+
+
 def test_tiny_and_degenerate():
     _say("[case] tiny")
     # 1x1, diagonal matrices, a 2x2 that needs no pivoting
