@@ -100,7 +100,8 @@ def copy_calibration():
 def _alg_bytes_doc():
     return ("spmv 12*nnz+20*N (FP64 CSR, int32 indices); sweep: 12 per dependency entry + "
             "(8 + rhs + 2*val [+ diag] [+ reset]) per row; resid_restrict 12*nnz + 40*N + 20*N_c; "
-            "ortho 8*N*(3k+6) for k basis vectors")
+            "ortho 8*N*(2k+3)+8*k^2 for k basis vectors from 33 to 384 (one Gram-corrected projection), "
+            "8*N*(3k+6) otherwise (two classical Gram-Schmidt passes)")
 
 
 def run_cpu_baseline(p, gpu_steps, budget_s=30.0):

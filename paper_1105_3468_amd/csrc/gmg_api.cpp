@@ -95,6 +95,8 @@ struct Solver {
   int mcap = 0;
   size_t ld = 0;
   DBuf<double> V, Z, w, xcol, bcol, coef;
+  size_t ldg = 0;
+  DBuf<double> gram, gcoef, gdots;  // the basis' Gram matrix (ldg x ldg), corrected coefficients, V^T w_new
   RedWork rw;
   DBuf<int> abort_flag;
   double* hpin = nullptr;      // pinned host scalars, then two Hessenberg columns (kPinCol each)
@@ -948,6 +950,10 @@ static void ensure_krylov(Solver& S, int m) {
   S.Z.alloc(S.ld * m);
   S.w.alloc(S.ld);
   S.coef.alloc(kMaxRestart + 8);
+  S.ldg = (size_t)m + 1;
+  S.gram.alloc(S.ldg * S.ldg);
+  S.gcoef.alloc((size_t)m + 8);
+  S.gdots.alloc((size_t)m + 8);
 }
 
 // ------------------------------------------------------------------ FGMRES
@@ -958,8 +964,13 @@ struct OneResult {
 };
 
 // Flexible GMRES(m) with right preconditioning (Algorithm 1's accelerator with
-// z_j = B~^{-1} v_j kept), classical Gram-Schmidt applied twice, Givens
-// rotations on the host (O(m) scalars per step).
+// z_j = B~^{-1} v_j kept), Givens rotations on the host (O(m) scalars per
+// step).  Orthogonalisation: classical Gram-Schmidt applied twice while the
+// basis is short or very long; in between, one projection whose coefficients
+// are corrected with the basis' Gram matrix G = V^T V, c = (2I - G) V^T w
+// (equal to the second pass's V^T (w - V h) = h - G h), where each new row of
+// G comes from the products V^T w_new taken in the same read of V that forms
+// w_new: two reads of V per step instead of three.
 static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b, double* x, double tol,
                         int maxit, int m, bool x0_given) {
   hipStream_t s = S.s;
@@ -1034,17 +1045,23 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       double* h1 = res;
       double* h2 = res + kc;
       double* nrm = res + 2 * kc;
+      const double* gdots = nullptr;  // V^T w_new when the pass took them (a Gram row), else the row is zero
+      const double* nrm_src = nrm;
       if (kc <= kFused) {
         Prof p(S, PC_ORTHO, 8.0 * n * (3 * kc + 6));
         launch_multidot(V, ld, kc, w, n, S.rw, h1, s);
         launch_update_dot(V, ld, kc, h1, w, n, S.rw, h2, s);
         launch_update_norm(V, ld, kc, h2, w, n, S.rw, nrm, s);
       } else if (kc <= many_max()) {
-        // the first update and the second dot product share one read of V
-        Prof p(S, PC_ORTHO, 8.0 * n * (3 * kc + 6));
+        // h1 = V^T w; c = (2I - G) h1 (its correction d = c - h1 into h2's
+        // slot, where the host adds it); w <- w - V c with V^T w and ||w||^2
+        // in the same read of V
+        Prof p(S, PC_ORTHO, 8.0 * n * (2 * kc + 3) + 8.0 * kc * kc);
         launch_multidot_many(V, ld, kc, w, n, S.rw, h1, s);
-        launch_update_dot_many(V, ld, kc, h1, w, n, S.rw, h2, s);
-        launch_update_many(V, ld, kc, h2, w, n, true, S.rw, nrm, s);
+        launch_gram_coef(kc, h1, S.gram.p, S.ldg, h2, S.gcoef.p, s);
+        launch_update_dot_many(V, ld, kc, S.gcoef.p, w, n, true, S.rw, S.gdots.p, s);
+        gdots = S.gdots.p;
+        nrm_src = S.gdots.p + kc;
       } else {
         Prof p(S, PC_ORTHO, 8.0 * n * (4 * kc + 4 * ((kc + kFused - 1) / kFused) + 4));
         for (int c0 = 0; c0 < kc; c0 += kFused)
@@ -1056,7 +1073,8 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       }
       {
         Prof p(S, PC_VECTOR, (double)n * 16);
-        launch_normalize(w, nrm, V + (size_t)(j + 1) * ld, n, s);
+        launch_normalize(w, nrm_src, V + (size_t)(j + 1) * ld, n, s);
+        launch_gram_row(j + 1, gdots, nrm_src, S.gram.p, S.ldg, nrm_src == nrm ? nullptr : nrm, s);
       }
       d2h(hp + (size_t)kPinCol * (1 + (j & 1)), res, 2 * kc + 1, s);
       HIPCK(hipEventRecord(S.colev[j & 1], s));
@@ -1225,20 +1243,22 @@ static void build_wave(WaveSweep& f, const WaveGrid& g, const std::vector<int>& 
   f.has_diag = dinv_dev != nullptr;
   const int64_t T2 = 2 * g.total;
   std::vector<int> cidx(T2), didx(f.has_diag ? g.total : 0);
-  for (int64_t p = 0; p < g.total; ++p) {
-    const int c = wave_cell_host(lower ? p : g.total - 1 - p, g);
-    int below = (int)nvals, left = (int)nvals;  // index nvals: zero
-    if (c >= 0) {
-      const int cb = lower ? c - g.nx : c + g.nx, cl = lower ? c - 1 : c + 1;
-      for (int q = dep_rp[c]; q < dep_rp[c + 1]; ++q) {
-        if (dep_ci[q] == cb) below = dep_src[q];
-        if (dep_ci[q] == cl) left = dep_src[q];
+  parallel_ranges((int)g.total, [&](int p0, int p1, int) {
+    for (int64_t p = p0; p < p1; ++p) {
+      const int c = wave_cell_host(lower ? p : g.total - 1 - p, g);
+      int below = (int)nvals, left = (int)nvals;  // index nvals: zero
+      if (c >= 0) {
+        const int cb = lower ? c - g.nx : c + g.nx, cl = lower ? c - 1 : c + 1;
+        for (int q = dep_rp[c]; q < dep_rp[c + 1]; ++q) {
+          if (dep_ci[q] == cb) below = dep_src[q];
+          if (dep_ci[q] == cl) left = dep_src[q];
+        }
       }
+      cidx[2 * p] = below;
+      cidx[2 * p + 1] = left;
+      if (f.has_diag) didx[p] = c >= 0 ? c : n;
     }
-    cidx[2 * p] = below;
-    cidx[2 * p + 1] = left;
-    if (f.has_diag) didx[p] = c >= 0 ? c : n;
-  }
+  });
   DBuf<double> vz;
   vz.alloc(nvals + 1);
   d2d(vz.p, vals_dev, nvals, s);
@@ -1451,25 +1471,30 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     S.fine_nd = true;
     phase("fine nested dissection");
   }
-  std::vector<int> hdpos(n);
-  for (int i = 0; i < n; ++i)
-    for (int p = hrp[i]; p < hrp[i + 1]; ++p)
-      if (hci[p] == i) hdpos[i] = p;
+  // diagonal positions and the dependency lists of the two forward fine
+  // sweeps (strict lower / strict upper entries of each row).  One thread on
+  // purpose: the ILUT started above keeps the other host threads busy.
+  std::vector<int> hdpos(n), l_rp(n + 1, 0), u_rp(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    int nl = 0, nu = 0;
+    for (int p = hrp[i]; p < hrp[i + 1]; ++p) {
+      if (hci[p] < i) ++nl;
+      else if (hci[p] > i) ++nu;
+      else hdpos[i] = p;
+    }
+    l_rp[i + 1] = l_rp[i] + nl;
+    u_rp[i + 1] = u_rp[i] + nu;
+  }
   S.dpos.alloc(n);
   h2d(S.dpos.p, hdpos.data(), n, s);
-  // dependency lists of the two forward fine sweeps
-  std::vector<int> l_rp(n + 1, 0), l_ci, l_src, u_rp(n + 1, 0), u_ci, u_src;
-  l_ci.reserve(nnz64 / 2);
-  l_src.reserve(nnz64 / 2);
-  u_ci.reserve(nnz64 / 2);
-  u_src.reserve(nnz64 / 2);
+  std::vector<int> l_ci(l_rp[n]), l_src(l_rp[n]), u_ci(u_rp[n]), u_src(u_rp[n]);
   for (int i = 0; i < n; ++i) {
+    int ql = l_rp[i], qu = u_rp[i];
     for (int p = hrp[i]; p < hrp[i + 1]; ++p) {
-      if (hci[p] < i) { l_ci.push_back(hci[p]); l_src.push_back(p); }
-      else if (hci[p] > i) { u_ci.push_back(hci[p]); u_src.push_back(p); }
+      const int c = hci[p];
+      if (c < i) { l_ci[ql] = c; l_src[ql++] = p; }
+      else if (c > i) { u_ci[qu] = c; u_src[qu++] = p; }
     }
-    l_rp[i + 1] = (int)l_ci.size();
-    u_rp[i + 1] = (int)u_ci.size();
   }
   phase("fine dependency lists");
   // ---- ILU(0), one launch per level of L0

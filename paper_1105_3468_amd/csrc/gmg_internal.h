@@ -278,12 +278,22 @@ void launch_update_norm(const double* V, size_t ld, int k, const double* h, doub
                         RedWork& rw, double* result, hipStream_t s);
 // any k (<= 2048): w -= V^T h (h device); if want_norm, result[0] = ||w_new||^2
 // Many-vector passes (up to many_max() vectors): result[0..k) = V^T w, and
-// w <- w - V h with result[0..k) = V^T w_new, each reading V once.
+// w <- w - V h with result[0..k) = V^T w_new (and result[k] = ||w_new||^2
+// when want_norm), each reading V once.
 int many_max();
 void launch_multidot_many(const double* V, size_t ld, int k, const double* w, int64_t n, RedWork& rw, double* result,
                           hipStream_t s);
-void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
-                            double* result, hipStream_t s);
+void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
+                            RedWork& rw, double* result, hipStream_t s);
+// c = (2I - G) h and d = c - h for the basis' Gram matrix G (row-major, ldg;
+// unit diagonal assumed): the coefficients of a projection corrected for the
+// basis' loss of orthogonality, as a second Gram-Schmidt pass would give
+void launch_gram_coef(int kc, const double* h, const double* gram, size_t ldg, double* d, double* c,
+                      hipStream_t s);
+// G[row][i] = G[i][row] = dots[i] / sqrt(*nrm2) (i < row; zeros if dots is
+// null), G[row][row] = 1; *nrm2_out = *nrm2 when nrm2_out is not null
+void launch_gram_row(int row, const double* dots, const double* nrm2, double* gram, size_t ldg, double* nrm2_out,
+                     hipStream_t s);
 void launch_update_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
                         RedWork& rw, double* result, hipStream_t s);
 // result[0] = ||x||^2

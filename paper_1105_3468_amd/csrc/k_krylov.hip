@@ -24,6 +24,7 @@ constexpr int MGRID = 256;        // blocks (one per CU)
 constexpr int MMAX = 384;         // longest basis they take (24 vectors per thread group)
 constexpr int MPARTS = 32;        // thread groups adding the block partials of one vector
 constexpr int MPIPE = 16;         // up to this many vectors per thread, the next chunk is loaded early
+constexpr int MSTR = MMAX + 8;    // stride of a block's row of partials (one extra slot for a norm)
 
 // Keeps the machine scheduler from sinking the loads issued above it into the
 // arithmetic below: without it the compiler reuses one register pair for all
@@ -178,7 +179,7 @@ void red_init(RedWork& rw, hipStream_t s) {
   rw.partial.alloc((size_t)KGRID * KMAX);
   rw.counter.alloc(1);
   rw.result.alloc(2 * KLDS + 8);
-  rw.mpart.alloc((size_t)MGRID * MMAX);
+  rw.mpart.alloc((size_t)MGRID * MSTR);
   launch_fill_u32(rw.counter.p, 0u, 1, s);
   launch_fill_f64_bits(rw.partial.p, SENT64, (size_t)KGRID * KMAX, s);
 }
@@ -271,6 +272,30 @@ void launch_normalize(const double* x, const double* nrm2, double* y, int64_t n,
   HIPCK(hipGetLastError());
 }
 
+// Row `row` of the basis' Gram matrix (and its mirror column) for the vector
+// just normalised from x: G[row][i] = (V[i] . x) / ||x|| for i < row, from the
+// products `dots` taken while x was formed (zeros when dots is null: a vector
+// orthogonalised by two full passes); optionally copies *nrm2 to nrm2_out.
+__global__ void k_gram_row(int row, const double* __restrict__ dots, const double* __restrict__ nrm2,
+                           double* __restrict__ gram, size_t ldg, double* __restrict__ nrm2_out) {
+  const double nv = *nrm2;
+  const double a = nv > 0.0 ? 1.0 / sqrt(nv) : 0.0;
+  for (int i = threadIdx.x; i < row; i += blockDim.x) {
+    const double gv = dots ? dots[i] * a : 0.0;
+    gram[(size_t)row * ldg + i] = gv;
+    gram[(size_t)i * ldg + row] = gv;
+  }
+  if (threadIdx.x == 0) {
+    gram[(size_t)row * ldg + row] = 1.0;
+    if (nrm2_out) *nrm2_out = nv;
+  }
+}
+void launch_gram_row(int row, const double* dots, const double* nrm2, double* gram, size_t ldg, double* nrm2_out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_row, dim3(1), dim3(256), 0, s, row, dots, nrm2, gram, ldg, nrm2_out);
+  HIPCK(hipGetLastError());
+}
+
 template <int K>
 __global__ void k_xupdate(double* __restrict__ x, const double* __restrict__ Z, size_t ld, int kc,
                           const double* __restrict__ c, int64_t n) {
@@ -354,7 +379,7 @@ __device__ __forceinline__ void many_block_sums(const double (&acc)[PER], int kc
       double t = 0.0;
       for (int q = 0; q < MRT; ++q) t += red[q][threadIdx.x];
       const int k = threadIdx.x + MG * u;
-      if (k < kc) mpart[(size_t)blockIdx.x * MMAX + k] = t;
+      if (k < kc) mpart[(size_t)blockIdx.x * MSTR + k] = t;
     }
     __syncthreads();
   }
@@ -420,13 +445,14 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// w <- w - sum_k h[k] V[k]; block partials of V[k] . w_new.  A chunk's new w
-// needs every vector group's partial sum (two barriers per chunk), so the
-// next chunk's basis values (and w) are loaded before them.
+// w <- w - sum_k h[k] V[k]; block partials of V[k] . w_new, and with
+// want_norm of ||w_new||^2 (slot kc).  A chunk's new w needs every vector
+// group's partial sum (two barriers per chunk), so the next chunk's basis
+// values (and w) are loaded before them.
 template <int PER>
 __global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restrict__ V, size_t ld, int kc,
                                                          const double* __restrict__ h, double* __restrict__ w,
-                                                         int64_t n, double* __restrict__ mpart) {
+                                                         int64_t n, int want_norm, double* __restrict__ mpart) {
   __shared__ double pr[MROWS][MG + 1];
   __shared__ double wn[MROWS];
   __shared__ double hs[MMAX];
@@ -451,6 +477,7 @@ __global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restric
     return (threadIdx.x < MROWS && c < nch && ii < n) ? w[ii] : 0.0;
   };
   double wc = load_w(blockIdx.x);
+  double nacc = 0.0;  // threads 0..MROWS-1 (wave 0): squares of their rows of w_new
   if constexpr (PER <= MPIPE) load(v, blockIdx.x);
   for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
     double2 vn[PER];
@@ -476,6 +503,7 @@ __global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restric
         w[ii] = t;
       }
       wn[threadIdx.x] = t;
+      nacc += t * t;
     }
     wc = wnext;
     lds_barrier();
@@ -488,6 +516,12 @@ __global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restric
   }
   __syncthreads();
   many_block_sums<PER>(acc, kc, mpart);
+  static_assert(MROWS == 64, "the norm is reduced within wave 0");
+  if (want_norm && threadIdx.x < MROWS) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nacc += __shfl_down(nacc, off, 64);
+    if (threadIdx.x == 0) mpart[(size_t)blockIdx.x * MSTR + kc] = nacc;
+  }
 }
 
 // result[k] = sum over blocks b (in order) of mpart[b][k]; 8 vectors per
@@ -506,7 +540,7 @@ __global__ __launch_bounds__(KB) void k_colsum(const double* __restrict__ mpart,
 #pragma unroll
     for (int u = 0; u < IN; ++u) {
       const int b = part + u * MPARTS;
-      v[u] = b < nb ? mpart[(size_t)b * MMAX + k] : 0.0;
+      v[u] = b < nb ? mpart[(size_t)b * MSTR + k] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < IN; ++u) s += v[u];
@@ -548,13 +582,41 @@ void launch_multidot_many(const double* V, size_t ld, int k, const double* w, in
   HIPCK(hipGetLastError());
 }
 
-void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
-                            double* result, hipStream_t s) {
+void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
+                            RedWork& rw, double* result, hipStream_t s) {
   if (k < 1 || k > MMAX) fail(GMG_ERR_INVALID_ARG, "update_dot_many: bad vector count");
   const unsigned nb = many_grid(n);
-  GMG_MANY(k_update_dot_many, k, dim3(nb), dim3(MKB), 0, s, V, ld, k, h, w, n, rw.mpart.p);
-  hipLaunchKernelGGL(k_colsum, dim3((k + KB / MPARTS - 1) / (KB / MPARTS)), dim3(KB), 0, s, rw.mpart.p, (int)nb, k,
-                     result);
+  const int wn = want_norm ? 1 : 0;
+  GMG_MANY(k_update_dot_many, k, dim3(nb), dim3(MKB), 0, s, V, ld, k, h, w, n, wn, rw.mpart.p);
+  hipLaunchKernelGGL(k_colsum, dim3((k + wn + KB / MPARTS - 1) / (KB / MPARTS)), dim3(KB), 0, s, rw.mpart.p, (int)nb,
+                     k + wn, result);
+  HIPCK(hipGetLastError());
+}
+
+// Gram-corrected coefficients of one projection: with G = V^T V (unit
+// diagonal taken as exact), c = h + d, d_i = -sum_{l != i} G[i][l] h[l],
+// i.e. c = (2I - G) h, the first-order form of G^{-1} h: the same as a second
+// classical Gram-Schmidt pass, V^T (w - V h) = h - G h, without reading V
+// again.  One wave per coefficient, lanes over l, added in a fixed order.
+__global__ __launch_bounds__(64) void k_gram_coef(int kc, const double* __restrict__ h,
+                                                  const double* __restrict__ gram, size_t ldg,
+                                                  double* __restrict__ d, double* __restrict__ c) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const double* gi = gram + (size_t)i * ldg;
+  double s = 0.0;
+  for (int l = lane; l < kc; l += 64)
+    if (l != i) s += gi[l] * h[l];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) {
+    d[i] = -s;
+    c[i] = h[i] + (-s);
+  }
+}
+void launch_gram_coef(int kc, const double* h, const double* gram, size_t ldg, double* d, double* c,
+                      hipStream_t s) {
+  if (kc < 1) return;
+  hipLaunchKernelGGL(k_gram_coef, dim3(kc), dim3(64), 0, s, kc, h, gram, ldg, d, c);
   HIPCK(hipGetLastError());
 }
 #undef GMG_MANY
