@@ -1385,7 +1385,9 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       for (int p = crp[i]; p < crp[i + 1]; ++p)
         if (cci[p] != i) { gci[fillp[i]++] = cci[p]; gci[fillp[cci[p]]++] = i; }
     // duplicates (both (i,j) and (j,i) stored) are harmless for the traversal
+    phase("nested dissection: graph");
     std::vector<int> perm = nd_numbering(nc, cnt, gci, &S.nd_tree);
+    phase("nested dissection: numbering");
     std::vector<int> rank(nc);
     for (int k = 0; k < nc; ++k) rank[perm[k]] = k;
     DBuf<int> drank;

@@ -463,7 +463,7 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
 // at least half of S cumulatively, clamped to [1, L-1]; then ND(d < m),
 // ND(d > m), and the separator d == m ascending.  Returns perm (position ->
 // vertex).
-std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci,
+std::vector<int> nd_numbering(int n, const std::vector<int>& rp_in, const std::vector<int>& ci_in,
                               std::vector<NdNode>* tree) {
   // A task owns a segment of seq (the vertices of one subgraph, ascending);
   // dissecting it stable-partitions the segment into [part a | part b |
@@ -475,11 +475,38 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
   // depth-first pass creates them (both children of a node on its visit).
   struct Task { int kind, start, len, node; };  // kind 0: dissect, 1: emit as is
   struct Node { int lo = 0, hi = 0, parent = -1, a = -1, b = -1; };
+  // small graphs are not worth the threads
+  const int nthreads = n >= 4096 ? host_threads() : 1;
+  // the neighbour lists without repeats (callers may list an edge from both
+  // ends, and the traversal only needs each neighbour once)
+  std::vector<int> rp(n + 1, 0), ci;
+  {
+    std::vector<int> cnt(n + 1, 0), tmp(ci_in.size());
+    const int nt = std::max(1, std::min(nthreads, n / 4096));
+    auto dedup = [&](int i0, int i1) {
+      for (int i = i0; i < i1; ++i) {
+        int* b = tmp.data() + rp_in[i];
+        std::copy(ci_in.begin() + rp_in[i], ci_in.begin() + rp_in[i + 1], b);
+        std::sort(b, b + (rp_in[i + 1] - rp_in[i]));
+        cnt[i + 1] = (int)(std::unique(b, b + (rp_in[i + 1] - rp_in[i])) - b);
+      }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(dedup, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt));
+    dedup(0, (int)((int64_t)n / nt));
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < n; ++i) rp[i + 1] = rp[i] + cnt[i + 1];
+    ci.resize(rp[n]);
+    for (int i = 0; i < n; ++i) std::copy(tmp.begin() + rp_in[i], tmp.begin() + rp_in[i] + cnt[i + 1], ci.begin() + rp[i]);
+  }
   std::vector<int> seq(n);
   for (int i = 0; i < n; ++i) seq[i] = i;
-  std::unique_ptr<std::atomic<int>[]> mark(new std::atomic<int>[n > 0 ? n : 1]);
-  for (int i = 0; i < n; ++i) mark[i].store(-1, std::memory_order_relaxed);
-  std::vector<int> dist(n > 0 ? n : 1, -1);
+  // per vertex: the tag of the task that owns it (high 32 bits) and its BFS
+  // distance + 1 in that task (low 32 bits, 0 = not reached), in one word so
+  // a neighbour test touches one cache line
+  std::unique_ptr<std::atomic<uint64_t>[]> mark(new std::atomic<uint64_t>[n > 0 ? n : 1]);
+  for (int i = 0; i < n; ++i) mark[i].store(~0ull, std::memory_order_relaxed);
+  auto dist_of = [&](int v) { return (int)(uint32_t)mark[v].load(std::memory_order_relaxed) - 1; };
   std::atomic<int> next_tag{0};
   std::vector<Node> nodes(1);
   std::mutex mu;
@@ -509,18 +536,19 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
       nodes[t.node].hi = t.start + t.len;
       return;
     }
-    const int tag = next_tag.fetch_add(1, std::memory_order_relaxed);
-    for (int* q = b; q != e; ++q) { mark[*q].store(tag, std::memory_order_relaxed); dist[*q] = -1; }
+    const uint64_t tag = (uint64_t)(uint32_t)next_tag.fetch_add(1, std::memory_order_relaxed) << 32;
+    for (int* q = b; q != e; ++q) mark[*q].store(tag, std::memory_order_relaxed);
     auto bfs = [&](int src) {
       queue.clear();
-      dist[src] = 0;
+      mark[src].store(tag | 1u, std::memory_order_relaxed);
       queue.push_back(src);
       for (size_t h = 0; h < queue.size(); ++h) {
         const int u = queue[h];
+        const uint64_t du = (uint32_t)mark[u].load(std::memory_order_relaxed);  // distance + 1
         for (int p = rp[u]; p < rp[u + 1]; ++p) {
           const int v = ci[p];
-          if (mark[v].load(std::memory_order_relaxed) == tag && dist[v] < 0) {
-            dist[v] = dist[u] + 1;
+          if (mark[v].load(std::memory_order_relaxed) == tag) {  // in the segment, not reached
+            mark[v].store(tag | (du + 1), std::memory_order_relaxed);
             queue.push_back(v);
           }
         }
@@ -529,7 +557,7 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
     bfs(*b);  // segments are kept ascending, so *b is the smallest vertex
     if ((int)queue.size() < t.len) {
       // disconnected: the component of *b, then the rest
-      int* mid = std::stable_partition(b, e, [&](int v) { return dist[v] >= 0; });
+      int* mid = std::stable_partition(b, e, [&](int v) { return dist_of(v) >= 0; });
       const int c0 = (int)(mid - b);
       {
         std::lock_guard<std::mutex> g(mu);
@@ -540,23 +568,30 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
       return;
     }
     int r = *b, far = 0;
-    for (int* q = b; q != e; ++q)
-      if (dist[*q] > far || (dist[*q] == far && *q < r)) { far = dist[*q]; r = *q; }
-    for (int* q = b; q != e; ++q) dist[*q] = -1;
+    for (int* q = b; q != e; ++q) {
+      const int d = dist_of(*q);
+      if (d > far || (d == far && *q < r)) { far = d; r = *q; }
+    }
+    for (int* q = b; q != e; ++q) mark[*q].store(tag, std::memory_order_relaxed);
     bfs(r);
+    std::vector<int>& dist = queue;  // the queue's job is done: reuse it for the distances in segment order
+    dist.resize(t.len);
     int L = 0;
-    for (int* q = b; q != e; ++q) L = std::max(L, dist[*q]);
+    for (int i = 0; i < t.len; ++i) {
+      dist[i] = dist_of(b[i]);
+      L = std::max(L, dist[i]);
+    }
     if (L < 2) {
       out.push_back({1, t.start, t.len, t.node});
       return;
     }
     std::vector<int> cnt(L + 1, 0);
-    for (int* q = b; q != e; ++q) cnt[dist[*q]]++;
+    for (int i = 0; i < t.len; ++i) cnt[dist[i]]++;
     int m = 0, cum = cnt[0];
     while (2.0 * cum < (double)t.len) cum += cnt[++m];
     m = std::min(std::max(m, 1), L - 1);
-    int* m1 = std::stable_partition(b, e, [&](int v) { return dist[v] < m; });
-    int* m2 = std::stable_partition(m1, e, [&](int v) { return dist[v] > m; });
+    int* m1 = std::stable_partition(b, e, [&](int v) { return dist_of(v) < m; });
+    int* m2 = std::stable_partition(m1, e, [&](int v) { return dist_of(v) > m; });
     const int c0 = (int)(m1 - b), c1 = (int)(m2 - m1);
     {
       std::lock_guard<std::mutex> g(mu);
@@ -601,8 +636,6 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vect
       cv.notify_all();
     }
   };
-  // small graphs are not worth the threads
-  const int nthreads = n >= 4096 ? host_threads() : 1;
   if (nthreads <= 1) {
     worker();
   } else {
