@@ -127,6 +127,7 @@ template void launch_perm_scatter<float>(int, const int*, float*, float*, hipStr
 // MODE 0: y = A x;  MODE 1: y = b - A x (b of type TB, converted to T).
 constexpr int SPMV_ROWS = 256;
 constexpr int SPMV_CAP = 4096;   // products held in LDS per tile
+constexpr int SPMV_BATCH = 8;    // entries per lane whose loads are in flight together
 
 template <class T, class TB, int MODE>
 __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -138,7 +139,23 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
   const int e0 = rp[r0], e1 = rp[r1];
   const int row = r0 + threadIdx.x;
   if (e1 - e0 <= SPMV_CAP) {
-    for (int e = e0 + threadIdx.x; e < e1; e += 256) prod[e - e0] = v[e] * x[ci[e]];
+    // a lane's entries e, e + 256, ... in batches of SPMV_BATCH: every column
+    // index of the batch is loaded, then every x and value, then the products
+    // (one round of dependent loads per batch instead of one per entry)
+    for (int e = e0 + threadIdx.x; e < e1; e += 256 * SPMV_BATCH) {
+      int c[SPMV_BATCH];
+      T a[SPMV_BATCH], xv[SPMV_BATCH];
+#pragma unroll
+      for (int u = 0; u < SPMV_BATCH; ++u) c[u] = e + 256 * u < e1 ? ci[e + 256 * u] : -1;
+#pragma unroll
+      for (int u = 0; u < SPMV_BATCH; ++u) {
+        a[u] = c[u] >= 0 ? v[e + 256 * u] : (T)0;
+        xv[u] = c[u] >= 0 ? x[c[u]] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < SPMV_BATCH; ++u)
+        if (c[u] >= 0) prod[e + 256 * u - e0] = a[u] * xv[u];
+    }
     __syncthreads();
     if (row < r1) {
       T s = (T)0;
