@@ -151,20 +151,21 @@ def test_iterates_equal_steps(case, steps):
     assert d <= 1e-10, (name, steps, d)
 
 
-@pytest.mark.parametrize("steps", [40, 120, 400])
-def test_long_basis_iterates(steps):
-    """Unrestarted FGMRES past 32 basis vectors, where one Gram-corrected
-    projection replaces the two Gram-Schmidt passes, and past 384, where the
-    two passes return: iterates at equal step counts within 1e-10 of the
-    oracle's (modified Gram-Schmidt), the same bar as above."""
-    _say(f"[case] long basis, {steps} steps")
+@pytest.mark.parametrize("steps,restart", [(40, 600), (120, 600), (400, 600), (130, 45)])
+def test_long_basis_iterates(steps, restart):
+    """FGMRES past 32 basis vectors, where one Gram-corrected projection
+    replaces the two Gram-Schmidt passes, past 384, where the two passes
+    return, and restarted at 45 (the Gram rows rebuilt every cycle): iterates
+    at equal step counts within 1e-10 of the oracle's (modified
+    Gram-Schmidt), the same bar as above."""
+    _say(f"[case] long basis, {steps} steps, restart {restart}")
     p = W.scaled("fv2d_rot", 96)
     A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
     S = Solver(p.rowptr, p.col, p.val)
     O = oracle.Oracle(p.rowptr, p.col, p.val)
     b = p.b[:, 0]
-    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=0.0, maxit=steps, restart=600)
-    xo, info = O.solve(b, tol=0.0, maxit=steps, restart=600)
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=0.0, maxit=steps, restart=restart)
+    xo, info = O.solve(b, tol=0.0, maxit=steps, restart=restart)
     assert res.info["iters"] == info.steps == steps
     d = np.linalg.norm(A @ (x.cpu().numpy() - xo)) / np.linalg.norm(b)
     assert d <= 1e-10, (steps, d)
