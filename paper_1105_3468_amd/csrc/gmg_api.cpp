@@ -1077,8 +1077,8 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       }
       {
         Prof p(S, PC_VECTOR, (double)n * 16);
-        launch_normalize(w, nrm_src, V + (size_t)(j + 1) * ld, n, s);
-        launch_gram_row(j + 1, gdots, nrm_src, S.gram.p, S.ldg, nrm_src == nrm ? nullptr : nrm, s);
+        launch_normalize_gram(w, nrm_src, V + (size_t)(j + 1) * ld, n, j + 1, gdots, S.gram.p, S.ldg,
+                              nrm_src == nrm ? nullptr : nrm, s);
       }
       d2h(hp + (size_t)kPinCol * (1 + (j & 1)), res, 2 * kc + 1, s);
       HIPCK(hipEventRecord(S.colev[j & 1], s));

@@ -290,18 +290,17 @@ void launch_update_dot_many(const double* V, size_t ld, int k, const double* h, 
 // basis' loss of orthogonality, as a second Gram-Schmidt pass would give
 void launch_gram_coef(int kc, const double* h, const double* gram, size_t ldg, double* d, double* c,
                       hipStream_t s);
+// y = x / sqrt(*nrm2) (zero when *nrm2 is zero), and the Gram row of y:
 // G[row][i] = G[i][row] = dots[i] / sqrt(*nrm2) (i < row; zeros if dots is
 // null), G[row][row] = 1; *nrm2_out = *nrm2 when nrm2_out is not null
-void launch_gram_row(int row, const double* dots, const double* nrm2, double* gram, size_t ldg, double* nrm2_out,
-                     hipStream_t s);
+void launch_normalize_gram(const double* x, const double* nrm2, double* y, int64_t n, int row, const double* dots,
+                           double* gram, size_t ldg, double* nrm2_out, hipStream_t s);
 void launch_update_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
                         RedWork& rw, double* result, hipStream_t s);
 // result[0] = ||x||^2
 void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s);
 // y = alpha * x
 void launch_scale(const double* x, double alpha, double* y, int64_t n, hipStream_t s);
-// y = x / sqrt(*nrm2) (zero when *nrm2 is zero); nrm2 on the device
-void launch_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
 // x += sum_i c[i] Z[i]  (c device)
 void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n,
                     hipStream_t s);

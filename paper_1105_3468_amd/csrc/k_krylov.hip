@@ -255,44 +255,39 @@ void launch_scale(const double* x, double a, double* y, int64_t n, hipStream_t s
   HIPCK(hipGetLastError());
 }
 
-// y = x / sqrt(*nrm2), or zero when the norm is zero (the squared norm is
-// read on the device, so the host need not wait for it)
-__global__ void k_normalize(const double* __restrict__ x, const double* __restrict__ nrm2, double* __restrict__ y,
-                            int64_t n) {
-  const double hn = sqrt(*nrm2);
+// y = x / sqrt(*nrm2) (zero when the norm is zero), and the basis' Gram
+// matrix row `row` (and its mirror column) for the new vector y: block 0
+// stores G[row][i] = (V[i] . x) / ||x|| for i < row from the products `dots`
+// taken while x was formed (zeros when dots is null: a vector orthogonalised
+// by two full passes) and G[row][row] = 1, and copies *nrm2 to nrm2_out when
+// that is not null.
+__global__ void k_normalize_gram(const double* __restrict__ x, const double* __restrict__ nrm2,
+                                 double* __restrict__ y, int64_t n, int row, const double* __restrict__ dots,
+                                 double* __restrict__ gram, size_t ldg, double* __restrict__ nrm2_out) {
+  const double nv = *nrm2;
+  const double hn = sqrt(nv);
   const double a = hn != 0.0 ? 1.0 / hn : 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = a * x[i];
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < row; i += blockDim.x) {
+      const double gv = dots ? dots[i] * a : 0.0;
+      gram[(size_t)row * ldg + i] = gv;
+      gram[(size_t)i * ldg + row] = gv;
+    }
+    if (threadIdx.x == 0) {
+      gram[(size_t)row * ldg + row] = 1.0;
+      if (nrm2_out) *nrm2_out = nv;
+    }
+  }
 }
-void launch_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s) {
+void launch_normalize_gram(const double* x, const double* nrm2, double* y, int64_t n, int row, const double* dots,
+                           double* gram, size_t ldg, double* nrm2_out, hipStream_t s) {
   if (n <= 0) return;
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_normalize, dim3((unsigned)g), dim3(256), 0, s, x, nrm2, y, n);
-  HIPCK(hipGetLastError());
-}
-
-// Row `row` of the basis' Gram matrix (and its mirror column) for the vector
-// just normalised from x: G[row][i] = (V[i] . x) / ||x|| for i < row, from the
-// products `dots` taken while x was formed (zeros when dots is null: a vector
-// orthogonalised by two full passes); optionally copies *nrm2 to nrm2_out.
-__global__ void k_gram_row(int row, const double* __restrict__ dots, const double* __restrict__ nrm2,
-                           double* __restrict__ gram, size_t ldg, double* __restrict__ nrm2_out) {
-  const double nv = *nrm2;
-  const double a = nv > 0.0 ? 1.0 / sqrt(nv) : 0.0;
-  for (int i = threadIdx.x; i < row; i += blockDim.x) {
-    const double gv = dots ? dots[i] * a : 0.0;
-    gram[(size_t)row * ldg + i] = gv;
-    gram[(size_t)i * ldg + row] = gv;
-  }
-  if (threadIdx.x == 0) {
-    gram[(size_t)row * ldg + row] = 1.0;
-    if (nrm2_out) *nrm2_out = nv;
-  }
-}
-void launch_gram_row(int row, const double* dots, const double* nrm2, double* gram, size_t ldg, double* nrm2_out,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_row, dim3(1), dim3(256), 0, s, row, dots, nrm2, gram, ldg, nrm2_out);
+  hipLaunchKernelGGL(k_normalize_gram, dim3((unsigned)g), dim3(256), 0, s, x, nrm2, y, n, row, dots, gram, ldg,
+                     nrm2_out);
   HIPCK(hipGetLastError());
 }
 

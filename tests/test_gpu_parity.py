@@ -238,13 +238,13 @@ def test_sweep_kernels_bitwise_equal(kind):
     _say(f"[case] sweep kernels {kind}")
     p = CASES[kind]()
     z = torch.as_tensor(np.random.default_rng(9).uniform(-1, 1, p.n_rows), device="cuda")
-    configs = [dict(sweep_kernel=1), dict(sweep_kernel=3), dict(sweep_kernel=2),
-               dict(sweep_kernel=3, sweep_wg_chunks=1), dict(sweep_kernel=3, sweep_wg_chunks=64)]
-    solvers = [Solver(p.rowptr, p.col, p.val, **c) for c in configs]
+    variants = [dict(sweep_kernel=1), dict(sweep_kernel=3), dict(sweep_kernel=2),
+                dict(sweep_kernel=3, sweep_wg_chunks=1), dict(sweep_kernel=3, sweep_wg_chunks=64)]
+    solvers = [Solver(p.rowptr, p.col, p.val, **c) for c in variants]
     tree = Solver(p.rowptr, p.col, p.val, sweep_kernel=0)
     for prec, adj in ((0, False), (1, False), (0, True)):
         ref = solvers[0].apply(z, precision=prec, adjoint=adj)
-        for c, s in zip(configs[1:], solvers[1:]):
+        for c, s in zip(variants[1:], solvers[1:]):
             a = s.apply(z, precision=prec, adjoint=adj)
             assert torch.equal(a, ref), (kind, c, prec, adj)
         t = tree.apply(z, precision=prec, adjoint=adj)
