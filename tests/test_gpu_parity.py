@@ -497,12 +497,16 @@ def test_tiny_and_degenerate():
         S_ = sp.csr_matrix(A)
         S_.sort_indices()
         rp, ci, v = S_.indptr.astype(np.int32), S_.indices.astype(np.int32), S_.data
-        s = Solver(rp, ci, v)
-        o = oracle.Oracle(rp, ci, v)
-        assert np.array_equal(s.aggregates().cpu().numpy(), o.aggregates())
-        b = np.arange(1, A.shape[0] + 1, dtype=float)
-        x, res = s.solve(torch.as_tensor(b, device="cuda"), tol=1e-12)
-        assert np.allclose(A @ x.cpu().numpy(), b, rtol=1e-11)
+        # default, GMG-ND smoother, SPAI coarse solve
+        for opts in ({}, dict(fine_order=1), dict(coarse_mode=2)):
+            s = Solver(rp, ci, v, **opts)
+            o = oracle.Oracle(rp, ci, v, **opts)
+            assert np.array_equal(s.aggregates().cpu().numpy(), o.aggregates())
+            b = np.arange(1, A.shape[0] + 1, dtype=float)
+            x, res = s.solve(torch.as_tensor(b, device="cuda"), tol=1e-12)
+            assert np.allclose(A @ x.cpu().numpy(), b, rtol=1e-11), opts
+            q = s.apply(torch.as_tensor(b, device="cuda")).cpu().numpy()
+            assert np.allclose(q, o.apply(b), rtol=1e-12, atol=1e-15), opts
     # zero right-hand side: x = 0 without iterations
     p = W.scaled("fv2d", 16)
     s = Solver(p.rowptr, p.col, p.val)
