@@ -102,7 +102,8 @@ def _alg_bytes_doc():
     return ("spmv 12*nnz+20*N (FP64 CSR, int32 indices); sweep: 12 per dependency entry + "
             "(8 + rhs + 2*val [+ diag] [+ reset]) per row; resid_restrict 12*nnz + 40*N + 20*N_c; "
             "ortho 8*N*(2k+3)+8*k^2 for k basis vectors from 33 to 384 (one Gram-corrected projection), "
-            "8*N*(3k+6) otherwise (two classical Gram-Schmidt passes)")
+            "8*N*(3k+6) up to 32 (two classical Gram-Schmidt passes), "
+            "8*N*(3k-k_last+4*blocks)+8*k^2 beyond 384 (the projection over blocks of 384)")
 
 
 def run_cpu_baseline(p, gpu_steps, budget_s=30.0):

@@ -970,7 +970,7 @@ struct OneResult {
 // Flexible GMRES(m) with right preconditioning (Algorithm 1's accelerator with
 // z_j = B~^{-1} v_j kept), Givens rotations on the host (O(m) scalars per
 // step).  Orthogonalisation: classical Gram-Schmidt applied twice while the
-// basis is short or very long; in between, one projection whose coefficients
+// basis is short (up to 32 vectors); beyond, one projection whose coefficients
 // are corrected with the basis' Gram matrix G = V^T V, c = (2I - G) V^T w
 // (equal to the second pass's V^T (w - V h) = h - G h), where each new row of
 // G comes from the products V^T w_new taken in the same read of V that forms
@@ -1067,13 +1067,23 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
         gdots = S.gdots.p;
         nrm_src = S.gdots.p + kc;
       } else {
-        Prof p(S, PC_ORTHO, 8.0 * n * (4 * kc + 4 * ((kc + kFused - 1) / kFused) + 4));
-        for (int c0 = 0; c0 < kc; c0 += kFused)
-          launch_multidot(V + (size_t)c0 * ld, ld, std::min(kFused, kc - c0), w, n, S.rw, h1 + c0, s);
-        launch_update_many(V, ld, kc, h1, w, n, false, S.rw, nullptr, s);
-        for (int c0 = 0; c0 < kc; c0 += kFused)
-          launch_multidot(V + (size_t)c0 * ld, ld, std::min(kFused, kc - c0), w, n, S.rw, h2 + c0, s);
-        launch_update_many(V, ld, kc, h2, w, n, true, S.rw, nrm, s);
+        // the same projection over blocks of mm vectors: h1 block by block;
+        // w -= V_b c_b for all blocks but the last, whose pass also takes its
+        // products with w_new and ||w_new||^2; then the other blocks'
+        // products with w_new (the Gram row)
+        const int mm = many_max(), nb = (kc + mm - 1) / mm, kl = kc - mm * (nb - 1);
+        Prof p(S, PC_ORTHO, 8.0 * n * (3 * kc - kl + 4 * nb) + 8.0 * kc * kc);
+        for (int b = 0; b < nb; ++b)
+          launch_multidot_many(V + (size_t)b * mm * ld, ld, std::min(mm, kc - b * mm), w, n, S.rw, h1 + b * mm, s);
+        launch_gram_coef(kc, h1, S.gram.p, S.ldg, h2, S.gcoef.p, s);
+        for (int b = 0; b + 1 < nb; ++b)
+          launch_update_many(V + (size_t)b * mm * ld, ld, mm, S.gcoef.p + b * mm, w, n, false, S.rw, nullptr, s);
+        const int b0 = mm * (nb - 1);
+        launch_update_dot_many(V + (size_t)b0 * ld, ld, kl, S.gcoef.p + b0, w, n, true, S.rw, S.gdots.p + b0, s);
+        for (int b = 0; b + 1 < nb; ++b)
+          launch_multidot_many(V + (size_t)b * mm * ld, ld, mm, w, n, S.rw, S.gdots.p + b * mm, s);
+        gdots = S.gdots.p;
+        nrm_src = S.gdots.p + kc;
       }
       {
         Prof p(S, PC_VECTOR, (double)n * 16);

@@ -151,13 +151,13 @@ def test_iterates_equal_steps(case, steps):
     assert d <= 1e-10, (name, steps, d)
 
 
-@pytest.mark.parametrize("steps,restart", [(40, 600), (120, 600), (400, 600), (130, 45)])
+@pytest.mark.parametrize("steps,restart", [(40, 600), (120, 600), (400, 600), (800, 1000), (130, 45)])
 def test_long_basis_iterates(steps, restart):
     """FGMRES past 32 basis vectors, where one Gram-corrected projection
-    replaces the two Gram-Schmidt passes, past 384, where the two passes
-    return, and restarted at 45 (the Gram rows rebuilt every cycle): iterates
-    at equal step counts within 1e-10 of the oracle's (modified
-    Gram-Schmidt), the same bar as above."""
+    replaces the two Gram-Schmidt passes, past 384 and 768, where that
+    projection runs over blocks of 384 vectors, and restarted at 45 (the Gram
+    rows rebuilt every cycle): iterates at equal step counts within 1e-10 of
+    the oracle's (modified Gram-Schmidt), the same bar as above."""
     _say(f"[case] long basis, {steps} steps, restart {restart}")
     p = W.scaled("fv2d_rot", 96)
     A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
