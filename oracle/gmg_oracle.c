@@ -903,7 +903,10 @@ void or_get_ilu0(const or_solver *S, double *vals) {
     memcpy(vals, S->ilu, sizeof(double) * (size_t)S->A.rp[S->A.n]);
 }
 /* the sparse approximate inverse of A_c (coarse_mode 2; A_c's pattern) */
-void or_get_spai(const or_solver *S, int *rp, int *ci, double *v) { get_csr(&S->Mc, rp, ci, v); }
+void or_get_spai(const or_solver *S, int *rp, int *ci, double *v) {
+    if (!S->Mc.rp) return;   /* no inverse unless coarse_mode 2 */
+    get_csr(&S->Mc, rp, ci, v);
+}
 /* the smoother's numbering (position -> fine unknown) and matrix F */
 void or_get_fine(const or_solver *S, int *perm, int *rp, int *ci, double *v) {
     memcpy(perm, S->fperm, sizeof(int) * (size_t)S->A.n);
