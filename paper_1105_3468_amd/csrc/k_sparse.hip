@@ -208,7 +208,20 @@ __global__ void k_restrict(int nc, const int* __restrict__ aptr, const int* __re
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   T s = (T)0;
-  for (int m = aptr[I]; m < aptr[I + 1]; ++m) s += r[amem[m]];
+  const int m0 = aptr[I], m1 = aptr[I + 1];
+  // members in batches of eight: every index, then every value, then the
+  // sums in member order (one round of dependent loads per batch)
+  for (int m = m0; m < m1; m += 8) {
+    int k[8];
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) k[u] = m + u < m1 ? amem[m + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = k[u] >= 0 ? r[k[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k[u] >= 0) s += v[u];
+  }
   rc[I] = s;
   if (reset) reset[I] = sentinel_of<T>(sent);
 }
