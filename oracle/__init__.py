@@ -172,7 +172,8 @@ class Oracle:
 
     def fine(self):
         """The smoother's numbering perm (position -> fine unknown; identity
-        unless fine_order = 1) and its matrix F = Q A Q^T as (rowptr, col, val)."""
+        unless fine_order is 1, nested dissection, or 2, colour classes) and its
+        matrix F = Q A Q^T as (rowptr, col, val)."""
         perm = np.empty(self.n, dtype=np.int32)
         rp = np.empty(self.n + 1, dtype=np.int32)
         ci = np.empty(self.nnz, dtype=np.int32)

@@ -12,6 +12,8 @@
  *   smoother S = L0 U0 = ILU(0)(A) ............... Section 2 (choice of S), Algorithm 1 setup
  *   ... or ILU(0) of A in nested-dissection order  the GMG-ND variant (Section 3.1 variant
  *       (S = Q^T L0 U0 Q) .......................  list and the comments on ND ordering)
+ *   ... or in colour-class order (multicolour) .. a reading of the same comments: any
+ *                                                  reordering that lets ILU(0) run in parallel
  *   inexact coarse factors ILUT(A_c) ............. Section 2 (ILU(t) paragraph), Algorithm 1 setup
  *   two-grid preconditioner B~ ................... Eq. (twogrid) and Algorithm 1 "SOLVE B~q=z",
  *                                                  "SOLVE M~g=h"
@@ -50,7 +52,8 @@ typedef struct {
     int coarse_sweeps;   /* Jacobi sweeps per factor when coarse_mode == 1        */
     int coarse_order;    /* 0: aggregates by smallest fine index; 1: nested dissection */
     int fine_order;      /* 0: ILU(0) smoother on A's numbering; 1: on A renumbered by
-                            nested dissection (the GMG-ND variant)                   */
+                            nested dissection (the GMG-ND variant); 2: by colour
+                            classes of a greedy colouring (multicolour ILU(0))      */
 } or_opts;
 
 typedef struct {
@@ -514,6 +517,36 @@ static int pair_cmp(const void *a, const void *b) {
     return (x[0] > y[0]) - (x[0] < y[0]);
 }
 
+/* Greedy colouring in natural order: vertex i takes the smallest colour not
+   used by a neighbour j < i (i ~ j when a_ij or a_ji is stored); perm lists
+   the vertices by colour, ascending within a colour.  On a 2D or 3D grid with
+   a 5- or 7-point stencil this is the red-black ordering. */
+static int color_order(const csr_t *A, int *perm) {
+    int n = A->n;
+    csr_t T = {0};
+    int st = transpose(A, &T);
+    int *color = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *seen = malloc(sizeof(int) * (size_t)(n + 1));
+    int *cnt = malloc(sizeof(int) * (size_t)(n + 2));
+    if (st || !color || !seen || !cnt) { csr_free(&T); free(color); free(seen); free(cnt); return st ? st : OR_ERR_OOM; }
+    for (int c = 0; c <= n; ++c) seen[c] = -1;
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int p = A->rp[i]; p < A->rp[i + 1]; ++p) if (A->ci[p] < i) seen[color[A->ci[p]]] = i;
+        for (int p = T.rp[i]; p < T.rp[i + 1]; ++p) if (T.ci[p] < i) seen[color[T.ci[p]]] = i;
+        int c = 0;
+        while (seen[c] == i) ++c;
+        color[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    for (int c = 0; c <= ncol; ++c) cnt[c] = 0;
+    for (int i = 0; i < n; ++i) cnt[color[i] + 1]++;
+    for (int c = 0; c < ncol; ++c) cnt[c + 1] += cnt[c];
+    for (int i = 0; i < n; ++i) perm[cnt[color[i]]++] = i;
+    csr_free(&T); free(color); free(seen); free(cnt);
+    return OR_OK;
+}
+
 static int smoother_matrix(or_solver *S) {
     const csr_t *A = &S->A;
     int n = A->n, nnz = A->rp[n];
@@ -530,7 +563,7 @@ static int smoother_matrix(or_solver *S) {
         memcpy(S->F.v, A->v, sizeof(double) * (size_t)nnz);
         return OR_OK;
     }
-    int st = nd_order(A, S->fperm);
+    int st = S->o.fine_order == 1 ? nd_order(A, S->fperm) : color_order(A, S->fperm);
     if (st) return st;
     int *rank = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
     int *pr = malloc(sizeof(int) * 2 * (size_t)(n > 0 ? n : 1));
@@ -815,7 +848,7 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, const or_opts
     if (!S) return OR_ERR_OOM;
     S->o = *opts;
     if (S->o.qbits < 0 || S->o.qbits > 52 || !(S->o.cf >= 1.0) || S->o.coarse_order < 0 || S->o.coarse_order > 1 ||
-        S->o.fine_order < 0 || S->o.fine_order > 1 || S->o.coarse_mode < 0 || S->o.coarse_mode > 2) {
+        S->o.fine_order < 0 || S->o.fine_order > 2 || S->o.coarse_mode < 0 || S->o.coarse_mode > 2) {
         or_destroy(S);
         return OR_ERR_INVALID;
     }

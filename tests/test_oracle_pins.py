@@ -492,17 +492,47 @@ def _nd_case(name):
 
 
 @pytest.mark.parametrize("case", ["fv2d_24", "fv3d_8", "rgg_500"])
-def test_fine_nd_smoother(oracle_mod, case):
-    """GMG-ND (Section 3.1 variants): the smoother is ILU(0) of A renumbered by
-    nested dissection.  The numbering equals the recursive definition on A's
-    graph; F = A[perm][:, perm]; its factors satisfy the ILU(0) definition
+def test_color_order(oracle_mod, case):
+    """Multicolour smoother numbering (fine_order 2): on 5- and 7-point grids
+    the greedy colouring is red-black, so the numbering is the cells with
+    even coordinate sum, ascending, then the odd ones; on any graph the
+    colouring is proper and each vertex has the smallest colour its earlier
+    neighbours leave free (brute force), and the numbering sorts by colour."""
+    rp, ci, v, n = _nd_case(case)
+    O = oracle_mod.Oracle(rp, ci, v, fine_order=2)
+    perm, _ = O.fine()
+    if case != "rgg_500":
+        g = round(n ** 0.5) if case == "fv2d_24" else round(n ** (1 / 3))
+        idx = np.arange(n)
+        par = (idx % g + (idx // g) % g + (idx // (g * g))) % 2
+        assert np.array_equal(perm, np.concatenate([idx[par == 0], idx[par == 1]]))
+    adj = B.coarse_pattern_adj(rp, ci, np.arange(n), n)
+    color = [0] * n
+    for i in range(n):
+        used = {color[j] for j in adj[i] if j < i}
+        c = 0
+        while c in used:
+            c += 1
+        color[i] = c
+    assert all(color[i] != color[j] for i in range(n) for j in adj[i])
+    assert np.array_equal(perm, np.array(sorted(range(n), key=lambda i: (color[i], i))))
+
+
+@pytest.mark.parametrize("fine_order", [1, 2])
+@pytest.mark.parametrize("case", ["fv2d_24", "fv3d_8", "rgg_500"])
+def test_fine_nd_smoother(oracle_mod, case, fine_order):
+    """GMG-ND (Section 3.1 variants) and the multicolour smoother: the smoother
+    is ILU(0) of A renumbered by nested dissection (fine_order 1; the
+    numbering equals the recursive definition on A's graph) or by colour
+    classes (fine_order 2; numbering pinned above); F = A[perm][:, perm]; its factors satisfy the ILU(0) definition
     (L U = F on F's pattern); the preconditioner and its adjoint equal the
     dense Eq. (twogrid) operator built with S = Q^T L U Q."""
     rp, ci, v, n = _nd_case(case)
-    O = oracle_mod.Oracle(rp, ci, v, fine_order=1)
+    O = oracle_mod.Oracle(rp, ci, v, fine_order=fine_order)
     perm, (frp, fci, fv) = O.fine()
-    ref = B.nd_order_ref(n, B.coarse_pattern_adj(rp, ci, np.arange(n), n))
-    assert np.array_equal(perm, np.array(ref))
+    if fine_order == 1:
+        ref = B.nd_order_ref(n, B.coarse_pattern_adj(rp, ci, np.arange(n), n))
+        assert np.array_equal(perm, np.array(ref))
     assert not np.array_equal(perm, np.arange(n))
     A = B.dense(rp, ci, v)
     F = B.dense(frp, fci, fv)
