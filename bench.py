@@ -8,7 +8,7 @@ FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
 before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K] [--fine-nd] [--spai]
+                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K] [--fine-nd] [--fine-color] [--spai]
        python bench.py --copy-calibration   (a plain 1 GiB device copy, run
                        under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
 
@@ -153,6 +153,8 @@ def main():
                     help="also time the coarse solve by a sparse approximate inverse of A_c, reported beside")
     ap.add_argument("--fine-nd", action="store_true",
                     help="also time GMG-ND (ILU(0) smoother in nested-dissection order), reported beside")
+    ap.add_argument("--fine-color", action="store_true",
+                    help="also time the multicolour ILU(0) smoother (colour classes of a greedy colouring)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -380,6 +382,30 @@ def main():
             kernels={k: dict(launches=v["launches"], total_ms=round(v["ms"], 4)) for k, v in prn.items()
                      if v["launches"]})
         print(f"[bench] GMG-ND step: {tn:.3f}s its={rn.info['iters']}", file=sys.stderr, flush=True)
+
+    if args.fine_color:
+        # the multicolour smoother: ILU(0) of A in the colour classes of a
+        # greedy colouring (red-black here), applied by level sweeps
+        def mc_step(profile=False):
+            Sm = Solver(rp, ci, va, cf=SOLVE_OPTS["cf"], ilut_tau=SOLVE_OPTS["ilut_tau"], fine_order=2)
+            if profile:
+                Sm.profile(True)
+            xm, rm = Sm.solve(b, tol=TOL, restart=SOLVE_OPTS["restart"], maxit=SOLVE_OPTS["maxit"])
+            return Sm, xm, rm, (Sm.profile_read() if profile else None)
+        mc_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sm, xm, rm, _ = mc_step()
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        _, _, _, prm = mc_step(True)
+        out["gmg_multicolor"] = dict(
+            time_s=round(tm, 6), setup_ms=round(Sm.setup_info["setup_ms"], 2), solve_ms=round(rm.info["solve_ms"], 2),
+            iters=rm.info["iters"], status=int(rm.status), levels_L0=Sm.setup_info["levels_L0"],
+            relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xm.cpu().numpy()) / np.linalg.norm(p.b[:, 0])),
+            kernels={k: dict(launches=v["launches"], total_ms=round(v["ms"], 4)) for k, v in prm.items()
+                     if v["launches"]})
+        print(f"[bench] multicolour smoother step: {tm:.3f}s its={rm.info['iters']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -94,8 +94,11 @@ typedef struct {
                            Section 3.1): S = Q^T L0 U0 Q with L0 U0 = ILU(0) of
                            Q A Q^T, applied over the dissection tree under
                            sweep_kernel 0 (level sweeps otherwise, or when a
-                           separator exceeds 2048 rows).  Aggregates, A_c and
-                           its ILUT do not depend on it.  No adjoint.           */
+                           separator exceeds 2048 rows); 2 colour classes of a
+                           greedy colouring in natural order (red-black on 5-
+                           and 7-point grids; multicolour ILU(0)), applied by
+                           level sweeps with one level per colour.  Aggregates,
+                           A_c and its ILUT do not depend on it.  No adjoint.   */
 } gmg_options;
 
 typedef struct {
@@ -171,8 +174,8 @@ gmg_status gmg_get_coarse(gmg_handle h, int32_t* rowptr, int32_t* col, double* v
 gmg_status gmg_get_ilu0(gmg_handle h, double* val);
 
 /* The smoother's numbering: perm (device int32[N]) with position k holding
- * fine unknown perm[k]; the identity under fine_order 0.  Section 3.1
- * (GMG-ND) and the dissection rule of the coarse numbering. */
+ * fine unknown perm[k]; the identity under fine_order 0, the nested
+ * dissection (GMG-ND, Section 3.1) under 1, the colour classes under 2. */
 gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm);
 
 /* The sparse approximate inverse of A_c (coarse_mode 2), a parallel inexact

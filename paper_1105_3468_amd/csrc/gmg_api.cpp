@@ -1311,7 +1311,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
       o.coarse_mode < 0 || o.coarse_mode > 2 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
       o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 3 ||
-      o.sweep_wg_chunks < 0 || o.fine_order < 0 || o.fine_order > 1)
+      o.sweep_wg_chunks < 0 || o.fine_order < 0 || o.fine_order > 2)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
   auto t0 = std::chrono::steady_clock::now();
   // GMG_LOG also prints the duration of each setup phase (it then waits for
@@ -1431,14 +1431,14 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
   std::vector<int> hci = to_host_int(S.A.ci.p, nnz64, s);
   HIPCK(hipStreamSynchronize(s));
-  // ---- GMG-ND: the smoother works on F = Q A Q^T, Q the nested-dissection
-  // numbering of A's graph (the coarse numbering's rule); from here on
-  // hrp/hci hold F's pattern
+  // ---- GMG-ND / multicolour: the smoother works on F = Q A Q^T, Q the
+  // nested-dissection numbering of A's graph (the coarse numbering's rule) or
+  // its colour classes; from here on hrp/hci hold F's pattern
   const int* frp_dev = S.A.rp.p;
   const int* fci_dev = S.A.ci.p;
   const double* fval_dev = S.A.v.p;
   DBuf<double> fval;
-  if (o.fine_order == 1) {
+  if (o.fine_order >= 1) {
     std::vector<int> cnt(n + 1, 0);
     for (int i = 0; i < n; ++i)
       for (int p = hrp[i]; p < hrp[i + 1]; ++p)
@@ -1448,7 +1448,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     for (int i = 0; i < n; ++i)
       for (int p = hrp[i]; p < hrp[i + 1]; ++p)
         if (hci[p] != i) { gci[fillp[i]++] = hci[p]; gci[fillp[hci[p]]++] = i; }
-    std::vector<int> perm = nd_numbering(n, cnt, gci, &S.fnd_tree);
+    std::vector<int> perm = o.fine_order == 1 ? nd_numbering(n, cnt, gci, &S.fnd_tree) : color_numbering(n, cnt, gci);
     std::vector<int> rank(n), brp(n + 1, 0), bci(nnz64), bsrc(nnz64);
     for (int k = 0; k < n; ++k) rank[perm[k]] = k;
     for (int k = 0; k < n; ++k) brp[k + 1] = brp[k] + hrp[perm[k] + 1] - hrp[perm[k]];
@@ -1485,7 +1485,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     fci_dev = S.fci.p;
     fval_dev = fval.p;
     S.fine_nd = true;
-    phase("fine nested dissection");
+    phase(o.fine_order == 1 ? "fine nested dissection" : "fine colouring");
   }
   // diagonal positions and the dependency lists of the two forward fine
   // sweeps (strict lower / strict upper entries of each row).  One thread on
@@ -1564,7 +1564,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       phase("wavefront layout");
     }
   }
-  if (S.fine_nd && o.sweep_kernel == 0) {
+  if (S.fine_nd && o.fine_order == 1 && o.sweep_kernel == 0) {
     // ILU(0) of F follows the dissection tree as the coarse ILUT does: the
     // tree solves apply it when every node fits
     std::vector<double> hilu(nnz64), hud(n);

@@ -340,6 +340,10 @@ struct NdNode {
 };
 std::vector<int> nd_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci,
                               std::vector<NdNode>* tree = nullptr);
+// Colour-class numbering (position -> vertex) of a symmetric graph: greedy
+// colouring in natural order (smallest colour unused by earlier neighbours),
+// vertices listed by colour, ascending within a colour.
+std::vector<int> color_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci);
 // Row-wise ILUT(tau) without pivoting on a host CSR; L strictly lower,
 // U with the diagonal first.  Returns GMG_OK / GMG_ERR_ZERO_PIVOT / NONFINITE.
 // With the nested-dissection tree of A's numbering, the tree's nodes are

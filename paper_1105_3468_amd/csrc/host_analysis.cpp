@@ -671,6 +671,28 @@ std::vector<int> nd_numbering(int n, const std::vector<int>& rp_in, const std::v
   return seq;
 }
 
+// Colour-class numbering: a greedy colouring in natural order (vertex i
+// takes the smallest colour no neighbour j < i has), then the vertices by
+// colour, ascending within a colour.  rp/ci: the symmetric neighbour lists
+// (repeats allowed).
+std::vector<int> color_numbering(int n, const std::vector<int>& rp, const std::vector<int>& ci) {
+  std::vector<int> color(n), last(n + 1, -1);
+  int ncol = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int q = rp[i]; q < rp[i + 1]; ++q)
+      if (ci[q] < i) last[color[ci[q]]] = i;
+    int c = 0;
+    while (last[c] == i) ++c;
+    color[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  std::vector<int> start(ncol + 1, 0), perm(n);
+  for (int i = 0; i < n; ++i) start[color[i] + 1]++;
+  for (int c = 0; c < ncol; ++c) start[c + 1] += start[c];
+  for (int i = 0; i < n; ++i) perm[start[color[i]]++] = i;
+  return perm;
+}
+
 // Sparse approximate inverse of A (square host CSR) with A's pattern: column
 // j of M minimises ||A m - e_j||_2 over m supported on column j's pattern J.
 // The rows that those columns reach form a small dense least-squares

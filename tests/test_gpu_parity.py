@@ -398,19 +398,21 @@ ND_CASES = {
 }
 
 
+@pytest.mark.parametrize("fo", [1, 2])
 @pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("name", list(ND_CASES))
-def test_fine_nd_smoother(name, kernel):
-    """GMG-ND (Section 3.1 variants): the smoother's nested-dissection
-    numbering and its ILU(0) factors bit-exact vs the oracle; one application
-    in FP64 within 1e-12, in FP32 within the FP32 bar; a converged solve
-    within one step of the oracle's; the adjoint refused.  kernel 0: tree
-    solves over the dissection tree; 1: whole-device level sweeps."""
-    _say(f"[case] fine_order=1 {name} sweep_kernel={kernel}")
+def test_fine_nd_smoother(name, kernel, fo):
+    """GMG-ND (Section 3.1 variants, fo = 1) and the multicolour smoother
+    (fo = 2): the smoother's numbering and its ILU(0) factors bit-exact vs the
+    oracle; one application in FP64 within 1e-12, in FP32 within the FP32 bar;
+    a converged solve within one step of the oracle's; the adjoint refused.
+    kernel 0: tree solves over the dissection tree (fo = 1) or the automatic
+    level sweeps (fo = 2); 1: whole-device level sweeps."""
+    _say(f"[case] fine_order={fo} {name} sweep_kernel={kernel}")
     p = ND_CASES[name]()
     A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
-    O = oracle.Oracle(p.rowptr, p.col, p.val, fine_order=1)
-    S = Solver(p.rowptr, p.col, p.val, fine_order=1, sweep_kernel=kernel)
+    O = oracle.Oracle(p.rowptr, p.col, p.val, fine_order=fo)
+    S = Solver(p.rowptr, p.col, p.val, fine_order=fo, sweep_kernel=kernel)
     perm, _ = O.fine()
     assert np.array_equal(S.fine_perm().cpu().numpy(), perm)
     assert np.array_equal(S.ilu0().cpu().numpy().view(np.uint64), O.ilu0().view(np.uint64))
@@ -433,7 +435,7 @@ def test_fine_nd_smoother(name, kernel):
     assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
     with pytest.raises(GmgError):
         S.apply(torch.as_tensor(z, device="cuda"), precision=0, adjoint=True)
-    if kernel == 0:
+    if kernel == 0 and fo == 1:
         S0 = Solver(p.rowptr, p.col, p.val)
         assert np.array_equal(S0.fine_perm().cpu().numpy(), np.arange(p.n_rows))
 
