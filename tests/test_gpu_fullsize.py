@@ -122,3 +122,36 @@ def test_converged_solve(big, fp32):
         if not fp32:
             assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
         assert np.linalg.norm(A @ (xh - xo)) / np.linalg.norm(b) <= 2 * tol
+
+
+VARIANTS = {"gmg_nd": dict(fine_order=1), "multicolour": dict(fine_order=2), "spai": dict(coarse_mode=2)}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_variants_full_size(variant):
+    """The paper's variants at the benchmark's size and options (fv2d_1024,
+    cf = 4, ILUT 1e-6): GMG-ND and the multicolour smoother (numbering and
+    ILU(0) factors bit-exact), the SPAI coarse solve (inverse bit-exact), and
+    one preconditioner application within 1e-12 of the oracle's, as for the
+    default method above."""
+    kw = VARIANTS[variant]
+    opts = dict(SETUPS["fv2d_1024"][0], **kw)
+    _say(f"[fullsize] fv2d_1024 {variant}: generating")
+    p = W.make("fv2d_1024")
+    _say(f"[fullsize] fv2d_1024 {variant}: oracle setup")
+    O = oracle.Oracle(p.rowptr, p.col, p.val, **opts)
+    _say(f"[fullsize] fv2d_1024 {variant}: GPU setup")
+    S = Solver(p.rowptr, p.col, p.val, **opts)
+    _say(f"[fullsize] fv2d_1024 {variant}: setup outputs")
+    assert np.array_equal(S.fine_perm().cpu().numpy(), O.fine()[0])
+    assert np.array_equal(S.ilu0().cpu().numpy().view(np.uint64), O.ilu0().view(np.uint64))
+    if "coarse_mode" in kw:
+        rp, ci, v = (t.cpu().numpy() for t in S.spai())
+        orp, oci, ov = O.spai()
+        assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+        assert np.array_equal(v.view(np.uint64), ov.view(np.uint64))
+    _say(f"[fullsize] fv2d_1024 {variant}: preconditioner")
+    z = np.random.default_rng(12).uniform(-1, 1, p.n_rows)
+    q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
+    ref = O.apply(z, 0)
+    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
