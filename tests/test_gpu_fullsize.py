@@ -124,16 +124,18 @@ def test_converged_solve(big, fp32):
         assert np.linalg.norm(A @ (xh - xo)) / np.linalg.norm(b) <= 2 * tol
 
 
-VARIANTS = {"gmg_nd": dict(fine_order=1), "multicolour": dict(fine_order=2), "spai": dict(coarse_mode=2)}
+VARIANTS = {"gmg_nd": dict(fine_order=1), "multicolour": dict(fine_order=2), "spai": dict(coarse_mode=2),
+            "jacobi": dict(coarse_mode=1, coarse_sweeps=3)}
 
 
 @pytest.mark.parametrize("variant", list(VARIANTS))
 def test_variants_full_size(variant):
     """The paper's variants at the benchmark's size and options (fv2d_1024,
     cf = 4, ILUT 1e-6): GMG-ND and the multicolour smoother (numbering and
-    ILU(0) factors bit-exact), the SPAI coarse solve (inverse bit-exact), and
-    one preconditioner application within 1e-12 of the oracle's, as for the
-    default method above."""
+    ILU(0) factors bit-exact), the SPAI coarse solve (inverse bit-exact), the
+    coarse solve by three Jacobi sweeps per ILUT factor (factors bit-exact),
+    and one preconditioner application within 1e-12 of the oracle's, as for
+    the default method above."""
     kw = VARIANTS[variant]
     opts = dict(SETUPS["fv2d_1024"][0], **kw)
     _say(f"[fullsize] fv2d_1024 {variant}: generating")
@@ -145,7 +147,12 @@ def test_variants_full_size(variant):
     _say(f"[fullsize] fv2d_1024 {variant}: setup outputs")
     assert np.array_equal(S.fine_perm().cpu().numpy(), O.fine()[0])
     assert np.array_equal(S.ilu0().cpu().numpy().view(np.uint64), O.ilu0().view(np.uint64))
-    if "coarse_mode" in kw:
+    if kw.get("coarse_mode") == 1:
+        (lrp, lci, lv), (urp, uci, uv) = [[t.cpu().numpy() for t in f] for f in S.ilut()]
+        (olrp, olci, olv), (ourp, ouci, ouv) = O.ilut()
+        assert np.array_equal(lci, olci) and np.array_equal(lv.view(np.uint64), olv.view(np.uint64))
+        assert np.array_equal(uci, ouci) and np.array_equal(uv.view(np.uint64), ouv.view(np.uint64))
+    if kw.get("coarse_mode") == 2:
         rp, ci, v = (t.cpu().numpy() for t in S.spai())
         orp, oci, ov = O.spai()
         assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
