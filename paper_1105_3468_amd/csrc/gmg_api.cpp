@@ -235,16 +235,76 @@ static void parallel_ranges(int n, F&& f) {
 
 // Lay a triangular factor out for the tree solve (k_tree.hip).  Row r's
 // entries are q in [rp[r] + skip, rp[r+1]) with column ci[q] and value
-// vals[src ? src[q] : q].  Returns false (and leaves ts empty) when the factor
+// vals[src ? src[q] : q].  Nodes above kTreeMaxRows rows are first cut into
+// chains (split_tree).  Returns false (and leaves ts empty) when the factor
 // does not follow the tree: an entry outside its row's node must point into a
-// descendant node (lower) or an ancestor node (upper), and every node must fit
-// kTreeMaxRows rows.  The host checks the structure and counts the outside
+// descendant node (lower) or an ancestor node (upper).  The host checks the structure and counts the outside
 // entries per row; the dense diagonal blocks and the outside-entry lists are
 // scattered on the GPU, then the blocks are inverted there.
-static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree, int n, const std::vector<int>& rp,
+// The dissection tree with every node cut to at most max_rows rows: a larger
+// node (a separator, dense after fill) becomes a chain of consecutive row
+// blocks, the first taking the node's children and each next one the block
+// before it, the last hanging from the first block of the node's parent.
+// Entries between blocks of one node then point into a descendant (lower
+// factor) or an ancestor (upper factor), like any other outside entry, so
+// the factor still follows the tree.  Node 0 stays the root; heights are
+// recomputed.
+static std::vector<NdNode> split_tree(const std::vector<NdNode>& t, int max_rows) {
+  const int nn = (int)t.size();
+  bool any = false;
+  for (const NdNode& d : t) any = any || d.hi - d.lo > max_rows;
+  if (!any) return t;
+  std::vector<int> nb(nn), first(nn);
+  int total = 0;
+  for (int x = 0; x < nn; ++x) {
+    const int sz = t[x].hi - t[x].lo;
+    nb[x] = std::max(1, (sz + max_rows - 1) / max_rows);
+    first[x] = total;
+    total += nb[x];
+  }
+  // chain of x: ids first[x] + k, k = 0 (bottom) .. nb[x] - 1 (top); the
+  // root's top is then moved to id 0
+  std::vector<NdNode> out(total);
+  for (int x = 0; x < nn; ++x) {
+    const int sz = t[x].hi - t[x].lo, b = (sz + nb[x] - 1) / std::max(1, nb[x]);
+    for (int k = 0; k < nb[x]; ++k) {
+      NdNode& d = out[first[x] + k];
+      d.lo = std::min(t[x].hi, t[x].lo + k * b);
+      d.hi = std::min(t[x].hi, t[x].lo + (k + 1) * b);
+      d.parent = k + 1 < nb[x] ? first[x] + k + 1 : (t[x].parent < 0 ? -1 : first[t[x].parent]);
+      d.height = 0;
+    }
+  }
+  const int root = first[0] + nb[0] - 1;
+  if (root != 0) {
+    std::swap(out[0], out[root]);
+    for (NdNode& d : out) {
+      if (d.parent == 0) d.parent = root;
+      else if (d.parent == root) d.parent = 0;
+    }
+  }
+  // heights: children before parents in a post-order from the root
+  std::vector<std::vector<int>> kids(total);
+  for (int k = 1; k < total; ++k) kids[out[k].parent].push_back(k);
+  std::vector<int> order, st{0};
+  while (!st.empty()) {
+    const int k = st.back();
+    st.pop_back();
+    order.push_back(k);
+    for (int c : kids[k]) st.push_back(c);
+  }
+  for (int i = (int)order.size() - 1; i >= 0; --i) {
+    const int k = order[i];
+    for (int c : kids[k]) out[k].height = std::max(out[k].height, out[c].height + 1);
+  }
+  return out;
+}
+
+static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree_in, int n, const std::vector<int>& rp,
                        const std::vector<int>& ci, const std::vector<int>* src, int skip,
                        const std::vector<double>& vals, bool lower, const std::vector<double>* dinv,
                        hipStream_t s) {
+  const std::vector<NdNode> tree = split_tree(tree_in, kTreeMaxRows);
   constexpr int kHelperEntries = 512, kHelperRows = 64;
   constexpr int kSliceLgRows = 4;             // rows per slice of a node above 64 rows: 16
   constexpr size_t kSmallInvLds = 40 * 1024;  // inversion chunks launched with this much LDS or less first

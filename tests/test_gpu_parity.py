@@ -442,7 +442,8 @@ def test_fine_nd_smoother(name, kernel, fo):
 
 def test_fine_nd_large_separator():
     """GMG-ND on 64^3 cells: the first separator has more rows than one tree
-    node may hold, so the level sweeps apply the factors; same bars."""
+    node may hold, so the tree layout cuts it into a chain of row blocks;
+    same bars."""
     _say("[case] fine_order=1 fv3d_64 (level sweeps)")
     p = W.scaled("fv3d", 64)
     O = oracle.Oracle(p.rowptr, p.col, p.val, fine_order=1)
