@@ -66,7 +66,12 @@ typedef struct {
   int coarse_mode;      /* 0: exact triangular sweeps with the ILUT factors;
                            1: coarse_sweeps Jacobi sweeps per factor (FP64);
                            2: e_c = M r_c with a sparse approximate inverse M of
-                           A_c on A_c's pattern (no ILUT is computed)           */
+                           A_c on A_c's pattern (no ILUT is computed);
+                           3: e_c = A_c^{-1} r_c with the dense inverse, the exact
+                           coarse solve of the EGMG variant of Section 3, for
+                           N_c <= 8192 (no ILUT is computed; larger N_c give
+                           GMG_ERR_INVALID_ARG at setup, a zero pivot of the
+                           no-pivot elimination GMG_ERR_ZERO_PIVOT)              */
   int coarse_sweeps;    /* (default 3)                                               */
   int restart;          /* FGMRES restart length m (default 30, at most 2048)        */
   int maxit;            /* total FGMRES steps at most (default 600)                  */
@@ -157,7 +162,7 @@ gmg_status gmg_get_info(gmg_handle h, gmg_info* info);
  * lower bound of cond(A_c) when A_c is SPD; *est_ilut = max_i |(L~U~)_ii| /
  * min_i |(L~U~)_ii|, the unsymmetric form of the factorization's estimate,
  * (L~U~)_ii = u_ii + sum_{j<i} l_ij u_ji.  Both are host doubles; a zero
- * denominator gives +inf.  GMG_ERR_INVALID_ARG under coarse_mode 2. */
+ * denominator gives +inf.  GMG_ERR_INVALID_ARG under coarse_mode 2 or 3. */
 gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut);
 
 /* Aggregate of every fine unknown: agg device int32[N]; ids 0..N_c-1 ordered
@@ -185,6 +190,11 @@ gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm);
  * rowptr[N_c+1], col[nnz_coarse], val[nnz_coarse]; GMG_ERR_INVALID_ARG under
  * another coarse_mode. */
 gmg_status gmg_get_spai(gmg_handle h, int32_t* rowptr, int32_t* col, double* val);
+
+/* The dense exact inverse of A_c (coarse_mode 3; the EGMG variant's exact
+ * coarse solve, Section 3) into the device array inv[N_c * N_c], row-major.
+ * GMG_ERR_INVALID_ARG under another coarse_mode. */
+gmg_status gmg_get_coarse_inverse(gmg_handle h, double* inv);
 
 /* ILUT factors of A_c: L~ strictly lower (unit diagonal implied) and U~ with
  * its diagonal first in each row; device arrays sized by gmg_get_info. */

@@ -61,6 +61,10 @@ struct Solver {
   DCsr dLc, dUc;               // coarse factors as CSR (Jacobi mode)
   HCsr hMc;                    // sparse approximate inverse of A_c (coarse_mode 2)
   DCsr dMc;
+  DBuf<double> cinv;           // dense A_c^{-1}, padded row-major (coarse_mode 3)
+  DBuf<float> cinv32;
+  DBuf<int> cbad;
+  int cnp = 0;                 // its padded size
   DBuf<double> ucdinv, jzero, jtmp;
   // forward V-cycle work vectors
   DBuf<double> y, t, r, rc, yc, ec;
@@ -823,6 +827,10 @@ static void vcycle(Solver& S, const double* z, double* q) {
       Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uc, sz, sz, true));
       run_tri<T>(S, S.Uc, yc, false, ec, yc);
     }
+  } else if (S.opt.coarse_mode == 3) {
+    // e_c = A_c^{-1} r_c with the dense inverse
+    Prof p(S, PC_SWEEP_COARSE, (double)S.nc * S.nc * sz + (double)S.nc * 2 * sz);
+    launch_dense_gemv<T>(S.nc, S.cnp, F32 ? (const T*)S.cinv32.p : (const T*)S.cinv.p, rc, ec, s);
   } else if (S.opt.coarse_mode == 2) {
     // e_c = M r_c with the sparse approximate inverse
     Prof p(S, PC_SWEEP_COARSE, (double)S.dMc.nnz * (4 + sz) + (double)S.nc * (4 + 2 * sz));
@@ -1369,7 +1377,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   if (!rowptr || !col || !val) fail(GMG_ERR_INVALID_ARG, "setup: null matrix pointer");
   const gmg_options& o = S.opt;
   if (!(o.cf >= 1.0) || o.max_passes < 0 || o.match_qbits < 0 || o.match_qbits > 52 || !(o.ilut_tau >= 0.0) ||
-      o.coarse_mode < 0 || o.coarse_mode > 2 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
+      o.coarse_mode < 0 || o.coarse_mode > 3 || o.coarse_sweeps < 0 || o.sweep_waves < 0 ||
       o.coarse_order < 0 || o.coarse_order > 1 || o.sweep_kernel < 0 || o.sweep_kernel > 3 ||
       o.sweep_wg_chunks < 0 || o.fine_order < 0 || o.fine_order > 2)
     fail(GMG_ERR_INVALID_ARG, "setup: option out of range");
@@ -1484,8 +1492,12 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       if (t.joinable()) t.join();
     }
   } ilut_job;
-  ilut_job.t = std::thread([&S, &hAc, &ilut_st, tau = o.ilut_tau, spai = o.coarse_mode == 2] {
-    ilut_st = spai ? host_spai(hAc, S.hMc) : host_ilut(hAc, tau, S.hLc, S.hUc, &S.nd_tree);
+  if (o.coarse_mode == 3 && S.nc > kDenseMaxCoarse)
+    fail(GMG_ERR_INVALID_ARG, "coarse_mode 3 (dense inverse) needs n_coarse <= 8192");
+  ilut_job.t = std::thread([&S, &hAc, &ilut_st, tau = o.ilut_tau, mode = o.coarse_mode] {
+    ilut_st = mode == 3   ? GMG_OK
+              : mode == 2 ? host_spai(hAc, S.hMc)
+                          : host_ilut(hAc, tau, S.hLc, S.hUc, &S.nd_tree);
   });
   // ---- host copy of A's pattern for the analysis
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
@@ -1660,7 +1672,22 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   }
   // ---- the ILUT started above
   ilut_job.t.join();
-  if (o.coarse_mode == 2) {
+  if (o.coarse_mode == 3) {
+    const int nc = S.nc;
+    S.cnp = (nc + 63) / 64 * 64;
+    const size_t nn = (size_t)S.cnp * S.cnp;
+    S.cinv.alloc(nn);
+    S.cinv32.alloc(nn);
+    S.cbad.alloc(1);
+    HIPCK(hipMemsetAsync(S.cbad.p, 0, sizeof(int), s));
+    launch_dense_inverse(nc, S.cnp, S.Ac.rp.p, S.Ac.ci.p, S.Ac.v.p, S.cinv.p, S.cbad.p, s);
+    launch_cast_f32(S.cinv.p, S.cinv32.p, nn, s);
+    int bad = 0;
+    HIPCK(hipMemcpyAsync(&bad, S.cbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (bad) fail(GMG_ERR_ZERO_PIVOT, "dense coarse inverse: zero or non-finite pivot");
+    phase("coarse dense inverse (after the fine level)");
+  } else if (o.coarse_mode == 2) {
     const gmg_status st = ilut_st;
     if (st == GMG_ERR_ZERO_PIVOT) fail(st, "SPAI: a column's least-squares problem is rank deficient");
     if (st != GMG_OK) fail(st, "SPAI: non-finite entry");
@@ -1907,7 +1934,7 @@ gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut)
     REQUIRE_HANDLE(h);
     if (!est_coarse || !est_ilut) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     gmg::Solver& S = h->S;
-    if (S.opt.coarse_mode == 2) gmg::fail(GMG_ERR_INVALID_ARG, "no ILUT factors under coarse_mode 2");
+    if (S.opt.coarse_mode >= 2) gmg::fail(GMG_ERR_INVALID_ARG, "no ILUT factors under coarse_mode 2 or 3");
     const int nc = S.nc;
     auto ratio = [](const std::vector<double>& d) {
       double mx = 0.0, mn = std::numeric_limits<double>::infinity();
@@ -2003,6 +2030,20 @@ gmg_status gmg_get_spai(gmg_handle h, int32_t* rowptr, int32_t* col, double* val
     gmg::d2d(rowptr, S.dMc.rp.p, S.nc + 1, S.s);
     gmg::d2d(col, S.dMc.ci.p, S.dMc.nnz, S.s);
     gmg::d2d(val, S.dMc.v.p, S.dMc.nnz, S.s);
+    HIPCK(hipStreamSynchronize(S.s));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_coarse_inverse(gmg_handle h, double* inv) {
+  return guarded([&]() -> gmg_status {
+    REQUIRE_HANDLE(h);
+    gmg::Solver& S = h->S;
+    if (S.opt.coarse_mode != 3) gmg::fail(GMG_ERR_INVALID_ARG, "no dense coarse inverse (coarse_mode != 3)");
+    if (!inv) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
+    if (S.nc > 0)
+      HIPCK(hipMemcpy2DAsync(inv, sizeof(double) * S.nc, S.cinv.p, sizeof(double) * S.cnp, sizeof(double) * S.nc,
+                             S.nc, hipMemcpyDeviceToDevice, S.s));
     HIPCK(hipStreamSynchronize(S.s));
     return GMG_OK;
   });

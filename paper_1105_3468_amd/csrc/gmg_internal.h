@@ -159,6 +159,7 @@ void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& u
 // s x s column-major at boff[node] (zeros where the factor has none); dinv:
 // reciprocal diagonal per row (factors with a stored diagonal).
 constexpr int kTreeMaxRows = 2048;  // rows of one node (its values are staged in LDS)
+constexpr int kDenseMaxCoarse = 8192;  // largest A_c of the dense exact coarse solve (512 MiB in FP64)
 // A triangular factor laid out for the tree solve: per task 8 ints (helper
 // or node slice), outside entries as CSR over rows (erp, ecol, eval), and per
 // node the inverse of its diagonal block, dense column-major at boff[node]
@@ -206,6 +207,13 @@ void launch_fill_f32_bits(float* p, uint32_t bits, size_t n, hipStream_t s);
 void launch_validate(int n, const int* rp, const int* ci, const double* v, int* flags,
                      hipStream_t s);
 void launch_cast_f32(const double* x, float* y, size_t n, hipStream_t s);
+// dense exact coarse solve (k_dense.hip): A (np x np, row-major, np a multiple
+// of 64 >= nc) <- blockdiag(A_c, I)^{-1}; *bad set to 1 on a zero or
+// non-finite pivot
+void launch_dense_inverse(int nc, int np, const int* rp, const int* ci, const double* v, double* A, int* bad,
+                          hipStream_t s);
+template <class T>
+void launch_dense_gemv(int n, int np, const T* M, const T* r, T* e, hipStream_t s);
 // CSR SpMV y = A x; T = value/vector type
 template <class T>
 void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y,

@@ -21,7 +21,7 @@ ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOT_SETUP, ERR_STALLED = -5, -6, -7, -8
 EXPORTED = [
     "gmg_default_options", "gmg_setup", "gmg_solve", "gmg_solve_adjoint", "gmg_apply_precond",
     "gmg_spmv", "gmg_get_info", "gmg_cond_estimate", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
-    "gmg_get_fine_perm", "gmg_get_spai",
+    "gmg_get_fine_perm", "gmg_get_spai", "gmg_get_coarse_inverse",
     "gmg_get_ilut", "gmg_set_stream", "gmg_profile_enable", "gmg_profile_read",
     "gmg_profile_name", "gmg_destroy", "gmg_last_error", "gmg_fv_nnz", "gmg_fv_assemble",
     "gmg_fv_kappa_grad", "gmg_pattern_grad",
@@ -82,6 +82,7 @@ def load():
         "gmg_get_ilu0": (I, [P, P]),
         "gmg_get_fine_perm": (I, [P, P]),
         "gmg_get_spai": (I, [P, P, P, P]),
+        "gmg_get_coarse_inverse": (I, [P, P]),
         "gmg_get_ilut": (I, [P, P, P, P, P, P, P]),
         "gmg_set_stream": (I, [P, P]),
         "gmg_profile_enable": (I, [P, I]),
@@ -224,6 +225,15 @@ class Solver:
         v = t.empty(max(nz, 1), dtype=t.float64, device="cuda")
         _check(load().gmg_get_spai(self._h, _ptr(rp), _ptr(ci), _ptr(v)), "spai")
         return rp, ci[:nz], v[:nz]
+
+    def coarse_inverse(self):
+        """Dense A_c^{-1} (N_c x N_c, FP64) of the exact coarse solve
+        (coarse_mode = 3)."""
+        nc = self.info()["n_coarse"]
+        t = self._torch
+        m = t.empty((nc, nc), dtype=t.float64, device="cuda")
+        _check(load().gmg_get_coarse_inverse(self._h, _ptr(m)), "coarse_inverse")
+        return m
 
     def fine_perm(self):
         """The smoother's numbering: position k holds fine unknown perm[k]."""

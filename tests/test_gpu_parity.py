@@ -492,6 +492,60 @@ def test_spai_coarse_solve(name):
         S.cond_estimate()
 
 
+
+DENSE_CASES = dict(ND_CASES, fv2d_8=lambda: W.scaled("fv2d", 8))
+
+
+@pytest.mark.parametrize("name", list(DENSE_CASES))
+def test_dense_coarse_inverse(name):
+    """coarse_mode 3, the EGMG variant's exact coarse solve by a dense inverse
+    (N_c from 11, one padded tile, to 1223, twenty tiles with a ragged tail):
+    A_c^{-1} against numpy's pivoted inverse of the oracle's A_c (relative
+    Frobenius error 1e-11: the same blocked no-pivot elimination run in
+    numpy stays within 1.1e-13 of it on these cases, condition numbers up to
+    2.6e8) and A_c X = I within 1e-9; one FP64 application against the
+    oracle's exact (tau = 0) two-grid operator within 1e-10, the FP32 form
+    within the FP32 bar; an unrestarted solve within one step of the oracle's
+    exact-coarse solve."""
+    _say(f"[case] coarse_mode=3 {name}")
+    p = DENSE_CASES[name]()
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    O = oracle.Oracle(p.rowptr, p.col, p.val, ilut_tau=0.0)
+    S = Solver(p.rowptr, p.col, p.val, coarse_mode=3)
+    assert S.info()["n_coarse"] == O.nc and S.info()["nnz_lc"] == 0
+    crp, cci, cv = O.coarse()
+    Ac = sp.csr_matrix((cv, cci, crp), shape=(O.nc, O.nc)).toarray()
+    X = S.coarse_inverse().cpu().numpy()
+    R = np.linalg.inv(Ac)
+    rel = np.linalg.norm(X - R) / np.linalg.norm(R)
+    assert rel <= 1e-11, (name, rel)
+    assert np.abs(Ac @ X - np.eye(O.nc)).max() <= 1e-9
+    z = np.random.default_rng(9).uniform(-1, 1, p.n_rows)
+    q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
+    ref = O.apply(z, 0)
+    assert np.linalg.norm(q - ref) <= 1e-10 * np.linalg.norm(ref), (name, np.linalg.norm(q - ref) / np.linalg.norm(ref))
+    q32 = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
+    ref32 = O.apply(z, 1)
+    e32 = np.linalg.norm(q32 - ref) / np.linalg.norm(ref)
+    e64 = np.linalg.norm(ref32 - ref) / np.linalg.norm(ref)
+    assert e32 <= max(1e-4, 10 * e64), (e32, e64)
+    b = p.b[:, 0]
+    x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, restart=600, maxit=600)
+    assert res.status == G.OK, res.info
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+    _, info = O.solve(b, tol=1e-8, restart=600, maxit=600)
+    assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
+    with pytest.raises(GmgError):
+        S.cond_estimate()
+
+
+def test_dense_coarse_inverse_size_limit():
+    """coarse_mode 3 refuses N_c above 8192 at setup (fv2d 256^2: N_c ~ 16k)."""
+    _say("[case] coarse_mode=3 size limit")
+    p = W.scaled("fv2d", 256)
+    with pytest.raises(GmgError):
+        Solver(p.rowptr, p.col, p.val, coarse_mode=3)
+
 def test_tiny_and_degenerate():
     _say("[case] tiny")
     # 1x1, diagonal matrices, a 2x2 that needs no pivoting
