@@ -8,7 +8,7 @@ FP32-preconditioned form (reported beside it).  Inputs are resident in HBM
 before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--jacobi K] [--fine-nd] [--fine-color] [--spai]
+                       [--no-cpu-baseline] [--no-fp32] [--egmg] [--dense-coarse] [--jacobi K] [--fine-nd] [--fine-color] [--spai]
        python bench.py --copy-calibration   (a plain 1 GiB device copy, run
                        under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
 
@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--egmg", action="store_true",
                     help="also time the exact coarse solve (ILUT tau = 0: complete LU of A_c), reported beside")
+    ap.add_argument("--dense-coarse", action="store_true",
+                    help="also time the dense exact coarse solve (coarse_mode 3, N_c <= 8192) against the sparse "
+                         "exact one on fv2d_rot 176^2 (the 1024^2 family at N_c = 4989), reported beside")
     ap.add_argument("--jacobi", type=int, default=0,
                     help="also time the coarse solve by K Jacobi sweeps per ILUT factor, reported beside")
     ap.add_argument("--spai", action="store_true",
@@ -326,6 +329,41 @@ def main():
             iters=re.info["iters"], nnz_ilut=int(Se.setup_info["nnz_lc"] + Se.setup_info["nnz_uc"]),
             relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xeh) / np.linalg.norm(p.b[:, 0])))
         print(f"[bench] exact coarse solve (EGMG) step: {te:.3f}s its={re.info['iters']}", file=sys.stderr, flush=True)
+
+    if args.dense_coarse:
+        # the exact coarse solve by a dense inverse needs N_c <= 8192, so it
+        # runs on a smaller member of the headline family (rotating velocity,
+        # kappa on 8x8 blocks, 176^2 cells), beside the sparse exact solve
+        pd = W.scaled("fv2d_rot", 176)
+        bd = torch.as_tensor(pd.b[:, 0], device="cuda")
+        Ad = sp.csr_matrix((pd.val, pd.col, pd.rowptr), shape=(pd.n_rows, pd.n_rows))
+        dres = dict(workload="fv2d_rot_176: 176x176 cells, kappa log-uniform in [1e-3,1e3] on 8x8 blocks, "
+                             "rotating velocity x10, seed 0")
+        for key, kw in (("dense", dict(coarse_mode=3)), ("sparse_exact", dict(ilut_tau=0.0))):
+            def dstep(profile=False):
+                Sd = Solver(pd.rowptr, pd.col, pd.val, cf=SOLVE_OPTS["cf"], **kw)
+                if profile:
+                    Sd.profile(True, classes=["sweep_coarse"])
+                xd, rd = Sd.solve(bd, tol=TOL, restart=SOLVE_OPTS["restart"], maxit=SOLVE_OPTS["maxit"])
+                return Sd, xd, rd
+            dstep()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Sd, xd, rd = dstep()
+            torch.cuda.synchronize()
+            td = time.perf_counter() - t0
+            Sp, _, _ = dstep(True)
+            pc = Sp.profile_read()["sweep_coarse"]
+            dres[key] = dict(time_s=round(td, 6), setup_ms=round(Sd.setup_info["setup_ms"], 2),
+                             solve_ms=round(rd.info["solve_ms"], 2), iters=rd.info["iters"],
+                             n_coarse=Sd.setup_info["n_coarse"],
+                             coarse_solve_avg_us=round(pc["ms"] / max(pc["launches"], 1) * 1e3, 3),
+                             coarse_solve_gbs=round(pc["bytes"] / (pc["ms"] * 1e-3) / 1e9, 2) if pc["ms"] > 0 else None,
+                             relres_host_check=float(np.linalg.norm(pd.b[:, 0] - Ad @ xd.cpu().numpy())
+                                                     / np.linalg.norm(pd.b[:, 0])))
+            print(f"[bench] {key} exact coarse solve on fv2d_rot_176: {td:.4f}s its={rd.info['iters']}",
+                  file=sys.stderr, flush=True)
+        out["dense_coarse"] = dres
 
     if args.jacobi > 0:
         # the parallel inexact coarse solve: K Jacobi sweeps on each ILUT factor

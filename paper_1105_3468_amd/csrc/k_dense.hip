@@ -29,30 +29,50 @@ __global__ void k_dense_scatter(int nc, int np, const int* __restrict__ rp, cons
   for (int q = rp[i]; q < rp[i + 1]; ++q) row[ci[q]] += v[q];
 }
 
-// in-place Gauss-Jordan inverse of the 64x64 diagonal block K (one workgroup)
+// in-place Gauss-Jordan inverse of the 64x64 diagonal block K (one workgroup):
+// thread t holds column t % 64, rows 16 (t / 64) .. +15 in registers; each
+// elimination step publishes the pivot column and the scaled pivot row
+// through LDS (double-buffered, two barriers a step)
 __global__ __launch_bounds__(256) void k_gj_diag(int np, int K, double* __restrict__ A, int* __restrict__ bad) {
-  __shared__ double a[DB][DB + 1];
-  const int t = threadIdx.x;
+  __shared__ double colk[2][DB], rowk[2][DB];
+  const int t = threadIdx.x, j = t & 63, g = t >> 6;
   double* blk = A + (size_t)K * DB * np + (size_t)K * DB;
-  for (int e = t; e < DB * DB; e += 256) a[e / DB][e % DB] = blk[(size_t)(e / DB) * np + e % DB];
-  __syncthreads();
+  double a[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) a[m] = blk[(size_t)(g * 16 + m) * np + j];
   for (int k = 0; k < DB; ++k) {
-    const double p = a[k][k];
-    if (t == 0 && !(fabs(p) > 0.0 && fabs(p) < INFINITY)) *bad = 1;
-    const double piv = 1.0 / p;
-    __syncthreads();
-    if (t < DB && t != k) a[k][t] *= piv;
-    __syncthreads();
-    for (int e = t; e < DB * DB; e += 256) {
-      const int i = e / DB, j = e % DB;
-      if (i != k && j != k) a[i][j] -= a[i][k] * a[k][j];
+    const int buf = k & 1;
+    if (j == k) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) colk[buf][g * 16 + m] = a[m];
     }
     __syncthreads();
-    if (t < DB && t != k) a[t][k] = -a[t][k] * piv;
-    if (t == 0) a[k][k] = piv;
+    const double p = colk[buf][k];
+    if (t == 0 && !(fabs(p) > 0.0 && fabs(p) < INFINITY)) *bad = 1;
+    const double piv = 1.0 / p;
+    if (g == (k >> 4)) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m)
+        if (m == (k & 15)) {
+          if (j != k) a[m] *= piv;
+          rowk[buf][j] = a[m];
+        }
+    }
     __syncthreads();
+    const double rkj = rowk[buf][j];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int i = g * 16 + m;
+      if (i != k) {
+        if (j != k) a[m] -= colk[buf][i] * rkj;
+        else a[m] = -a[m] * piv;
+      } else if (j == k) {
+        a[m] = piv;
+      }
+    }
   }
-  for (int e = t; e < DB * DB; e += 256) blk[(size_t)(e / DB) * np + e % DB] = a[e / DB][e % DB];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) blk[(size_t)(g * 16 + m) * np + j] = a[m];
 }
 
 // MODE 0: A_Kj <- D A_Kj (row panel, blockIdx.x = j block)
@@ -90,11 +110,14 @@ __global__ __launch_bounds__(256) void k_gj_panel(int np, int K, double* __restr
   for (int r = 0; r < 16; ++r) tile[(size_t)(r0 + r) * np + c] = MODE == 0 ? acc[r] : -acc[r];
 }
 
-// A_ij <- A_ij - A_iK A_Kj for i, j != K; grid (j block, i block)
+// A_ij <- A_ij - A_iK A_Kj for i, j != K; grid (j block, i block).  Thread t
+// accumulates a 4x4 block: rows t/16 + 16 r (r < 4), columns 4 (t % 16) .. +3;
+// the A_iK tile's rows are padded to 65 so the four rows a wave reads at one
+// k fall in distinct banks
 __global__ __launch_bounds__(256) void k_gj_update(int np, int K, double* __restrict__ A) {
   const int jb = blockIdx.x, ib = blockIdx.y;
   if (ib == K || jb == K) return;
-  __shared__ double p[DB][DB];
+  __shared__ double p[DB][DB + 1];
   __shared__ double q[DB][DB];
   const int t = threadIdx.x;
   const double* pk = A + (size_t)ib * DB * np + (size_t)K * DB;
@@ -104,18 +127,28 @@ __global__ __launch_bounds__(256) void k_gj_update(int np, int K, double* __rest
     q[e / DB][e % DB] = qk[(size_t)(e / DB) * np + e % DB];
   }
   __syncthreads();
-  const int c = t & 63, r0 = (t >> 6) * 16;
-  double acc[16];
+  const int cx = (t & 15) * 4, ry = t >> 4;
+  double acc[4][4];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
   for (int k = 0; k < DB; ++k) {
-    const double qk_ = q[k][c];
+    double pr[4], qc[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] += p[r0 + r][k] * qk_;
+    for (int r = 0; r < 4; ++r) pr[r] = p[ry + 16 * r][k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) qc[c] = q[k][cx + c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] += pr[r] * qc[c];
   }
   double* out = A + (size_t)ib * DB * np + (size_t)jb * DB;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) out[(size_t)(r0 + r) * np + c] -= acc[r];
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[(size_t)(ry + 16 * r) * np + cx + c] -= acc[r][c];
 }
 
 void launch_dense_inverse(int nc, int np, const int* rp, const int* ci, const double* v, double* A, int* bad,
