@@ -40,6 +40,9 @@ __global__ __launch_bounds__(256) void k_gj_diag(int np, int K, double* __restri
   double a[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) a[m] = blk[(size_t)(g * 16 + m) * np + j];
+  // fully unrolled over k, so every register index is static and the
+  // per-element cases are selects rather than branches
+#pragma unroll
   for (int k = 0; k < DB; ++k) {
     const int buf = k & 1;
     if (j == k) {
@@ -51,24 +54,19 @@ __global__ __launch_bounds__(256) void k_gj_diag(int np, int K, double* __restri
     if (t == 0 && !(fabs(p) > 0.0 && fabs(p) < INFINITY)) *bad = 1;
     const double piv = 1.0 / p;
     if (g == (k >> 4)) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m)
-        if (m == (k & 15)) {
-          if (j != k) a[m] *= piv;
-          rowk[buf][j] = a[m];
-        }
+      const double v = j != k ? a[k & 15] * piv : a[k & 15];
+      a[k & 15] = v;
+      rowk[buf][j] = v;
     }
     __syncthreads();
     const double rkj = rowk[buf][j];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int i = g * 16 + m;
-      if (i != k) {
-        if (j != k) a[m] -= colk[buf][i] * rkj;
-        else a[m] = -a[m] * piv;
-      } else if (j == k) {
-        a[m] = piv;
-      }
+      const double upd = a[m] - colk[buf][i] * rkj;
+      const double colv = -a[m] * piv;
+      const double rowv = j == k ? piv : a[m];
+      a[m] = i != k ? (j != k ? upd : colv) : rowv;
     }
   }
 #pragma unroll
