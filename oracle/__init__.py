@@ -46,34 +46,41 @@ class _Opts(C.Structure):
 _lib = None
 
 
+def _load(path: str):
+    """Open an oracle library built from gmg_oracle.c and declare its entry
+    points (also used by the tests that build deliberately broken copies of
+    the oracle to show that its pins catch them)."""
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.or_setup.argtypes = [C.c_int, P, P, P, C.POINTER(_Opts), P, C.POINTER(P)]
+    lib.or_setup.restype = C.c_int
+    lib.or_destroy.argtypes = [P]
+    lib.or_sizes.argtypes = [P, P]
+    lib.or_get_agg.argtypes = [P, P]
+    lib.or_get_members.argtypes = [P, P, P]
+    lib.or_get_graph.argtypes = [P, P, P, P]
+    lib.or_get_coarse.argtypes = [P, P, P, P]
+    lib.or_get_ilut.argtypes = [P, P, P, P, P, P, P]
+    lib.or_get_ilu0.argtypes = [P, P]
+    lib.or_get_fine.argtypes = [P, P, P, P, P]
+    lib.or_get_spai.argtypes = [P, P, P, P]
+    lib.or_precond_apply.argtypes = [P, C.c_int, P, P]
+    lib.or_precond_apply_twosolve.argtypes = [P, P, P]
+    lib.or_precond_apply_adjoint.argtypes = [P, P, P]
+    lib.or_fgmres.argtypes = [P, C.c_int, C.c_int, P, P, C.c_double, C.c_int, C.c_int,
+                              C.c_int, P, P, P, C.c_int]
+    lib.or_fgmres.restype = C.c_int
+    lib.or_match_once.argtypes = [C.c_int, P, P, P, C.c_int, C.c_uint64, P, P]
+    lib.or_match_once.restype = C.c_int
+    lib.or_spmv.argtypes = [P, C.c_int, P, P]
+    lib.or_default_opts.argtypes = [C.POINTER(_Opts)]
+    return lib
+
+
 def _L():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
-        P = C.c_void_p
-        _lib.or_setup.argtypes = [C.c_int, P, P, P, C.POINTER(_Opts), P, C.POINTER(P)]
-        _lib.or_setup.restype = C.c_int
-        _lib.or_destroy.argtypes = [P]
-        _lib.or_sizes.argtypes = [P, P]
-        for f in ("or_get_agg",):
-            getattr(_lib, f).argtypes = [P, P]
-        _lib.or_get_members.argtypes = [P, P, P]
-        _lib.or_get_graph.argtypes = [P, P, P, P]
-        _lib.or_get_coarse.argtypes = [P, P, P, P]
-        _lib.or_get_ilut.argtypes = [P, P, P, P, P, P, P]
-        _lib.or_get_ilu0.argtypes = [P, P]
-        _lib.or_get_fine.argtypes = [P, P, P, P, P]
-        _lib.or_get_spai.argtypes = [P, P, P, P]
-        _lib.or_precond_apply.argtypes = [P, C.c_int, P, P]
-        _lib.or_precond_apply_twosolve.argtypes = [P, P, P]
-        _lib.or_precond_apply_adjoint.argtypes = [P, P, P]
-        _lib.or_fgmres.argtypes = [P, C.c_int, C.c_int, P, P, C.c_double, C.c_int, C.c_int,
-                                   C.c_int, P, P, P, C.c_int]
-        _lib.or_fgmres.restype = C.c_int
-        _lib.or_match_once.argtypes = [C.c_int, P, P, P, C.c_int, C.c_uint64, P, P]
-        _lib.or_match_once.restype = C.c_int
-        _lib.or_spmv.argtypes = [P, C.c_int, P, P]
-        _lib.or_default_opts.argtypes = [C.POINTER(_Opts)]
+        _lib = _load(build())
     return _lib
 
 
@@ -107,6 +114,7 @@ class Oracle:
 
     def __init__(self, rowptr, col, val, agg=None, **opts):
         lib = _L()
+        self._lib = lib
         o = _Opts()
         lib.or_default_opts(C.byref(o))
         for k, v in opts.items():
@@ -129,34 +137,34 @@ class Oracle:
          self.rounds, self.nnz_graph) = (int(t) for t in s)
 
     def __del__(self):
-        if getattr(self, "_h", None) is not None and _lib is not None:
-            _lib.or_destroy(self._h)
+        if getattr(self, "_h", None) is not None and getattr(self, "_lib", None) is not None:
+            self._lib.or_destroy(self._h)
             self._h = None
 
     # --- setup products ----------------------------------------------------
     def aggregates(self):
         a = np.empty(self.n, dtype=np.int32)
-        _L().or_get_agg(self._h, _p(a))
+        self._lib.or_get_agg(self._h, _p(a))
         return a
 
     def members(self):
         aptr = np.empty(self.nc + 1, dtype=np.int32)
         amem = np.empty(self.n, dtype=np.int32)
-        _L().or_get_members(self._h, _p(aptr), _p(amem))
+        self._lib.or_get_members(self._h, _p(aptr), _p(amem))
         return aptr, amem
 
     def graph(self):
         rp = np.empty(self.n + 1, dtype=np.int32)
         ci = np.empty(self.nnz_graph, dtype=np.int32)
         w = np.empty(self.nnz_graph, dtype=np.float64)
-        _L().or_get_graph(self._h, _p(rp), _p(ci), _p(w))
+        self._lib.or_get_graph(self._h, _p(rp), _p(ci), _p(w))
         return rp, ci, w
 
     def coarse(self):
         rp = np.empty(self.nc + 1, dtype=np.int32)
         ci = np.empty(self.nnz_c, dtype=np.int32)
         v = np.empty(self.nnz_c, dtype=np.float64)
-        _L().or_get_coarse(self._h, _p(rp), _p(ci), _p(v))
+        self._lib.or_get_coarse(self._h, _p(rp), _p(ci), _p(v))
         return rp, ci, v
 
     def spai(self):
@@ -167,7 +175,7 @@ class Oracle:
         rp = np.empty(self.nc + 1, dtype=np.int32)
         ci = np.empty(self.nnz_c, dtype=np.int32)
         v = np.empty(self.nnz_c, dtype=np.float64)
-        _L().or_get_spai(self._h, _p(rp), _p(ci), _p(v))
+        self._lib.or_get_spai(self._h, _p(rp), _p(ci), _p(v))
         return rp, ci, v
 
     def fine(self):
@@ -178,14 +186,14 @@ class Oracle:
         rp = np.empty(self.n + 1, dtype=np.int32)
         ci = np.empty(self.nnz, dtype=np.int32)
         v = np.empty(self.nnz, dtype=np.float64)
-        _L().or_get_fine(self._h, _p(perm), _p(rp), _p(ci), _p(v))
+        self._lib.or_get_fine(self._h, _p(perm), _p(rp), _p(ci), _p(v))
         return perm, (rp, ci, v)
 
     def ilu0(self):
         """ILU(0) values on the pattern of the smoother's matrix F (A itself
         unless fine_order = 1; strict lower part = L0, rest = U0)."""
         v = np.empty(self.nnz, dtype=np.float64)
-        _L().or_get_ilu0(self._h, _p(v))
+        self._lib.or_get_ilu0(self._h, _p(v))
         return v
 
     def ilut(self):
@@ -196,32 +204,32 @@ class Oracle:
         urp = np.empty(self.nc + 1, dtype=np.int32)
         uci = np.empty(self.nnz_uc, dtype=np.int32)
         uv = np.empty(self.nnz_uc, dtype=np.float64)
-        _L().or_get_ilut(self._h, _p(lrp), _p(lci), _p(lv), _p(urp), _p(uci), _p(uv))
+        self._lib.or_get_ilut(self._h, _p(lrp), _p(lci), _p(lv), _p(urp), _p(uci), _p(uv))
         return (lrp, lci, lv), (urp, uci, uv)
 
     # --- solve-phase operations -------------------------------------------
     def apply(self, z, precision: int = 0):
         z = np.ascontiguousarray(z, dtype=np.float64)
         q = np.empty(self.n)
-        _L().or_precond_apply(self._h, precision, _p(z), _p(q))
+        self._lib.or_precond_apply(self._h, precision, _p(z), _p(q))
         return q
 
     def apply_twosolve(self, z):
         z = np.ascontiguousarray(z, dtype=np.float64)
         q = np.empty(self.n)
-        _L().or_precond_apply_twosolve(self._h, _p(z), _p(q))
+        self._lib.or_precond_apply_twosolve(self._h, _p(z), _p(q))
         return q
 
     def apply_adjoint(self, z):
         z = np.ascontiguousarray(z, dtype=np.float64)
         q = np.empty(self.n)
-        _L().or_precond_apply_adjoint(self._h, _p(z), _p(q))
+        self._lib.or_precond_apply_adjoint(self._h, _p(z), _p(q))
         return q
 
     def spmv(self, x, transposed=False):
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.empty(self.n)
-        _L().or_spmv(self._h, int(transposed), _p(x), _p(y))
+        self._lib.or_spmv(self._h, int(transposed), _p(x), _p(y))
         return y
 
     def solve(self, b, tol=1e-8, maxit=600, restart=30, x0=None, adjoint=False, precision=0,
@@ -231,7 +239,7 @@ class Oracle:
         info = np.zeros(4)
         zd = np.zeros((restart, self.n)) if zdump else None
         hist = np.zeros(maxit) if history else None
-        st = _L().or_fgmres(self._h, int(adjoint), int(precision), _p(b), _p(x), float(tol),
+        st = self._lib.or_fgmres(self._h, int(adjoint), int(precision), _p(b), _p(x), float(tol),
                             int(maxit), int(restart), int(x0 is not None), _p(info),
                             None if zd is None else _p(zd), None if hist is None else _p(hist),
                             0 if hist is None else len(hist))

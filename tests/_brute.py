@@ -163,9 +163,12 @@ def random_mmatrix(n, rng, density=0.1, sym=False, integer=False):
     return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64), A
 
 
-def nd_order_ref(n, adj):
+def nd_order_ref(n, adj, nodes=None):
     """Nested-dissection numbering, recursive, from the definition: returns
-    the list of vertices in their new order.  adj: list of neighbour sets."""
+    the list of vertices in their new order.  adj: list of neighbour sets.
+    nodes (a list) receives (first position, |part 1|, |part 2|, |separator|)
+    of every split: a bisection (separator > 0) or a split into the component
+    of the smallest vertex and the rest (separator 0)."""
     import sys
     sys.setrecursionlimit(max(10000, 4 * n))
 
@@ -179,7 +182,7 @@ def nd_order_ref(n, adj):
                     q.append(v)
         return d
 
-    def nd(S):
+    def nd(S, start):
         S = sorted(S)
         if len(S) <= 64:
             return S
@@ -188,7 +191,9 @@ def nd_order_ref(n, adj):
         if len(d) < len(S):
             comp = sorted(d)
             rest = [v for v in S if v not in d]
-            return nd(comp) + nd(rest)
+            if nodes is not None:
+                nodes.append((start, len(comp), len(rest), 0))
+            return nd(comp, start) + nd(rest, start + len(comp))
         far = max(d.values())
         r = min(v for v in S if d[v] == far)
         d = bfs(Sset, r)
@@ -207,9 +212,11 @@ def nd_order_ref(n, adj):
         A = [v for v in S if d[v] < m]
         Bp = [v for v in S if d[v] > m]
         sep = [v for v in S if d[v] == m]
-        return nd(A) + nd(Bp) + sep
+        if nodes is not None:
+            nodes.append((start, len(A), len(Bp), len(sep)))
+        return nd(A, start) + nd(Bp, start + len(A)) + sep
 
-    return nd(list(range(n)))
+    return nd(list(range(n)), 0)
 
 
 def coarse_pattern_adj(rowptr, col, agg, nc):

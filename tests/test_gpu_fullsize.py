@@ -5,10 +5,11 @@ The oracle finishes the whole setup at these sizes in seconds, so the setup
 outputs are compared in full: aggregates, A_c, ILU(0) and ILUT bit-exact.  A
 full FGMRES run of the oracle on 1024^2 would take about a minute, so the solve
 is checked by sampled outputs and properties: one preconditioner application
-(FP64 within 1e-12 relative, as in the small cases), the iterate after five
+(FP64 within 1e-12 of the magnitudes that flow into each entry, entry by
+entry, as in the small cases), the iterate after five
 FGMRES steps (within 1e-10 in ||A dx|| / ||b||), and the converged GPU solve's
 true residual.  rgg_500k converges in a few steps, so its converged solution is
-compared with the oracle's as well.  fv3d_128 runs the V-cycle in FP32 inside
+compared with the oracle's as well, on each of its four seeds.  fv3d_128 runs the V-cycle in FP32 inside
 FP64 FGMRES; its error against the FP64 oracle is bounded by FP32 rounding.
 """
 from __future__ import annotations
@@ -31,11 +32,19 @@ import bench  # noqa: E402  (the timed options)
 import oracle  # noqa: E402
 from paper_1105_3468_amd import Solver  # noqa: E402
 from paper_1105_3468_amd import gmg as G  # noqa: E402
+from tests import _errbound as EB  # noqa: E402
 
 
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def _elementwise(O, A, z, q, ref, tol, what):
+    """|q - ref| <= tol * scale entry by entry (tests/_errbound.py)."""
+    scale = EB.apply_scale(O, A, z)
+    r = EB.check_elementwise(q, ref, scale, tol, what)
+    _say(f"  {what}: max |diff|/scale = {r:.2e} (bar {tol:g})")
 
 
 # workload -> (setup options, FGMRES restart, tolerance, maxit)
@@ -46,14 +55,17 @@ SETUPS = {
     # the 3D problem needs a tighter coarse factor to converge without restart
     "fv3d_128": (dict(cf=4.0, ilut_tau=1e-5), 600, 1e-8, 600),
 }
+# the random geometric graph is specified on four seeds
+CASES = ["fv2d_1024", "rgg_500k:0", "rgg_500k:1", "rgg_500k:2", "rgg_500k:3", "fv3d_128"]
 
 
-@pytest.fixture(scope="module", params=list(SETUPS))
+@pytest.fixture(scope="module", params=CASES)
 def big(request):
-    name = request.param
+    name, _, seed = request.param.partition(":")
+    seed = int(seed or 0)
     opts, restart, tol, maxit = SETUPS[name]
-    _say(f"[fullsize] {name}: generating")
-    p = W.make(name)
+    _say(f"[fullsize] {name} seed {seed}: generating")
+    p = W.make(name, seed=seed)
     _say(f"[fullsize] {name}: oracle setup")
     O = oracle.Oracle(p.rowptr, p.col, p.val, **opts)
     _say(f"[fullsize] {name}: GPU setup")
@@ -85,7 +97,7 @@ def test_preconditioner_apply(big):
     z = np.random.default_rng(2).uniform(-1, 1, p.n_rows)
     q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
     ref = O.apply(z, 0)
-    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref), name
+    _elementwise(O, A, z, q, ref, 1e-12, f"{name} fp64")
     # FP32 cycle: against the oracle's FP32 cycle to a few FP32 ulps (amplified
     # by the sweeps), and its error against the FP64 oracle within FP32 accuracy
     q32 = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
@@ -95,6 +107,7 @@ def test_preconditioner_apply(big):
     _say(f"[fullsize] {name}: FP32 cycle error vs FP64 oracle {e_gpu:.2e} (oracle's own FP32 cycle {e_or:.2e})")
     assert np.linalg.norm(q32 - ref32) / np.linalg.norm(ref32) <= max(1e-4, 10 * e_or)
     assert e_gpu <= max(1e-4, 10 * e_or)
+    _elementwise(O, A, z, q32, ref32, 2e-5, f"{name} fp32")
 
 
 def test_five_step_iterates(big):
@@ -161,4 +174,10 @@ def test_variants_full_size(variant):
     z = np.random.default_rng(12).uniform(-1, 1, p.n_rows)
     q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
     ref = O.apply(z, 0)
-    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    coarse = None
+    if kw.get("coarse_mode") == 2:
+        coarse = ("spai", sp.csr_matrix((ov, oci, orp), shape=(O.nc, O.nc)))
+    scale = EB.apply_scale(O, A, z, coarse=coarse)
+    r = EB.check_elementwise(q, ref, scale, 1e-12, variant)
+    _say(f"  {variant}: max |diff|/scale = {r:.2e} (bar 1e-12)")

@@ -3,9 +3,10 @@
 Bars: integer results (aggregates, patterns) bit-exact; setup values that the
 definition fixes in FP64 without multiplications (A_c sums) bit-exact; ILU(0)
 and ILUT values bit-exact (same operation order, no contraction); one
-preconditioner application in FP64 within 1e-12 relative (FMA contraction and
-reciprocal-multiply in the sweeps: a few ulps per row, amplified by at most the
-factors' growth); iterates at equal step counts within ||A (x - x_oracle)|| /
+preconditioner application in FP64 entry by entry within 1e-12 of the
+magnitudes that flow into that entry (tests/_errbound.py; FMA contraction,
+reciprocal-multiply and another summation order move each entry by a few ulps
+of those magnitudes); iterates at equal step counts within ||A (x - x_oracle)|| /
 ||b|| <= 1e-10; converged solves at true relative residual < tol.
 """
 from __future__ import annotations
@@ -28,11 +29,20 @@ if not torch.cuda.is_available():
 import oracle  # noqa: E402
 from paper_1105_3468_amd import GmgError, Solver  # noqa: E402
 from paper_1105_3468_amd import gmg as G  # noqa: E402
+from tests import _errbound as EB  # noqa: E402
 
 
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def _elementwise(O, A, z, q, ref, tol, what, adjoint=False, coarse=None):
+    """|q - ref| <= tol * scale entry by entry, scale = the magnitudes that
+    flow into each entry of the application (tests/_errbound.py)."""
+    scale = EB.apply_scale(O, A, z, adjoint=adjoint, coarse=coarse)
+    r = EB.check_elementwise(q, ref, scale, tol, what)
+    _say(f"  {what}: max |diff|/scale = {r:.2e} (bar {tol:g})")
 
 
 CASES = {
@@ -109,7 +119,7 @@ def test_preconditioner_fp64(case, adjoint):
         z = rng.uniform(-1, 1, p.n_rows)
         q = S.apply(torch.as_tensor(z, device="cuda"), precision=0, adjoint=adjoint).cpu().numpy()
         ref = O.apply_adjoint(z) if adjoint else O.apply(z, 0)
-        assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref), name
+        _elementwise(O, A, z, q, ref, 1e-12, f"{name} fp64 adjoint={adjoint}", adjoint=adjoint)
 
 
 def test_preconditioner_fp32(case):
@@ -124,6 +134,7 @@ def test_preconditioner_fp32(case):
     e32 = np.linalg.norm(q - ref32) / np.linalg.norm(ref32)
     e64 = np.linalg.norm(ref32 - ref64) / np.linalg.norm(ref64)
     assert e32 <= max(1e-4, 10 * e64), (e32, e64)
+    _elementwise(O, A, z, q, ref32, 2e-5, f"{name} fp32")
 
 
 def test_solve_converges_and_matches_oracle(case):
@@ -279,7 +290,7 @@ def test_exact_coarse_solve(kind):
     t = sp.linalg.spsolve_triangular(U0, sp.linalg.spsolve_triangular(L0, z, lower=True), lower=False)
     ref = t + P @ np.linalg.solve(Ac, P.T @ (z - A @ t))
     q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
-    assert np.linalg.norm(q - ref) <= 1e-10 * np.linalg.norm(ref), (kind, np.linalg.norm(q - ref) / np.linalg.norm(ref))
+    _elementwise(O, A, z, q, ref, 1e-10, f"exact coarse {kind}")
     # and the solve converges to tol
     b = p.b[:, 0]
     x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8)
@@ -299,18 +310,18 @@ def test_jacobi_coarse_solve(kind):
     zt = torch.as_tensor(z, device="cuda")
     S0 = Solver(p.rowptr, p.col, p.val)
     nc = S0.info()["n_coarse"]
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
     for k in (3, nc):
         S = Solver(p.rowptr, p.col, p.val, coarse_mode=1, coarse_sweeps=k)
         O = oracle.Oracle(p.rowptr, p.col, p.val, coarse_mode=1, coarse_sweeps=k)
         q = S.apply(zt, precision=0).cpu().numpy()
         ref = O.apply(z, 0)
-        assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref), (kind, k)
+        _elementwise(O, A, z, q, ref, 1e-12, f"jacobi {kind} k={k}")
     exact = S0.apply(zt, precision=0).cpu().numpy()
-    assert np.linalg.norm(q - exact) <= 1e-10 * np.linalg.norm(exact), kind
+    _elementwise(O, A, z, q, exact, 1e-10, f"jacobi {kind} k=N_c vs exact")
     S = Solver(p.rowptr, p.col, p.val, coarse_mode=1, coarse_sweeps=3)
     b = p.b[:, 0]
     x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, restart=600)
-    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
     assert res.status == G.OK and np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
 
 
@@ -421,12 +432,13 @@ def test_fine_nd_smoother(name, kernel, fo):
         z = rng.uniform(-1, 1, p.n_rows)
         q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
         ref = O.apply(z, 0)
-        assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref), name
+        _elementwise(O, A, z, q, ref, 1e-12, f"fine_order={fo} {name} fp64")
     q32 = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
     ref32 = O.apply(z, 1)
     e32 = np.linalg.norm(q32 - ref32) / np.linalg.norm(ref32)
     e64 = np.linalg.norm(ref32 - ref) / np.linalg.norm(ref)
     assert e32 <= max(1e-4, 10 * e64), (e32, e64)
+    _elementwise(O, A, z, q32, ref32, 2e-5, f"fine_order={fo} {name} fp32")
     b = p.b[:, 0]
     x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8)
     xh = x.cpu().numpy()
@@ -454,7 +466,8 @@ def test_fine_nd_large_separator():
     z = np.random.default_rng(6).uniform(-1, 1, p.n_rows)
     q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
     ref = O.apply(z, 0)
-    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    _elementwise(O, A, z, q, ref, 1e-12, "fine_order=1 fv3d_64")
 
 
 @pytest.mark.parametrize("name", list(ND_CASES))
@@ -475,7 +488,8 @@ def test_spai_coarse_solve(name):
     z = np.random.default_rng(8).uniform(-1, 1, p.n_rows)
     q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
     ref = O.apply(z, 0)
-    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
+    M = sp.csr_matrix((ov, oci, orp), shape=(O.nc, O.nc))
+    _elementwise(O, A, z, q, ref, 1e-12, f"spai {name}", coarse=("spai", M))
     q32 = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
     ref32 = O.apply(z, 1)
     e32 = np.linalg.norm(q32 - ref32) / np.linalg.norm(ref32)
@@ -523,7 +537,7 @@ def test_dense_coarse_inverse(name):
     z = np.random.default_rng(9).uniform(-1, 1, p.n_rows)
     q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
     ref = O.apply(z, 0)
-    assert np.linalg.norm(q - ref) <= 1e-10 * np.linalg.norm(ref), (name, np.linalg.norm(q - ref) / np.linalg.norm(ref))
+    _elementwise(O, A, z, q, ref, 1e-10, f"dense coarse {name}", coarse=("dense", R))
     q32 = S.apply(torch.as_tensor(z, device="cuda"), precision=1).cpu().numpy()
     ref32 = O.apply(z, 1)
     e32 = np.linalg.norm(q32 - ref) / np.linalg.norm(ref)
