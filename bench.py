@@ -9,6 +9,7 @@ before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--no-cpu-baseline] [--no-fp32] [--egmg] [--dense-coarse] [--jacobi K] [--fine-nd] [--fine-color] [--spai]
+                       [--paper-curve]
        python bench.py --copy-calibration   (a plain 1 GiB device copy, run
                        under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE)
 
@@ -163,6 +164,9 @@ def main():
                     help="also time GMG-ND (ILU(0) smoother in nested-dissection order), reported beside")
     ap.add_argument("--fine-color", action="store_true",
                     help="also time the multicolour ILU(0) smoother (colour classes of a greedy colouring)")
+    ap.add_argument("--paper-curve", action="store_true",
+                    help="also run Figure F:curveJUMP's case (DC3D 50^3, GMRES(30), exact and ILUT(1e-4) coarse "
+                         "solves): time, steps and residual history of each")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     global SOLVE_OPTS
@@ -452,6 +456,36 @@ def main():
             kernels={k: dict(launches=v["launches"], total_ms=round(v["ms"], 4)) for k, v in prm.items()
                      if v["launches"]})
         print(f"[bench] multicolour smoother step: {tm:.3f}s its={rm.info['iters']}", file=sys.stderr, flush=True)
+
+    if args.paper_curve:
+        # Figure F:curveJUMP: residual histories of the exact and the inexact
+        # coarse solve on DC3D 50^3 (GMRES(30), cf = 4), one warm and one
+        # timed setup + solve each
+        pc = W.paper_problem("dc1_3d", 50)
+        bc = torch.as_tensor(pc.b[:, 0], device="cuda")
+        Ac = sp.csr_matrix((pc.val, pc.col, pc.rowptr), shape=(pc.n_rows, pc.n_rows))
+        curve = dict(workload="DC3D (DC1 3D of Section 3.1) 50^3 cells, kappa jumps 1e3, zero velocity, "
+                              "GMRES(30), cf 4, tol 1e-8, seed 0")
+        for key, tau in (("exact", 0.0), ("ilut_1e-4", 1e-4)):
+            def cstep():
+                Sc = Solver(pc.rowptr, pc.col, pc.val, cf=4.0, ilut_tau=tau)
+                xc, rc_ = Sc.solve(bc, tol=TOL, restart=30, maxit=600)
+                return Sc, xc, rc_
+            cstep()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Sc, xc, rc_ = cstep()
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - t0
+            curve[key] = dict(time_s=round(tc, 6), setup_ms=round(Sc.setup_info["setup_ms"], 2),
+                              solve_ms=round(rc_.info["solve_ms"], 2), iters=rc_.info["iters"],
+                              nnz_ilut=int(Sc.setup_info["nnz_lc"] + Sc.setup_info["nnz_uc"]),
+                              relres_host_check=float(np.linalg.norm(pc.b[:, 0] - Ac @ xc.cpu().numpy())
+                                                      / np.linalg.norm(pc.b[:, 0])),
+                              history=[float(f"{v:.4e}") for v in Sc.history()])
+            print(f"[bench] paper curve DC3D 50^3 {key}: {tc:.3f}s its={rc_.info['iters']}", file=sys.stderr,
+                  flush=True)
+        out["paper_curve_dc3d_50"] = curve
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

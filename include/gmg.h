@@ -156,6 +156,13 @@ gmg_status gmg_spmv(gmg_handle h, int transposed, const double* x, double* y);
 /* Setup statistics (sizes, passes, levels, setup time) into *info (host). */
 gmg_status gmg_get_info(gmg_handle h, gmg_info* info);
 
+/* Residual history of the last gmg_solve / gmg_solve_adjoint on h: the
+ * FGMRES estimate |g_{j+1}| / ||b|| after every step, right-hand sides one
+ * after another, restarts included (the convergence curves of Section 3,
+ * Figures F:curvePres and F:curveJUMP).  Copies min(cap, count) values into
+ * the host array hist and the number of steps into *count (host). */
+gmg_status gmg_get_history(gmg_handle h, int cap, double* hist, int* count);
+
 /* Cheap condition estimates of Section 3 (the lemma on diagonal entries and
  * the estimate for an incomplete factorization that follows it), computed on
  * demand on the host: *est_coarse = max_i |(A_c)_ii| / min_i |(A_c)_ii|, a

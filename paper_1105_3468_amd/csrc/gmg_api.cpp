@@ -107,6 +107,7 @@ struct Solver {
   hipEvent_t colev[2] = {nullptr, nullptr};  // a column's copy into hpin finished
   gmg_info info{};
   int log_every = 0;           // GMG_LOG=k prints the residual estimate every k steps
+  std::vector<double> hist;    // FGMRES residual estimates of the last solve, per step
   // profiling
   bool prof = false;
   unsigned prof_mask = 0;      // classes that record events (bit c: class c)
@@ -1189,6 +1190,7 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       ++total;
       k = j + 1;
       out.est = std::fabs(g[j + 1]) / bnorm;
+      S.hist.push_back(out.est);
       if (S.log_every > 0 && total % S.log_every == 0) {
         std::fprintf(stderr, "[gmg] step %d  estimated relres %.3e\n", total, out.est);
         std::fflush(stderr);
@@ -1236,6 +1238,7 @@ static gmg_status solve_impl(Solver& S, bool adjoint, const double* b, double* x
     fail(GMG_ERR_INVALID_ARG, "the adjoint solve needs coarse_mode 0, fine_order 0 and FP64");
   auto t0 = std::chrono::steady_clock::now();
   reset_cycle_buffers(S);
+  S.hist.clear();
   gmg_status worst = GMG_OK;
   int iters = 0, restarts = 0, conv = 0;
   double rel = 0.0, est = 0.0;
@@ -1925,6 +1928,16 @@ gmg_status gmg_get_info(gmg_handle h, gmg_info* info) {
     REQUIRE_HANDLE(h);
     if (!info) gmg::fail(GMG_ERR_INVALID_ARG, "null info");
     *info = h->S.info;
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_get_history(gmg_handle h, int cap, double* hist, int* count) {
+  return guarded([&]() -> gmg_status {
+    if (!h || cap < 0 || !count || (cap > 0 && !hist)) gmg::fail(GMG_ERR_INVALID_ARG, "get_history: bad arguments");
+    const auto& v = h->S.hist;
+    *count = (int)v.size();
+    std::copy(v.begin(), v.begin() + std::min<size_t>(v.size(), (size_t)cap), hist);
     return GMG_OK;
   });
 }

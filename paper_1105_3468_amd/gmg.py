@@ -20,7 +20,7 @@ ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOT_SETUP, ERR_STALLED = -5, -6, -7, -8
 
 EXPORTED = [
     "gmg_default_options", "gmg_setup", "gmg_solve", "gmg_solve_adjoint", "gmg_apply_precond",
-    "gmg_spmv", "gmg_get_info", "gmg_cond_estimate", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
+    "gmg_spmv", "gmg_get_info", "gmg_get_history", "gmg_cond_estimate", "gmg_get_aggregates", "gmg_get_coarse", "gmg_get_ilu0",
     "gmg_get_fine_perm", "gmg_get_spai", "gmg_get_coarse_inverse",
     "gmg_get_ilut", "gmg_set_stream", "gmg_profile_enable", "gmg_profile_read",
     "gmg_profile_name", "gmg_destroy", "gmg_last_error", "gmg_fv_nnz", "gmg_fv_assemble",
@@ -76,6 +76,7 @@ def load():
         "gmg_apply_precond": (I, [P, P, P, I, I]),
         "gmg_spmv": (I, [P, I, P, P]),
         "gmg_get_info": (I, [P, C.POINTER(Info)]),
+        "gmg_get_history": (I, [P, I, P, C.POINTER(C.c_int)]),
         "gmg_cond_estimate": (I, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "gmg_get_aggregates": (I, [P, P]),
         "gmg_get_coarse": (I, [P, P, P, P]),
@@ -303,6 +304,16 @@ class Solver:
         y = t.empty_like(x)
         _check(load().gmg_spmv(self._h, int(transposed), _ptr(x), _ptr(y)), "spmv")
         return y
+
+    def history(self):
+        """FGMRES residual estimates after every step of the last solve (numpy)."""
+        import numpy as np
+        cnt = C.c_int(0)
+        lib = load()
+        _check(lib.gmg_get_history(self._h, 0, None, C.byref(cnt)), "history")
+        out = np.zeros(max(cnt.value, 1))
+        _check(lib.gmg_get_history(self._h, cnt.value, out.ctypes.data_as(C.c_void_p), C.byref(cnt)), "history")
+        return out[:cnt.value]
 
     def cond_estimate(self):
         """(max/min |diag A_c|, max/min |diag L~U~|): the cheap condition
