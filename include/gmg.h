@@ -248,6 +248,24 @@ gmg_status gmg_fv_assemble(int n, int dim, const double* kappa, const double* ve
                            const double* vel_y, const double* vel_z, int32_t* rowptr,
                            int32_t* col, double* val, void* stream);
 
+/* gmg_fv_assemble for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that forbid hipMalloc): the same arguments,
+ * layout and results (bitwise identical), with no hipMalloc, hipFree or other
+ * allocation.  Its only scratch, the block sums of the row-pointer scan, is a
+ * static device array of GMG_FV_NOALLOC_SCRATCH_INTS ints (128 KiB) that each
+ * GPU the library runs on holds until the process ends; the row counts are
+ * formed in rowptr itself.  The first call on a device looks the array up
+ * (make it outside graph capture).  Limit: n^dim <= GMG_FV_NOALLOC_MAX_CELLS,
+ * else GMG_ERR_INVALID_ARG before any device work.  Unlike gmg_fv_assemble it
+ * does not synchronise: the results are complete in the order of `stream`.
+ * All calls on one GPU share its array, so calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller. */
+#define GMG_FV_NOALLOC_SCRATCH_INTS 32768
+#define GMG_FV_NOALLOC_MAX_CELLS 33553407LL
+gmg_status gmg_fv_assemble_noalloc(int n, int dim, const double* kappa, const double* vel_x,
+                                   const double* vel_y, const double* vel_z, int32_t* rowptr,
+                                   int32_t* col, double* val, void* stream);
+
 /* dL/dkappa for L(x(kappa)) given the adjoint lambda = A^{-T} dL/dx and the
  * solution x, nrhs columns (device (N, nrhs) row-major each), summed over the
  * right-hand sides: dL/dkappa_c = -sum_r lambda_r^T (dA/dkappa_c) x_r.

@@ -19,6 +19,8 @@ namespace gmg {
 
 static thread_local std::string g_last_error;
 
+void set_error_message(const std::string& msg) { g_last_error = msg; }
+
 [[noreturn]] void fail(gmg_status code, const std::string& msg) { throw Error{code, msg}; }
 
 void hip_check(hipError_t e, const char* what, const char* file, int line) {

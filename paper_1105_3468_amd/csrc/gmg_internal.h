@@ -250,6 +250,10 @@ void launch_perm_gather(int n, const int* perm, const double* z, T* zp, hipStrea
 template <class T>
 void launch_perm_scatter(int n, const int* perm, T* tp, T* t, hipStream_t s);
 void launch_exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, DBuf<int>& tmp);
+void launch_exclusive_scan_int_ws(const int* in, int* out, int n, int* bsum, hipStream_t s);
+constexpr int SCAN_BLOCK = 1024;  // elements per block of the exclusive scan
+// message returned by gmg_last_error() on this thread
+void set_error_message(const std::string& msg);
 
 // Triangular sweeps (k_sweep.hip)
 template <class T>

@@ -7,6 +7,8 @@
 // add 2 kc / h^2; Neumann faces add nothing; first-order upwind convection on
 // face-averaged velocities.  The arithmetic order matches the generator that
 // builds the same matrices on the host, so both give identical bits.
+#include <mutex>
+
 #include "gmg_internal.h"
 #include "kcommon.h"
 
@@ -39,9 +41,11 @@ __device__ __forceinline__ int fv_row_count(int n, int dim, int c) {
   return k;
 }
 
+// cnt[c] = entries of row c for c < N, cnt[N] = 0 (N + 1 threads)
 __global__ void k_fv_count(int n, int dim, int N, int* cnt) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < N) cnt[c] = fv_row_count(n, dim, c);
+  else if (c == N) cnt[N] = 0;
 }
 
 __global__ void k_fv_fill(FvGeom g, const double* __restrict__ kap, const int* __restrict__ rp,
@@ -139,6 +143,30 @@ __global__ void k_pattern_grad(int n, const int* __restrict__ rp, const int* __r
   }
 }
 
+// Scratch of gmg_fv_assemble_noalloc: the block sums of its row-pointer scan
+// (one int per SCAN_BS cells, plus the total), in a static array that every
+// GPU the library runs on holds until the process ends.
+static __device__ __align__(256) int scratch[GMG_FV_NOALLOC_SCRATCH_INTS];
+
+// Device address of this GPU's copy of `scratch` (the array's name in host
+// code is a host-side stand-in, not a device address): looked up once per
+// device, with that device current.
+static int* fv_scratch_ptr() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static int* ptr[kMaxDevices] = {};
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(GMG_ERR_INVALID_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ptr[dev] = static_cast<int*>(p);
+  }
+  return ptr[dev];
+}
+
 }  // namespace gmg
 
 using namespace gmg;
@@ -146,8 +174,10 @@ using namespace gmg;
 template <class F>
 static gmg_status fv_guard(F&& f) {
   try {
+    set_error_message("");
     return f();
   } catch (const Error& e) {
+    set_error_message(e.msg);
     return e.code;
   }
 }
@@ -171,13 +201,43 @@ extern "C" gmg_status gmg_fv_assemble(int n, int dim, const double* kappa, const
     hipStream_t s = (hipStream_t)stream;
     DBuf<int> cnt, tmp;
     cnt.alloc((size_t)N + 1);
-    launch_fill_u32(reinterpret_cast<unsigned*>(cnt.p), 0u, (size_t)N + 1, s);
-    hipLaunchKernelGGL(k_fv_count, dim3((N + 255) / 256), dim3(256), 0, s, n, dim, N, cnt.p);
+    hipLaunchKernelGGL(k_fv_count, dim3((N + 1 + 255) / 256), dim3(256), 0, s, n, dim, N, cnt.p);
     launch_exclusive_scan_int(cnt.p, rowptr, N + 1, s, tmp);
     FvGeom g{n, dim, {vel_x, vel_y, dim == 3 ? vel_z : nullptr}};
     hipLaunchKernelGGL(k_fv_fill, dim3((N + 255) / 256), dim3(256), 0, s, g, kappa, rowptr, col, val, N);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(s));
+    return GMG_OK;
+  });
+}
+
+extern "C" gmg_status gmg_fv_assemble_noalloc(int n, int dim, const double* kappa, const double* vel_x,
+                                              const double* vel_y, const double* vel_z, int32_t* rowptr,
+                                              int32_t* col, double* val, void* stream) {
+  return fv_guard([&]() -> gmg_status {
+    // every argument is checked before any device call
+    if (n < 1 || (dim != 2 && dim != 3) || !kappa || !vel_x || !vel_y || (dim == 3 && !vel_z) || !rowptr ||
+        !col || !val)
+      return GMG_ERR_INVALID_ARG;
+    const int64_t N64 = dim == 2 ? (int64_t)n * n : (int64_t)n * n * n;
+    if (N64 > GMG_FV_NOALLOC_MAX_CELLS) {
+      set_error_message("gmg_fv_assemble_noalloc: " + std::to_string(N64) + " cells exceed the limit of " +
+                        std::to_string((long long)GMG_FV_NOALLOC_MAX_CELLS));
+      return GMG_ERR_INVALID_ARG;
+    }
+    static_assert((int64_t)GMG_FV_NOALLOC_SCRATCH_INTS * SCAN_BLOCK >= GMG_FV_NOALLOC_MAX_CELLS + 1 + SCAN_BLOCK,
+                  "scratch holds one block sum per scan block plus the total");
+    const int N = (int)N64;
+    hipStream_t s = (hipStream_t)stream;
+    int* bsum = fv_scratch_ptr();
+    // the row counts go straight into rowptr and are scanned in place; the
+    // scan's block sums live in the scratch array (every entry it reads is
+    // written earlier in the same call, so nothing needs clearing)
+    hipLaunchKernelGGL(k_fv_count, dim3((N + 1 + 255) / 256), dim3(256), 0, s, n, dim, N, rowptr);
+    launch_exclusive_scan_int_ws(rowptr, rowptr, N + 1, bsum, s);
+    FvGeom g{n, dim, {vel_x, vel_y, dim == 3 ? vel_z : nullptr}};
+    hipLaunchKernelGGL(k_fv_fill, dim3((N + 255) / 256), dim3(256), 0, s, g, kappa, rowptr, col, val, N);
+    HIPCK(hipGetLastError());
     return GMG_OK;
   });
 }

@@ -295,8 +295,7 @@ void launch_resid_adj(int n, const int* rp, const int* ci, const double* v, cons
 // Exclusive scan of n ints (out may alias in), three phases.
 constexpr int SCAN_BS = 1024;
 
-__global__ __launch_bounds__(SCAN_BS) void k_scan_block(const int* __restrict__ in, int* __restrict__ out,
-                                                        int n, int* __restrict__ bsum) {
+__global__ __launch_bounds__(SCAN_BS) void k_scan_block(const int* in, int* out, int n, int* __restrict__ bsum) {
   __shared__ int sh[SCAN_BS];
   int i = blockIdx.x * SCAN_BS + threadIdx.x;
   int v = i < n ? in[i] : 0;
@@ -324,14 +323,23 @@ __global__ void k_scan_add(int* out, int n, const int* bsum) {
   if (i < n) out[i] += bsum[blockIdx.x];
 }
 
+static_assert(SCAN_BS == SCAN_BLOCK, "scan block size");
+
+// bsum: caller's workspace of at least n / SCAN_BS + 2 ints
+void launch_exclusive_scan_int_ws(const int* in, int* out, int n, int* bsum, hipStream_t s) {
+  if (n <= 0) return;
+  int nb = (n + SCAN_BS - 1) / SCAN_BS;
+  hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(SCAN_BS), 0, s, in, out, n, bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, bsum, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BS), 0, s, out, n, bsum);
+  HIPCK(hipGetLastError());
+}
+
 void launch_exclusive_scan_int(const int* in, int* out, int n, hipStream_t s, DBuf<int>& tmp) {
   if (n <= 0) return;
   int nb = (n + SCAN_BS - 1) / SCAN_BS;
   if ((int)tmp.n < nb + 1) tmp.alloc(nb + 1);
-  hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(SCAN_BS), 0, s, in, out, n, tmp.p);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, tmp.p, nb);
-  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BS), 0, s, out, n, tmp.p);
-  HIPCK(hipGetLastError());
+  launch_exclusive_scan_int_ws(in, out, n, tmp.p, s);
 }
 
 // ---------------------------------------------------------------- transpose

@@ -24,8 +24,12 @@ EXPORTED = [
     "gmg_get_fine_perm", "gmg_get_spai", "gmg_get_coarse_inverse",
     "gmg_get_ilut", "gmg_set_stream", "gmg_profile_enable", "gmg_profile_read",
     "gmg_profile_name", "gmg_destroy", "gmg_last_error", "gmg_fv_nnz", "gmg_fv_assemble",
-    "gmg_fv_kappa_grad", "gmg_pattern_grad",
+    "gmg_fv_assemble_noalloc", "gmg_fv_kappa_grad", "gmg_pattern_grad",
 ]
+
+# limits of gmg_fv_assemble_noalloc (include/gmg.h)
+FV_NOALLOC_SCRATCH_INTS = 32768
+FV_NOALLOC_MAX_CELLS = 33553407
 
 
 class Options(C.Structure):
@@ -93,6 +97,7 @@ def load():
         "gmg_last_error": (C.c_char_p, []),
         "gmg_fv_nnz": (I64, [I, I]),
         "gmg_fv_assemble": (I, [I, I, P, P, P, P, P, P, P, P]),
+        "gmg_fv_assemble_noalloc": (I, [I, I, P, P, P, P, P, P, P, P]),
         "gmg_fv_kappa_grad": (I, [I, I, P, P, P, I, P, P]),
         "gmg_pattern_grad": (I, [I64, P, P, P, P, I, P, P]),
     }
@@ -353,21 +358,29 @@ class Solver:
 
 
 # ------------------------------------------------------------------ FV ops
-def fv_assemble(n, dim, kappa, vel, stream=None):
+def fv_assemble(n, dim, kappa, vel, stream=None, out=None, noalloc=False):
     """A(kappa) of the FV discretisation on the GPU; vel = list of face-velocity
-    tensors (x, y[, z]).  Returns (rowptr, col, val) device tensors."""
+    tensors (x, y[, z]).  Returns (rowptr, col, val) device tensors (the
+    caller's `out` triple when given).  noalloc: the library entry point that
+    allocates no device memory (gmg_fv_assemble_noalloc)."""
     torch = _torch()
     lib = load()
     kap = _dev(kappa, torch.float64)
     vs = [_dev(v, torch.float64).reshape(-1) for v in vel]
     N = n ** dim
     nnz = lib.gmg_fv_nnz(n, dim)
-    rp = torch.empty(N + 1, dtype=torch.int32, device="cuda")
-    ci = torch.empty(nnz, dtype=torch.int32, device="cuda")
-    va = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    if out is None:
+        rp = torch.empty(N + 1, dtype=torch.int32, device="cuda")
+        ci = torch.empty(nnz, dtype=torch.int32, device="cuda")
+        va = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    else:
+        rp, ci, va = out
+        if rp.numel() < N + 1 or ci.numel() < nnz or va.numel() < nnz:
+            raise ValueError("fv_assemble: output tensors too small")
     vz = _ptr(vs[2]) if dim == 3 else None
-    _check(lib.gmg_fv_assemble(n, dim, _ptr(kap), _ptr(vs[0]), _ptr(vs[1]), vz, _ptr(rp), _ptr(ci),
-                               _ptr(va), _stream(stream)), "fv_assemble")
+    fn = lib.gmg_fv_assemble_noalloc if noalloc else lib.gmg_fv_assemble
+    _check(fn(n, dim, _ptr(kap), _ptr(vs[0]), _ptr(vs[1]), vz, _ptr(rp), _ptr(ci), _ptr(va),
+              _stream(stream)), "fv_assemble_noalloc" if noalloc else "fv_assemble")
     return rp, ci, va
 
 

@@ -96,3 +96,20 @@ def test_struct_layout_matches_header(tmp_path):
         want.append(ctypes.sizeof(py))
         want += [getattr(py, f).offset for f, _ in py._fields_]
     assert got == want
+
+
+def test_noalloc_assembly_limit_checked_before_device_work(lib):
+    """gmg_fv_assemble_noalloc refuses grids beyond its scratch before it
+    touches a device (so this runs without a GPU); the header's limit and the
+    binding's agree."""
+    from paper_1105_3468_amd import gmg
+    src = open(os.path.join(ROOT, "include", "gmg.h")).read()
+    assert re.search(r"GMG_FV_NOALLOC_MAX_CELLS\s+%dLL" % gmg.FV_NOALLOC_MAX_CELLS, src)
+    assert re.search(r"GMG_FV_NOALLOC_SCRATCH_INTS\s+%d\b" % gmg.FV_NOALLOC_SCRATCH_INTS, src)
+    # one block sum per 1024 cells (and the total) must fit the scratch
+    assert (gmg.FV_NOALLOC_MAX_CELLS + 1 + 1023) // 1024 + 1 <= gmg.FV_NOALLOC_SCRATCH_INTS
+    L = gmg.load()
+    fake = ctypes.c_void_p(8)   # never dereferenced: the size check comes first
+    assert L.gmg_fv_assemble_noalloc(323, 3, fake, fake, fake, fake, fake, fake, fake, None) == gmg.ERR_INVALID_ARG
+    assert b"exceed" in L.gmg_last_error()
+    assert L.gmg_fv_assemble_noalloc(0, 2, fake, fake, fake, None, fake, fake, fake, None) == gmg.ERR_INVALID_ARG
