@@ -45,6 +45,20 @@ struct ProfRec {
   double bytes;
 };
 
+// Workspace of the multi-right-hand-side solve: up to BATCH_MAX columns,
+// column-major, fine vectors ld apart, coarse vectors ldc apart, Krylov bases
+// of m steps (step j of column c at V + (j * cap + c) * ld).
+struct BatchWork {
+  int cap = 0, m = 0;
+  size_t ld = 0, ldc = 0;
+  bool f32 = false, adj = false;
+  DBuf<double> t, rc, yc, ec, wz, wy, wt, text;                    // FP64 cycle
+  DBuf<float> t32, rc32, yc32, ec32, wz32, wy32, wt32, text32;     // FP32 cycle
+  DBuf<int> ncLc, ncUc, ncUct, ncLct;                              // tree node counters per column
+  DBuf<double> abc, auc, aec, as, at;                              // adjoint cycle
+  DBuf<double> V, Z, w, x, b, coef;                                // Krylov
+};
+
 struct Solver {
   hipStream_t s = nullptr;
   gmg_options opt{};
@@ -104,12 +118,16 @@ struct Solver {
   size_t ldg = 0;
   DBuf<double> gram, gcoef, gdots;  // the basis' Gram matrix (ldg x ldg), corrected coefficients, V^T w_new
   RedWork rw;
+  BatchWork bw;                // multi-right-hand-side solve (allocated on first use)
   DBuf<int> abort_flag;
   double* hpin = nullptr;      // pinned host scalars, then two Hessenberg columns (kPinCol each)
   hipEvent_t colev[2] = {nullptr, nullptr};  // a column's copy into hpin finished
   gmg_info info{};
   int log_every = 0;           // GMG_LOG=k prints the residual estimate every k steps
   std::vector<double> hist;    // FGMRES residual estimates of the last solve, per step
+  bool force_column_loop = false;  // GMG_COLUMN_LOOP=1: solve several RHS one after another (timing reference)
+  int spmv_g = 0;              // lanes per row of the SpMV (A and A^T have the same average row length)
+  bool fused_rr = false;       // residual + restriction in one kernel (GMG_FUSED_RR=1)
   // profiling
   bool prof = false;
   unsigned prof_mask = 0;      // classes that record events (bit c: class c)
@@ -761,19 +779,13 @@ static void reset_cycle_buffers(Solver& S) {
 }
 
 // ------------------------------------------------------ preconditioner apply
-// q = B~^{-1} z: t = U0^{-1} L0^{-1} z; r = z - A t; rc = P^T r;
-// ec = U~^{-1} L~^{-1} rc; q = t + P ec  (precision T)
+// t = S^{-1} z, the ILU(0) smoothing step (precision T; t is the output of a
+// triangular sweep, so it holds the sentinel on entry)
 template <class T>
-static void vcycle(Solver& S, const double* z, double* q) {
+static void smooth_apply(Solver& S, const double* z, T* t) {
   constexpr bool F32 = sizeof(T) == 4;
   hipStream_t s = S.s;
   T* y = F32 ? (T*)S.y32.p : (T*)S.y.p;
-  T* t = F32 ? (T*)S.t32.p : (T*)S.t.p;
-  T* r = F32 ? (T*)S.r32.p : (T*)S.r.p;
-  T* rc = F32 ? (T*)S.rc32.p : (T*)S.rc.p;
-  T* yc = F32 ? (T*)S.yc32.p : (T*)S.yc.p;
-  T* ec = F32 ? (T*)S.ec32.p : (T*)S.ec.p;
-  const T* Av = F32 ? (const T*)S.A.v32.p : (const T*)S.A.v.p;
   const size_t sz = sizeof(T);
   if (S.wave) {
     Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0, sz, 8, false) + sweep_bytes(S.U0, sz, sz, true));
@@ -805,12 +817,16 @@ static void vcycle(Solver& S, const double* z, double* q) {
       run_tri<T>(S, S.U0, y, false, t, y);
     }
   }
-  {
-    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 8 + 3 * sz + 4) +
-                                     (double)S.nc * (4 + 2 * sz));
-    launch_resid_fine<T>(S.n, S.A.rp.p, S.A.ci.p, Av, t, z, r, s);
-    launch_restrict<T>(S.nc, S.aptr.p, S.amem.p, r, rc, ec, 0, s);
-  }
+}
+
+// ec = A~_c^{-1} rc, the inexact coarse solve (precision T; ec holds the
+// sentinel on entry, as the restriction leaves it)
+template <class T>
+static void coarse_apply(Solver& S, T* rc, T* ec) {
+  constexpr bool F32 = sizeof(T) == 4;
+  hipStream_t s = S.s;
+  T* yc = F32 ? (T*)S.yc32.p : (T*)S.yc.p;
+  const size_t sz = sizeof(T);
   if (S.opt.coarse_mode == 0 && S.tree) {
     T* ext = F32 ? (T*)S.text32.p : (T*)S.text.p;
     {
@@ -837,7 +853,8 @@ static void vcycle(Solver& S, const double* z, double* q) {
   } else if (S.opt.coarse_mode == 2) {
     // e_c = M r_c with the sparse approximate inverse
     Prof p(S, PC_SWEEP_COARSE, (double)S.dMc.nnz * (4 + sz) + (double)S.nc * (4 + 2 * sz));
-    launch_spmv<T>(S.nc, S.dMc.rp.p, S.dMc.ci.p, F32 ? (const T*)S.dMc.v32.p : (const T*)S.dMc.v.p, rc, ec, s);
+    launch_spmv<T>(S.nc, S.dMc.rp.p, S.dMc.ci.p, F32 ? (const T*)S.dMc.v32.p : (const T*)S.dMc.v.p, rc, ec, s,
+                   spmv_lanes(S.dMc.nnz, S.nc));
   } else {
     if (F32) fail(GMG_ERR_INVALID_ARG, "coarse_mode 1 runs in FP64 only");
     // Jacobi sweeps on each factor: y <- rc - (L~ - I) y from y = rc, then
@@ -860,6 +877,34 @@ static void vcycle(Solver& S, const double* z, double* q) {
     }
     if (e0 != (double*)ec) d2d((double*)ec, e0, S.nc, s);
   }
+}
+
+// q = B~^{-1} z: t = U0^{-1} L0^{-1} z; r = z - A t; rc = P^T r;
+// ec = U~^{-1} L~^{-1} rc; q = t + P ec  (precision T)
+template <class T>
+static void vcycle(Solver& S, const double* z, double* q) {
+  constexpr bool F32 = sizeof(T) == 4;
+  hipStream_t s = S.s;
+  T* t = F32 ? (T*)S.t32.p : (T*)S.t.p;
+  T* r = F32 ? (T*)S.r32.p : (T*)S.r.p;
+  T* rc = F32 ? (T*)S.rc32.p : (T*)S.rc.p;
+  T* ec = F32 ? (T*)S.ec32.p : (T*)S.ec.p;
+  const T* Av = F32 ? (const T*)S.A.v32.p : (const T*)S.A.v.p;
+  const size_t sz = sizeof(T);
+  smooth_apply<T>(S, z, t);
+  if (S.fused_rr) {
+    // r_c = P^T (z - A t) in one pass: A, t, z and the member lists read
+    // once, no fine residual written
+    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 4 + 8 + sz) +
+                                     (double)S.nc * (4 + 2 * sz));
+    launch_resid_restrict_cols<T>(S.nc, S.aptr.p, S.amem.p, S.A.rp.p, S.A.ci.p, Av, t, 0, z, 0, rc, ec, 0, 1, s);
+  } else {
+    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 8 + 3 * sz + 4) +
+                                     (double)S.nc * (4 + 2 * sz));
+    launch_resid_fine<T>(S.n, S.A.rp.p, S.A.ci.p, Av, t, z, r, s, S.spmv_g);
+    launch_restrict<T>(S.nc, S.aptr.p, S.amem.p, r, rc, ec, 0, s);
+  }
+  coarse_apply<T>(S, rc, ec);
   {
     Prof p(S, PC_PROLONG, (double)S.n * (4 + 2 * sz + 8) + (double)S.nc * sz);
     launch_prolong<T>(S.n, S.agg.p, t, ec, q, 0, s);
@@ -1010,7 +1055,7 @@ static void vcycle_adjoint(Solver& S, const double* z, double* q) {
 static void apply_op(Solver& S, bool adjoint, const double* x, double* y) {
   Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)S.n * 20);
   const DCsr& M = adjoint ? S.AT : S.A;
-  launch_spmv<double>(S.n, M.rp.p, M.ci.p, M.v.p, x, y, S.s);
+  launch_spmv<double>(S.n, M.rp.p, M.ci.p, M.v.p, x, y, S.s, S.spmv_g);
 }
 
 static void ensure_krylov(Solver& S, int m) {
@@ -1080,7 +1125,7 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
     {
       Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)n * 28);
       const DCsr& M = adjoint ? S.AT : S.A;
-      launch_residual(S.n, M.rp.p, M.ci.p, M.v.p, x, b, w, s);
+      launch_residual(S.n, M.rp.p, M.ci.p, M.v.p, x, b, w, s, S.spmv_g);
     }
     {
       Prof p(S, PC_VECTOR, (double)n * 8);
@@ -1219,7 +1264,415 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
     }
   }
   out.steps = total;
+  // a reduction that gave up on a partial (its bounded wait ran out) may see
+  // that partial land later: start the next solve from clean partials
+  if (out.st == GMG_ERR_NONFINITE || out.st == GMG_ERR_BREAKDOWN) red_reset(S.rw, s);
   HIPCK(hipStreamSynchronize(s));
+  return out;
+}
+
+// ------------------------------------------------------- multi-RHS solve
+// Several right-hand sides share every launch: the fine wavefront sweeps and
+// the coarse tree solves run all columns in one launch (a column's
+// dependency chains interleave with the others', so the latency-bound sweeps
+// cost about what one column costs), the matrix, the aggregates and the
+// factors are read once per step for all columns, and the Krylov kernels run
+// one recurrence per column of their grid.
+constexpr int kBatchRS = 2 * kFused + 8;  // result doubles per column: h1, h2, ||w||^2
+
+static void ensure_batch(Solver& S, int nb, int m, bool f32, bool adjoint) {
+  BatchWork& B = S.bw;
+  hipStream_t s = S.s;
+  const bool grow = nb > B.cap || m > B.m;
+  if (grow) {
+    B = BatchWork();
+    B.cap = BATCH_MAX;
+    B.m = std::max(m, kFused);
+    B.ld = ((size_t)S.n + 63) / 64 * 64;
+    B.ldc = ((size_t)std::max(S.nc, 1) + 63) / 64 * 64;
+    const size_t nf = B.ld * B.cap, ncv = B.ldc * B.cap;
+    B.t.alloc(nf);
+    B.rc.alloc(ncv);
+    B.yc.alloc(ncv);
+    B.ec.alloc(ncv);
+    B.text.alloc(ncv);
+    launch_fill_f64_bits(B.t.p, kSent64, nf, s);
+    launch_fill_f64_bits(B.yc.p, kSent64, ncv, s);
+    launch_fill_f64_bits(B.ec.p, kSent64, ncv, s);
+    launch_fill_f64_bits(B.text.p, kSent64, ncv, s);
+    if (S.wave) {
+      const size_t nw = (size_t)S.wg.total * B.cap;
+      B.wz.alloc(nw);
+      B.wy.alloc(nw);
+      B.wt.alloc(nw);
+      launch_fill_f64_bits(B.wy.p, kSent64, nw, s);
+      launch_fill_f64_bits(B.wt.p, kSent64, nw, s);
+    }
+    auto counters = [&](DBuf<int>& c, const TreeSolve& t) {
+      if (!t.ncount.p) return;
+      c.alloc(t.ncount.n * B.cap);
+      launch_fill_u32(reinterpret_cast<unsigned*>(c.p), 0u, c.n, s);
+    };
+    counters(B.ncLc, S.tLc);
+    counters(B.ncUc, S.tUc);
+    B.V.alloc(B.ld * B.cap * (B.m + 1));
+    B.Z.alloc(B.ld * B.cap * B.m);
+    B.w.alloc(nf);
+    B.x.alloc(nf);
+    B.b.alloc(nf);
+    B.coef.alloc((size_t)B.cap * (B.m + 1));
+  }
+  if (f32 && !B.f32) {
+    const size_t nf = B.ld * B.cap, ncv = B.ldc * B.cap;
+    B.t32.alloc(nf);
+    B.rc32.alloc(ncv);
+    B.yc32.alloc(ncv);
+    B.ec32.alloc(ncv);
+    B.text32.alloc(ncv);
+    launch_fill_f32_bits(B.t32.p, kSent32, nf, s);
+    launch_fill_f32_bits(B.yc32.p, kSent32, ncv, s);
+    launch_fill_f32_bits(B.ec32.p, kSent32, ncv, s);
+    launch_fill_f32_bits(B.text32.p, kSent32, ncv, s);
+    if (S.wave) {
+      const size_t nw = (size_t)S.wg.total * B.cap;
+      B.wz32.alloc(nw);
+      B.wy32.alloc(nw);
+      B.wt32.alloc(nw);
+      launch_fill_f32_bits(B.wy32.p, kSent32, nw, s);
+      launch_fill_f32_bits(B.wt32.p, kSent32, nw, s);
+    }
+    B.f32 = true;
+  }
+  if (adjoint && !B.adj) {
+    const size_t nf = B.ld * B.cap, ncv = B.ldc * B.cap;
+    B.abc.alloc(ncv);
+    B.auc.alloc(ncv);
+    B.aec.alloc(ncv);
+    B.as.alloc(nf);
+    B.at.alloc(nf);
+    launch_fill_f64_bits(B.auc.p, kSent64, ncv, s);
+    launch_fill_f64_bits(B.aec.p, kSent64, ncv, s);
+    launch_fill_f64_bits(B.at.p, kSent64, nf, s);
+    auto counters = [&](DBuf<int>& c, const TreeSolve& t) {
+      if (!t.ncount.p) return;
+      c.alloc(t.ncount.n * B.cap);
+      launch_fill_u32(reinterpret_cast<unsigned*>(c.p), 0u, c.n, s);
+    };
+    counters(B.ncUct, S.tUct);
+    counters(B.ncLct, S.tLct);
+    B.adj = true;
+  }
+}
+
+// Every value-as-flag buffer of the batch back to its idle state (sentinels,
+// zero node counters), so a solve never inherits state from one that stopped
+// early.
+static void reset_batch_buffers(Solver& S) {
+  BatchWork& B = S.bw;
+  hipStream_t s = S.s;
+  for (DBuf<double>* b : {&B.t, &B.yc, &B.ec, &B.text, &B.wy, &B.wt, &B.auc, &B.aec, &B.at})
+    if (b->p) launch_fill_f64_bits(b->p, kSent64, b->n, s);
+  for (DBuf<float>* b : {&B.t32, &B.yc32, &B.ec32, &B.text32, &B.wy32, &B.wt32})
+    if (b->p) launch_fill_f32_bits(b->p, kSent32, b->n, s);
+  for (DBuf<int>* c : {&B.ncLc, &B.ncUc, &B.ncUct, &B.ncLct})
+    if (c->p) launch_fill_u32(reinterpret_cast<unsigned*>(c->p), 0u, c->n, s);
+}
+
+// q_c = B~^{-1} z_c for the columns c < nb (z_c = z + c * ldz, q_c = q + c * ldq)
+template <class T>
+static void vcycle_batch(Solver& S, const double* z, size_t ldz, double* q, size_t ldq, int nb) {
+  constexpr bool F32 = sizeof(T) == 4;
+  BatchWork& B = S.bw;
+  hipStream_t s = S.s;
+  T* t = F32 ? (T*)B.t32.p : (T*)B.t.p;
+  T* rc = F32 ? (T*)B.rc32.p : (T*)B.rc.p;
+  T* yc = F32 ? (T*)B.yc32.p : (T*)B.yc.p;
+  T* ec = F32 ? (T*)B.ec32.p : (T*)B.ec.p;
+  const T* Av = F32 ? (const T*)S.A.v32.p : (const T*)S.A.v.p;
+  const size_t sz = sizeof(T), ld = B.ld, ldc = B.ldc;
+  if (S.wave) {
+    Prof p(S, PC_SWEEP_FINE, nb * (sweep_bytes(S.L0, sz, 8, false) + sweep_bytes(S.U0, sz, sz, true)));
+    launch_wave_pair<T>(S.wg, S.wL0, S.wU0, z, true, F32 ? (T*)B.wz32.p : (T*)B.wz.p, F32 ? (T*)B.wy32.p : (T*)B.wy.p,
+                        F32 ? (T*)B.wt32.p : (T*)B.wt.p, t, S.abort_flag.p, s, nb, ldz, ld);
+  } else {
+    for (int c = 0; c < nb; ++c) smooth_apply<T>(S, z + c * ldz, t + c * ld);
+  }
+  {
+    // the fused form reads A once for every column and writes no fine residual
+    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * 4 +
+                                     nb * ((double)S.n * (8 + sz) + (double)S.nc * 2 * sz) + (double)S.nc * 4);
+    launch_resid_restrict_cols<T>(S.nc, S.aptr.p, S.amem.p, S.A.rp.p, S.A.ci.p, Av, t, ld, z, ldz, rc, ec, ldc, nb, s);
+  }
+  if (S.opt.coarse_mode == 0 && S.tree) {
+    T* ext = F32 ? (T*)B.text32.p : (T*)B.text.p;
+    {
+      Prof p(S, PC_SWEEP_COARSE, nb * sweep_bytes(S.Lc, sz, sz, false));
+      launch_tree<T>(S.tLc, rc, false, yc, nullptr, ext, S.abort_flag.p, s, nb, ldc, B.ncLc.p);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, nb * sweep_bytes(S.Uc, sz, sz, true));
+      launch_tree<T>(S.tUc, yc, false, ec, yc, ext, S.abort_flag.p, s, nb, ldc, B.ncUc.p);
+    }
+  } else {
+    for (int c = 0; c < nb; ++c) coarse_apply<T>(S, rc + c * ldc, ec + c * ldc);
+  }
+  {
+    Prof p(S, PC_PROLONG, nb * ((double)S.n * (4 + 2 * sz + 8) + (double)S.nc * sz));
+    launch_prolong_cols<T>(S.n, S.agg.p, t, ld, ec, ldc, q, ldq, nb, s);
+  }
+}
+
+// q_c = B~^{-T} z_c (FP64) for the columns c < nb
+static void vcycle_adjoint_batch(Solver& S, const double* z, size_t ldz, double* q, size_t ldq, int nb) {
+  ensure_adjoint(S);
+  ensure_batch(S, nb, S.bw.m, false, true);
+  BatchWork& B = S.bw;
+  hipStream_t s = S.s;
+  const size_t ld = B.ld, ldc = B.ldc;
+  {
+    Prof p(S, PC_RESID_RESTRICT, nb * ((double)S.n * 12 + (double)S.nc * 16));
+    launch_restrict_cols(S.nc, S.aptr.p, S.amem.p, z, ldz, B.abc.p, B.aec.p, ldc, nb, s);
+  }
+  if (S.tree_adj) {
+    {
+      Prof p(S, PC_SWEEP_COARSE, nb * sweep_bytes(S.Uct, 8, 8, false));
+      launch_tree<double>(S.tUct, B.abc.p, false, B.auc.p, nullptr, B.text.p, S.abort_flag.p, s, nb, ldc, B.ncUct.p);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, nb * sweep_bytes(S.Lct, 8, 8, true));
+      launch_tree<double>(S.tLct, B.auc.p, false, B.aec.p, B.auc.p, B.text.p, S.abort_flag.p, s, nb, ldc, B.ncLct.p);
+    }
+  } else {
+    for (int c = 0; c < nb; ++c) {
+      {
+        Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
+        run_tri<double>(S, S.Uct, B.abc.p + c * ldc, false, S.auc.p, nullptr);
+      }
+      {
+        Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
+        run_tri<double>(S, S.Lct, S.auc.p, false, B.aec.p + c * ldc, S.auc.p);
+      }
+    }
+  }
+  {
+    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * 12 + (double)S.n * 4 + nb * ((double)S.n * 24 + (double)S.nc * 8));
+    launch_resid_adj_cols(S.n, S.AT.rp.p, S.AT.ci.p, S.AT.v.p, S.agg.p, B.aec.p, ldc, z, ldz, B.as.p, ld, nb, s);
+  }
+  if (S.wave) {
+    Prof p(S, PC_SWEEP_FINE, nb * (sweep_bytes(S.U0t, 8, 8, false) + sweep_bytes(S.L0t, 8, 8, true)));
+    launch_wave_pair<double>(S.wg, S.wU0t, S.wL0t, B.as.p, true, B.wz.p, B.wy.p, B.wt.p, B.at.p, S.abort_flag.p, s, nb,
+                             ld, ld);
+  } else {
+    for (int c = 0; c < nb; ++c) {
+      {
+        Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
+        run_tri<double>(S, S.U0t, B.as.p + c * ld, false, S.aw.p, nullptr);
+      }
+      {
+        Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
+        run_tri<double>(S, S.L0t, S.aw.p, false, B.at.p + c * ld, S.aw.p);
+      }
+    }
+  }
+  {
+    Prof p(S, PC_PROLONG, nb * ((double)S.n * 28 + (double)S.nc * 8));
+    launch_prolong_cols<double>(S.n, S.agg.p, B.at.p, ld, B.aec.p, ldc, q, ldq, nb, s);
+  }
+}
+
+struct BatchResult {
+  gmg_status st = GMG_OK;
+  int steps = 0, restarts = 0, converged = 0;
+  double relres = 0.0, est = 0.0;
+};
+
+// FGMRES(m), m <= 32, on nb columns at once (columns c0 .. c0 + nb - 1 of the
+// caller's (N, nrhs) arrays): one recurrence per column, every launch shared.
+// Each column keeps its own Hessenberg matrix, rotations and step count; a
+// column that has converged is carried along (its further steps are not
+// used) until the cycle ends, then left out of the restarts.
+static BatchResult fgmres_batch(Solver& S, bool adjoint, int precision, const double* Bu, double* Xu, int nrhs,
+                                int c0, int nb, double tol, int maxit, int m, bool x0_given) {
+  hipStream_t s = S.s;
+  const int64_t n = S.n;
+  if (adjoint) ensure_adjoint(S);   // the transposed factors, before their per-column counters
+  ensure_batch(S, nb, m, precision == 1, adjoint);
+  reset_batch_buffers(S);
+  BatchWork& W = S.bw;
+  const size_t ld = W.ld, cap = (size_t)W.cap;
+  double* res = S.rw.result.p;
+  double* hp = S.hpin;
+  BatchResult out;
+  const BatchCols bcol{nb, ld, ld, (size_t)kBatchRS, (size_t)kBatchRS};
+  const DCsr& M = adjoint ? S.AT : S.A;
+  launch_cols_from_rows(Bu, nrhs, c0, W.b.p, ld, n, nb, s);
+  if (x0_given) launch_cols_from_rows(Xu, nrhs, c0, W.x.p, ld, n, nb, s);
+  else HIPCK(hipMemsetAsync(W.x.p, 0, sizeof(double) * ld * nb, s));
+  {
+    Prof p(S, PC_VECTOR, (double)n * 8 * nb);
+    launch_norm2(W.b.p, n, S.rw, res, s, nb, ld, 1);
+  }
+  d2h(hp, res, nb, s);
+  HIPCK(hipStreamSynchronize(s));
+  std::vector<double> bnorm(nb);
+  for (int c = 0; c < nb; ++c) {
+    bnorm[c] = std::sqrt(hp[c]);
+    if (!std::isfinite(bnorm[c])) { out.st = GMG_ERR_NONFINITE; return out; }
+  }
+  const int mm = m + 1;
+  std::vector<double> H((size_t)nb * mm * m, 0.0), cs((size_t)nb * mm), sn((size_t)nb * mm), g((size_t)nb * (m + 2)),
+      yv((size_t)nb * mm), coef((size_t)cap * mm, 0.0), relres(nb, 0.0), est(nb, 0.0);
+  auto HH = [&](int c, int i, int j) -> double& { return H[((size_t)c * mm + i) * m + j]; };
+  std::vector<int> total(nb, 0), kc_used(nb, 0), restarts(nb, 0);
+  std::vector<char> done(nb, 0), live(nb, 0);
+  std::vector<std::vector<double>> hist(nb);
+  for (int c = 0; c < nb; ++c)
+    if (bnorm[c] == 0.0) done[c] = 1;   // x = 0 (set below) is exact
+  for (;;) {
+    // r_c = b_c - A x_c and its norm, every column
+    {
+      Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)n * 4 + (double)n * 20 * nb);
+      launch_residual_cols((int)n, M.rp.p, M.ci.p, M.v.p, W.x.p, ld, W.b.p, ld, W.w.p, ld, nb, s);
+    }
+    {
+      Prof p(S, PC_VECTOR, (double)n * 8 * nb);
+      launch_norm2(W.w.p, n, S.rw, res, s, nb, ld, 1);
+    }
+    d2h(hp, res, nb, s);
+    HIPCK(hipStreamSynchronize(s));
+    bool any = false;
+    for (int c = 0; c < nb; ++c) {
+      if (done[c] && bnorm[c] == 0.0) { relres[c] = 0.0; continue; }
+      const double beta = std::sqrt(hp[c]);
+      relres[c] = beta / bnorm[c];
+      live[c] = 0;
+      if (!std::isfinite(relres[c])) { out.st = GMG_ERR_NONFINITE; red_reset(S.rw, s); return out; }
+      if (relres[c] < tol) { done[c] = 1; continue; }
+      if (total[c] >= maxit) { done[c] = 1; continue; }
+      if (total[c] > 0) ++restarts[c];
+      live[c] = 1;
+      any = true;
+      std::fill(&g[(size_t)c * (m + 2)], &g[(size_t)c * (m + 2)] + (m + 2), 0.0);
+      g[(size_t)c * (m + 2)] = beta;
+      kc_used[c] = 0;
+    }
+    if (!any) break;
+    // v_1 = r / ||r|| for every column (finished ones carried along)
+    {
+      Prof p(S, PC_VECTOR, (double)n * 16 * nb);
+      launch_normalize_cols(W.w.p, ld, res, 1, W.V.p, ld, n, nb, s);
+    }
+    bool breakdown = false;
+    auto enqueue_step = [&](int j) {
+      double* vj = W.V.p + (size_t)j * cap * ld;
+      double* zj = W.Z.p + (size_t)j * cap * ld;
+      if (adjoint) vcycle_adjoint_batch(S, vj, ld, zj, ld, nb);
+      else if (precision == 1) vcycle_batch<float>(S, vj, ld, zj, ld, nb);
+      else vcycle_batch<double>(S, vj, ld, zj, ld, nb);
+      {
+        Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)n * 4 + (double)n * 16 * nb);
+        launch_spmm<double>((int)n, M.rp.p, M.ci.p, M.v.p, zj, ld, W.w.p, ld, nb, s);
+      }
+      const int kc = j + 1;
+      {
+        // classical Gram-Schmidt twice, every column in each launch
+        Prof p(S, PC_ORTHO, 8.0 * n * (3 * kc + 6) * nb);
+        launch_multidot(W.V.p, cap * ld, kc, W.w.p, n, S.rw, res, s, bcol);
+        launch_update_dot(W.V.p, cap * ld, kc, res, W.w.p, n, S.rw, res + kc, s, bcol);
+        launch_update_norm(W.V.p, cap * ld, kc, res + kc, W.w.p, n, S.rw, res + 2 * kc, s, bcol);
+      }
+      {
+        Prof p(S, PC_VECTOR, (double)n * 16 * nb);
+        launch_normalize_cols(W.w.p, ld, res + 2 * kc, kBatchRS, W.V.p + (size_t)(j + 1) * cap * ld, ld, n, nb, s);
+      }
+      d2h(hp + (size_t)kPinCol * (1 + (j & 1)), res, (size_t)nb * kBatchRS, s);
+      HIPCK(hipEventRecord(S.colev[j & 1], s));
+    };
+    // true when every column's cycle has ended with step j
+    auto process_step = [&](int j) -> bool {
+      HIPCK(hipEventSynchronize(S.colev[j & 1]));
+      const int kc = j + 1;
+      bool all_ended = true;
+      for (int c = 0; c < nb; ++c) {
+        if (!live[c]) continue;
+        const double* col = hp + (size_t)kPinCol * (1 + (j & 1)) + (size_t)c * kBatchRS;
+        double* gc = &g[(size_t)c * (m + 2)];
+        double* csc = &cs[(size_t)c * mm];
+        double* snc = &sn[(size_t)c * mm];
+        for (int i = 0; i <= j; ++i) HH(c, i, j) = col[i] + col[kc + i];
+        const double hn = std::sqrt(col[2 * kc]);
+        HH(c, j + 1, j) = hn;
+        for (int i = 0; i < j; ++i) {
+          const double a = HH(c, i, j), b2 = HH(c, i + 1, j);
+          HH(c, i, j) = csc[i] * a + snc[i] * b2;
+          HH(c, i + 1, j) = -snc[i] * a + csc[i] * b2;
+        }
+        const double rho = std::hypot(HH(c, j, j), HH(c, j + 1, j));
+        if (rho == 0.0 || !std::isfinite(rho)) {
+          out.st = std::isfinite(rho) ? GMG_ERR_BREAKDOWN : GMG_ERR_NONFINITE;
+          breakdown = true;
+          return true;
+        }
+        csc[j] = HH(c, j, j) / rho;
+        snc[j] = HH(c, j + 1, j) / rho;
+        HH(c, j, j) = rho;
+        HH(c, j + 1, j) = 0.0;
+        gc[j + 1] = -snc[j] * gc[j];
+        gc[j] = csc[j] * gc[j];
+        ++total[c];
+        kc_used[c] = j + 1;
+        est[c] = std::fabs(gc[j + 1]) / bnorm[c];
+        hist[c].push_back(est[c]);
+        if (est[c] < tol || hn == 0.0 || total[c] >= maxit) live[c] = 0;
+        else all_ended = false;
+      }
+      return all_ended;
+    };
+    std::vector<char> in_cycle(live);
+    bool ended = false;
+    for (int j = 0; j < m && !ended; ++j) {
+      enqueue_step(j);
+      if (j > 0) ended = process_step(j - 1);
+    }
+    if (!ended) process_step(m - 1);
+    check_abort(S);
+    if (breakdown) { red_reset(S.rw, s); break; }
+    // x_c += Z_c y_c with each column's own step count (zeros for the others)
+    int kmax = 0;
+    std::fill(coef.begin(), coef.end(), 0.0);
+    for (int c = 0; c < nb; ++c) {
+      if (!in_cycle[c]) continue;
+      const int k = kc_used[c];
+      kmax = std::max(kmax, k);
+      double* y = &yv[(size_t)c * mm];
+      const double* gc = &g[(size_t)c * (m + 2)];
+      for (int i = k - 1; i >= 0; --i) {
+        double sum = gc[i];
+        for (int l = i + 1; l < k; ++l) sum -= HH(c, i, l) * y[l];
+        y[i] = sum / HH(c, i, i);
+      }
+      for (int i = 0; i < k; ++i) coef[(size_t)c * mm + i] = y[i];
+      live[c] = 0;
+    }
+    if (kmax > 0) {
+      h2d(W.coef.p, coef.data(), (size_t)nb * mm, s);
+      Prof p(S, PC_VECTOR, 8.0 * n * (kmax + 2) * nb);
+      launch_xupdate(W.x.p, W.Z.p, cap * ld, kmax, W.coef.p, n, s, nb, ld, ld, (size_t)mm);
+    }
+  }
+  for (int c = 0; c < nb; ++c)
+    if (bnorm[c] == 0.0) HIPCK(hipMemsetAsync(W.x.p + (size_t)c * ld, 0, sizeof(double) * n, s));
+  launch_rows_from_cols(Xu, nrhs, c0, W.x.p, ld, n, nb, s);
+  HIPCK(hipStreamSynchronize(s));
+  for (int c = 0; c < nb; ++c) {
+    S.hist.insert(S.hist.end(), hist[c].begin(), hist[c].end());
+    out.steps += total[c];
+    out.restarts += restarts[c];
+    out.relres = std::max(out.relres, relres[c]);
+    out.est = std::max(out.est, est[c]);
+    if (relres[c] < tol || bnorm[c] == 0.0) ++out.converged;
+  }
+  if (out.st == GMG_OK && out.converged < nb) out.st = GMG_NOT_CONVERGED;
   return out;
 }
 
@@ -1244,30 +1697,49 @@ static gmg_status solve_impl(Solver& S, bool adjoint, const double* b, double* x
   gmg_status worst = GMG_OK;
   int iters = 0, restarts = 0, conv = 0;
   double rel = 0.0, est = 0.0;
-  ensure_krylov(S, opt.restart);
-  if (nrhs > 1 && !S.xcol.p) {
-    S.xcol.alloc(S.n);
-    S.bcol.alloc(S.n);
-  }
-  for (int c = 0; c < nrhs; ++c) {
-    const double* bc = b;
-    double* xc = x;
-    if (nrhs > 1) {
-      launch_get_col(b, nrhs, c, S.bcol.p, S.n, S.s);
-      if (opt.x0_given) launch_get_col(x, nrhs, c, S.xcol.p, S.n, S.s);
-      bc = S.bcol.p;
-      xc = S.xcol.p;
+  // several right-hand sides with a short restart (the register-resident
+  // Krylov kernels) share every launch, in batches of BATCH_MAX columns;
+  // otherwise the columns are solved one after another
+  const bool batched = nrhs > 1 && opt.restart <= kFused && !S.force_column_loop;
+  if (batched) {
+    for (int c0 = 0; c0 < nrhs; c0 += BATCH_MAX) {
+      const int nb = std::min(BATCH_MAX, nrhs - c0);
+      BatchResult r = fgmres_batch(S, adjoint, opt.precond_fp32 ? 1 : 0, b, x, nrhs, c0, nb, tol, opt.maxit,
+                                   opt.restart, opt.x0_given != 0);
+      iters += r.steps;
+      restarts += r.restarts;
+      conv += r.converged;
+      rel = std::max(rel, r.relres);
+      est = std::max(est, r.est);
+      if (r.st < 0) { worst = r.st; break; }
+      if (r.st > 0 && worst == GMG_OK) worst = r.st;
     }
-    OneResult r = fgmres(S, adjoint, opt.precond_fp32 ? 1 : 0, bc, xc, tol, opt.maxit, opt.restart,
-                         opt.x0_given != 0);
-    if (nrhs > 1) launch_set_col(x, nrhs, c, S.xcol.p, S.n, S.s);
-    iters += r.steps;
-    restarts += r.restarts;
-    rel = std::max(rel, r.relres);
-    est = std::max(est, r.est);
-    if (r.st == GMG_OK) ++conv;
-    if (r.st < 0) { worst = r.st; break; }
-    if (r.st > 0 && worst == GMG_OK) worst = r.st;
+  } else {
+    ensure_krylov(S, opt.restart);
+    if (nrhs > 1 && !S.xcol.p) {
+      S.xcol.alloc(S.n);
+      S.bcol.alloc(S.n);
+    }
+    for (int c = 0; c < nrhs; ++c) {
+      const double* bc = b;
+      double* xc = x;
+      if (nrhs > 1) {
+        launch_get_col(b, nrhs, c, S.bcol.p, S.n, S.s);
+        if (opt.x0_given) launch_get_col(x, nrhs, c, S.xcol.p, S.n, S.s);
+        bc = S.bcol.p;
+        xc = S.xcol.p;
+      }
+      OneResult r = fgmres(S, adjoint, opt.precond_fp32 ? 1 : 0, bc, xc, tol, opt.maxit, opt.restart,
+                           opt.x0_given != 0);
+      if (nrhs > 1) launch_set_col(x, nrhs, c, S.xcol.p, S.n, S.s);
+      iters += r.steps;
+      restarts += r.restarts;
+      rel = std::max(rel, r.relres);
+      est = std::max(est, r.est);
+      if (r.st == GMG_OK) ++conv;
+      if (r.st < 0) { worst = r.st; break; }
+      if (r.st > 0 && worst == GMG_OK) worst = r.st;
+    }
   }
   HIPCK(hipStreamSynchronize(S.s));
   auto t1 = std::chrono::steady_clock::now();
@@ -1400,6 +1872,9 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   const int n = (int)n64;
   S.n = n;
   S.nnz = nnz64;
+  S.spmv_g = 0;
+  if (const char* e = std::getenv("GMG_SPMV_LANES")) S.spmv_g = std::atoi(e);   // 0: the LDS-staged form
+  if (const char* e = std::getenv("GMG_FUSED_RR")) S.fused_rr = std::atoi(e) != 0;
   HIPCK(hipHostMalloc(&S.hpin, sizeof(double) * 3 * kPinCol, hipHostMallocDefault));
   for (auto& e : S.colev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   S.abort_flag.alloc(1);
@@ -1870,6 +2345,7 @@ gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowpt
     std::unique_ptr<gmg_solver> sv(new gmg_solver());
     sv->S.s = (hipStream_t)stream;
     if (const char* e = std::getenv("GMG_LOG")) sv->S.log_every = std::max(0, std::atoi(e));
+    if (const char* e = std::getenv("GMG_COLUMN_LOOP")) sv->S.force_column_loop = std::atoi(e) != 0;
     if (opts) sv->S.opt = *opts;
     else gmg_default_options(&sv->S.opt);
     gmg::setup_impl(sv->S, n, nnz, rowptr, col, val);

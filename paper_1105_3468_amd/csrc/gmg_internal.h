@@ -149,7 +149,8 @@ struct WaveSweep {
 // all-sentinel on entry and left so.
 template <class T>
 void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& up, const void* z, bool z_f64, T* zs,
-                      T* ys, T* ts, T* t, int* abort_flag, hipStream_t s);
+                      T* ys, T* ts, T* t, int* abort_flag, hipStream_t s, int nb = 1, size_t ldz = 0,
+                      size_t ldt = 0);
 
 // A triangular factor solved over the nested-dissection tree (k_tree.hip):
 // tasks in tree order, 8 ints each (kind 0: helper for rows [r0, r1) of a
@@ -175,7 +176,7 @@ struct TreeSolve {
 };
 template <class T>
 void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, T* reset_rhs, T* ext,
-                 int* abort_flag, hipStream_t s);
+                 int* abort_flag, hipStream_t s, int nb = 1, size_t ld = 0, int* ncount = nullptr);
 // Setup: inverses of the diagonal blocks blk (same layout as inv) into inv,
 // one workgroup per task (8 ints: lo, s, c0, node, log2 W; a chunk of W
 // columns of one node), with `lds` bytes of LDS (tree_inv_lds of each task,
@@ -214,17 +215,20 @@ void launch_dense_inverse(int nc, int np, const int* rp, const int* ci, const do
                           hipStream_t s);
 template <class T>
 void launch_dense_gemv(int n, int np, const T* M, const T* r, T* e, hipStream_t s);
-// CSR SpMV y = A x; T = value/vector type
+// CSR SpMV y = A x; T = value/vector type.  lanes: lanes per row (4, 8, 16
+// or 32; spmv_lanes picks it from the average row length), 0 = one lane per
+// row with the row's products staged in LDS
+int spmv_lanes(int64_t nnz, int64_t n);
 template <class T>
 void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y,
-                 hipStream_t s);
+                 hipStream_t s, int lanes = 0);
 // r = b - A x  (r may alias nothing); FP64 only
 void launch_residual(int n, const int* rp, const int* ci, const double* v, const double* x,
-                     const double* b, double* r, hipStream_t s);
+                     const double* b, double* r, hipStream_t s, int lanes = 0);
 // Fine residual of the smoothed iterate: r[k] = z[k] - (A t)[k]  (Tz = input type)
 template <class T>
 void launch_resid_fine(int n, const int* rp, const int* ci, const T* v, const T* t,
-                       const double* z, T* r, hipStream_t s);
+                       const double* z, T* r, hipStream_t s, int lanes = 0);
 // rc[I] = sum_{k in G_I} r[k]; also writes the sentinel into reset[I]
 template <class T>
 void launch_restrict(int nc, const int* aptr, const int* amem, const T* r, T* rc, T* reset,
@@ -279,15 +283,24 @@ struct RedWork {  // scratch for deterministic two-level reductions
   int blocks = 0;
 };
 void red_init(RedWork& rw, hipStream_t s);
+void red_reset(RedWork& rw, hipStream_t s);
+// Independent recurrences batched in one launch of the k <= 32 Krylov
+// kernels: column c (c < nb) works on V + c * vcol, w + c * wcol, h + c * hcol
+// and writes result + c * rcol.
+constexpr int KCOLS = 16;
+struct BatchCols {
+  int nb = 1;
+  size_t vcol = 0, wcol = 0, rcol = 0, hcol = 0;
+};
 // result[0..k) = V[0..k)^T w   (V rows with stride ld)
 void launch_multidot(const double* V, size_t ld, int k, const double* w, int64_t n,
-                     RedWork& rw, double* result, hipStream_t s);
+                     RedWork& rw, double* result, hipStream_t s, const BatchCols& bc = BatchCols());
 // w -= V[0..k)^T h  (h device), then result[0..k) = V^T w_new
 void launch_update_dot(const double* V, size_t ld, int k, const double* h, double* w, int64_t n,
-                       RedWork& rw, double* result, hipStream_t s);
+                       RedWork& rw, double* result, hipStream_t s, const BatchCols& bc = BatchCols());
 // w -= V^T h, then result[0] = ||w||^2
 void launch_update_norm(const double* V, size_t ld, int k, const double* h, double* w, int64_t n,
-                        RedWork& rw, double* result, hipStream_t s);
+                        RedWork& rw, double* result, hipStream_t s, const BatchCols& bc = BatchCols());
 // any k (<= 2048): w -= V^T h (h device); if want_norm, result[0] = ||w_new||^2
 // Many-vector passes (up to many_max() vectors): result[0..k) = V^T w, and
 // w <- w - V h with result[0..k) = V^T w_new (and result[k] = ||w_new||^2
@@ -310,15 +323,49 @@ void launch_normalize_gram(const double* x, const double* nrm2, double* y, int64
 void launch_update_many(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, bool want_norm,
                         RedWork& rw, double* result, hipStream_t s);
 // result[0] = ||x||^2
-void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s);
+void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s, int nb = 1,
+                  size_t xcol = 0, size_t rcol = 0);
+// y_c = x_c / sqrt(nrm2[c * rcol]) for columns c < nb (x_c = x + c * xcol, ...)
+void launch_normalize_cols(const double* x, size_t xcol, const double* nrm2, size_t rcol, double* y, size_t ycol,
+                           int64_t n, int nb, hipStream_t s);
 // y = alpha * x
 void launch_scale(const double* x, double alpha, double* y, int64_t n, hipStream_t s);
 // x += sum_i c[i] Z[i]  (c device)
 void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n,
-                    hipStream_t s);
+                    hipStream_t s, int nb = 1, size_t xcol = 0, size_t zcol = 0, size_t ccol = 0);
 // strided column gather/scatter for multi-RHS
 void launch_get_col(const double* X, int nrhs, int col, double* x, int64_t n, hipStream_t s);
 void launch_set_col(double* X, int nrhs, int col, const double* x, int64_t n, hipStream_t s);
+
+// Multi-right-hand-side kernels (k_batch.hip): nb <= BATCH_MAX columns per
+// launch, column c of a batch at base + c * ld.
+constexpr int BATCH_MAX = 16;
+template <class T>
+void launch_spmm(int n, const int* rp, const int* ci, const T* v, const T* x, size_t ldx, T* y, size_t ldy, int nb,
+                 hipStream_t s);
+// r_c = b_c - A x_c
+void launch_residual_cols(int n, const int* rp, const int* ci, const double* v, const double* x, size_t ldx,
+                          const double* b, size_t ldb, double* r, size_t ldr, int nb, hipStream_t s);
+// out_c = z_c - A^T P ec_c (rp/ci/v: A^T as CSR)
+void launch_resid_adj_cols(int n, const int* rp, const int* ci, const double* v, const int* agg, const double* ec,
+                           size_t ldc, const double* z, size_t ldz, double* out, size_t ldo, int nb, hipStream_t s);
+// rc_c = P^T (z_c - A t_c), fused; reset_c <- sentinel (reset may be null)
+template <class T>
+void launch_resid_restrict_cols(int nc, const int* aptr, const int* amem, const int* rp, const int* ci, const T* v,
+                                const T* t, size_t ldt, const double* z, size_t ldz, T* rc, T* reset, size_t ldc,
+                                int nb, hipStream_t s);
+// rc_c = P^T z_c; reset_c <- sentinel (reset may be null)
+void launch_restrict_cols(int nc, const int* aptr, const int* amem, const double* z, size_t ldz, double* rc,
+                          double* reset, size_t ldc, int nb, hipStream_t s);
+// q_c = t_c + P ec_c (widened to FP64); t_c <- sentinel
+template <class T>
+void launch_prolong_cols(int n, const int* agg, T* t, size_t ldt, const T* ec, size_t ldc, double* q, size_t ldq,
+                         int nb, hipStream_t s);
+// out_c[i] = X[i * nrhs + c0 + c] (c < nb), and the reverse
+void launch_cols_from_rows(const double* X, int nrhs, int c0, double* out, size_t ld, int64_t n, int nb,
+                           hipStream_t s);
+void launch_rows_from_cols(double* X, int nrhs, int c0, const double* in, size_t ld, int64_t n, int nb,
+                           hipStream_t s);
 
 // Setup kernels (k_setup.hip)
 void build_graph(int n, const int* rp, const int* ci, const double* v, const int* trp,

@@ -108,10 +108,25 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[K], int kcount,
 
 // result[k] = sum_i V[k][i] w[i], k < K.  The vector count is a compile-time
 // constant so the K loads of an element are unconditional and all in flight.
+// Batched forms (several independent FGMRES recurrences per launch): column
+// c = blockIdx.y works on V + c * vcol, w + c * wcol and writes result +
+// c * rcol, with its own block partials and counter.
+#define KRYLOV_COLUMN()                                   \
+  do {                                                    \
+    const size_t col_ = blockIdx.y;                       \
+    V += col_ * vcol;                                     \
+    w += col_ * wcol;                                     \
+    result += col_ * rcol;                                \
+    partial += col_ * (size_t)KGRID * KMAX;               \
+    counter += col_;                                      \
+  } while (0)
+
 template <int K>
 __global__ __launch_bounds__(KB) void k_multidot(const double* __restrict__ V, size_t ld, int kc,
                                                  const double* __restrict__ w, int64_t n, double* partial,
-                                                 unsigned* counter, double* result) {
+                                                 unsigned* counter, double* result, size_t vcol, size_t wcol,
+                                                 size_t rcol) {
+  KRYLOV_COLUMN();
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
@@ -132,7 +147,10 @@ template <int K>
 __global__ __launch_bounds__(KB) void k_update_dot(const double* __restrict__ V, size_t ld, int kc,
                                                    const double* __restrict__ h, double* __restrict__ w,
                                                    int64_t n, double* partial, unsigned* counter,
-                                                   double* result) {
+                                                   double* result, size_t vcol, size_t wcol, size_t rcol,
+                                                   size_t hcol) {
+  KRYLOV_COLUMN();
+  h += blockIdx.y * hcol;
   double acc[K], hk[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) { acc[k] = 0.0; hk[k] = h[k]; }
@@ -156,7 +174,10 @@ template <int K>
 __global__ __launch_bounds__(KB) void k_update_norm(const double* __restrict__ V, size_t ld, int kc,
                                                     const double* __restrict__ h, double* __restrict__ w,
                                                     int64_t n, double* partial, unsigned* counter,
-                                                    double* result) {
+                                                    double* result, size_t vcol, size_t wcol, size_t rcol,
+                                                    size_t hcol) {
+  KRYLOV_COLUMN();
+  h += blockIdx.y * hcol;
   double acc[1] = {0.0}, hk[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) hk[k] = h[k];
@@ -176,12 +197,20 @@ __global__ __launch_bounds__(KB) void k_update_norm(const double* __restrict__ V
 
 void red_init(RedWork& rw, hipStream_t s) {
   rw.blocks = KGRID;
-  rw.partial.alloc((size_t)KGRID * KMAX);
-  rw.counter.alloc(1);
+  rw.partial.alloc((size_t)KGRID * KMAX * KCOLS);
+  rw.counter.alloc(KCOLS);
   rw.result.alloc(2 * KLDS + 8);
   rw.mpart.alloc((size_t)MGRID * MSTR);
-  launch_fill_u32(rw.counter.p, 0u, 1, s);
-  launch_fill_f64_bits(rw.partial.p, SENT64, (size_t)KGRID * KMAX, s);
+  launch_fill_u32(rw.counter.p, 0u, KCOLS, s);
+  launch_fill_f64_bits(rw.partial.p, SENT64, (size_t)KGRID * KMAX * KCOLS, s);
+}
+
+// Back to the state red_init leaves (every partial the sentinel, counters
+// zero), after a reduction may have given up on a partial (its bounded wait
+// ran out): a partial that lands later must not be read by the next one.
+void red_reset(RedWork& rw, hipStream_t s) {
+  launch_fill_u32(rw.counter.p, 0u, KCOLS, s);
+  launch_fill_f64_bits(rw.partial.p, SENT64, (size_t)KGRID * KMAX * KCOLS, s);
 }
 
 static unsigned red_grid(int64_t n) {
@@ -207,30 +236,40 @@ static unsigned red_grid(int64_t n) {
     }                                                                                                     \
   } while (0)
 
+static void check_cols(const BatchCols& bc) {
+  if (bc.nb < 1 || bc.nb > KCOLS) fail(GMG_ERR_INVALID_ARG, "Krylov kernels: bad column count");
+}
 void launch_multidot(const double* V, size_t ld, int k, const double* w, int64_t n, RedWork& rw,
-                     double* result, hipStream_t s) {
+                     double* result, hipStream_t s, const BatchCols& bc) {
   if (k < 1 || k > KMAX) fail(GMG_ERR_INVALID_ARG, "multidot: bad vector count");
-  GMG_DISPATCH_K(k, k_multidot, dim3(red_grid(n)), dim3(KB), 0, s, V, ld, k, w, n, rw.partial.p, rw.counter.p,
-                 result);
+  check_cols(bc);
+  GMG_DISPATCH_K(k, k_multidot, dim3(red_grid(n), bc.nb), dim3(KB), 0, s, V, ld, k, w, n, rw.partial.p,
+                 rw.counter.p, result, bc.vcol, bc.wcol, bc.rcol);
   HIPCK(hipGetLastError());
 }
 void launch_update_dot(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
-                       double* result, hipStream_t s) {
+                       double* result, hipStream_t s, const BatchCols& bc) {
   if (k < 1 || k > KMAX) fail(GMG_ERR_INVALID_ARG, "update_dot: bad vector count");
-  GMG_DISPATCH_K(k, k_update_dot, dim3(red_grid(n)), dim3(KB), 0, s, V, ld, k, h, w, n, rw.partial.p,
-                 rw.counter.p, result);
+  check_cols(bc);
+  GMG_DISPATCH_K(k, k_update_dot, dim3(red_grid(n), bc.nb), dim3(KB), 0, s, V, ld, k, h, w, n, rw.partial.p,
+                 rw.counter.p, result, bc.vcol, bc.wcol, bc.rcol, bc.hcol);
   HIPCK(hipGetLastError());
 }
 void launch_update_norm(const double* V, size_t ld, int k, const double* h, double* w, int64_t n, RedWork& rw,
-                        double* result, hipStream_t s) {
+                        double* result, hipStream_t s, const BatchCols& bc) {
   if (k < 1 || k > KMAX) fail(GMG_ERR_INVALID_ARG, "update_norm: bad vector count");
-  GMG_DISPATCH_K(k, k_update_norm, dim3(red_grid(n)), dim3(KB), 0, s, V, ld, k, h, w, n, rw.partial.p,
-                 rw.counter.p, result);
+  check_cols(bc);
+  GMG_DISPATCH_K(k, k_update_norm, dim3(red_grid(n), bc.nb), dim3(KB), 0, s, V, ld, k, h, w, n, rw.partial.p,
+                 rw.counter.p, result, bc.vcol, bc.wcol, bc.rcol, bc.hcol);
   HIPCK(hipGetLastError());
 }
 
 __global__ __launch_bounds__(KB) void k_norm2(const double* __restrict__ x, int64_t n, double* partial,
-                                              unsigned* counter, double* result) {
+                                              unsigned* counter, double* result, size_t xcol, size_t rcol) {
+  x += blockIdx.y * xcol;
+  result += blockIdx.y * rcol;
+  partial += blockIdx.y * (size_t)KGRID * KMAX;
+  counter += blockIdx.y;
   double acc[1] = {0.0};
   for (int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KB) {
     const double v = x[i];
@@ -238,8 +277,32 @@ __global__ __launch_bounds__(KB) void k_norm2(const double* __restrict__ x, int6
   }
   block_reduce_store<1>(acc, 1, partial, counter, result);
 }
-void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm2, dim3(red_grid(n)), dim3(KB), 0, s, x, n, rw.partial.p, rw.counter.p, result);
+void launch_norm2(const double* x, int64_t n, RedWork& rw, double* result, hipStream_t s, int nb, size_t xcol,
+                  size_t rcol) {
+  if (nb < 1 || nb > KCOLS) fail(GMG_ERR_INVALID_ARG, "norm2: bad column count");
+  hipLaunchKernelGGL(k_norm2, dim3(red_grid(n), nb), dim3(KB), 0, s, x, n, rw.partial.p, rw.counter.p, result, xcol,
+                     rcol);
+  HIPCK(hipGetLastError());
+}
+
+// y_c = x_c / sqrt(nrm2[c * rcol]) for the columns c < nb (zero when the
+// norm is zero); x_c = x + c * xcol, y_c = y + c * ycol
+__global__ void k_normalize_cols(const double* __restrict__ x, size_t xcol, const double* __restrict__ nrm2,
+                                 size_t rcol, double* __restrict__ y, size_t ycol, int64_t n) {
+  const double nv = nrm2[blockIdx.y * rcol];
+  const double hn = sqrt(nv);
+  const double a = hn != 0.0 ? 1.0 / hn : 0.0;
+  x += blockIdx.y * xcol;
+  y += blockIdx.y * ycol;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+void launch_normalize_cols(const double* x, size_t xcol, const double* nrm2, size_t rcol, double* y, size_t ycol,
+                           int64_t n, int nb, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 2048) g = 2048;
+  hipLaunchKernelGGL(k_normalize_cols, dim3((unsigned)g, nb), dim3(256), 0, s, x, xcol, nrm2, rcol, y, ycol, n);
   HIPCK(hipGetLastError());
 }
 
@@ -293,7 +356,10 @@ void launch_normalize_gram(const double* x, const double* nrm2, double* y, int64
 
 template <int K>
 __global__ void k_xupdate(double* __restrict__ x, const double* __restrict__ Z, size_t ld, int kc,
-                          const double* __restrict__ c, int64_t n) {
+                          const double* __restrict__ c, int64_t n, size_t xcol, size_t zcol, size_t ccol) {
+  x += blockIdx.y * xcol;
+  Z += blockIdx.y * zcol;
+  c += blockIdx.y * ccol;
   double ck[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) ck[k] = c[k];
@@ -661,12 +727,15 @@ void launch_set_col(double* X, int nrhs, int col, const double* x, int64_t n, hi
   HIPCK(hipGetLastError());
 }
 
-void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n, hipStream_t s) {
+void launch_xupdate(double* x, const double* Z, size_t ld, int k, const double* c, int64_t n, hipStream_t s, int nb,
+                    size_t xcol, size_t zcol, size_t ccol) {
   if (n <= 0 || k <= 0) return;
+  if (nb < 1 || nb > KCOLS || (nb > 1 && k > KMAX)) fail(GMG_ERR_INVALID_ARG, "xupdate: bad column count");
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
+  if (nb > 1 && g > 1024) g = 1024;
   if (k <= KMAX) {
-    GMG_DISPATCH_K(k, k_xupdate, dim3((unsigned)g), dim3(256), 0, s, x, Z, ld, k, c, n);
+    GMG_DISPATCH_K(k, k_xupdate, dim3((unsigned)g, nb), dim3(256), 0, s, x, Z, ld, k, c, n, xcol, zcol, ccol);
   } else {
     if (k > KLDS) fail(GMG_ERR_INVALID_ARG, "xupdate: bad vector count");
     hipLaunchKernelGGL(k_xupdate_many, dim3((unsigned)g), dim3(KB), 0, s, x, Z, ld, k, c, n);

@@ -1,5 +1,7 @@
 // Sparse streaming kernels: SpMV, residual, restriction over aggregates,
 // prolongation, CSR transpose, scans, fills.  All wave64, HBM-bound.
+#include <algorithm>
+
 #include "gmg_internal.h"
 #include "kcommon.h"
 
@@ -170,34 +172,114 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
   }
 }
 
-template <class T>
-void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y, hipStream_t s) {
+// G lanes per row (a power of two near the average row length): every lane
+// of a row's group loads one of its entries (column, value, then x at that
+// column), the group adds its products with cross-lane shuffles, and its
+// first lane writes the row.  A wave holds 64 / G rows; it takes U such row
+// sets at once and issues all their loads before the first use, so several
+// dependent load rounds are in flight per wave.  The wave's loads of column
+// indices and values cover its rows' contiguous entries, so they are fully
+// coalesced; no LDS, no barrier.  Rows longer than G take further rounds.
+// MODE 0: y = A x;  MODE 1: y = b - A x.
+constexpr int SPMV_U = 4;
+constexpr int SPMV_WAVES = 4;   // waves per workgroup
+
+template <class T, class TB, int MODE, int G>
+__global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_g(int n, const int* __restrict__ rp,
+                                                            const int* __restrict__ ci, const T* __restrict__ v,
+                                                            const T* __restrict__ x, const TB* __restrict__ b,
+                                                            T* __restrict__ y) {
+  constexpr int RPW = 64 / G;                  // rows per wave and row set
+  const int lane = threadIdx.x & 63, sub = lane & (G - 1), slot = lane / G;
+  const int64_t wave = (int64_t)blockIdx.x * SPMV_WAVES + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * SPMV_WAVES;
+  for (int64_t base = wave * RPW * SPMV_U; base < n; base += nwaves * RPW * SPMV_U) {
+    int p[SPMV_U], pe[SPMV_U];
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u) {
+      const int64_t row = base + u * RPW + slot;
+      p[u] = row < n ? rp[row] : 0;
+      pe[u] = row < n ? rp[row + 1] : 0;
+    }
+    T acc[SPMV_U];
+    int c[SPMV_U];
+    T a[SPMV_U];
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u) {
+      const int k = p[u] + sub;
+      c[u] = k < pe[u] ? ci[k] : -1;
+      a[u] = k < pe[u] ? v[k] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u) acc[u] = c[u] >= 0 ? a[u] * x[c[u]] : (T)0;
+    // rows longer than G
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u)
+      for (int k = p[u] + sub + G; k < pe[u]; k += G) acc[u] += v[k] * x[ci[k]];
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u) {
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, 64);
+    }
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u) {
+      const int64_t row = base + u * RPW + slot;
+      if (sub == 0 && row < n) y[row] = MODE == 0 ? acc[u] : (T)b[row] - acc[u];
+    }
+  }
+}
+
+// lanes per row for a matrix with nnz entries in n rows: the power of two at
+// or above the average row length, between 4 and 32
+int spmv_lanes(int64_t nnz, int64_t n) {
+  const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
+  int g = 4;
+  while (g < 32 && g < avg) g <<= 1;
+  return g;
+}
+
+template <class T, class TB, int MODE>
+static void spmv_dispatch(int n, const int* rp, const int* ci, const T* v, const T* x, const TB* b, T* y, int lanes,
+                          hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_spmv<T, T, 0>), dim3((n + SPMV_ROWS - 1) / SPMV_ROWS), dim3(256), 0, s,
-                     n, rp, ci, v, x, (const T*)nullptr, y);
+  if (lanes == 0) {
+    hipLaunchKernelGGL((k_spmv<T, TB, MODE>), dim3((n + SPMV_ROWS - 1) / SPMV_ROWS), dim3(256), 0, s, n, rp, ci, v, x,
+                       b, y);
+    HIPCK(hipGetLastError());
+    return;
+  }
+  const int64_t rows_per_block = (int64_t)(64 / lanes) * SPMV_U * SPMV_WAVES;
+  const unsigned grid = (unsigned)std::min<int64_t>(8192, (n + rows_per_block - 1) / rows_per_block);
+  const dim3 blk(64 * SPMV_WAVES);
+  switch (lanes) {
+    case 4: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 4>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
+    case 8: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 8>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
+    case 16: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 16>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
+    case 32: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 32>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
+    default: fail(GMG_ERR_INVALID_ARG, "spmv: lanes per row must be 0, 4, 8, 16 or 32");
+  }
   HIPCK(hipGetLastError());
 }
-template void launch_spmv<double>(int, const int*, const int*, const double*, const double*, double*, hipStream_t);
-template void launch_spmv<float>(int, const int*, const int*, const float*, const float*, float*, hipStream_t);
+
+template <class T>
+void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y, hipStream_t s, int lanes) {
+  spmv_dispatch<T, T, 0>(n, rp, ci, v, x, (const T*)nullptr, y, lanes, s);
+}
+template void launch_spmv<double>(int, const int*, const int*, const double*, const double*, double*, hipStream_t, int);
+template void launch_spmv<float>(int, const int*, const int*, const float*, const float*, float*, hipStream_t, int);
 
 void launch_residual(int n, const int* rp, const int* ci, const double* v, const double* x,
-                     const double* b, double* r, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL((k_spmv<double, double, 1>), dim3((n + SPMV_ROWS - 1) / SPMV_ROWS), dim3(256), 0, s,
-                     n, rp, ci, v, x, b, r);
-  HIPCK(hipGetLastError());
+                     const double* b, double* r, hipStream_t s, int lanes) {
+  spmv_dispatch<double, double, 1>(n, rp, ci, v, x, b, r, lanes, s);
 }
 
 template <class T>
 void launch_resid_fine(int n, const int* rp, const int* ci, const T* v, const T* t, const double* z, T* r,
-                       hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL((k_spmv<T, double, 1>), dim3((n + SPMV_ROWS - 1) / SPMV_ROWS), dim3(256), 0, s,
-                     n, rp, ci, v, t, z, r);
-  HIPCK(hipGetLastError());
+                       hipStream_t s, int lanes) {
+  spmv_dispatch<T, double, 1>(n, rp, ci, v, t, z, r, lanes, s);
 }
-template void launch_resid_fine<double>(int, const int*, const int*, const double*, const double*, const double*, double*, hipStream_t);
-template void launch_resid_fine<float>(int, const int*, const int*, const float*, const float*, const double*, float*, hipStream_t);
+template void launch_resid_fine<double>(int, const int*, const int*, const double*, const double*, const double*, double*, hipStream_t, int);
+template void launch_resid_fine<float>(int, const int*, const int*, const float*, const float*, const double*, float*, hipStream_t, int);
 
 // ----------------------------------------------- restriction / prolongation
 // rc[I] = sum over members k of G_I (ascending) of r[k]; reset[I] <- sentinel.

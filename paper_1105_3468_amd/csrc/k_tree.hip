@@ -54,15 +54,29 @@ __device__ __forceinline__ T tree_poll(const T* p, int* abort_flag, uint64_t lim
 
 // task[8t ..]: helper: 0, lo, s, r0, r1, node, 1, log2 G
 //               slice:  1, lo, s, a, b, node, has_ext | log2 R << 1, slices
+//
+// nb > 1 solves nb right-hand sides in one launch: workgroup t * nb + c runs
+// task t for column c, whose vectors (rhs, out, ext, reset_rhs) start at
+// c * ld and whose node counters at c * nnode.  A task waits only on earlier
+// tasks of its own column, which have lower workgroup indices.
 template <class T, class TR, bool LOWER>
 __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ task, const int64_t* __restrict__ boff,
                                                        const int* __restrict__ erp, const int* __restrict__ ecol,
                                                        const T* __restrict__ eval, const T* __restrict__ inv,
                                                        int* ncount, const TR* rhs, T* out, T* ext, TR* reset_rhs,
-                                                       int* abort_flag, uint64_t limit) {
+                                                       int* abort_flag, uint64_t limit, int nb, size_t ld, int nnode) {
   extern __shared__ __align__(16) unsigned char tree_smem[];
   T* y = reinterpret_cast<T*>(tree_smem);
-  const int* tk = task + 8 * (size_t)blockIdx.x;
+  const int tix = blockIdx.x / nb;
+  {
+    const int col = blockIdx.x - tix * nb;
+    rhs += col * ld;
+    out += col * ld;
+    ext += col * ld;
+    if (reset_rhs) reset_rhs += col * ld;
+    ncount += (size_t)col * nnode;
+  }
+  const int* tk = task + 8 * (size_t)tix;
   const int kind = tk[0], lo = tk[1], s = tk[2];
 
   if (kind == 0) {
@@ -206,8 +220,12 @@ static uint64_t tree_limit_ticks() {
 
 template <class T>
 void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, T* reset_rhs, T* ext, int* abort_flag,
-                 hipStream_t s) {
+                 hipStream_t s, int nb, size_t ld, int* ncount) {
   if (ts.ntasks == 0) return;
+  if (nb < 1 || (int64_t)ts.ntasks * nb > 0x7fffffff) fail(GMG_ERR_INVALID_ARG, "tree solve: bad column count");
+  if (nb > 1 && !ncount) fail(GMG_ERR_INVALID_ARG, "tree solve: columns need their own node counters");
+  int* cnt = ncount ? ncount : ts.ncount.p;
+  const int nnode = (int)ts.ncount.n;
   constexpr bool F32 = sizeof(T) == 4;
   const T* ev = F32 ? (const T*)ts.eval32.p : (const T*)ts.eval.p;
   const T* iv = F32 ? (const T*)ts.inv32.p : (const T*)ts.inv.p;
@@ -221,9 +239,9 @@ void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kTreeMaxRows * sizeof(double)))); \
       attr = true;                                                                                                 \
     }                                                                                                              \
-    hipLaunchKernelGGL((k_tree<T, TR_, LO_>), dim3(ts.ntasks), dim3(TREE_THREADS), lds, s, ts.task.p, ts.boff.p,   \
-                       ts.erp.p, ts.ecol.p, ev, iv, ts.ncount.p, (const TR_*)RHS_, out, ext, RESET_, abort_flag,    \
-                       lim);                                                                                       \
+    hipLaunchKernelGGL((k_tree<T, TR_, LO_>), dim3(ts.ntasks * nb), dim3(TREE_THREADS), lds, s, ts.task.p,        \
+                       ts.boff.p, ts.erp.p, ts.ecol.p, ev, iv, cnt, (const TR_*)RHS_, out, ext, RESET_, abort_flag, \
+                       lim, nb, ld, nnode);                                                                        \
   } while (0)
 #define GMG_TREE_RHS(TR_, RHS_, RESET_)                \
   do {                                                 \
@@ -236,8 +254,10 @@ void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, 
 #undef GMG_TREE
   HIPCK(hipGetLastError());
 }
-template void launch_tree<double>(const TreeSolve&, const void*, bool, double*, double*, double*, int*, hipStream_t);
-template void launch_tree<float>(const TreeSolve&, const void*, bool, float*, float*, float*, int*, hipStream_t);
+template void launch_tree<double>(const TreeSolve&, const void*, bool, double*, double*, double*, int*, hipStream_t,
+                                  int, size_t, int*);
+template void launch_tree<float>(const TreeSolve&, const void*, bool, float*, float*, float*, int*, hipStream_t, int,
+                                 size_t, int*);
 
 // ---------------------------------------------------------------- setup
 // Inverse of a node's diagonal block T (unit diagonal, or diagonal 1/dinv):

@@ -112,11 +112,17 @@ __device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_
 // neighbour); UP_FIRST: the neighbour below has the smaller original column
 // (lower factors), else the left one (upper factors).  REV: the right-hand
 // side is read at total - 1 - p.
+//
+// nb > 1 sweeps nb right-hand sides in one launch: workgroup w * nb + r runs
+// band w of column r, whose right-hand side and output are the position
+// layouts at rhs + r * total and out + r * total.  A band waits only on the
+// band before it in the same column, which has the lower workgroup index, so
+// the launch drains as with one column.
 template <class T, bool DIAG, bool UP_FIRST, bool REV>
 __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t total,
                                                        const typename Pair<T>::type* __restrict__ coef,
                                                        const T* __restrict__ dinv, const T* __restrict__ rhs, T* out,
-                                                       int* abort_flag, uint64_t limit) {
+                                                       int* abort_flag, uint64_t limit, int nb) {
   using P2 = typename Pair<T>::type;
   __shared__ WaveOp<T> r_op[WAVE_RING][64];
   __shared__ T r_x[WAVE_XRING];              // previous band's boundary values
@@ -125,7 +131,12 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
   __shared__ int consumed;                  // steps finished by the consumer
   // the role is the same for the whole wave: taken from lane 0 so the role
   // branches are scalar and no role's pending loads reach another's code
-  const int w = blockIdx.x, l = threadIdx.x & 63, role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = blockIdx.x / nb, l = threadIdx.x & 63, role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  {
+    const int col = blockIdx.x - w * nb;
+    rhs += (int64_t)col * total;
+    out += (int64_t)col * total;
+  }
   const int64_t p0 = (int64_t)w * S * 64 + l;
   const int nchunks = S / WAVE_CH;
   if (threadIdx.x < WAVE_PRODUCERS) produced[threadIdx.x] = 0;
@@ -313,8 +324,12 @@ __device__ __forceinline__ int wave_cell(int64_t q, int S, int nx, int ny) {
   return (i >= 0 && i < nx && j < ny) ? j * nx + i : -1;
 }
 
+// column blockIdx.y: z + col * ldz (cell order) -> zs + col * total
 template <class T, class TR>
-__global__ void k_wave_gather(int64_t total, int S, int nx, int ny, const TR* __restrict__ z, T* __restrict__ zs) {
+__global__ void k_wave_gather(int64_t total, int S, int nx, int ny, const TR* __restrict__ z, T* __restrict__ zs,
+                              size_t ldz) {
+  z += blockIdx.y * ldz;
+  zs += blockIdx.y * total;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
     const int c = wave_cell(p, S, nx, ny);
     zs[p] = c >= 0 ? (T)z[c] : (T)0;
@@ -326,7 +341,10 @@ __global__ void k_wave_gather(int64_t total, int S, int nx, int ny, const TR* __
 // pair of sweeps
 template <class T>
 __global__ void k_wave_scatter(int64_t total, int S, int nx, int ny, T* __restrict__ ts, T* __restrict__ ys,
-                               T* __restrict__ t) {
+                               T* __restrict__ t, size_t ldt) {
+  ts += blockIdx.y * total;
+  ys += blockIdx.y * total;
+  t += blockIdx.y * ldt;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
     const int c = wave_cell(total - 1 - p, S, nx, ny);
     if (c >= 0) t[c] = ts[p];
@@ -351,40 +369,42 @@ static uint64_t wave_limit_ticks() {
 
 template <class T>
 void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& up, const void* z, bool z_f64, T* zs,
-                      T* ys, T* ts, T* t, int* abort_flag, hipStream_t s) {
+                      T* ys, T* ts, T* t, int* abort_flag, hipStream_t s, int nb, size_t ldz, size_t ldt) {
   constexpr bool F32 = sizeof(T) == 4;
   using P2 = typename Pair<T>::type;
   if (g.S % (2 * WAVE_CH) != 0) fail(GMG_ERR_INVALID_ARG, "wavefront layout: steps not a multiple of two chunks");
+  if (nb < 1 || nb > 65535) fail(GMG_ERR_INVALID_ARG, "wavefront sweep: bad column count");
   const unsigned gb = (unsigned)std::min<int64_t>(4096, (g.total + 255) / 256);
   if (z_f64)
-    hipLaunchKernelGGL((k_wave_gather<T, double>), dim3(gb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny,
-                       (const double*)z, zs);
+    hipLaunchKernelGGL((k_wave_gather<T, double>), dim3(gb, nb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny,
+                       (const double*)z, zs, ldz);
   else
-    hipLaunchKernelGGL((k_wave_gather<T, T>), dim3(gb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, (const T*)z, zs);
+    hipLaunchKernelGGL((k_wave_gather<T, T>), dim3(gb, nb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, (const T*)z,
+                       zs, ldz);
   const uint64_t lim = wave_limit_ticks();
   auto co = [&](const WaveSweep& f) { return F32 ? (const P2*)f.coef32.p : (const P2*)f.coef.p; };
   auto di = [&](const WaveSweep& f) { return F32 ? (const T*)f.dinv32.p : (const T*)f.dinv.p; };
   // lower factor: neighbour below first; upper factor: left neighbour first,
   // right-hand side = the lower sweep's output read backwards
-  const dim3 blk(WAVE_THREADS);
+  const dim3 blk(WAVE_THREADS), grid((unsigned)(g.W * nb));
   if (lo.has_diag)
-    hipLaunchKernelGGL((k_wave<T, true, true, false>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
-                       ys, abort_flag, lim);
+    hipLaunchKernelGGL((k_wave<T, true, true, false>), grid, blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
+                       ys, abort_flag, lim, nb);
   else
-    hipLaunchKernelGGL((k_wave<T, false, true, false>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
-                       ys, abort_flag, lim);
+    hipLaunchKernelGGL((k_wave<T, false, true, false>), grid, blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
+                       ys, abort_flag, lim, nb);
   if (up.has_diag)
-    hipLaunchKernelGGL((k_wave<T, true, false, true>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
-                       ts, abort_flag, lim);
+    hipLaunchKernelGGL((k_wave<T, true, false, true>), grid, blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
+                       ts, abort_flag, lim, nb);
   else
-    hipLaunchKernelGGL((k_wave<T, false, false, true>), dim3(g.W), blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
-                       ts, abort_flag, lim);
-  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, ts, ys, t);
+    hipLaunchKernelGGL((k_wave<T, false, false, true>), grid, blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
+                       ts, abort_flag, lim, nb);
+  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gb, nb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, ts, ys, t, ldt);
   HIPCK(hipGetLastError());
 }
 template void launch_wave_pair<double>(const WaveGrid&, const WaveSweep&, const WaveSweep&, const void*, bool,
-                                       double*, double*, double*, double*, int*, hipStream_t);
+                                       double*, double*, double*, double*, int*, hipStream_t, int, size_t, size_t);
 template void launch_wave_pair<float>(const WaveGrid&, const WaveSweep&, const WaveSweep&, const void*, bool,
-                                      float*, float*, float*, float*, int*, hipStream_t);
+                                      float*, float*, float*, float*, int*, hipStream_t, int, size_t, size_t);
 
 }  // namespace gmg

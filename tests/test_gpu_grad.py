@@ -79,30 +79,28 @@ def test_pattern_gradient_matches_dense():
     assert np.abs(val.grad.cpu().numpy() - ref).max() <= 1e-6 * np.abs(ref).max()
 
 
-def test_gradients_match_central_fd_512():
-    """The 512x512 workload with 16 RHS: dL/dkappa on 32 seeded cells against
-    Richardson-extrapolated central differences, the perturbed systems solved
-    directly (sparse LU on the host)."""
-    _say("[case] fd 512x512")
+@pytest.fixture(scope="module")
+def fd512():
+    """Central-difference reference on the 512x512 workload with 16 RHS, the
+    perturbed systems solved directly (sparse LU on the host), contracted
+    with the exact dL/dX = 2 (X - X_t) at the base point; Richardson
+    extrapolation of steps d and 2d (d = 1e-3 kappa_c) removes the O(d^2)
+    term while keeping the rounding noise of the two solves small against the
+    difference.  32 seeded cells, and one seeded direction u for the
+    directional derivative d/dh L(kappa * (1 + h u)) at h = 0 (a JVP of the
+    whole solve, contracted with dL/dX)."""
+    import scipy.sparse.linalg as spla
     p = W.make("fv2d_512_grad")
     n, dim = 512, 2
-    vt = AG.face_velocities(n, dim, p.velocity)
-    kap = torch.as_tensor(p.kappa, device="cuda").requires_grad_(True)
-    B = torch.as_tensor(p.b, device="cuda")
-    Xt = torch.as_tensor(p.x_target, device="cuda")
-    t0 = time.time()
-    X = AG.fv_solve(kap, B, n, dim, vt, tol=1e-11, ilut_tau=1e-6, restart=300, maxit=600)
-    loss = ((X - Xt) ** 2).sum()
-    loss.backward()
-    g = kap.grad.cpu().numpy()
-    _say(f"  gpu forward+backward {time.time() - t0:.1f}s")
-    cells = np.random.default_rng(7).choice(n * n, 32, replace=False)
-    # central differences of X (direct sparse solves), contracted with the
-    # exact dL/dX = 2 (X - X_t) at the base point
+
     def direct(Am):
         return spla.splu(sp.csc_matrix(Am)).solve(p.b)
-    A0 = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(n * n, n * n))
-    X0 = direct(A0)
+
+    def solve_at(kp):
+        rp, ci, va = W.fv_matrix(n, dim, kp, p.velocity)
+        return direct(sp.csr_matrix((va, ci, rp), shape=(n * n, n * n)))
+
+    X0 = solve_at(p.kappa)
     dLdX = 2.0 * (X0 - p.x_target)
 
     def central(c, d):
@@ -110,14 +108,10 @@ def test_gradients_match_central_fd_512():
         for sgn in (1, -1):
             kp = p.kappa.copy()
             kp[c] += sgn * d
-            rp, ci, va = W.fv_matrix(n, dim, kp, p.velocity)
-            Xs.append(direct(sp.csr_matrix((va, ci, rp), shape=(n * n, n * n))))
+            Xs.append(solve_at(kp))
         return np.sum(dLdX * (Xs[0] - Xs[1])) / (2 * d)
 
-    # central differences of X (direct sparse solves), contracted with the
-    # exact dL/dX = 2 (X - X_t); Richardson extrapolation of steps d and 2d
-    # (d = 1e-3 kappa_c) removes the O(d^2) term while keeping the rounding
-    # noise of the two solves small against the difference
+    cells = np.random.default_rng(7).choice(n * n, 32, replace=False)
     fd = np.empty(32)
     t0 = time.time()
     for i, c in enumerate(cells):
@@ -125,6 +119,58 @@ def test_gradients_match_central_fd_512():
         fd[i] = (4.0 * central(c, d) - central(c, 2 * d)) / 3.0
         if i % 8 == 7:
             _say(f"  fd {i + 1}/32 ({time.time() - t0:.0f}s)")
+    u = np.random.default_rng(8).uniform(-1.0, 1.0, n * n)
+
+    def along(h):
+        return np.sum(dLdX * (solve_at(p.kappa * (1 + h * u)) - solve_at(p.kappa * (1 - h * u)))) / (2 * h)
+
+    h = 1e-3
+    dirfd = (4.0 * along(h) - along(2 * h)) / 3.0
+    _say(f"  fd reference done ({time.time() - t0:.0f}s)")
+    return p, cells, fd, u, dirfd
+
+
+def _grad512(p, **opts):
+    n, dim = 512, 2
+    vt = AG.face_velocities(n, dim, p.velocity)
+    kap = torch.as_tensor(p.kappa, device="cuda").requires_grad_(True)
+    B = torch.as_tensor(p.b, device="cuda")
+    Xt = torch.as_tensor(p.x_target, device="cuda")
+    t0 = time.time()
+    X = AG.fv_solve(kap, B, n, dim, vt, tol=1e-11, ilut_tau=1e-6, maxit=600, **opts)
+    loss = ((X - Xt) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    _say(f"  gpu forward+backward {time.time() - t0:.2f}s ({opts})")
+    return kap.grad.cpu().numpy()
+
+
+def _check_cells(g, cells, fd):
     ref = np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
     err = np.abs(g[cells] - fd) / ref
+    _say(f"  max relative error on 32 cells {err.max():.2e}")
     assert err.max() <= 1e-6, err.max()
+
+
+def test_gradients_match_central_fd_512(fd512):
+    """The 512x512 workload with 16 RHS solved one column after another
+    (unrestarted FGMRES): dL/dkappa on 32 seeded cells against the
+    central-difference reference."""
+    _say("[case] fd 512x512, column loop")
+    p, cells, fd, u, dirfd = fd512
+    _check_cells(_grad512(p, restart=300), cells, fd)
+
+
+def test_gradients_batched_fgmres30_512(fd512):
+    """The differentiable configuration as specified: 16 RHS batched through
+    FGMRES(30) forward and adjoint (the batched path), dL/dkappa on the 32
+    cells and the directional derivative along a random direction (every
+    cell at once) against central differences, both within 1e-6."""
+    _say("[case] fd 512x512, batched FGMRES(30)")
+    p, cells, fd, u, dirfd = fd512
+    g = _grad512(p, restart=30)
+    _check_cells(g, cells, fd)
+    dirg = float(np.sum(g * p.kappa * u))
+    _say(f"  directional derivative {dirg:.10e} vs fd {dirfd:.10e}")
+    assert abs(dirg - dirfd) <= 1e-6 * abs(dirfd), (dirg, dirfd)
+
