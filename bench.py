@@ -112,35 +112,204 @@ def _alg_bytes_doc():
             "8*N*(3k-k_last+4*blocks)+8*k^2 beyond 384 (the projection over blocks of 384)")
 
 
-def run_cpu_baseline(p, gpu_steps, budget_s=30.0):
-    """The oracle, as it stands, on this host: its setup, then two bounded runs
-    of k1 < k2 FGMRES steps; without restarts a step's cost grows linearly with
-    the basis size, so t(k) = a k + b k^2 / 2 is fitted to the two runs and
-    evaluated at the GPU's step count."""
+def run_cpu_baseline(p):
+    """The oracle, as it stands, on this host: one full setup + solve to the
+    same tolerance with the benchmark's settings (single-threaded FP64)."""
     import oracle
     oracle.build()
     t0 = time.perf_counter()
     O = oracle.Oracle(p.rowptr, p.col, p.val, cf=SOLVE_OPTS["cf"], ilut_tau=SOLVE_OPTS["ilut_tau"])
     t_setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    _, info = O.solve(p.b[:, 0], tol=TOL, maxit=SOLVE_OPTS["maxit"], restart=SOLVE_OPTS["restart"])
+    t_solve = time.perf_counter() - t1
+    return dict(t_setup=t_setup, t_solve=t_solve, steps=info.steps, relres=info.relres, status=info.status)
 
-    def run(k):
-        t = time.perf_counter()
-        O.solve(p.b[:, 0], tol=0.0, maxit=k, restart=SOLVE_OPTS["restart"])
-        return time.perf_counter() - t
 
-    k1 = 4
-    t1 = run(k1)
-    per = t1 / k1
-    # the step cost grows with the basis: aim the second run at about a third
-    # of the remaining budget at the initial step cost, and at most 120 steps
-    k2 = int(max(2 * k1, min(gpu_steps, 120, (budget_s - t_setup - t1) / max(per, 1e-9) / 3.0)))
-    t2 = run(k2)
-    # t = a k + b k^2 / 2 through (k1, t1), (k2, t2)
-    b = 2.0 * (t2 / k2 - t1 / k1) / (k2 - k1)
-    a = t1 / k1 - b * k1 / 2.0
-    b = max(b, 0.0)
-    est = t_setup + a * gpu_steps + b * gpu_steps ** 2 / 2.0
-    return dict(t_setup=t_setup, k1=k1, t1=t1, k2=k2, t2=t2, est=est)
+# --------------------------------------------------------------- configs
+# The other workloads of the benchmark's configuration list, each measured in
+# the default run beside the headline (settings as their full-size tests).
+CONFIG_OPTS = {
+    "fv2d_64": dict(cf=4.0, ilut_tau=1e-4, restart=30, maxit=600),
+    "fv3d_128": dict(cf=4.0, ilut_tau=1e-5, restart=600, maxit=600),
+    "rgg_500k": dict(cf=4.0, ilut_tau=1e-4, restart=30, maxit=600),
+}
+# the differentiable configuration: FGMRES(30), ILUT 1e-6 (GMRES(30) with
+# ILUT 1e-4 needs ~580 steps per column to reach the gradients' tolerance),
+# forward and adjoint to 1e-11 for gradients good to 1e-6
+GRAD_OPTS = dict(cf=4.0, ilut_tau=1e-6, restart=30, maxit=600)
+GRAD_TOL = 1e-11
+# measured per-step latencies of the triangular sweeps on this GPU: a
+# published value polled across CUs (agent scope), and one step of the
+# wavefront kernel (a wave walking 64 grid rows)
+HOP_US = 0.55
+WAVE_STEP_US = 0.072
+
+
+def _sync_time(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def _roofline_of(prof):
+    dom = max(prof.items(), key=lambda kv: kv[1]["ms"])[0]
+    d = prof[dom]
+    ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    return dict(bound="hbm", kernel=dom, achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 5), traffic=None,
+                avg_launch_us=round(d["ms"] / d["launches"] * 1e3, 3),
+                bytes_per_launch=round(d["bytes"] / d["launches"]))
+
+
+def _kernels_of(prof, setup_info, grid2d):
+    """Per-class time and rate; for the sweeps also the latency floor of
+    their dependency chains (levels x measured step or hop)."""
+    out = {}
+    for name, a in prof.items():
+        if a["launches"] == 0:
+            continue
+        e = dict(launches=a["launches"], total_ms=round(a["ms"], 4), avg_us=round(a["ms"] / a["launches"] * 1e3, 3),
+                 gbs=round(a["bytes"] / (a["ms"] * 1e-3) / 1e9, 2) if a["ms"] > 0 else None)
+        if name == "sweep_fine":
+            lv = setup_info["levels_L0"] + setup_info["levels_U0"]
+            per = WAVE_STEP_US if grid2d else HOP_US
+            e.update(levels=lv, latency_floor_us=round(lv * per, 2),
+                     floor="levels x %s" % ("wavefront step 0.072 us" if grid2d else "agent-scope hop 0.55 us"))
+        if name == "sweep_coarse":
+            lv = setup_info["levels_Lc"] + setup_info["levels_Uc"]
+            e.update(levels=lv, latency_floor_us=round(lv * 2 * HOP_US, 2),
+                     floor="tree levels x 2 hops (helper, slice) x 0.55 us")
+        out[name] = e
+    return out
+
+
+def measure_config(torch, W, Solver, name, seed=0, fp32=True):
+    """Setup + solve of one workload: a warm-up, a timed FP64 run, a profiled
+    FP64 run (per-class breakdown, roofline of the dominant class) and, with
+    fp32, a timed run with the FP32 V-cycle and its distance to FP64."""
+    import numpy as np
+    import scipy.sparse as sp
+    o = CONFIG_OPTS[name]
+    p = W.make(name, seed=seed)
+    dev = "cuda"
+    rp, ci, va = (torch.as_tensor(a, device=dev) for a in (p.rowptr, p.col, p.val))
+    b = torch.as_tensor(p.b[:, 0], device=dev)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
+    bn = np.linalg.norm(p.b[:, 0])
+
+    def run(fp, profile=False):
+        S = Solver(rp, ci, va, cf=o["cf"], ilut_tau=o["ilut_tau"])
+        if profile:
+            S.profile(True)
+        x, res = S.solve(b, tol=TOL, restart=o["restart"], maxit=o["maxit"], precond_fp32=int(fp))
+        return S, x, res
+
+    run(False)
+    (S, x, res), t = _sync_time(torch, lambda: run(False))
+    xh = x.cpu().numpy()
+    entry = dict(workload=WORKLOAD_DESC.get(name, name) + f", seed {seed}", options=dict(o, tol=TOL),
+                 time_s=round(t, 6), setup_ms=round(S.setup_info["setup_ms"], 2),
+                 solve_ms=round(res.info["solve_ms"], 2), iters=res.info["iters"], status=int(res.status),
+                 n_coarse=S.setup_info["n_coarse"],
+                 relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xh) / bn))
+    Sp, _, _ = run(False, True)
+    prof = Sp.profile_read()
+    grid2d = name.startswith("fv2d")
+    entry["kernels"] = _kernels_of(prof, Sp.setup_info, grid2d)
+    entry["roofline"] = _roofline_of(prof)
+    if fp32:
+        (S32, x32, r32), t32 = _sync_time(torch, lambda: run(True))
+        x32h = x32.cpu().numpy()
+        entry["fp32_precond"] = dict(
+            time_s=round(t32, 6), iters=r32.info["iters"], status=int(r32.status),
+            solve_ms=round(r32.info["solve_ms"], 2),
+            relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ x32h) / bn),
+            rel_diff_vs_fp64=float(np.linalg.norm(x32h - xh) / np.linalg.norm(xh)))
+    print(f"[bench] {name} seed {seed}: {t:.3f}s its={res.info['iters']}"
+          + (f"; fp32 {entry['fp32_precond']['time_s']:.3f}s" if fp32 else ""), file=sys.stderr, flush=True)
+    return entry
+
+
+def measure_grad(torch, W):
+    """The differentiable configuration: A(kappa) assembled on the GPU, 16
+    right-hand sides solved forward, the adjoint solved for the loss
+    ||X - X_t||^2, and dL/dkappa formed; batched (every launch shared by the
+    16 columns) against the same work one column after another."""
+    import numpy as np
+    from paper_1105_3468_amd import autograd as AG
+    p = W.make("fv2d_512_grad")
+    n, dim = 512, 2
+    vt = AG.face_velocities(n, dim, p.velocity)
+    B = torch.as_tensor(p.b, device="cuda")
+    Xt = torch.as_tensor(p.x_target, device="cuda")
+
+    def fwd_bwd():
+        kap = torch.as_tensor(p.kappa, device="cuda").requires_grad_(True)
+        X = AG.fv_solve(kap, B, n, dim, vt, tol=GRAD_TOL, **GRAD_OPTS)
+        loss = ((X - Xt) ** 2).sum()
+        loss.backward()
+        return kap.grad
+
+    res = dict(workload="fv2d_512_grad: 512x512 cells (262,144 unknowns), kappa per cell from the 8x8-block law "
+                        "log-uniform in [1e-3,1e3], a=(1,0.5), 16 RHS and x_target U(-1,1), seed 0; "
+                        "loss ||X - X_t||^2; forward + adjoint solves + dL/dkappa",
+               options=dict(GRAD_OPTS, tol=GRAD_TOL))
+    grads = {}
+    for key, loop in (("batched", "0"), ("column_loop", "1")):
+        os.environ["GMG_COLUMN_LOOP"] = loop
+        fwd_bwd()
+        g, t = _sync_time(torch, fwd_bwd)
+        grads[key] = g.cpu().numpy()
+        res[key] = dict(time_s=round(t, 6))
+        print(f"[bench] gradient config {key}: {t:.3f}s", file=sys.stderr, flush=True)
+    os.environ["GMG_COLUMN_LOOP"] = "0"
+    res["speedup_batched"] = round(res["column_loop"]["time_s"] / res["batched"]["time_s"], 3)
+    res["grad_rel_diff_batched_vs_loop"] = float(np.linalg.norm(grads["batched"] - grads["column_loop"])
+                                                 / np.linalg.norm(grads["column_loop"]))
+    # the forward solve's kernels, batched, for the SpMM rate
+    from paper_1105_3468_amd import Solver
+    from paper_1105_3468_amd import gmg as G
+    rp, ci, va = G.fv_assemble(n, dim, torch.as_tensor(p.kappa, device="cuda"), vt)
+    S = Solver(rp, ci, va, cf=GRAD_OPTS["cf"], ilut_tau=GRAD_OPTS["ilut_tau"])
+    S.profile(True)
+    _, r = S.solve(B, tol=GRAD_TOL, restart=GRAD_OPTS["restart"], maxit=GRAD_OPTS["maxit"])
+    prof = S.profile_read()
+    res["forward_iters_sum"] = r.info["iters"]
+    res["forward_kernels"] = _kernels_of(prof, S.setup_info, True)
+    res["roofline"] = _roofline_of(prof)
+    return res
+
+
+def cold_spmv(torch, S, n, nnz, reps=10):
+    """SpMV with the 256 MB last-level cache (MALL) flushed before every
+    launch by a 1 GiB write, timed by the library's own events around the
+    kernel on the solver's stream; beside it the same launches back to back
+    (the matrix partly resident in the MALL)."""
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    junk = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    S.profile(True, classes=["spmv"])
+    for r in range(reps):
+        junk.fill_(float(r))
+        torch.cuda.synchronize()
+        S.spmv(x)
+    cold = S.profile_read()["spmv"]
+    S.profile(True, classes=["spmv"])
+    for r in range(reps):
+        S.spmv(x)
+    warm = S.profile_read()["spmv"]
+    S.profile(False)
+    del junk
+    byt = 12 * nnz + 20 * n
+    out = {}
+    for key, d in (("cold", cold), ("warm", warm)):
+        us = d["ms"] / d["launches"] * 1e3
+        out[key] = dict(avg_us=round(us, 3), gbs=round(byt / (us * 1e-6) / 1e9, 2))
+    out["reps"] = reps
+    out["note"] = "cold: each launch after a 1 GiB fill that evicts the 256 MB MALL; warm: back to back"
+    return out
 
 
 def main():
@@ -167,6 +336,11 @@ def main():
     ap.add_argument("--paper-curve", action="store_true",
                     help="also run Figure F:curveJUMP's case (DC3D 50^3, GMRES(30), exact and ILUT(1e-4) coarse "
                          "solves): time, steps and residual history of each")
+    ap.add_argument("--restarts", default="",
+                    help="comma-separated FGMRES restart lengths to time on the headline workload beside the "
+                         "unrestarted metric (same ILUT and tolerance)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the other configurations (3D, random graphs x4 seeds, gradients, 64^2)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     global SOLVE_OPTS
@@ -298,14 +472,19 @@ def main():
         out["spmv_gbs"] = round(spmv["bytes"] / (spmv["ms"] * 1e-3) / 1e9, 2)
 
     if not args.no_fp32:
+        # the same steps as the metric, unprofiled, then one profiled step
+        one_step(True, False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        S32, x32, r32, pr32 = one_step(True, True)
+        for _ in range(args.steps):
+            S32, x32, r32, _ = one_step(True, False)
         torch.cuda.synchronize()
-        t32 = time.perf_counter() - t0
+        t32 = (time.perf_counter() - t0) / args.steps
+        _, _, _, pr32 = one_step(True, True)
         x32h = x32.cpu().numpy()
         out["fp32_precond"] = dict(
-            time_s=round(t32, 6), iters=r32.info["iters"], solve_ms=round(r32.info["solve_ms"], 2),
+            time_s=round(t32, 6), steps=args.steps, iters=r32.info["iters"],
+            setup_ms=round(S32.setup_info["setup_ms"], 2), solve_ms=round(r32.info["solve_ms"], 2),
             relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ x32h) / np.linalg.norm(p.b[:, 0])),
             rel_diff_vs_fp64=float(np.linalg.norm(x32h - xh) / np.linalg.norm(xh)),
             kernels={k: dict(launches=v["launches"], total_ms=round(v["ms"], 4)) for k, v in pr32.items()
@@ -457,6 +636,25 @@ def main():
                      if v["launches"]})
         print(f"[bench] multicolour smoother step: {tm:.3f}s its={rm.info['iters']}", file=sys.stderr, flush=True)
 
+    if args.restarts:
+        # the same solve with restarts: shorter bases cost fewer bytes per
+        # step but need more steps
+        rs = {}
+        for m in [int(t) for t in args.restarts.split(",") if t]:
+            def rstep():
+                Sr = Solver(rp, ci, va, cf=SOLVE_OPTS["cf"], ilut_tau=SOLVE_OPTS["ilut_tau"])
+                xr, rr = Sr.solve(b, tol=TOL, restart=m, maxit=SOLVE_OPTS["maxit"])
+                return Sr, xr, rr
+            rstep()
+            (Sr, xr, rr), tr = _sync_time(torch, rstep)
+            rs[str(m)] = dict(time_s=round(tr, 6), solve_ms=round(rr.info["solve_ms"], 2), iters=rr.info["iters"],
+                              restarts=rr.info["restarts"], status=int(rr.status),
+                              relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xr.cpu().numpy())
+                                                      / np.linalg.norm(p.b[:, 0])))
+            print(f"[bench] FGMRES({m}): {tr:.3f}s its={rr.info['iters']} status={rr.status}", file=sys.stderr,
+                  flush=True)
+        out["restart_lengths"] = rs
+
     if args.paper_curve:
         # Figure F:curveJUMP: residual histories of the exact and the inexact
         # coarse solve on DC3D 50^3 (GMRES(30), cf = 4), one warm and one
@@ -466,7 +664,7 @@ def main():
         Ac = sp.csr_matrix((pc.val, pc.col, pc.rowptr), shape=(pc.n_rows, pc.n_rows))
         curve = dict(workload="DC3D (DC1 3D of Section 3.1) 50^3 cells, kappa jumps 1e3, zero velocity, "
                               "GMRES(30), cf 4, tol 1e-8, seed 0")
-        for key, tau in (("exact", 0.0), ("ilut_1e-4", 1e-4)):
+        for key, tau in (("exact", 0.0), ("ilut_1e-4", 1e-4), ("ilut_1e-6", 1e-6)):
             def cstep():
                 Sc = Solver(pc.rowptr, pc.col, pc.val, cf=4.0, ilut_tau=tau)
                 xc, rc_ = Sc.solve(bc, tol=TOL, restart=30, maxit=600)
@@ -487,15 +685,25 @@ def main():
                   flush=True)
         out["paper_curve_dc3d_50"] = curve
 
+    # the SpMV with a cold last-level cache, beside its in-solve rate
+    out["spmv_cold"] = cold_spmv(torch, S, p.n_rows, p.nnz)
+
+    if args.workload == "fv2d_1024" and not args.headline_only:
+        configs = {}
+        configs["fv2d_64"] = measure_config(torch, W, Solver, "fv2d_64", fp32=True)
+        configs["fv3d_128"] = measure_config(torch, W, Solver, "fv3d_128", fp32=True)
+        configs["rgg_500k"] = [measure_config(torch, W, Solver, "rgg_500k", seed=sd, fp32=True) for sd in range(4)]
+        configs["fv2d_512_grad"] = measure_grad(torch, W)
+        out["configs"] = configs
+
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        gpu_steps = infos[-1]["iters"]
-        cb = run_cpu_baseline(p, gpu_steps)
+        print("[bench] cpu baseline (oracle, full run) ...", file=sys.stderr, flush=True)
+        cb = run_cpu_baseline(p)
         out["cpu_baseline"] = dict(
-            value=round(cb["est"], 3), unit="s", cores=1, kind="oracle",
-            sample=(f"oracle setup ({cb['t_setup']:.2f}s) plus {cb['k1']} and {cb['k2']} FGMRES steps "
-                    f"({cb['t1']:.2f}s, {cb['t2']:.2f}s) on the same workload and settings; per-step cost "
-                    f"a + b*j fitted to the two runs and summed to the GPU's {gpu_steps} steps"))
+            value=round(cb["t_setup"] + cb["t_solve"], 3), unit="s", cores=1, kind="oracle",
+            sample=(f"one full oracle run on the same workload and settings: setup {cb['t_setup']:.2f}s, "
+                    f"solve {cb['t_solve']:.2f}s, {cb['steps']} FGMRES steps to relres {cb['relres']:.2e} "
+                    f"(single thread, FP64)"))
         print(f"[bench] cpu baseline done: {json.dumps(out['cpu_baseline'])}", file=sys.stderr, flush=True)
 
     print(json.dumps(out))

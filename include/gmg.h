@@ -131,29 +131,41 @@ gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowpt
                      const int32_t* col, const double* val, const gmg_options* opts,
                      void* stream);
 
-/* Solve A x = b to ||b - A x|| / ||b|| < tol for each of nrhs columns
- * (device arrays of N*nrhs doubles, row-major).  Uses the options given to
- * gmg_setup, except x0_given/maxit/restart/precond_fp32, taken from `opts`
- * when it is not NULL.  `info` (host, may be NULL) receives statistics. */
+/* Solve phase of Algorithm 1: A x = b to ||b - A x|| / ||b|| < tol for each
+ * of nrhs columns (device arrays of N*nrhs doubles, row-major) by flexible
+ * GMRES preconditioned with B~.  Uses the options given to gmg_setup, except
+ * x0_given/maxit/restart/precond_fp32, taken from `opts` when it is not NULL.
+ * With nrhs > 1 and restart <= 32 the columns are solved in batches of up to
+ * 16 that share every kernel launch (one FGMRES recurrence per column; each
+ * column stops at its own tolerance); otherwise one after another.  `info`
+ * (host, may be NULL) receives statistics, steps summed over the columns.
+ * GMG_NOT_CONVERGED when a column is not at tol after maxit steps (its best
+ * iterate is returned). */
 gmg_status gmg_solve(gmg_handle h, const double* b, double* x, int nrhs, double tol,
                      const gmg_options* opts, gmg_info* info);
 
 /* Adjoint solve A^T lambda = g, preconditioned by B~^{-T} (the exact transpose
- * of the two-grid operator: coarse correction with the transposed ILUT
- * factors, residual with A^T, transposed ILU(0) sweeps).  Requires
- * coarse_mode 0 and FP64. */
+ * of the two-grid operator of Eq. (twogrid): coarse correction with the
+ * transposed ILUT factors, residual with A^T, transposed ILU(0) sweeps).  Not
+ * in the paper: the backward pass of a differentiable solve.  Same layout,
+ * batching and statuses as gmg_solve; requires coarse_mode 0, fine_order 0
+ * and FP64 (else GMG_ERR_INVALID_ARG). */
 gmg_status gmg_solve_adjoint(gmg_handle h, const double* g, double* lambda, int nrhs,
                              double tol, const gmg_options* opts, gmg_info* info);
 
-/* One application q = B~^{-1} z (adjoint: q = B~^{-T} z) of the preconditioner
+/* One application q = B~^{-1} z (adjoint: q = B~^{-T} z) of the two-grid
+ * preconditioner, Algorithm 1 "SOLVE B~q = z" in its one-coarse-solve form
  * (device vectors of N doubles).  precision 0: FP64; 1: FP32 internally. */
 gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int precision,
                              int adjoint);
 
-/* y = A x (transposed != 0: y = A^T x), device vectors of N doubles. */
+/* y = A x (transposed != 0: y = A^T x), device vectors of N doubles: the
+ * product with the system matrix that every Arnoldi step of Algorithm 1 takes
+ * (w = A z_j), with the library's copy of A. */
 gmg_status gmg_spmv(gmg_handle h, int transposed, const double* x, double* y);
 
-/* Setup statistics (sizes, passes, levels, setup time) into *info (host). */
+/* Setup statistics (sizes, passes, levels, setup time) into *info (host).
+ * Not a step of the paper: inspection of the setup phase. */
 gmg_status gmg_get_info(gmg_handle h, gmg_info* info);
 
 /* Residual history of the last gmg_solve / gmg_solve_adjoint on h: the
@@ -172,17 +184,24 @@ gmg_status gmg_get_history(gmg_handle h, int cap, double* hist, int* count);
  * denominator gives +inf.  GMG_ERR_INVALID_ARG under coarse_mode 2 or 3. */
 gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut);
 
-/* Aggregate of every fine unknown: agg device int32[N]; ids 0..N_c-1 ordered
- * by each aggregate's smallest fine index. */
+/* Aggregate of every fine unknown (the sets G_i of Eq. (aggr), column i of
+ * the boolean P of Eq. (interp)): agg device int32[N], ids 0..N_c-1 in the
+ * numbering of the coarse unknowns: nested dissection of A_c's graph under
+ * coarse_order 1 (the default), by each aggregate's smallest fine index
+ * under coarse_order 0. */
 gmg_status gmg_get_aggregates(gmg_handle h, int32_t* agg);
 
-/* A_c as CSR into device arrays rowptr[N_c+1], col[nnz_coarse], val[nnz_coarse]. */
+/* The Galerkin coarse matrix A_c = P^T A P of Eq. (E:galerkin) as CSR, rows
+ * and columns in the coarse numbering of gmg_get_aggregates, into device
+ * arrays rowptr[N_c+1], col[nnz_coarse], val[nnz_coarse] (sizes from
+ * gmg_get_info; structural zeros kept). */
 gmg_status gmg_get_coarse(gmg_handle h, int32_t* rowptr, int32_t* col, double* val);
 
-/* ILU(0) factors as values on the pattern of the smoother's matrix (device
- * double[nnz]): A's pattern, or under fine_order 1 that of Q A Q^T (row k is
- * row perm[k] of A, columns renumbered and ascending).  The strictly lower
- * part is L0 (unit diagonal implied), the rest is U0. */
+/* The smoother S = L0 U0 = ILU(0) (Section 2, the paragraph defining S;
+ * Algorithm 1's setup) as values on the pattern of the smoother's matrix
+ * (device double[nnz]): A's pattern, or under fine_order 1 or 2 that of
+ * Q A Q^T (row k is row perm[k] of A, columns renumbered and ascending).
+ * The strictly lower part is L0 (unit diagonal implied), the rest is U0. */
 gmg_status gmg_get_ilu0(gmg_handle h, double* val);
 
 /* The smoother's numbering: perm (device int32[N]) with position k holding
@@ -203,15 +222,19 @@ gmg_status gmg_get_spai(gmg_handle h, int32_t* rowptr, int32_t* col, double* val
  * GMG_ERR_INVALID_ARG under another coarse_mode. */
 gmg_status gmg_get_coarse_inverse(gmg_handle h, double* inv);
 
-/* ILUT factors of A_c: L~ strictly lower (unit diagonal implied) and U~ with
- * its diagonal first in each row; device arrays sized by gmg_get_info. */
+/* ILUT(tau) factors of A_c (Section 2, the ILU(t) paragraph; Algorithm 1's
+ * setup of the inexact coarse solve): L~ strictly lower (unit diagonal
+ * implied) and U~ with its diagonal first in each row; device arrays sized by
+ * gmg_get_info (nothing to copy under coarse_mode 2 or 3, which compute no
+ * ILUT: nnz_lc = nnz_uc = 0). */
 gmg_status gmg_get_ilut(gmg_handle h, int32_t* lrowptr, int32_t* lcol, double* lval,
                         int32_t* urowptr, int32_t* ucol, double* uval);
 
-/* Change the stream used by later calls on h. */
+/* Change the stream used by later calls on h (not from the paper). */
 gmg_status gmg_set_stream(gmg_handle h, void* stream);
 
-/* Per-kernel-class timing with HIP events on the handle's stream.
+/* Per-kernel-class timing with HIP events on the handle's stream (not from
+ * the paper: the measurement of this implementation).
  * gmg_profile_enable(h, 1) starts recording every class (resets the
  * counters); enable > 1 records only the classes c whose bit c + 1 is set
  * (each recorded class boundary costs the stream a few microseconds); 0 stops;
@@ -224,10 +247,10 @@ gmg_status gmg_profile_read(gmg_handle h, int cap, int* count, int64_t* launches
                             double* ms, double* bytes);
 const char* gmg_profile_name(int cls);
 
-/* Release everything owned by h (NULL is ignored). */
+/* Release everything owned by h (NULL is ignored; not from the paper). */
 void gmg_destroy(gmg_handle h);
 
-/* Message of the last error on this thread ("" if none). */
+/* Message of the last error on this thread ("" if none; not from the paper). */
 const char* gmg_last_error(void);
 
 /* ---------------------------------------------------------------------------
@@ -268,13 +291,17 @@ gmg_status gmg_fv_assemble_noalloc(int n, int dim, const double* kappa, const do
 
 /* dL/dkappa for L(x(kappa)) given the adjoint lambda = A^{-T} dL/dx and the
  * solution x, nrhs columns (device (N, nrhs) row-major each), summed over the
- * right-hand sides: dL/dkappa_c = -sum_r lambda_r^T (dA/dkappa_c) x_r.
- * grad: device double[N], overwritten. */
+ * right-hand sides: dL/dkappa_c = -sum_r lambda_r^T (dA/dkappa_c) x_r, with
+ * dA/dkappa_c from the discretisation of Eq. (pde) above.  Not in the paper
+ * (the gradient of the differentiable solve).  grad: device double[N],
+ * overwritten. */
 gmg_status gmg_fv_kappa_grad(int n, int dim, const double* kappa, const double* lambda,
                              const double* x, int nrhs, double* grad, void* stream);
 
-/* dL/dA on A's pattern: gval[p] = -sum_r lambda[i(p), r] * x[j(p), r]
- * (device arrays; gval double[nnz], overwritten). */
+/* dL/dA on A's pattern: gval[p] = -sum_r lambda[i(p), r] * x[j(p), r], the
+ * gradient of a loss through x = A^{-1} b restricted to the stored entries
+ * (not in the paper).  Device arrays: rowptr/col of A (n rows), lambda and x
+ * (N, nrhs) row-major, gval double[nnz], overwritten. */
 gmg_status gmg_pattern_grad(int64_t n, const int32_t* rowptr, const int32_t* col,
                             const double* lambda, const double* x, int nrhs, double* gval,
                             void* stream);

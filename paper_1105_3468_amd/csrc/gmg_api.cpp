@@ -56,6 +56,8 @@ struct BatchWork {
   DBuf<float> t32, rc32, yc32, ec32, wz32, wy32, wt32, text32;     // FP32 cycle
   DBuf<int> ncLc, ncUc, ncUct, ncLct;                              // tree node counters per column
   DBuf<double> abc, auc, aec, as, at;                              // adjoint cycle
+  DBuf<double> r;                                                  // fine residuals before the restriction
+  DBuf<float> r32;
   DBuf<double> V, Z, w, x, b, coef;                                // Krylov
 };
 
@@ -126,8 +128,7 @@ struct Solver {
   int log_every = 0;           // GMG_LOG=k prints the residual estimate every k steps
   std::vector<double> hist;    // FGMRES residual estimates of the last solve, per step
   bool force_column_loop = false;  // GMG_COLUMN_LOOP=1: solve several RHS one after another (timing reference)
-  int spmv_g = 0;              // lanes per row of the SpMV (A and A^T have the same average row length)
-  bool fused_rr = false;       // residual + restriction in one kernel (GMG_FUSED_RR=1)
+  int spmv_cap = 4096;         // LDS products per SpMV tile (from A's largest 256-row tile)
   // profiling
   bool prof = false;
   unsigned prof_mask = 0;      // classes that record events (bit c: class c)
@@ -546,6 +547,7 @@ static void build_sweep(Sweep& sw, int n, const std::vector<int>& dep_rp, const 
   level_c0[levels] = (int)chunk.size() / 3;
   level_e0[levels] = (int)rows.size();
   make_segments(sw, level_c0, level_e0, levels, wg_chunks, all_wg);
+  sw.lvl_c0 = level_c0;
   const int ne_rows = (int)rows.size();
   std::vector<int> dp(ne_rows + 1, 0);
   for (int e = 0; e < ne_rows; ++e) dp[e + 1] = dp[e] + dep_rp[rows[e] + 1] - dep_rp[rows[e]];
@@ -735,6 +737,11 @@ static void run_tri(Solver& S, Sweep& sw, const void* rhs, bool rhs_f64, T* out,
     return;
   }
   const T* di = sw.has_diag ? (F32 ? (const T*)sw.dinv32.p : (const T*)sw.dinv.p) : nullptr;
+  if (S.opt.sweep_kernel == 0 && sw.levels <= kLevelLaunchMax && (int)sw.lvl_c0.size() == sw.levels + 1) {
+    // a few wide levels (colour classes): one plain launch per level
+    launch_sweep_levels<T>(sw, F32 ? (const T*)sw.dval32.p : (const T*)sw.dval.p, di, rhs, rhs_f64, out, reset, S.s);
+    return;
+  }
   const int waves = S.opt.sweep_waves > 0 ? S.opt.sweep_waves : sw.waves;
   launch_sweep<T>(sw, F32 ? (const T*)sw.dval32.p : (const T*)sw.dval.p, di, rhs, rhs_f64, out, reset, waves,
                   S.opt.sweep_kernel == 1, S.abort_flag.p, S.s);
@@ -853,8 +860,7 @@ static void coarse_apply(Solver& S, T* rc, T* ec) {
   } else if (S.opt.coarse_mode == 2) {
     // e_c = M r_c with the sparse approximate inverse
     Prof p(S, PC_SWEEP_COARSE, (double)S.dMc.nnz * (4 + sz) + (double)S.nc * (4 + 2 * sz));
-    launch_spmv<T>(S.nc, S.dMc.rp.p, S.dMc.ci.p, F32 ? (const T*)S.dMc.v32.p : (const T*)S.dMc.v.p, rc, ec, s,
-                   spmv_lanes(S.dMc.nnz, S.nc));
+    launch_spmv<T>(S.nc, S.dMc.rp.p, S.dMc.ci.p, F32 ? (const T*)S.dMc.v32.p : (const T*)S.dMc.v.p, rc, ec, s);
   } else {
     if (F32) fail(GMG_ERR_INVALID_ARG, "coarse_mode 1 runs in FP64 only");
     // Jacobi sweeps on each factor: y <- rc - (L~ - I) y from y = rc, then
@@ -892,22 +898,19 @@ static void vcycle(Solver& S, const double* z, double* q) {
   const T* Av = F32 ? (const T*)S.A.v32.p : (const T*)S.A.v.p;
   const size_t sz = sizeof(T);
   smooth_apply<T>(S, z, t);
-  if (S.fused_rr) {
-    // r_c = P^T (z - A t) in one pass: A, t, z and the member lists read
-    // once, no fine residual written
-    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 4 + 8 + sz) +
-                                     (double)S.nc * (4 + 2 * sz));
-    launch_resid_restrict_cols<T>(S.nc, S.aptr.p, S.amem.p, S.A.rp.p, S.A.ci.p, Av, t, 0, z, 0, rc, ec, 0, 1, s);
-  } else {
+  {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * (4 + 8 + 3 * sz + 4) +
                                      (double)S.nc * (4 + 2 * sz));
-    launch_resid_fine<T>(S.n, S.A.rp.p, S.A.ci.p, Av, t, z, r, s, S.spmv_g);
+    launch_resid_fine<T>(S.n, S.A.rp.p, S.A.ci.p, Av, t, z, r, s, S.spmv_cap);
     launch_restrict<T>(S.nc, S.aptr.p, S.amem.p, r, rc, ec, 0, s);
   }
   coarse_apply<T>(S, rc, ec);
   {
-    Prof p(S, PC_PROLONG, (double)S.n * (4 + 2 * sz + 8) + (double)S.nc * sz);
-    launch_prolong<T>(S.n, S.agg.p, t, ec, q, 0, s);
+    // t is polled for (and so reset to the sentinel) only when the level
+    // sweeps produce it; the wavefront and permuted smoothers write it plainly
+    const bool reset_t = !S.wave && !S.fine_nd;
+    Prof p(S, PC_PROLONG, (double)S.n * (4 + (reset_t ? 2 : 1) * sz + 8) + (double)S.nc * sz);
+    launch_prolong<T>(S.n, S.agg.p, t, ec, q, 0, s, reset_t);
   }
 }
 
@@ -1048,14 +1051,14 @@ static void vcycle_adjoint(Solver& S, const double* z, double* q) {
   }
   {
     Prof p(S, PC_PROLONG, (double)S.n * 28 + (double)S.nc * 8);
-    launch_prolong<double>(S.n, S.agg.p, S.at.p, S.aec.p, q, 0, s);
+    launch_prolong<double>(S.n, S.agg.p, S.at.p, S.aec.p, q, 0, s, !S.wave);
   }
 }
 
 static void apply_op(Solver& S, bool adjoint, const double* x, double* y) {
   Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)S.n * 20);
   const DCsr& M = adjoint ? S.AT : S.A;
-  launch_spmv<double>(S.n, M.rp.p, M.ci.p, M.v.p, x, y, S.s, S.spmv_g);
+  launch_spmv<double>(S.n, M.rp.p, M.ci.p, M.v.p, x, y, S.s, S.spmv_cap);
 }
 
 static void ensure_krylov(Solver& S, int m) {
@@ -1121,11 +1124,12 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m + 1), sn(m + 1), g(m + 2), yv(m + 1);
   auto HH = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
   int total = 0;
+  double rate = 1.0;   // last ratio of successive residual estimates
   for (;;) {
     {
       Prof p(S, PC_SPMV, (double)S.nnz * 12 + (double)n * 28);
       const DCsr& M = adjoint ? S.AT : S.A;
-      launch_residual(S.n, M.rp.p, M.ci.p, M.v.p, x, b, w, s, S.spmv_g);
+      launch_residual(S.n, M.rp.p, M.ci.p, M.v.p, x, b, w, s, S.spmv_cap);
     }
     {
       Prof p(S, PC_VECTOR, (double)n * 8);
@@ -1236,7 +1240,9 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       g[j] = cs[j] * g[j];
       ++total;
       k = j + 1;
+      const double prev = out.est;
       out.est = std::fabs(g[j + 1]) / bnorm;
+      if (prev > 0.0 && j > 0) rate = out.est / prev;
       S.hist.push_back(out.est);
       if (S.log_every > 0 && total % S.log_every == 0) {
         std::fprintf(stderr, "[gmg] step %d  estimated relres %.3e\n", total, out.est);
@@ -1244,10 +1250,21 @@ static OneResult fgmres(Solver& S, bool adjoint, int precision, const double* b,
       }
       return out.est < tol || hn == 0.0 || total >= maxit;
     };
+    // Near the end of a cycle (the next step reaches maxit, or at the recent
+    // rate of decrease it reaches tol) step j - 1 is processed before step j
+    // is enqueued, so no step past the last one needed is launched.
     bool ended = false;
     for (int j = 0; j < m && !ended; ++j) {
-      enqueue_step(j);
-      if (j > 0) ended = process_step(j - 1);
+      const bool near_end =
+          j > 0 && (total + 1 >= maxit || (out.est > 0.0 && out.est * std::min(rate, 1.0) < 2.0 * tol));
+      if (near_end) {
+        ended = process_step(j - 1);
+        if (ended) break;
+        enqueue_step(j);
+      } else {
+        enqueue_step(j);
+        if (j > 0) ended = process_step(j - 1);
+      }
     }
     if (!ended) process_step(m - 1);
     check_abort(S);
@@ -1292,6 +1309,7 @@ static void ensure_batch(Solver& S, int nb, int m, bool f32, bool adjoint) {
     B.ldc = ((size_t)std::max(S.nc, 1) + 63) / 64 * 64;
     const size_t nf = B.ld * B.cap, ncv = B.ldc * B.cap;
     B.t.alloc(nf);
+    B.r.alloc(nf);
     B.rc.alloc(ncv);
     B.yc.alloc(ncv);
     B.ec.alloc(ncv);
@@ -1325,6 +1343,7 @@ static void ensure_batch(Solver& S, int nb, int m, bool f32, bool adjoint) {
   if (f32 && !B.f32) {
     const size_t nf = B.ld * B.cap, ncv = B.ldc * B.cap;
     B.t32.alloc(nf);
+    B.r32.alloc(nf);
     B.rc32.alloc(ncv);
     B.yc32.alloc(ncv);
     B.ec32.alloc(ncv);
@@ -1398,10 +1417,15 @@ static void vcycle_batch(Solver& S, const double* z, size_t ldz, double* q, size
     for (int c = 0; c < nb; ++c) smooth_apply<T>(S, z + c * ldz, t + c * ld);
   }
   {
-    // the fused form reads A once for every column and writes no fine residual
-    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * 4 +
-                                     nb * ((double)S.n * (8 + sz) + (double)S.nc * 2 * sz) + (double)S.nc * 4);
-    launch_resid_restrict_cols<T>(S.nc, S.aptr.p, S.amem.p, S.A.rp.p, S.A.ci.p, Av, t, ld, z, ldz, rc, ec, ldc, nb, s);
+    // the residual over the column batch (A read once for every column),
+    // then the restriction; measured faster than one kernel that sums each
+    // aggregate's members' residuals itself (gathers by member are not
+    // coalesced: 306 us against 81 us for 16 columns on 512^2)
+    Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * (4 + sz) + (double)S.n * 8 +
+                                     nb * ((double)S.n * (8 + 3 * sz + 4) + (double)S.nc * 2 * sz));
+    T* r = F32 ? (T*)B.r32.p : (T*)B.r.p;
+    launch_resid_fine_cols<T>(S.n, S.A.rp.p, S.A.ci.p, Av, t, ld, z, ldz, r, ld, nb, s);
+    launch_restrict_cols_t<T>(S.nc, S.aptr.p, S.amem.p, r, ld, rc, ec, ldc, nb, s);
   }
   if (S.opt.coarse_mode == 0 && S.tree) {
     T* ext = F32 ? (T*)B.text32.p : (T*)B.text.p;
@@ -1872,9 +1896,6 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   const int n = (int)n64;
   S.n = n;
   S.nnz = nnz64;
-  S.spmv_g = 0;
-  if (const char* e = std::getenv("GMG_SPMV_LANES")) S.spmv_g = std::atoi(e);   // 0: the LDS-staged form
-  if (const char* e = std::getenv("GMG_FUSED_RR")) S.fused_rr = std::atoi(e) != 0;
   HIPCK(hipHostMalloc(&S.hpin, sizeof(double) * 3 * kPinCol, hipHostMallocDefault));
   for (auto& e : S.colev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   S.abort_flag.alloc(1);
@@ -1983,6 +2004,12 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
   std::vector<int> hci = to_host_int(S.A.ci.p, nnz64, s);
   HIPCK(hipStreamSynchronize(s));
+  {
+    // entries of A's largest 256-row tile: the SpMV's LDS capacity
+    int64_t mt = 0;
+    for (int r0 = 0; r0 < n; r0 += 256) mt = std::max<int64_t>(mt, hrp[std::min(n, r0 + 256)] - hrp[r0]);
+    S.spmv_cap = spmv_cap(mt);
+  }
   // ---- GMG-ND / multicolour: the smoother works on F = Q A Q^T, Q the
   // nested-dissection numbering of A's graph (the coarse numbering's rule) or
   // its colour classes; from here on hrp/hci hold F's pattern
@@ -2065,20 +2092,35 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     }
   }
   phase("fine dependency lists");
-  // ---- ILU(0), one launch per level of L0
+  // 2D-grid structure of both fine factors (their transposes then have it
+  // too: the same offsets, mirrored): wavefront sweeps, and an ILU(0) in one
+  // launch over the grid's anti-diagonals
+  int grid_nx = 0;
+  if ((o.sweep_kernel == 0 || o.sweep_kernel == 3) && !S.fine_nd) {
+    const int nx = grid2d_nx(n, l_rp, l_ci, true);
+    if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx) grid_nx = nx;
+  }
+  // ---- ILU(0)
   S.ilu.alloc(nnz64);
   d2d(S.ilu.p, fval_dev, nnz64, s);
   {
-    std::vector<int> sched, lptr;
-    int levels = 0;
-    make_schedule(l_rp, l_ci, true, sched, lptr, &levels);
-    DBuf<int> dsched, bad;
-    dsched.alloc(sched.size() > 0 ? sched.size() : 1);
+    DBuf<int> bad;
     bad.alloc(1);
-    h2d(dsched.p, sched.data(), sched.size(), s);
     launch_fill_u32(reinterpret_cast<unsigned*>(bad.p), 0u, 1, s);
-    for (int l = 0; l < levels; ++l)
-      launch_ilu0_level(dsched.p + lptr[l], lptr[l + 1] - lptr[l], frp_dev, fci_dev, S.dpos.p, S.ilu.p, bad.p, s);
+    if (grid_nx > 0 && ilu0_grid_fits(grid_nx, n / grid_nx)) {
+      launch_ilu0_grid(n, grid_nx, frp_dev, fci_dev, S.dpos.p, S.ilu.p, bad.p, s);
+    } else {
+      // one launch per level of L0
+      std::vector<int> sched, lptr;
+      int levels = 0;
+      make_schedule(l_rp, l_ci, true, sched, lptr, &levels);
+      DBuf<int> dsched;
+      dsched.alloc(sched.size() > 0 ? sched.size() : 1);
+      h2d(dsched.p, sched.data(), sched.size(), s);
+      for (int l = 0; l < levels; ++l)
+        launch_ilu0_level(dsched.p + lptr[l], lptr[l + 1] - lptr[l], frp_dev, fci_dev, S.dpos.p, S.ilu.p, bad.p, s);
+      HIPCK(hipStreamSynchronize(s));
+    }
     int hb = 0;
     d2h(&hb, bad.p, 1, s);
     HIPCK(hipStreamSynchronize(s));
@@ -2089,13 +2131,12 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   S.u0dinv.alloc(n);
   hipLaunchKernelGGL(k_recip_diag, dim3((n + 255) / 256), dim3(256), 0, s, n, S.ilu.p, S.dpos.p, S.u0dinv.p);
   HIPCK(hipGetLastError());
-  // wavefront form when both fine factors have 2D-grid structure (their
-  // transposes then have it too: the same offsets, mirrored); else the
+  // wavefront form when both fine factors have 2D-grid structure; else the
   // level-scheduled sweeps
   S.wave = false;
-  if ((o.sweep_kernel == 0 || o.sweep_kernel == 3) && !S.fine_nd) {
-    const int nx = grid2d_nx(n, l_rp, l_ci, true);
-    if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx) {
+  if (grid_nx > 0) {
+    const int nx = grid_nx;
+    {
       WaveGrid& g = S.wg;
       g.nx = nx;
       g.ny = n / nx;

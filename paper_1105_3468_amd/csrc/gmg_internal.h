@@ -124,6 +124,7 @@ struct Sweep {
   // dcol[q] when it lies in the same range, else -1 - dcol[q].
   std::vector<int> seg_c0, seg_c1, seg_e0, seg_e1;
   std::vector<char> seg_wg;
+  std::vector<int> lvl_c0;   // first chunk of each dependency level (levels + 1 entries)
   DBuf<int> dslot;
   std::unique_ptr<CuSweep> cu;  // single-CU form, for narrow factors (null otherwise)
 };
@@ -215,28 +216,28 @@ void launch_dense_inverse(int nc, int np, const int* rp, const int* ci, const do
                           hipStream_t s);
 template <class T>
 void launch_dense_gemv(int n, int np, const T* M, const T* r, T* e, hipStream_t s);
-// CSR SpMV y = A x; T = value/vector type.  lanes: lanes per row (4, 8, 16
-// or 32; spmv_lanes picks it from the average row length), 0 = one lane per
-// row with the row's products staged in LDS
-int spmv_lanes(int64_t nnz, int64_t n);
+// CSR SpMV y = A x; T = value/vector type.  cap: products of a 256-row tile
+// staged in LDS (2048 or 4096; spmv_cap picks it from the largest tile, and
+// tiles beyond it are computed from global memory)
+int spmv_cap(int64_t max_tile_nnz);
 template <class T>
 void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y,
-                 hipStream_t s, int lanes = 0);
+                 hipStream_t s, int cap = 4096);
 // r = b - A x  (r may alias nothing); FP64 only
 void launch_residual(int n, const int* rp, const int* ci, const double* v, const double* x,
-                     const double* b, double* r, hipStream_t s, int lanes = 0);
+                     const double* b, double* r, hipStream_t s, int cap = 4096);
 // Fine residual of the smoothed iterate: r[k] = z[k] - (A t)[k]  (Tz = input type)
 template <class T>
 void launch_resid_fine(int n, const int* rp, const int* ci, const T* v, const T* t,
-                       const double* z, T* r, hipStream_t s, int lanes = 0);
+                       const double* z, T* r, hipStream_t s, int cap = 4096);
 // rc[I] = sum_{k in G_I} r[k]; also writes the sentinel into reset[I]
 template <class T>
 void launch_restrict(int nc, const int* aptr, const int* amem, const T* r, T* rc, T* reset,
                      uint64_t sentinel_bits, hipStream_t s);
-// q[k] = t[k] + ec[agg[k]] (q in double); t[k] <- sentinel
+// q[k] = t[k] + ec[agg[k]] (q in double); t[k] <- sentinel when reset_t
 template <class T>
 void launch_prolong(int n, const int* agg, T* t, const T* ec, double* q, uint64_t sentinel_bits,
-                    hipStream_t s);
+                    hipStream_t s, bool reset_t = true);
 // Adjoint helpers
 void launch_restrict_plain(int nc, const int* aptr, const int* amem, const double* z,
                            double* bc, double* reset, uint64_t sentinel_bits, hipStream_t s);
@@ -260,6 +261,12 @@ constexpr int SCAN_BLOCK = 1024;  // elements per block of the exclusive scan
 void set_error_message(const std::string& msg);
 
 // Triangular sweeps (k_sweep.hip)
+// One launch per dependency level (no polling: a level reads earlier levels'
+// results as final values); for factors with a few wide levels.
+constexpr int kLevelLaunchMax = 16;
+template <class T>
+void launch_sweep_levels(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64, T* out,
+                         T* reset_rhs, hipStream_t s);
 template <class T>
 void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64,
                   T* out, T* reset_rhs, int waves, bool whole, int* abort_flag, hipStream_t s);
@@ -268,6 +275,12 @@ constexpr int kSweepLdsRows = 16384;
 template <class T>
 void launch_cu_sweep(CuSweep& cs, const T* wval, const T* dinv_e, const void* rhs, bool rhs_is_f64, T* out,
                      T* reset_rhs, T* rhs_s, T* out_s, hipStream_t s);
+// ILU(0) of a matrix with the 2D-grid structure (offsets -/+1 within grid
+// rows and -/+nx, nx >= 3, ny <= 4096): one launch over the anti-diagonals,
+// bitwise equal to the level-scheduled kernel
+bool ilu0_grid_fits(int nx, int ny);
+void launch_ilu0_grid(int n, int nx, const int* rp, const int* ci, const int* dpos, double* a, int* bad,
+                      hipStream_t s);
 void launch_ilu0_level(const int* rows, int count, const int* rp, const int* ci, const int* dpos,
                        double* a, int* bad, hipStream_t s);
 // yout[i] = (b[i] - sum_{j != i} F_ij yin[j]) * (dinv ? dinv[i] : 1)
@@ -349,11 +362,14 @@ void launch_residual_cols(int n, const int* rp, const int* ci, const double* v, 
 // out_c = z_c - A^T P ec_c (rp/ci/v: A^T as CSR)
 void launch_resid_adj_cols(int n, const int* rp, const int* ci, const double* v, const int* agg, const double* ec,
                            size_t ldc, const double* z, size_t ldz, double* out, size_t ldo, int nb, hipStream_t s);
-// rc_c = P^T (z_c - A t_c), fused; reset_c <- sentinel (reset may be null)
+// r_c = z_c - A t_c (t and r in precision T, z FP64)
 template <class T>
-void launch_resid_restrict_cols(int nc, const int* aptr, const int* amem, const int* rp, const int* ci, const T* v,
-                                const T* t, size_t ldt, const double* z, size_t ldz, T* rc, T* reset, size_t ldc,
-                                int nb, hipStream_t s);
+void launch_resid_fine_cols(int n, const int* rp, const int* ci, const T* v, const T* t, size_t ldt, const double* z,
+                            size_t ldz, T* r, size_t ldr, int nb, hipStream_t s);
+// rc_c = P^T r_c in precision T; reset_c <- sentinel (reset may be null)
+template <class T>
+void launch_restrict_cols_t(int nc, const int* aptr, const int* amem, const T* r, size_t ldr, T* rc, T* reset,
+                            size_t ldc, int nb, hipStream_t s);
 // rc_c = P^T z_c; reset_c <- sentinel (reset may be null)
 void launch_restrict_cols(int nc, const int* aptr, const int* amem, const double* z, size_t ldz, double* rc,
                           double* reset, size_t ldc, int nb, hipStream_t s);

@@ -6,10 +6,7 @@
 //
 //   k_spmm           y_c = A x_c, or y_c = b_c - A x_c (the FGMRES residual),
 //                    or y_c = z_c - A^T P e_c (the adjoint cycle's residual)
-//   k_resid_restrict r_c = P^T (z_c - A t_c) in one pass: no fine residual
-//                    is written (the restriction of Algorithm 1's smoothed
-//                    residual, taken member by member in ascending order)
-//   k_restrict_cols  r_c = P^T z_c
+//   k_restrict_cols  r_c = P^T z_c (members in ascending order)
 //   k_prolong_cols   q_c = t_c + P e_c
 //   k_cols_from_rows / k_rows_from_cols: between the caller's (N, nrhs)
 //                    row-major arrays and the column-major batch
@@ -103,147 +100,51 @@ void launch_resid_adj_cols(int n, const int* rp, const int* ci, const double* v,
   spmm_launch<double, double, 2>(n, rp, ci, v, agg, ec, ldc, z, ldz, out, ldo, nb, s);
 }
 
-// rc_c[I] = sum over the members k of G_I (ascending) of (z_c[k] - (A t_c)[k]),
-// the row's products subtracted in CSR order; reset_c[I] <- sentinel.  One
-// lane per aggregate; the residual never leaves registers.
+// r_c = z_c - A t_c over the column batch (t in the cycle's precision T, z
+// in FP64): the fine residual of the smoothed iterate
 template <class T>
-__global__ __launch_bounds__(256) void k_resid_restrict(int nc, const int* __restrict__ aptr,
-                                                        const int* __restrict__ amem, const int* __restrict__ rp,
-                                                        const int* __restrict__ ci, const T* __restrict__ v,
-                                                        const T* __restrict__ t, size_t ldt,
-                                                        const double* __restrict__ z, size_t ldz,
-                                                        T* __restrict__ rc, T* __restrict__ reset, size_t ldc,
-                                                        int nb) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  T sum[BATCH_MAX];
-#pragma unroll
-  for (int c = 0; c < BATCH_MAX; ++c) sum[c] = (T)0;
-  const int m1 = aptr[I + 1];
-  for (int m = aptr[I]; m < m1; ++m) {
-    const int k = amem[m];
-    T r[BATCH_MAX];
-#pragma unroll
-    for (int c = 0; c < BATCH_MAX; ++c) r[c] = c < nb ? (T)z[c * ldz + k] : (T)0;
-    const int p1 = rp[k + 1];
-    for (int p = rp[k]; p < p1; ++p) {
-      const int j = ci[p];
-      const T a = v[p];
-      T tv[BATCH_MAX];
-#pragma unroll
-      for (int c = 0; c < BATCH_MAX; ++c) tv[c] = c < nb ? t[c * ldt + j] : (T)0;
-#pragma unroll
-      for (int c = 0; c < BATCH_MAX; ++c) r[c] -= a * tv[c];
-    }
-#pragma unroll
-    for (int c = 0; c < BATCH_MAX; ++c) sum[c] += r[c];
-  }
-#pragma unroll
-  for (int c = 0; c < BATCH_MAX; ++c)
-    if (c < nb) {
-      rc[c * ldc + I] = sum[c];
-      if (reset) reset[c * ldc + I] = sentinel_of<T>(0);
-    }
+void launch_resid_fine_cols(int n, const int* rp, const int* ci, const T* v, const T* t, size_t ldt, const double* z,
+                            size_t ldz, T* r, size_t ldr, int nb, hipStream_t s) {
+  spmm_launch<T, double, 1>(n, rp, ci, v, nullptr, t, ldt, z, ldz, r, ldr, nb, s);
 }
-
-// One column: the same sums with the loads of a pair of members issued
-// together (their indices, row bounds, z, then up to RR_E entries of each row
-// and the t values at their columns), so a pair costs a few dependent load
-// rounds instead of one per entry.  Same operation order as k_resid_restrict.
-constexpr int RR_M = 2;   // members per round
-constexpr int RR_E = 8;   // entries per row per round
-
-template <class T>
-__global__ __launch_bounds__(256) void k_resid_restrict1(int nc, const int* __restrict__ aptr,
-                                                         const int* __restrict__ amem, const int* __restrict__ rp,
-                                                         const int* __restrict__ ci, const T* __restrict__ v,
-                                                         const T* __restrict__ t, const double* __restrict__ z,
-                                                         T* __restrict__ rc, T* __restrict__ reset) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  T sum = (T)0;
-  const int m0 = aptr[I], m1 = aptr[I + 1];
-  for (int mb = m0; mb < m1; mb += RR_M) {
-    int k[RR_M], p0[RR_M], p1[RR_M];
-#pragma unroll
-    for (int u = 0; u < RR_M; ++u) k[u] = mb + u < m1 ? amem[mb + u] : -1;
-    T r[RR_M];
-#pragma unroll
-    for (int u = 0; u < RR_M; ++u) {
-      p0[u] = k[u] >= 0 ? rp[k[u]] : 0;
-      p1[u] = k[u] >= 0 ? rp[k[u] + 1] : 0;
-      r[u] = k[u] >= 0 ? (T)z[k[u]] : (T)0;
-    }
-    int c[RR_M][RR_E];
-    T a[RR_M][RR_E], tv[RR_M][RR_E];
-#pragma unroll
-    for (int u = 0; u < RR_M; ++u)
-#pragma unroll
-      for (int e = 0; e < RR_E; ++e) {
-        const int q = p0[u] + e;
-        c[u][e] = q < p1[u] ? ci[q] : -1;
-        a[u][e] = q < p1[u] ? v[q] : (T)0;
-      }
-#pragma unroll
-    for (int u = 0; u < RR_M; ++u)
-#pragma unroll
-      for (int e = 0; e < RR_E; ++e) tv[u][e] = c[u][e] >= 0 ? t[c[u][e]] : (T)0;
-#pragma unroll
-    for (int u = 0; u < RR_M; ++u) {
-#pragma unroll
-      for (int e = 0; e < RR_E; ++e)
-        if (c[u][e] >= 0) r[u] -= a[u][e] * tv[u][e];
-      for (int q = p0[u] + RR_E; q < p1[u]; ++q) r[u] -= v[q] * t[ci[q]];
-    }
-#pragma unroll
-    for (int u = 0; u < RR_M; ++u)
-      if (k[u] >= 0) sum += r[u];
-  }
-  rc[I] = sum;
-  if (reset) reset[I] = sentinel_of<T>(0);
-}
-
-template <class T>
-void launch_resid_restrict_cols(int nc, const int* aptr, const int* amem, const int* rp, const int* ci, const T* v,
-                                const T* t, size_t ldt, const double* z, size_t ldz, T* rc, T* reset, size_t ldc,
-                                int nb, hipStream_t s) {
-  if (nc <= 0) return;
-  if (nb < 1 || nb > BATCH_MAX) fail(GMG_ERR_INVALID_ARG, "resid_restrict: bad column count");
-  if (nb == 1)
-    hipLaunchKernelGGL(k_resid_restrict1<T>, dim3((nc + 255) / 256), dim3(256), 0, s, nc, aptr, amem, rp, ci, v, t, z,
-                       rc, reset);
-  else
-    hipLaunchKernelGGL(k_resid_restrict<T>, dim3((nc + 255) / 256), dim3(256), 0, s, nc, aptr, amem, rp, ci, v, t,
-                       ldt, z, ldz, rc, reset, ldc, nb);
-  HIPCK(hipGetLastError());
-}
-template void launch_resid_restrict_cols<double>(int, const int*, const int*, const int*, const int*, const double*,
-                                                 const double*, size_t, const double*, size_t, double*, double*,
-                                                 size_t, int, hipStream_t);
-template void launch_resid_restrict_cols<float>(int, const int*, const int*, const int*, const int*, const float*,
-                                                const float*, size_t, const double*, size_t, float*, float*, size_t,
-                                                int, hipStream_t);
+template void launch_resid_fine_cols<double>(int, const int*, const int*, const double*, const double*, size_t,
+                                             const double*, size_t, double*, size_t, int, hipStream_t);
+template void launch_resid_fine_cols<float>(int, const int*, const int*, const float*, const float*, size_t,
+                                            const double*, size_t, float*, size_t, int, hipStream_t);
 
 // rc_c[I] = sum over members (ascending) of z_c[k]; reset_c[I] <- sentinel
 // (column blockIdx.y)
+template <class T, class TZ>
 __global__ void k_restrict_cols(int nc, const int* __restrict__ aptr, const int* __restrict__ amem,
-                                const double* __restrict__ z, size_t ldz, double* __restrict__ rc,
-                                double* __restrict__ reset, size_t ldc) {
+                                const TZ* __restrict__ z, size_t ldz, T* __restrict__ rc, T* __restrict__ reset,
+                                size_t ldc) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   z += blockIdx.y * ldz;
-  double s = 0.0;
-  for (int m = aptr[I]; m < aptr[I + 1]; ++m) s += z[amem[m]];
+  T s = (T)0;
+  for (int m = aptr[I]; m < aptr[I + 1]; ++m) s += (T)z[amem[m]];
   rc[blockIdx.y * ldc + I] = s;
-  if (reset) reset[blockIdx.y * ldc + I] = sentinel_of<double>(0);
+  if (reset) reset[blockIdx.y * ldc + I] = sentinel_of<T>(0);
 }
 void launch_restrict_cols(int nc, const int* aptr, const int* amem, const double* z, size_t ldz, double* rc,
                           double* reset, size_t ldc, int nb, hipStream_t s) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_restrict_cols, dim3((nc + 255) / 256, nb), dim3(256), 0, s, nc, aptr, amem, z, ldz, rc, reset,
-                     ldc);
+  hipLaunchKernelGGL((k_restrict_cols<double, double>), dim3((nc + 255) / 256, nb), dim3(256), 0, s, nc, aptr, amem, z,
+                     ldz, rc, reset, ldc);
   HIPCK(hipGetLastError());
 }
+template <class T>
+void launch_restrict_cols_t(int nc, const int* aptr, const int* amem, const T* r, size_t ldr, T* rc, T* reset,
+                            size_t ldc, int nb, hipStream_t s) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL((k_restrict_cols<T, T>), dim3((nc + 255) / 256, nb), dim3(256), 0, s, nc, aptr, amem, r, ldr, rc,
+                     reset, ldc);
+  HIPCK(hipGetLastError());
+}
+template void launch_restrict_cols_t<double>(int, const int*, const int*, const double*, size_t, double*, double*,
+                                             size_t, int, hipStream_t);
+template void launch_restrict_cols_t<float>(int, const int*, const int*, const float*, size_t, float*, float*, size_t,
+                                            int, hipStream_t);
 
 // q_c[k] = t_c[k] + ec_c[agg[k]] (in T, widened); t_c[k] <- sentinel
 template <class T>

@@ -131,16 +131,16 @@ constexpr int SPMV_ROWS = 256;
 constexpr int SPMV_CAP = 4096;   // products held in LDS per tile
 constexpr int SPMV_BATCH = 8;    // entries per lane whose loads are in flight together
 
-template <class T, class TB, int MODE>
+template <class T, class TB, int MODE, int CAP>
 __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                               const T* __restrict__ v, const T* __restrict__ x,
                                               const TB* __restrict__ b, T* __restrict__ y) {
-  __shared__ T prod[SPMV_CAP];
+  __shared__ T prod[CAP];
   const int r0 = blockIdx.x * SPMV_ROWS;
   const int r1 = min(r0 + SPMV_ROWS, n);
   const int e0 = rp[r0], e1 = rp[r1];
   const int row = r0 + threadIdx.x;
-  if (e1 - e0 <= SPMV_CAP) {
+  if (e1 - e0 <= CAP) {
     // a lane's entries e, e + 256, ... in batches of SPMV_BATCH: every column
     // index of the batch is loaded, then every x and value, then the products
     // (one round of dependent loads per batch instead of one per entry)
@@ -172,111 +172,37 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
   }
 }
 
-// G lanes per row (a power of two near the average row length): every lane
-// of a row's group loads one of its entries (column, value, then x at that
-// column), the group adds its products with cross-lane shuffles, and its
-// first lane writes the row.  A wave holds 64 / G rows; it takes U such row
-// sets at once and issues all their loads before the first use, so several
-// dependent load rounds are in flight per wave.  The wave's loads of column
-// indices and values cover its rows' contiguous entries, so they are fully
-// coalesced; no LDS, no barrier.  Rows longer than G take further rounds.
-// MODE 0: y = A x;  MODE 1: y = b - A x.
-constexpr int SPMV_U = 4;
-constexpr int SPMV_WAVES = 4;   // waves per workgroup
-
-template <class T, class TB, int MODE, int G>
-__global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_g(int n, const int* __restrict__ rp,
-                                                            const int* __restrict__ ci, const T* __restrict__ v,
-                                                            const T* __restrict__ x, const TB* __restrict__ b,
-                                                            T* __restrict__ y) {
-  constexpr int RPW = 64 / G;                  // rows per wave and row set
-  const int lane = threadIdx.x & 63, sub = lane & (G - 1), slot = lane / G;
-  const int64_t wave = (int64_t)blockIdx.x * SPMV_WAVES + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * SPMV_WAVES;
-  for (int64_t base = wave * RPW * SPMV_U; base < n; base += nwaves * RPW * SPMV_U) {
-    int p[SPMV_U], pe[SPMV_U];
-#pragma unroll
-    for (int u = 0; u < SPMV_U; ++u) {
-      const int64_t row = base + u * RPW + slot;
-      p[u] = row < n ? rp[row] : 0;
-      pe[u] = row < n ? rp[row + 1] : 0;
-    }
-    T acc[SPMV_U];
-    int c[SPMV_U];
-    T a[SPMV_U];
-#pragma unroll
-    for (int u = 0; u < SPMV_U; ++u) {
-      const int k = p[u] + sub;
-      c[u] = k < pe[u] ? ci[k] : -1;
-      a[u] = k < pe[u] ? v[k] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < SPMV_U; ++u) acc[u] = c[u] >= 0 ? a[u] * x[c[u]] : (T)0;
-    // rows longer than G
-#pragma unroll
-    for (int u = 0; u < SPMV_U; ++u)
-      for (int k = p[u] + sub + G; k < pe[u]; k += G) acc[u] += v[k] * x[ci[k]];
-#pragma unroll
-    for (int u = 0; u < SPMV_U; ++u) {
-#pragma unroll
-      for (int off = G / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, 64);
-    }
-#pragma unroll
-    for (int u = 0; u < SPMV_U; ++u) {
-      const int64_t row = base + u * RPW + slot;
-      if (sub == 0 && row < n) y[row] = MODE == 0 ? acc[u] : (T)b[row] - acc[u];
-    }
-  }
-}
-
-// lanes per row for a matrix with nnz entries in n rows: the power of two at
-// or above the average row length, between 4 and 32
-int spmv_lanes(int64_t nnz, int64_t n) {
-  const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
-  int g = 4;
-  while (g < 32 && g < avg) g <<= 1;
-  return g;
-}
+// The tile's capacity in LDS: 4096 products (32 KB in FP64: five
+// workgroups per CU), or 2048 when every tile fits (16 KB: eight workgroups,
+// the CU's wave limit, so more loads in flight).
+int spmv_cap(int64_t max_tile_nnz) { return max_tile_nnz <= 2048 ? 2048 : 4096; }
 
 template <class T, class TB, int MODE>
-static void spmv_dispatch(int n, const int* rp, const int* ci, const T* v, const T* x, const TB* b, T* y, int lanes,
+static void spmv_dispatch(int n, const int* rp, const int* ci, const T* v, const T* x, const TB* b, T* y, int cap,
                           hipStream_t s) {
   if (n <= 0) return;
-  if (lanes == 0) {
-    hipLaunchKernelGGL((k_spmv<T, TB, MODE>), dim3((n + SPMV_ROWS - 1) / SPMV_ROWS), dim3(256), 0, s, n, rp, ci, v, x,
-                       b, y);
-    HIPCK(hipGetLastError());
-    return;
-  }
-  const int64_t rows_per_block = (int64_t)(64 / lanes) * SPMV_U * SPMV_WAVES;
-  const unsigned grid = (unsigned)std::min<int64_t>(8192, (n + rows_per_block - 1) / rows_per_block);
-  const dim3 blk(64 * SPMV_WAVES);
-  switch (lanes) {
-    case 4: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 4>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
-    case 8: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 8>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
-    case 16: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 16>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
-    case 32: hipLaunchKernelGGL((k_spmv_g<T, TB, MODE, 32>), dim3(grid), blk, 0, s, n, rp, ci, v, x, b, y); break;
-    default: fail(GMG_ERR_INVALID_ARG, "spmv: lanes per row must be 0, 4, 8, 16 or 32");
-  }
+  const dim3 grid((n + SPMV_ROWS - 1) / SPMV_ROWS), blk(256);
+  if (cap == 2048) hipLaunchKernelGGL((k_spmv<T, TB, MODE, 2048>), grid, blk, 0, s, n, rp, ci, v, x, b, y);
+  else hipLaunchKernelGGL((k_spmv<T, TB, MODE, SPMV_CAP>), grid, blk, 0, s, n, rp, ci, v, x, b, y);
   HIPCK(hipGetLastError());
 }
 
 template <class T>
-void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y, hipStream_t s, int lanes) {
-  spmv_dispatch<T, T, 0>(n, rp, ci, v, x, (const T*)nullptr, y, lanes, s);
+void launch_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, T* y, hipStream_t s, int cap) {
+  spmv_dispatch<T, T, 0>(n, rp, ci, v, x, (const T*)nullptr, y, cap, s);
 }
 template void launch_spmv<double>(int, const int*, const int*, const double*, const double*, double*, hipStream_t, int);
 template void launch_spmv<float>(int, const int*, const int*, const float*, const float*, float*, hipStream_t, int);
 
 void launch_residual(int n, const int* rp, const int* ci, const double* v, const double* x,
-                     const double* b, double* r, hipStream_t s, int lanes) {
-  spmv_dispatch<double, double, 1>(n, rp, ci, v, x, b, r, lanes, s);
+                     const double* b, double* r, hipStream_t s, int cap) {
+  spmv_dispatch<double, double, 1>(n, rp, ci, v, x, b, r, cap, s);
 }
 
 template <class T>
 void launch_resid_fine(int n, const int* rp, const int* ci, const T* v, const T* t, const double* z, T* r,
-                       hipStream_t s, int lanes) {
-  spmv_dispatch<T, double, 1>(n, rp, ci, v, t, z, r, lanes, s);
+                       hipStream_t s, int cap) {
+  spmv_dispatch<T, double, 1>(n, rp, ci, v, t, z, r, cap, s);
 }
 template void launch_resid_fine<double>(int, const int*, const int*, const double*, const double*, const double*, double*, hipStream_t, int);
 template void launch_resid_fine<float>(int, const int*, const int*, const float*, const float*, const double*, float*, hipStream_t, int);
@@ -322,24 +248,26 @@ void launch_restrict_plain(int nc, const int* aptr, const int* amem, const doubl
   launch_restrict<double>(nc, aptr, amem, z, bc, reset, sent, s);
 }
 
-// q[k] = t[k] + ec[agg[k]] in T, widened to double; t[k] <- sentinel
-template <class T>
+// q[k] = t[k] + ec[agg[k]] in T, widened to double; with RESET t[k] <-
+// sentinel (t is then the output of a sweep that polls for its values)
+template <class T, bool RESET>
 __global__ void k_prolong(int n, const int* __restrict__ agg, T* __restrict__ t, const T* __restrict__ ec,
                           double* __restrict__ q, uint64_t sent) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     T v = t[k] + ec[agg[k]];
     q[k] = (double)v;
-    t[k] = sentinel_of<T>(sent);
+    if (RESET) t[k] = sentinel_of<T>(sent);
   }
 }
 template <class T>
-void launch_prolong(int n, const int* agg, T* t, const T* ec, double* q, uint64_t sent, hipStream_t s) {
+void launch_prolong(int n, const int* agg, T* t, const T* ec, double* q, uint64_t sent, hipStream_t s, bool reset_t) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(n)), dim3(256), 0, s, n, agg, t, ec, q, sent);
+  if (reset_t) hipLaunchKernelGGL((k_prolong<T, true>), dim3(grid_for(n)), dim3(256), 0, s, n, agg, t, ec, q, sent);
+  else hipLaunchKernelGGL((k_prolong<T, false>), dim3(grid_for(n)), dim3(256), 0, s, n, agg, t, ec, q, sent);
   HIPCK(hipGetLastError());
 }
-template void launch_prolong<double>(int, const int*, double*, const double*, double*, uint64_t, hipStream_t);
-template void launch_prolong<float>(int, const int*, float*, const float*, double*, uint64_t, hipStream_t);
+template void launch_prolong<double>(int, const int*, double*, const double*, double*, uint64_t, hipStream_t, bool);
+template void launch_prolong<float>(int, const int*, float*, const float*, double*, uint64_t, hipStream_t, bool);
 
 // adjoint residual: out[k] = z[k] - sum_l AT[k,l] * ec[agg[l]]
 __global__ __launch_bounds__(256) void k_resid_adj(int n, const int* __restrict__ rp, const int* __restrict__ ci,

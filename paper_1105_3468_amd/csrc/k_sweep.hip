@@ -100,6 +100,20 @@ struct LdsSrc {
   }
 };
 
+// Dependency values that are final before the launch (rows of earlier
+// levels, each level its own launch): plain loads, nothing to poll.
+template <class T>
+struct FinalSrc {
+  const T* out;
+  static constexpr bool kSleep = false;
+  __device__ void fetch(const int (&c)[SWEEP_BATCH], T (&v)[SWEEP_BATCH]) const {
+#pragma unroll
+    for (int u = 0; u < SWEEP_BATCH; ++u) v[u] = out[c[u]];
+  }
+  __device__ unsigned pending(const int (&)[SWEEP_BATCH], const T (&)[SWEEP_BATCH], unsigned) const { return 0u; }
+  __device__ void refetch(const int (&)[SWEEP_BATCH], T (&)[SWEEP_BATCH], unsigned) const {}
+};
+
 // acc = sum of this lane's share of row e's entries: entries q0+sub,
 // q0+sub+G, ... (q0 < q1), SWEEP_BATCH at a time.  Every batch loads its
 // entries unconditionally (past the row's end at the row's last entry, not
@@ -219,6 +233,27 @@ __global__ __launch_bounds__(256) void k_sweep(const int* __restrict__ chunk, co
   }
 }
 
+// The chunks of one dependency level, a wave per chunk: every dependency
+// belongs to an earlier level, complete when this launch starts, so the
+// values are read as they are.  Used for factors with a few wide levels (the
+// colour classes of a multicolour ordering), where one launch per level costs
+// less than the device-wide sweep's publishing and polling.
+template <class T, class TR, bool DIAG>
+__global__ __launch_bounds__(256) void k_sweep_level(const int* __restrict__ chunk, const int* __restrict__ rows,
+                                                     const int* __restrict__ dp, const int* __restrict__ dcol,
+                                                     const T* __restrict__ dval, const T* __restrict__ dinv,
+                                                     const TR* rhs, T* out, TR* reset_rhs, unsigned nchunks) {
+  const unsigned t = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (t >= nchunks) return;
+  const FinalSrc<T> src{out};
+  int e, r;
+  T y;
+  if (chunk_rows<T, TR, DIAG>(src, chunk, t, rows, dp, dcol, dval, dinv, rhs, nullptr, 0, e, r, y)) {
+    out[r] = y;
+    if (reset_rhs) reset_rhs[r] = sentinel_of<TR>(0);
+  }
+}
+
 // One workgroup over the chunks of a level range whose rows are entries
 // [e0, e0 + m); their results live in LDS slots e - e0 (dynamic LDS of m
 // values, reset to the sentinel at start).  dslot holds the LDS slot or the
@@ -264,6 +299,36 @@ static uint64_t wall_limit_ticks() {
   }
   return ticks;
 }
+
+template <class T>
+void launch_sweep_levels(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64, T* out,
+                         T* reset_rhs, hipStream_t s) {
+  if (sw.nchunks == 0) return;
+  if ((int)sw.lvl_c0.size() != sw.levels + 1) fail(GMG_ERR_INVALID_ARG, "level sweep: no level table");
+  for (int l = 0; l < sw.levels; ++l) {
+    const int c0 = sw.lvl_c0[l];
+    const unsigned nchunks = (unsigned)(sw.lvl_c0[l + 1] - c0);
+    if (nchunks == 0) continue;
+    const int* ch = sw.chunk.p + 3 * (size_t)c0;
+    const unsigned blocks = (nchunks + 3) / 4;
+#define GMG_SWV(TR_, DG_, RHS_, RESET_)                                                                       \
+  hipLaunchKernelGGL((k_sweep_level<T, TR_, DG_>), dim3(blocks), dim3(256), 0, s, ch, sw.rows.p, sw.dp.p,    \
+                     sw.dcol.p, dval, dinv, (const TR_*)RHS_, out, RESET_, nchunks)
+    if (rhs_is_f64 && sizeof(T) == 4) {
+      if (sw.has_diag) GMG_SWV(double, true, rhs, (double*)nullptr);
+      else GMG_SWV(double, false, rhs, (double*)nullptr);
+    } else {
+      if (sw.has_diag) GMG_SWV(T, true, rhs, reset_rhs);
+      else GMG_SWV(T, false, rhs, reset_rhs);
+    }
+#undef GMG_SWV
+    HIPCK(hipGetLastError());
+  }
+}
+template void launch_sweep_levels<double>(Sweep&, const double*, const double*, const void*, bool, double*, double*,
+                                          hipStream_t);
+template void launch_sweep_levels<float>(Sweep&, const float*, const float*, const void*, bool, float*, float*,
+                                         hipStream_t);
 
 template <class T>
 void launch_sweep(Sweep& sw, const T* dval, const T* dinv, const void* rhs, bool rhs_is_f64, T* out,
@@ -537,6 +602,132 @@ __global__ void k_ilu0_level(const int* __restrict__ rows, int count, const int*
   else if (!isfinite(d)) atomicOr(bad, 2);
 }
 #pragma clang fp contract(on)
+
+// ILU(0) of a matrix with the 2D-grid structure of the wavefront sweeps (row
+// k = iy * nx + ix couples only to k -/+ 1 within its grid row and k -/+ nx;
+// nx >= 3): the elimination of row i only updates its diagonal,
+//   l1 = a(i, i-nx) / u(i-nx, i-nx);  d = a_ii - l1 * a(i-nx, i);
+//   l2 = a(i, i-1)  / u(i-1, i-1);    d = d - l2 * a(i-1, i),
+// (the terms of absent neighbours left out) in the order of the IKJ
+// definition, so the result is the level-scheduled kernel's bit for bit.  A
+// pivot depends on the previous anti-diagonal only: one workgroup walks the
+// nx + ny - 1 anti-diagonals, thread y owning grid row y (and y + 1024, ...),
+// with the previous diagonal's pivots in LDS and the next diagonal's
+// operands loaded before the barrier.
+// op[5 * i ..]: a_ii, a(i, i-nx), a(i-nx, i), a(i, i-1), a(i-1, i) (0 when
+// absent); pos[2 * i ..]: positions of a(i, i-nx) and a(i, i-1) (or -1).
+constexpr int ILUG_THREADS = 1024;
+constexpr int ILUG_ROWS = 4;     // grid rows per thread at most (ny <= 4096)
+
+__global__ void k_ilu0_grid_ops(int n, int nx, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const int* __restrict__ dpos, const double* __restrict__ a, double* __restrict__ op,
+                                int* __restrict__ pos) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = dpos[i];
+  double o[5] = {a[d], 0.0, 0.0, 0.0, 0.0};
+  int pd = -1, pl = -1;
+  for (int p = rp[i]; p < d; ++p) {
+    if (ci[p] == i - nx) pd = p;
+    if (ci[p] == i - 1) pl = p;
+  }
+  if (pd >= 0) {
+    o[1] = a[pd];
+    const int k = i - nx;
+    for (int p = dpos[k] + 1; p < rp[k + 1]; ++p)
+      if (ci[p] == i) o[2] = a[p];
+  }
+  if (pl >= 0) {
+    o[3] = a[pl];
+    const int k = i - 1;
+    for (int p = dpos[k] + 1; p < rp[k + 1]; ++p)
+      if (ci[p] == i) o[4] = a[p];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) op[5 * (size_t)i + q] = o[q];
+  pos[2 * (size_t)i] = pd;
+  pos[2 * (size_t)i + 1] = pl;
+}
+
+#pragma clang fp contract(off)
+__global__ __launch_bounds__(ILUG_THREADS) void k_ilu0_grid(int nx, int ny, const double* __restrict__ op,
+                                                            const int* __restrict__ pos, const int* __restrict__ dpos,
+                                                            double* __restrict__ a, int* bad) {
+  extern __shared__ double piv[];   // two diagonals of pivots, indexed by grid row
+  double* cur = piv;
+  double* prv = piv + ny;
+  const int steps = nx + ny - 1;
+  double o[ILUG_ROWS][5];
+  auto load = [&](int t) {
+#pragma unroll
+    for (int r = 0; r < ILUG_ROWS; ++r) {
+      const int y = threadIdx.x + r * ILUG_THREADS, x = t - y;
+      if (y < ny && x >= 0 && x < nx) {
+        const size_t i = (size_t)y * nx + x;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[r][q] = op[5 * i + q];
+      }
+    }
+  };
+  load(0);
+  int flags = 0;
+  for (int t = 0; t < steps; ++t) {
+    double d[ILUG_ROWS];
+#pragma unroll
+    for (int r = 0; r < ILUG_ROWS; ++r) {
+      const int y = threadIdx.x + r * ILUG_THREADS, x = t - y;
+      d[r] = 0.0;
+      if (y < ny && x >= 0 && x < nx) {
+        const size_t i = (size_t)y * nx + x;
+        double v = o[r][0];
+        const int pd = pos[2 * i], pl = pos[2 * i + 1];
+        if (pd >= 0) {
+          const double l1 = o[r][1] / prv[y - 1];    // pivot of (x, y - 1), diagonal t - 1
+          a[pd] = l1;
+          v = v - l1 * o[r][2];
+        }
+        if (pl >= 0) {
+          const double l2 = o[r][3] / prv[y];        // pivot of (x - 1, y), diagonal t - 1
+          a[pl] = l2;
+          v = v - l2 * o[r][4];
+        }
+        a[dpos[i]] = v;
+        d[r] = v;
+        if (v == 0.0) flags |= 1;
+        else if (!isfinite(v)) flags |= 2;
+      }
+    }
+    if (t + 1 < steps) load(t + 1);
+#pragma unroll
+    for (int r = 0; r < ILUG_ROWS; ++r) {
+      const int y = threadIdx.x + r * ILUG_THREADS;
+      if (y < ny) cur[y] = d[r];
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  if (flags) atomicOr(bad, flags);
+}
+#pragma clang fp contract(on)
+
+bool ilu0_grid_fits(int nx, int ny) { return nx >= 3 && ny >= 1 && ny <= ILUG_THREADS * ILUG_ROWS; }
+
+void launch_ilu0_grid(int n, int nx, const int* rp, const int* ci, const int* dpos, double* a, int* bad,
+                      hipStream_t s) {
+  const int ny = n / nx;
+  if (!ilu0_grid_fits(nx, ny) || (int64_t)nx * ny != n) fail(GMG_ERR_INVALID_ARG, "grid ILU(0): unsupported shape");
+  DBuf<double> op;
+  DBuf<int> pos;
+  op.alloc((size_t)5 * n);
+  pos.alloc((size_t)2 * n);
+  hipLaunchKernelGGL(k_ilu0_grid_ops, dim3((n + 255) / 256), dim3(256), 0, s, n, nx, rp, ci, dpos, a, op.p, pos.p);
+  const size_t lds = (size_t)2 * ny * sizeof(double);
+  hipLaunchKernelGGL(k_ilu0_grid, dim3(1), dim3(ILUG_THREADS), lds, s, nx, ny, op.p, pos.p, dpos, a, bad);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(s));   // before op and pos are freed
+}
 
 void launch_ilu0_level(const int* rows, int count, const int* rp, const int* ci, const int* dpos, double* a,
                        int* bad, hipStream_t s) {

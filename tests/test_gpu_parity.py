@@ -380,15 +380,15 @@ def test_paper_problems_exact_vs_inexact(case, n):
 
 def test_paper_curve_dc3d_50():
     """Figure F:curveJUMP regenerated from the GPU path: DC3D (DC1 3D) on
-    50^3 cells, GMRES(30), cf = 4, exact (tau = 0) and inexact (tau = 1e-4)
-    coarse solves.  Each GPU residual history (the FGMRES estimate after every
+    50^3 cells, GMRES(30), cf = 4, exact (tau = 0) and inexact (tau = 1e-4
+    and 1e-6) coarse solves.  Each GPU residual history (the FGMRES estimate after every
     step, read through gmg_get_history) follows the oracle's step by step
     (relative 1e-6 while above 1e-11) and ends within one step of it."""
     _say("[case] paper curve dc1_3d n=50")
     p = W.paper_problem("dc1_3d", 50)
     b = p.b[:, 0]
     A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n_rows, p.n_rows))
-    for tau in (0.0, 1e-4):
+    for tau in (0.0, 1e-4, 1e-6):
         S = Solver(p.rowptr, p.col, p.val, cf=4.0, ilut_tau=tau)
         x, res = S.solve(torch.as_tensor(b, device="cuda"), tol=1e-8, restart=30, maxit=600)
         assert res.status == G.OK and np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
@@ -578,6 +578,47 @@ def test_dense_coarse_inverse(name):
     assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
     with pytest.raises(GmgError):
         S.cond_estimate()
+
+
+def _zero_leading_coarse_pivot(block_sum_zero=True):
+    """8 unknowns in two strongly coupled chains of four, weakly coupled to
+    each other: matching makes the chains the two aggregates, and the first
+    chain's entries sum to zero, so A_c = [[0, -0.1], [-0.1, 4]] is invertible
+    but has a zero leading pivot without pivoting; ILU(0) of A itself has
+    nonzero pivots (3, 1.67, 2.35, -1.2, ...)."""
+    A = np.zeros((8, 8))
+    for o, d in ((0, (3.0, 3.0, 2.5, 0.5 if block_sum_zero else 1.5)), (4, (3.5, 3.0, 3.0, 3.5))):
+        A[o, o + 1] = A[o + 1, o] = -2.0
+        A[o + 1, o + 2] = A[o + 2, o + 1] = -0.5
+        A[o + 2, o + 3] = A[o + 3, o + 2] = -2.0
+        for k in range(4):
+            A[o + k, o + k] = d[k]
+    A[3, 4] = A[4, 3] = -0.1
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    return M
+
+
+def test_coarse_zero_pivot_reported():
+    """The no-pivot elimination of A_c meets a zero pivot: the dense inverse
+    (coarse_mode 3) and the complete LU (ILUT tau = 0) both report
+    GMG_ERR_ZERO_PIVOT at setup, as the oracle does; with a nonzero pivot the
+    same structure sets up and applies."""
+    _say("[case] coarse zero pivot")
+    M = _zero_leading_coarse_pivot()
+    for kw in (dict(coarse_mode=3), dict(ilut_tau=0.0)):
+        with pytest.raises(GmgError) as ei:
+            Solver(M.indptr, M.indices, M.data, coarse_order=0, **kw)
+        assert ei.value.code == G.ERR_ZERO_PIVOT, kw
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.Oracle(M.indptr, M.indices, M.data, coarse_order=0, ilut_tau=0.0)
+    assert eo.value.code == oracle.ERR_ZERO_PIVOT
+    M2 = _zero_leading_coarse_pivot(False)
+    S = Solver(M2.indptr, M2.indices, M2.data, coarse_order=0, coarse_mode=3)
+    O = oracle.Oracle(M2.indptr, M2.indices, M2.data, coarse_order=0, ilut_tau=0.0)
+    z = np.random.default_rng(3).uniform(-1, 1, 8)
+    q = S.apply(torch.as_tensor(z, device="cuda"), precision=0).cpu().numpy()
+    assert np.allclose(q, O.apply(z, 0), rtol=1e-12, atol=1e-14)
 
 
 def test_dense_coarse_inverse_size_limit():

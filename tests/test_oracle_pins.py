@@ -552,6 +552,35 @@ def test_error_codes(oracle_mod):
     assert info.status == oracle_mod.NOT_CONVERGED and info.steps == 2
 
 
+def test_zero_coarse_pivot_is_an_error(oracle_mod):
+    """Two chains of four unknowns, weakly coupled: matching aggregates each
+    chain (brute-force aggregation agrees), the first chain's entries sum to
+    zero, so A_c = [[0, -0.1], [-0.1, 4]]: ILU(0) of A succeeds, the coarse
+    factorisation without pivoting meets a zero pivot and says so."""
+    A = np.zeros((8, 8))
+    for o, d in ((0, (3.0, 3.0, 2.5, 0.5)), (4, (3.5, 3.0, 3.0, 3.5))):
+        A[o, o + 1] = A[o + 1, o] = -2.0
+        A[o + 1, o + 2] = A[o + 2, o + 1] = -0.5
+        A[o + 2, o + 3] = A[o + 3, o + 2] = -2.0
+        for k in range(4):
+            A[o + k, o + k] = d[k]
+    A[3, 4] = A[4, 3] = -0.1
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    o = oracle_mod.default_options()
+    agg, _ = B.multipass_aggregation(M.indptr, M.indices, M.data, 4.0, 8, o["qbits"], o["seed"])
+    assert np.array_equal(agg, [0, 0, 0, 0, 1, 1, 1, 1])
+    P = B.prolongation(agg, 2)
+    assert np.array_equal(P.T @ A @ P, np.array([[0.0, -0.1], [-0.1, 4.0]]))
+    with pytest.raises(oracle_mod.OracleError) as e:
+        oracle_mod.Oracle(M.indptr, M.indices, M.data, coarse_order=0, ilut_tau=0.0)
+    assert e.value.code == oracle_mod.ERR_ZERO_PIVOT
+    A[3, 3] = 1.5
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    assert oracle_mod.Oracle(M.indptr, M.indices, M.data, coarse_order=0, ilut_tau=0.0).nc == 2
+
+
 def test_nested_dissection_numbering(oracle_mod):
     """ND numbering of a grid-like coarse graph: equals the recursive definition;
     at every dissection step the separator (numbered last) disconnects the two
