@@ -34,19 +34,27 @@
 
 namespace gmg {
 
-// One workgroup per 64 grid rows: wave 0 computes; waves 1 and 2 stream the
-// operands of alternate chunks of WAVE_CH steps into an LDS ring of
-// WAVE_RING steps, each keeping WAVE_D chunks of loads in flight; wave 3
-// polls the previous band's boundary values into a second ring of WAVE_XRING
-// steps.  The computing wave thus issues no global loads: its stores, which
-// share the in-order memory counter with loads, never hold it up.
+// One workgroup per 64 grid rows: wave 0 computes; waves 1 .. WAVE_PRODUCERS
+// stream the operands of chunks of WAVE_CH steps into an LDS ring of
+// WAVE_SLOTS chunks (producer k takes chunks k, k + P, k + 2P, ..., each
+// keeping WAVE_D chunks of loads in flight) and flag each chunk ready; the
+// last wave polls the previous band's boundary values into a second ring of
+// WAVE_XRING steps.  The computing wave thus issues no global loads: its
+// stores, which share the in-order memory counter with loads, never hold it
+// up.  Its step is a handful of instructions (a wave issues at most one per
+// four cycles), so everything else is moved off it: ring offsets are taken
+// once per chunk, and the producers screen the right-hand side for the
+// not-yet-computed marker (a NaN carrying the marker's payload becomes a plain
+// NaN), so that no result can carry the marker and results are published
+// without a test.
 constexpr int WAVE_CH = 8;
 constexpr int WAVE_D = 2;
-constexpr int WAVE_RING = 48;
-constexpr int WAVE_PRODUCERS = 2;
+constexpr int WAVE_SLOTS = 6;
+constexpr int WAVE_RING = WAVE_CH * WAVE_SLOTS;
+constexpr int WAVE_PRODUCERS = 4;
 constexpr int WAVE_XRING = 256;
 constexpr int WAVE_THREADS = 64 * (2 + WAVE_PRODUCERS);
-static_assert(WAVE_PRODUCERS == 2, "the consumer takes even chunks from producer 0, odd ones from producer 1");
+static_assert(WAVE_XRING % WAVE_CH == 0, "a chunk's boundary values must not wrap around the ring");
 
 // Lane l receives lane l - 1's value v; lane 0 keeps lane0 (DPP wave_shr:1
 // without bound control leaves the destination of a lane with no source).
@@ -103,6 +111,21 @@ __device__ __forceinline__ bool wait_lds_at_least(const int* ctr, int want, int*
   return true;
 }
 
+// Bounded wait for an LDS flag to equal `want` (the computing wave: relaxed
+// loads, no sleep, no global load on its path); false when abandoned.
+__device__ __forceinline__ bool wait_lds_equal(const int* flag, int want, int* abort_flag, uint64_t limit) {
+  const uint64_t t0 = wall_clock64();
+  unsigned it = 0;
+#pragma clang loop unroll(disable)
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != want) {
+    if ((++it & 255u) == 0 && wall_clock64() - t0 > limit) {
+      st_agent(abort_flag, 1);
+      return false;
+    }
+  }
+  return true;
+}
+
 // LDS-only release / acquire: orders the ring's data against its counters
 // without waiting for global memory operations.
 __device__ __forceinline__ void lds_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local"); }
@@ -125,10 +148,10 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
                                                        int* abort_flag, uint64_t limit, int nb) {
   using P2 = typename Pair<T>::type;
   __shared__ WaveOp<T> r_op[WAVE_RING][64];
-  __shared__ T r_x[WAVE_XRING];              // previous band's boundary values
-  __shared__ int produced[WAVE_PRODUCERS];  // chunks written by each producer
-  __shared__ int xready;                    // boundary values in r_x
-  __shared__ int consumed;                  // steps finished by the consumer
+  __shared__ T r_x[WAVE_XRING];      // previous band's boundary values
+  __shared__ int ready[WAVE_SLOTS];  // chunk c + 1 once chunk c is in its slot c % WAVE_SLOTS
+  __shared__ int xready;             // boundary values in r_x
+  __shared__ int consumed;           // steps finished by the consumer
   // the role is the same for the whole wave: taken from lane 0 so the role
   // branches are scalar and no role's pending loads reach another's code
   const int w = blockIdx.x / nb, l = threadIdx.x & 63, role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -139,7 +162,7 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
   }
   const int64_t p0 = (int64_t)w * S * 64 + l;
   const int nchunks = S / WAVE_CH;
-  if (threadIdx.x < WAVE_PRODUCERS) produced[threadIdx.x] = 0;
+  if (threadIdx.x < WAVE_SLOTS) ready[threadIdx.x] = 0;
   if (threadIdx.x == 0) { consumed = 0; xready = 0; }
   // the boundary ring starts at zero: the consumer reads it for every step,
   // and steps without a boundary value (first band, padding) have a zero
@@ -205,27 +228,25 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
       const int c = k + d * WAVE_PRODUCERS;
       if (c < nchunks) issue(c, d);
     }
-    int done = 0;  // chunks of this producer written to the ring
     for (int d0 = 0;; d0 += WAVE_D) {
 #pragma unroll
       for (int dd = 0; dd < WAVE_D; ++dd) {
         const int c = k + (d0 + dd) * WAVE_PRODUCERS;
         if (c >= nchunks) return;
-        // the ring slots of this chunk were last used WAVE_RING steps earlier
-        if (!wait_lds_at_least<4>(&consumed, (c + 1) * WAVE_CH - WAVE_RING, abort_flag, limit)) return;
+        // the ring slot of chunk c last held chunk c - WAVE_SLOTS
+        if (!wait_lds_at_least<4>(&consumed, (c + 1 - WAVE_SLOTS) * WAVE_CH, abort_flag, limit)) return;
+        const int rb0 = (c % WAVE_SLOTS) * WAVE_CH;
 #pragma unroll
         for (int u = 0; u < WAVE_CH; ++u) {
-          const int st = (c * WAVE_CH + u) % WAVE_RING;
           WaveOp<T> op;
           op.cb = rc[dd][u].x;
           op.cl = rc[dd][u].y;
-          op.b = rb[dd][u];
+          op.b = is_sentinel(rb[dd][u]) ? (T)__builtin_nan("") : rb[dd][u];
           op.d = DIAG ? rd[dd][u] : (T)1;
-          r_op[st][l] = op;
+          r_op[rb0 + u][l] = op;
         }
         lds_release();
-        ++done;
-        if (l == 0) __hip_atomic_store(&produced[k], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (l == 0) __hip_atomic_store(&ready[c % WAVE_SLOTS], c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         const int cn = c + WAVE_D * WAVE_PRODUCERS;
         if (cn < nchunks) issue(cn, dd);
       }
@@ -236,29 +257,20 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
   // Chunks of WAVE_CH steps, two at a time (S is a multiple of 2 WAVE_CH):
   // set A holds the operands of the even chunk, set B of the odd one, each
   // read from the ring while the other set computes, so no values are moved
-  // between registers; even chunks come from producer 0, odd ones from
-  // producer 1.  A wait that is abandoned (abort flag, time limit) only marks
-  // the sweep dead: the rest runs without waiting and its results are
-  // discarded by the host, so the loop has no early exit.
+  // between registers.  A wait that is abandoned (abort flag, time limit)
+  // only marks the sweep dead: the rest runs without waiting and its results
+  // are discarded by the host, so the loop has no early exit.
   const bool reads_prev = w > 0;
   bool live = true;
-  int seen_prod[WAVE_PRODUCERS], seen_x = 0;
-#pragma unroll
-  for (int k = 0; k < WAVE_PRODUCERS; ++k) seen_prod[k] = 0;
+  int seen_x = 0;
   WaveOp<T> opA[WAVE_CH], opB[WAVE_CH];
   T xA[WAVE_CH], xB[WAVE_CH];
-  // wait until chunk c (of producer K) and its boundary values are in LDS,
-  // then read its operands
-  auto take = [&](auto kc, int c, WaveOp<T>(&op)[WAVE_CH], T(&xv)[WAVE_CH]) {
-    constexpr int K = decltype(kc)::value;
-    const int need_p = c / WAVE_PRODUCERS + 1;
-    if (live && seen_prod[K] < need_p) {
-      seen_prod[K] = __hip_atomic_load(&produced[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (seen_prod[K] < need_p) {
-        live = wait_lds_at_least<0, false>(&produced[K], need_p, abort_flag, limit);
-        seen_prod[K] = need_p;
-      }
-    }
+  // wait until chunk c and its boundary values are in LDS, then read its
+  // operands (ring offsets fixed per chunk: the reads take immediate offsets)
+  auto take = [&](int c, WaveOp<T>(&op)[WAVE_CH], T(&xv)[WAVE_CH]) {
+    const int slot = c % WAVE_SLOTS;
+    if (live && __hip_atomic_load(&ready[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != c + 1)
+      live = wait_lds_equal(&ready[slot], c + 1, abort_flag, limit);
     const int s0 = c * WAVE_CH;
     if (reads_prev && s0 < xn) {
       const int need = std::min(s0 + WAVE_CH, xn);
@@ -271,19 +283,20 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
       }
     }
     lds_acquire();
+    const WaveOp<T>* ro = &r_op[slot * WAVE_CH][l];
+    const T* rx = r_x + s0 % WAVE_XRING;
 #pragma unroll
     for (int u = 0; u < WAVE_CH; ++u) {
-      op[u] = r_op[(s0 + u) % WAVE_RING][l];
-      xv[u] = r_x[(s0 + u) % WAVE_XRING];
+      op[u] = ro[u * 64];
+      xv[u] = rx[u];
     }
   };
   T yp = (T)0;  // this lane's result of the previous step
   // the steps of chunk c; results stored with immediate offsets from one
-  // base, each one step later in program order so that its check and store
-  // fill the latency of the next step's chain instead of lengthening it
+  // base, each one step later in program order so that its store fills the
+  // latency of the next step's chain instead of lengthening it
   auto run = [&](int c, const WaveOp<T>(&op)[WAVE_CH], const T(&xv)[WAVE_CH]) {
     T* ob = out + p0 + (int64_t)c * WAVE_CH * 64;
-    auto publish = [&](int u, T y) { st_agent(ob + u * 64, is_sentinel(y) ? (T)__builtin_nan("") : y); };
 #pragma unroll
     for (int u = 0; u < WAVE_CH; ++u) {
       const T upv = lane_shr1(xv[u], yp);
@@ -297,20 +310,18 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
       }
       T y = op[u].b - acc;
       if (DIAG) y *= op[u].d;
-      if (u > 0) publish(u - 1, yp);
+      if (u > 0) st_agent(ob + (u - 1) * 64, yp);
       yp = y;
     }
-    publish(WAVE_CH - 1, yp);
+    st_agent(ob + (WAVE_CH - 1) * 64, yp);
     lds_release();
     if (l == 0) __hip_atomic_store(&consumed, (c + 1) * WAVE_CH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  using K0 = std::integral_constant<int, 0>;
-  using K1 = std::integral_constant<int, 1>;
-  take(K0{}, 0, opA, xA);
+  take(0, opA, xA);
   for (int c = 0; c < nchunks; c += 2) {
-    take(K1{}, c + 1, opB, xB);
+    take(c + 1, opB, xB);
     run(c, opA, xA);
-    if (c + 2 < nchunks) take(K0{}, c + 2, opA, xA);
+    if (c + 2 < nchunks) take(c + 2, opA, xA);
     run(c + 1, opB, xB);
   }
 }
