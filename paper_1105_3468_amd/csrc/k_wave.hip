@@ -265,12 +265,20 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
   int seen_x = 0;
   WaveOp<T> opA[WAVE_CH], opB[WAVE_CH];
   T xA[WAVE_CH], xB[WAVE_CH];
-  // wait until chunk c and its boundary values are in LDS, then read its
-  // operands (ring offsets fixed per chunk: the reads take immediate offsets)
-  auto take = [&](int c, WaveOp<T>(&op)[WAVE_CH], T(&xv)[WAVE_CH]) {
+  // The ready flag of a chunk is read one chunk ahead, while the chunk before
+  // it computes, so its value is at hand (the LDS wait at the end of every
+  // chunk covers it) when the chunk's operands are read; only a chunk that
+  // was not ready then is waited for.
+  auto flag_of = [&](int c) {
+    return c < nchunks ? __hip_atomic_load(&ready[c % WAVE_SLOTS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                       : 0;
+  };
+  // make sure chunk c and its boundary values are in LDS (seen: its ready
+  // flag as read earlier), then read its operands (ring offsets fixed per
+  // chunk: the reads take immediate offsets)
+  auto take = [&](int c, int seen, WaveOp<T>(&op)[WAVE_CH], T(&xv)[WAVE_CH]) {
     const int slot = c % WAVE_SLOTS;
-    if (live && __hip_atomic_load(&ready[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != c + 1)
-      live = wait_lds_equal(&ready[slot], c + 1, abort_flag, limit);
+    if (live && seen != c + 1) live = wait_lds_equal(&ready[slot], c + 1, abort_flag, limit);
     const int s0 = c * WAVE_CH;
     if (reads_prev && s0 < xn) {
       const int need = std::min(s0 + WAVE_CH, xn);
@@ -283,11 +291,11 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
       }
     }
     lds_acquire();
-    const WaveOp<T>* ro = &r_op[slot * WAVE_CH][l];
+    const int r0 = slot * WAVE_CH;
     const T* rx = r_x + s0 % WAVE_XRING;
 #pragma unroll
     for (int u = 0; u < WAVE_CH; ++u) {
-      op[u] = ro[u * 64];
+      op[u] = r_op[r0 + u][l];
       xv[u] = rx[u];
     }
   };
@@ -317,11 +325,14 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
     lds_release();
     if (l == 0) __hip_atomic_store(&consumed, (c + 1) * WAVE_CH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  take(0, opA, xA);
+  take(0, flag_of(0), opA, xA);
+  int fnext = flag_of(1);
   for (int c = 0; c < nchunks; c += 2) {
-    take(c + 1, opB, xB);
+    take(c + 1, fnext, opB, xB);
+    fnext = flag_of(c + 2);
     run(c, opA, xA);
-    if (c + 2 < nchunks) take(c + 2, opA, xA);
+    if (c + 2 < nchunks) take(c + 2, fnext, opA, xA);
+    fnext = flag_of(c + 3);
     run(c + 1, opB, xB);
   }
 }
