@@ -142,7 +142,12 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
   const int rl = threadIdx.x & (R - 1), cg = threadIdx.x >> lgR;
   const int i = a + rl < b ? a + rl : a;
   const int ncol = j1 - j0, cw = (ncol + G - 1) / G;
-  const int jb = j0 + cg * cw, je = jb + cw < j1 ? jb + cw : j1;
+  const int jg = j0 + cg * cw, jge = jg + cw < j1 ? jg + cw : j1;
+  // the inverse of a triangular block is triangular: row i has no terms
+  // past its diagonal (lower: columns <= i, upper: columns >= i), so each
+  // thread reads only its row's side of the diagonal
+  const int jb = LOWER ? jg : (jg > i ? jg : i);
+  const int je = LOWER ? (jge < i + 1 ? jge : i + 1) : jge;
   const T* col = inv + boff[node] + i;  // column-major: Tinv[j][i] at j * s + i
   // the first batch of the block's entries does not depend on the
   // right-hand side: in flight while the inputs are awaited
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
     if (jb + u < je) acc += m[u] * y[jb + u - j0];
   for (int j = jb + TREE_MBATCH; j < je; j += TREE_MBATCH) {
 #pragma unroll
-    for (int u = 0; u < TREE_MBATCH; ++u) m[u] = col[(int64_t)(j + u < je ? j + u : je - 1) * s];
+    for (int u = 0; u < TREE_MBATCH; ++u) m[u] = j + u < je ? col[(int64_t)(j + u) * s] : (T)0;
 #pragma unroll
     for (int u = 0; u < TREE_MBATCH; ++u)
       if (j + u < je) acc += m[u] * y[j + u - j0];
