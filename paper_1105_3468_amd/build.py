@@ -28,7 +28,7 @@ COMMON = [
 
 SOURCES = ["k_sparse.hip", "k_sweep.hip", "k_wave.hip", "k_tree.hip", "k_krylov.hip", "k_setup.hip", "k_fv.hip", "k_dense.hip",
            "k_batch.hip",
-           "host_analysis.cpp", "gmg_api.cpp"]
+           "host_analysis.cpp", "pool.cpp", "gmg_api.cpp"]
 HEADERS = ["gmg_internal.h", "kcommon.h"]
 
 

@@ -2383,6 +2383,7 @@ gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowpt
   return guarded([&]() -> gmg_status {
     if (!h) gmg::fail(GMG_ERR_INVALID_ARG, "setup: null handle pointer");
     *h = nullptr;
+    gmg::PoolStream pool_scope((hipStream_t)stream);
     std::unique_ptr<gmg_solver> sv(new gmg_solver());
     sv->S.s = (hipStream_t)stream;
     if (const char* e = std::getenv("GMG_LOG")) sv->S.log_every = std::max(0, std::atoi(e));
@@ -2399,6 +2400,7 @@ gmg_status gmg_solve(gmg_handle h, const double* b, double* x, int nrhs, double 
                      gmg_info* info) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     return gmg::solve_impl(h->S, false, b, x, nrhs, tol, opts, info);
   });
 }
@@ -2407,6 +2409,7 @@ gmg_status gmg_solve_adjoint(gmg_handle h, const double* g, double* lambda, int 
                              const gmg_options* opts, gmg_info* info) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     return gmg::solve_impl(h->S, true, g, lambda, nrhs, tol, opts, info);
   });
 }
@@ -2414,6 +2417,7 @@ gmg_status gmg_solve_adjoint(gmg_handle h, const double* g, double* lambda, int 
 gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int precision, int adjoint) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!z || !q) gmg::fail(GMG_ERR_INVALID_ARG, "apply: null vector");
     Solver& S = h->S;
     gmg::reset_cycle_buffers(S);
@@ -2435,6 +2439,7 @@ gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int preci
 gmg_status gmg_spmv(gmg_handle h, int transposed, const double* x, double* y) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!x || !y) gmg::fail(GMG_ERR_INVALID_ARG, "spmv: null vector");
     gmg::apply_op(h->S, transposed != 0, x, y);
     HIPCK(hipStreamSynchronize(h->S.s));
@@ -2445,6 +2450,7 @@ gmg_status gmg_spmv(gmg_handle h, int transposed, const double* x, double* y) {
 gmg_status gmg_get_info(gmg_handle h, gmg_info* info) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!info) gmg::fail(GMG_ERR_INVALID_ARG, "null info");
     *info = h->S.info;
     return GMG_OK;
@@ -2464,6 +2470,7 @@ gmg_status gmg_get_history(gmg_handle h, int cap, double* hist, int* count) {
 gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!est_coarse || !est_ilut) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     gmg::Solver& S = h->S;
     if (S.opt.coarse_mode >= 2) gmg::fail(GMG_ERR_INVALID_ARG, "no ILUT factors under coarse_mode 2 or 3");
@@ -2506,6 +2513,7 @@ gmg_status gmg_cond_estimate(gmg_handle h, double* est_coarse, double* est_ilut)
 gmg_status gmg_get_aggregates(gmg_handle h, int32_t* agg) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!agg) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     gmg::d2d(agg, h->S.agg.p, h->S.n, h->S.s);
     HIPCK(hipStreamSynchronize(h->S.s));
@@ -2516,6 +2524,7 @@ gmg_status gmg_get_aggregates(gmg_handle h, int32_t* agg) {
 gmg_status gmg_get_coarse(gmg_handle h, int32_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!rowptr || !col || !val) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     Solver& S = h->S;
     gmg::d2d(rowptr, S.Ac.rp.p, S.nc + 1, S.s);
@@ -2529,6 +2538,7 @@ gmg_status gmg_get_coarse(gmg_handle h, int32_t* rowptr, int32_t* col, double* v
 gmg_status gmg_get_ilu0(gmg_handle h, double* val) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!val) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     gmg::d2d(val, h->S.ilu.p, h->S.nnz, h->S.s);
     HIPCK(hipStreamSynchronize(h->S.s));
@@ -2539,6 +2549,7 @@ gmg_status gmg_get_ilu0(gmg_handle h, double* val) {
 gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!perm) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     gmg::Solver& S = h->S;
     if (S.fine_nd) {
@@ -2556,6 +2567,7 @@ gmg_status gmg_get_fine_perm(gmg_handle h, int32_t* perm) {
 gmg_status gmg_get_spai(gmg_handle h, int32_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     gmg::Solver& S = h->S;
     if (S.opt.coarse_mode != 2) gmg::fail(GMG_ERR_INVALID_ARG, "no sparse approximate inverse (coarse_mode != 2)");
     if (!rowptr || !col || !val) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
@@ -2570,6 +2582,7 @@ gmg_status gmg_get_spai(gmg_handle h, int32_t* rowptr, int32_t* col, double* val
 gmg_status gmg_get_coarse_inverse(gmg_handle h, double* inv) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     gmg::Solver& S = h->S;
     if (S.opt.coarse_mode != 3) gmg::fail(GMG_ERR_INVALID_ARG, "no dense coarse inverse (coarse_mode != 3)");
     if (!inv) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
@@ -2585,6 +2598,7 @@ gmg_status gmg_get_ilut(gmg_handle h, int32_t* lrp, int32_t* lci, double* lv, in
                         double* uv) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     if (!lrp || !lci || !lv || !urp || !uci || !uv) gmg::fail(GMG_ERR_INVALID_ARG, "null output");
     Solver& S = h->S;
     gmg::h2d(lrp, S.hLc.rp.data(), S.hLc.rp.size(), S.s);
@@ -2602,6 +2616,7 @@ gmg_status gmg_set_stream(gmg_handle h, void* stream) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
     HIPCK(hipStreamSynchronize(h->S.s));
+    gmg::pool_idle(h->S.s);
     h->S.s = (hipStream_t)stream;
     return GMG_OK;
   });
@@ -2610,6 +2625,7 @@ gmg_status gmg_set_stream(gmg_handle h, void* stream) {
 gmg_status gmg_profile_enable(gmg_handle h, int enable) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     Solver& S = h->S;
     gmg::prof_flush(S);
     for (int c = 0; c < gmg::PC_COUNT; ++c) { S.pc_launch[c] = 0; S.pc_ms[c] = 0; S.pc_bytes[c] = 0; }
@@ -2623,6 +2639,7 @@ gmg_status gmg_profile_enable(gmg_handle h, int enable) {
 gmg_status gmg_profile_read(gmg_handle h, int cap, int* count, int64_t* launches, double* ms, double* bytes) {
   return guarded([&]() -> gmg_status {
     REQUIRE_HANDLE(h);
+    gmg::PoolStream pool_scope(h->S.s);
     Solver& S = h->S;
     gmg::prof_flush(S);
     if (count) *count = gmg::PC_COUNT;
@@ -2642,8 +2659,15 @@ const char* gmg_profile_name(int cls) {
 
 void gmg_destroy(gmg_handle h) {
   if (!h) return;
-  (void)hipStreamSynchronize(h->S.s);
-  delete h;
+  const hipStream_t s = h->S.s;
+  (void)hipStreamSynchronize(s);
+  {
+    // everything queued on s has finished: the solver's memory goes back to
+    // the cache, free for any stream
+    gmg::PoolStream pool_scope(s);
+    delete h;
+  }
+  gmg::pool_idle(s);
 }
 
 const char* gmg_last_error(void) { return gmg::g_last_error.c_str(); }

@@ -23,6 +23,27 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 #define HIPCK(x) ::gmg::hip_check((x), #x, __FILE__, __LINE__)
 
 // ---------------------------------------------------------------- memory
+// Device memory comes from a per-device cache of freed blocks (pool.cpp):
+// pool_alloc returns nullptr on failure.  While a PoolStream is alive on the
+// calling thread, blocks freed by it are tagged with its stream and reused on
+// that stream without waiting; without one they go back to the runtime.
+// pool_idle(s): the caller has synchronised s, so blocks freed on s may be
+// reused on any stream.
+void* pool_alloc(size_t bytes);
+void pool_free(void* p);
+void pool_idle(hipStream_t s);
+class PoolStream {
+ public:
+  explicit PoolStream(hipStream_t s);
+  ~PoolStream();
+  PoolStream(const PoolStream&) = delete;
+  PoolStream& operator=(const PoolStream&) = delete;
+
+ private:
+  bool had_;
+  hipStream_t prev_;
+};
+
 // Owning device buffer (library-allocated).
 template <class T>
 struct DBuf {
@@ -41,16 +62,14 @@ struct DBuf {
     release();
     n = count;
     if (count == 0) return;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-      p = nullptr;
+    p = static_cast<T*>(pool_alloc(count * sizeof(T)));
+    if (!p) {
       n = 0;
-      (void)hipGetLastError();
-      fail(GMG_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      fail(GMG_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
     }
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p);
     p = nullptr;
     n = 0;
   }

@@ -199,6 +199,7 @@ extern "C" gmg_status gmg_fv_assemble(int n, int dim, const double* kappa, const
     if (N64 >= (1LL << 31) / 8) return GMG_ERR_INVALID_ARG;
     const int N = (int)N64;
     hipStream_t s = (hipStream_t)stream;
+    PoolStream pool_scope(s);  // declared before the buffers: they return to the cache first
     DBuf<int> cnt, tmp;
     cnt.alloc((size_t)N + 1);
     hipLaunchKernelGGL(k_fv_count, dim3((N + 1 + 255) / 256), dim3(256), 0, s, n, dim, N, cnt.p);

@@ -183,6 +183,12 @@ class Solver:
         self._h = h
         self.setup_info = self.info()
 
+    def set_stream(self, stream=None):
+        """Queue the solver's later work on `stream` (torch.cuda.Stream; None:
+        torch's current stream); the library first waits for its old stream."""
+        _check(load().gmg_set_stream(self._h, _stream(stream)), "set_stream")
+        self._stream = stream
+
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.gmg_destroy(self._h)
