@@ -422,15 +422,31 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
     uoff[q + 1] = uoff[q] + (int64_t)rows[order[q]].uci.size();
   }
   if (loff[nt] > INT32_MAX || uoff[nt] > INT32_MAX) return GMG_ERR_OOM;  // int32 row pointers
-  L.rp.assign(n + 1, 0);
-  U.rp.assign(n + 1, 0);
-  L.ci.resize(loff[nt]);
-  L.v.resize(loff[nt]);
-  U.ci.resize(uoff[nt]);
-  U.v.resize(uoff[nt]);
+  // the four entry arrays are sized (zero-filled, first-touched) by four
+  // threads at once, then the nodes' rows are copied by all threads, each
+  // node's own vectors released as soon as they are copied
+  const int nthreads = std::min(host_threads(), nt);
+  {
+    auto sized = [&](int which) {
+      switch (which) {
+        case 0: L.ci.resize(loff[nt]); L.rp.assign(n + 1, 0); break;
+        case 1: L.v.resize(loff[nt]); break;
+        case 2: U.ci.resize(uoff[nt]); U.rp.assign(n + 1, 0); break;
+        default: U.v.resize(uoff[nt]); break;
+      }
+    };
+    if (nthreads >= 4) {
+      std::vector<std::thread> pool;
+      for (int w = 1; w < 4; ++w) pool.emplace_back(sized, w);
+      sized(0);
+      for (auto& t : pool) t.join();
+    } else {
+      for (int w = 0; w < 4; ++w) sized(w);
+    }
+  }
   auto copy_nodes = [&](int q0, int q1) {
     for (int q = q0; q < q1; ++q) {
-      const IlutNodeRows& R = rows[order[q]];
+      IlutNodeRows& R = rows[order[q]];
       const int nr = (int)R.lrp.size() - 1;
       for (int r = 0; r < nr; ++r) {
         L.rp[R.lo + r + 1] = (int)loff[q] + R.lrp[r + 1];
@@ -440,9 +456,9 @@ gmg_status host_ilut(const HCsr& A, double tau, HCsr& L, HCsr& U, const std::vec
       std::copy(R.lv.begin(), R.lv.end(), L.v.begin() + loff[q]);
       std::copy(R.uci.begin(), R.uci.end(), U.ci.begin() + uoff[q]);
       std::copy(R.uv.begin(), R.uv.end(), U.v.begin() + uoff[q]);
+      R = IlutNodeRows();
     }
   };
-  const int nthreads = std::min(host_threads(), nt);
   if (nthreads <= 1) {
     copy_nodes(0, nt);
   } else {
