@@ -1951,19 +1951,19 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     // number the aggregates in nested-dissection order of A_c's graph, then
     // rebuild P^T and A_c (same sums, permuted rows and columns)
     const int nc = S.nc;
-    std::vector<int> crp = to_host_int(S.Ac.rp.p, nc + 1, s);
-    std::vector<int> cci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
-    HIPCK(hipStreamSynchronize(s));
-    std::vector<int> cnt(nc + 1, 0);
-    for (int i = 0; i < nc; ++i)
-      for (int p = crp[i]; p < crp[i + 1]; ++p)
-        if (cci[p] != i) { cnt[i + 1]++; cnt[cci[p] + 1]++; }
-    for (int i = 0; i < nc; ++i) cnt[i + 1] += cnt[i];
-    std::vector<int> gci(cnt[nc]), fillp(cnt.begin(), cnt.end() - 1);
-    for (int i = 0; i < nc; ++i)
-      for (int p = crp[i]; p < crp[i + 1]; ++p)
-        if (cci[p] != i) { gci[fillp[i]++] = cci[p]; gci[fillp[cci[p]]++] = i; }
-    // duplicates (both (i,j) and (j,i) stored) are harmless for the traversal
+    // the graph of A_c + A_c^T without the diagonal, built on the device (the
+    // same merge as the fine graph's; the weights are not needed here)
+    std::vector<int> cnt, gci;
+    {
+      DBuf<int> trp, tci, grp, gcd;
+      DBuf<double> tv, gw;
+      transpose_csr(nc, nc, S.Ac.nnz, S.Ac.rp.p, S.Ac.ci.p, S.Ac.v.p, trp, tci, &tv, nullptr, s);
+      build_graph(nc, S.Ac.rp.p, S.Ac.ci.p, S.Ac.v.p, trp.p, tci.p, tv.p, grp, gcd, gw, s);
+      cnt = to_host_int(grp.p, nc + 1, s);
+      HIPCK(hipStreamSynchronize(s));
+      gci = to_host_int(gcd.p, cnt[nc], s);
+      HIPCK(hipStreamSynchronize(s));
+    }
     phase("nested dissection: graph");
     std::vector<int> perm = nd_numbering(nc, cnt, gci, &S.nd_tree);
     phase("nested dissection: numbering");
