@@ -1095,24 +1095,42 @@ void or_precond_apply_twosolve(const or_solver *S, const double *z, double *q) {
     free(y); free(t); free(at); free(hc); free(gc);
 }
 
-/* Transposed preconditioner.  From Eq. (twogrid),
-   B~^{-1} = S^{-1} + M~^{-1} (I - A S^{-1}), hence
-   B~^{-T} = M~^{-T} + S^{-T} (I - A^T M~^{-T}) with M~^{-T} = P (L~ U~)^{-T} P^T
-   and S^{-T} = Q^T (L0 U0)^{-T} Q:
-     e_c = L~^{-T} U~^{-T} P^T z,  f = P e_c,  s = z - A^T f,
-     t = L0^{-T} U0^{-T} s,  q = f + t.
-   Only the exact coarse solve has a transpose here. */
-void or_precond_apply_adjoint(const or_solver *S, const double *z, double *q) {
-    const csr_t *A = &S->A;
-    int n = A->n, nc = S->nc;
+/* Transpose of the coarse solve, e = M~^{-T} b (b is overwritten).
+   coarse_mode 0: U~^T then L~^T by substitution.  coarse_mode 2: e = M^T b.
+   coarse_mode 1: the forward solve is J_U J_L with J_L = sum_{i<=k} (-N_L)^i
+   (L~ = I + N_L) and J_U = sum_{i<=k} (-D^{-1} N_U)^i D^{-1} (U~ = D + N_U);
+   since D^{-1} (-N_U^T D^{-1})^i = (-D^{-1} N_U^T)^i D^{-1}, its transpose
+   J_L^T J_U^T is k Jacobi sweeps on U~^T (diagonal D) followed by k sweeps on
+   L~^T, the products with N^T taken column by column from the rows of N. */
+static void coarse_solve_adjoint(const or_solver *S, double *b, double *e, double *t1, double *t2) {
+    int nc = S->nc;
     const csr_t *L = &S->Lc, *U = &S->Uc;
-    double *b = malloc(sizeof(double) * (size_t)nc + 8), *e = malloc(sizeof(double) * (size_t)nc + 8);
-    double *f = malloc(sizeof(double) * (size_t)n + 8), *s = malloc(sizeof(double) * (size_t)n + 8);
-    double *t = malloc(sizeof(double) * (size_t)n + 8);
-    double *u = malloc(sizeof(double) * (size_t)n + 8), *tt = malloc(sizeof(double) * (size_t)n + 8);
-    const csr_t *F = &S->F;
-    for (int I = 0; I < nc; ++I) b[I] = 0.0;
-    for (int k = 0; k < n; ++k) b[S->agg[k]] += z[k];
+    if (S->o.coarse_mode == 2) {
+        const csr_t *M = &S->Mc;
+        for (int j = 0; j < nc; ++j) e[j] = 0.0;
+        for (int i = 0; i < nc; ++i)
+            for (int p = M->rp[i]; p < M->rp[i + 1]; ++p) e[M->ci[p]] = e[M->ci[p]] + M->v[p] * b[i];
+        return;
+    }
+    if (S->o.coarse_mode == 1) {
+        /* J_U^T: t1 <- D^{-1} (b - N_U^T t1), t1 = D^{-1} b first */
+        for (int i = 0; i < nc; ++i) t1[i] = b[i] / U->v[U->rp[i]];
+        for (int sw = 0; sw < S->o.coarse_sweeps; ++sw) {
+            for (int i = 0; i < nc; ++i) t2[i] = b[i];
+            for (int j = 0; j < nc; ++j)
+                for (int p = U->rp[j] + 1; p < U->rp[j + 1]; ++p) t2[U->ci[p]] = t2[U->ci[p]] - U->v[p] * t1[j];
+            for (int i = 0; i < nc; ++i) t1[i] = t2[i] / U->v[U->rp[i]];
+        }
+        /* J_L^T: e <- t1 - N_L^T e, e = t1 first */
+        for (int i = 0; i < nc; ++i) e[i] = t1[i];
+        for (int sw = 0; sw < S->o.coarse_sweeps; ++sw) {
+            for (int i = 0; i < nc; ++i) t2[i] = t1[i];
+            for (int j = 0; j < nc; ++j)
+                for (int p = L->rp[j]; p < L->rp[j + 1]; ++p) t2[L->ci[p]] = t2[L->ci[p]] - L->v[p] * e[j];
+            for (int i = 0; i < nc; ++i) e[i] = t2[i];
+        }
+        return;
+    }
     /* U~^T e = b: U~^T is lower triangular, column-oriented substitution */
     for (int i = 0; i < nc; ++i) {
         e[i] = b[i] / U->v[U->rp[i]];
@@ -1121,6 +1139,26 @@ void or_precond_apply_adjoint(const or_solver *S, const double *z, double *q) {
     /* L~^T x = e: unit upper triangular */
     for (int i = nc - 1; i >= 0; --i)
         for (int p = L->rp[i]; p < L->rp[i + 1]; ++p) e[L->ci[p]] -= L->v[p] * e[i];
+}
+
+/* Transposed preconditioner.  From Eq. (twogrid),
+   B~^{-1} = S^{-1} + M~^{-1} (I - A S^{-1}), hence
+   B~^{-T} = M~^{-T} + S^{-T} (I - A^T M~^{-T}) with M~^{-T} = P (M~_c)^{-T} P^T
+   (M~_c the coarse solve) and S^{-T} = Q^T (L0 U0)^{-T} Q:
+     e_c = M~_c^{-T} P^T z,  f = P e_c,  s = z - A^T f,
+     t = L0^{-T} U0^{-T} s,  q = f + t. */
+void or_precond_apply_adjoint(const or_solver *S, const double *z, double *q) {
+    const csr_t *A = &S->A;
+    int n = A->n, nc = S->nc;
+    double *b = malloc(sizeof(double) * (size_t)nc + 8), *e = malloc(sizeof(double) * (size_t)nc + 8);
+    double *t1 = malloc(sizeof(double) * (size_t)nc + 8), *t2 = malloc(sizeof(double) * (size_t)nc + 8);
+    double *f = malloc(sizeof(double) * (size_t)n + 8), *s = malloc(sizeof(double) * (size_t)n + 8);
+    double *t = malloc(sizeof(double) * (size_t)n + 8);
+    double *u = malloc(sizeof(double) * (size_t)n + 8), *tt = malloc(sizeof(double) * (size_t)n + 8);
+    const csr_t *F = &S->F;
+    for (int I = 0; I < nc; ++I) b[I] = 0.0;
+    for (int k = 0; k < n; ++k) b[S->agg[k]] += z[k];
+    coarse_solve_adjoint(S, b, e, t1, t2);
     for (int k = 0; k < n; ++k) f[k] = e[S->agg[k]];
     spmv_t(A, f, s);
     for (int k = 0; k < n; ++k) s[k] = z[k] - s[k];
@@ -1135,7 +1173,7 @@ void or_precond_apply_adjoint(const or_solver *S, const double *z, double *q) {
         for (int p = F->rp[i]; p < S->dpos[i]; ++p) tt[F->ci[p]] -= S->ilu[p] * tt[i];
     for (int k = 0; k < n; ++k) t[S->fperm[k]] = tt[k];
     for (int k = 0; k < n; ++k) q[k] = f[k] + t[k];
-    free(b); free(e); free(f); free(s); free(t); free(u); free(tt);
+    free(b); free(e); free(t1); free(t2); free(f); free(s); free(t); free(u); free(tt);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1155,7 +1193,6 @@ int or_fgmres(const or_solver *S, int adjoint, int precision, const double *b, d
               double *hist, int hist_len) {
     int n = S->A.n;
     if (m < 1) return OR_ERR_INVALID;
-    if (adjoint && S->o.coarse_mode != 0) return OR_ERR_INVALID;
     for (int i = 0; i < n; ++i) if (!isfinite(b[i])) return OR_ERR_NONFINITE;
     if (!x0_given) for (int i = 0; i < n; ++i) x[i] = 0.0;
     double *V = malloc(sizeof(double) * (size_t)n * (m + 1) + 8);

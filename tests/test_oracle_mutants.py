@@ -36,6 +36,12 @@ MUTANTS = [
     ("jacobi_zero_start",
      [("for (int i = 0; i < nc; ++i) yc[i] = rc[i];  ", "for (int i = 0; i < nc; ++i) yc[i] = (T)0;   ")],
      pins.check_jacobi_closed_form),
+    ("adjoint_jacobi_untransposed",
+     [("t2[U->ci[p]] = t2[U->ci[p]] - U->v[p] * t1[j];", "t2[j] = t2[j] - U->v[p] * t1[U->ci[p]];")],
+     pins.check_adjoint_transpose),
+    ("adjoint_spai_untransposed",
+     [("e[M->ci[p]] = e[M->ci[p]] + M->v[p] * b[i];", "e[i] = e[i] + M->v[p] * b[M->ci[p]];")],
+     pins.check_adjoint_spai),
 ]
 
 

@@ -786,3 +786,45 @@ def test_spai_special_cases(oracle_mod):
     O0 = _mk(oracle_mod, A, agg=agg, coarse_mode=0, ilut_tau=0.0)
     z = rng.uniform(-1, 1, n)
     assert np.allclose(O2.apply(z), O0.apply(z), rtol=1e-12, atol=1e-13)
+
+
+ADJOINT_VARIANTS = {
+    "jacobi1": dict(coarse_mode=1, coarse_sweeps=1),
+    "jacobi3": dict(coarse_mode=1, coarse_sweeps=3),
+    "spai": dict(coarse_mode=2),
+    "nd": dict(fine_order=1),
+    "color": dict(fine_order=2),
+    "nd_jacobi": dict(fine_order=1, coarse_mode=1, coarse_sweeps=2),
+}
+
+
+def check_adjoint_transpose(oracle_mod, variant="jacobi3", case="fv2d"):
+    """The adjoint application of a variant is the transpose of its forward
+    application (column by column on the identity), and the adjoint FGMRES
+    solves A^T lambda = g."""
+    p = W.scaled("fv2d", 12) if case == "fv2d" else W.scaled("rgg", 300)
+    rp, ci, v = p.rowptr, p.col, p.val
+    O = oracle_mod.Oracle(rp, ci, v, **ADJOINT_VARIANTS[variant])
+    n = O.n
+    I = np.eye(n)
+    Bf = np.column_stack([O.apply(I[:, j]) for j in range(n)])
+    Ba = np.column_stack([O.apply_adjoint(I[:, j]) for j in range(n)])
+    err = np.abs(Ba - Bf.T).max() / np.abs(Bf).max()
+    assert err <= 1e-12, (variant, err)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    g = np.random.default_rng(1).uniform(-1, 1, n)
+    lam, info = O.solve(g, tol=1e-10, restart=n, maxit=n, adjoint=True)
+    assert info.status == 0 and np.linalg.norm(g - A.T @ lam) / np.linalg.norm(g) < 1e-10
+
+
+def check_adjoint_spai(oracle_mod):
+    check_adjoint_transpose(oracle_mod, "spai", "fv2d")
+
+
+@pytest.mark.parametrize("variant", list(ADJOINT_VARIANTS))
+@pytest.mark.parametrize("case", ["fv2d", "rgg"])
+def test_adjoint_apply_is_transpose_of_variants(oracle_mod, variant, case):
+    """For the inexact coarse solves (Jacobi sweeps, sparse approximate
+    inverse) and the reordered smoothers (the transposes of Eq. (twogrid)'s
+    parts, taken in reverse order)."""
+    check_adjoint_transpose(oracle_mod, variant, case)
