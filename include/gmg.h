@@ -103,7 +103,7 @@ typedef struct {
                            greedy colouring in natural order (red-black on 5-
                            and 7-point grids; multicolour ILU(0)), applied by
                            level sweeps with one level per colour.  Aggregates,
-                           A_c and its ILUT do not depend on it.  No adjoint.   */
+                           A_c and its ILUT do not depend on it.                */
 } gmg_options;
 
 typedef struct {
@@ -145,17 +145,20 @@ gmg_status gmg_solve(gmg_handle h, const double* b, double* x, int nrhs, double 
                      const gmg_options* opts, gmg_info* info);
 
 /* Adjoint solve A^T lambda = g, preconditioned by B~^{-T} (the exact transpose
- * of the two-grid operator of Eq. (twogrid): coarse correction with the
- * transposed ILUT factors, residual with A^T, transposed ILU(0) sweeps).  Not
- * in the paper: the backward pass of a differentiable solve.  Same layout,
- * batching and statuses as gmg_solve; requires coarse_mode 0, fine_order 0
- * and FP64 (else GMG_ERR_INVALID_ARG). */
+ * of the two-grid operator of Eq. (twogrid): the transposed coarse solve
+ * (transposed ILUT factors; for coarse_mode 1 the Jacobi sweeps on U~^T, then
+ * on L~^T; for 2 and 3 the transposed approximate or dense inverse), the
+ * residual with A^T, the transposed ILU(0) sweeps in the smoother's
+ * numbering).  Not in the paper: the backward pass of a differentiable solve.
+ * Same layout, batching and statuses as gmg_solve; every coarse_mode and
+ * fine_order; FP64 only (precond_fp32 must be 0, else GMG_ERR_INVALID_ARG). */
 gmg_status gmg_solve_adjoint(gmg_handle h, const double* g, double* lambda, int nrhs,
                              double tol, const gmg_options* opts, gmg_info* info);
 
 /* One application q = B~^{-1} z (adjoint: q = B~^{-T} z) of the two-grid
  * preconditioner, Algorithm 1 "SOLVE B~q = z" in its one-coarse-solve form
- * (device vectors of N doubles).  precision 0: FP64; 1: FP32 internally. */
+ * (device vectors of N doubles).  precision 0: FP64; 1: FP32 internally
+ * (the adjoint application is FP64 only). */
 gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int precision,
                              int adjoint);
 

@@ -77,6 +77,9 @@ struct Solver {
   Sweep L0, U0, Lc, Uc;        // forward factors
   Sweep U0t, L0t, Uct, Lct;    // transposed factors (adjoint)
   DCsr dLc, dUc;               // coarse factors as CSR (Jacobi mode)
+  DCsr dLcT, dUcT;             // their transposes (adjoint Jacobi sweeps)
+  DCsr dMcT;                   // transposed sparse approximate inverse (adjoint)
+  DBuf<double> cinvT;          // transposed dense inverse (adjoint)
   HCsr hMc;                    // sparse approximate inverse of A_c (coarse_mode 2)
   DCsr dMc;
   DBuf<double> cinv;           // dense A_c^{-1}, padded row-major (coarse_mode 3)
@@ -111,6 +114,8 @@ struct Solver {
   DBuf<int> fperm, frp, fci;
   std::vector<NdNode> fnd_tree;
   TreeSolve tL0, tU0;
+  TreeSolve tU0t, tL0t;       // their transposes (adjoint), when both follow the tree
+  bool ftree_adj = false;
   DBuf<double> fext, fzp, ftp;
   DBuf<float> fext32, fzp32, ftp32;
   // Krylov workspace
@@ -928,10 +933,22 @@ static void ensure_adjoint(Solver& S) {
   const int64_t nnz64 = S.nnz;
   const gmg_options& o = S.opt;
   {
-    // row j of U0^T lists i < j with (i, j) in strict U; of L0^T lists i > j with (i, j) in strict L
-    std::vector<int> hat_rp = to_host_int(S.AT.rp.p, n + 1, s);
-    std::vector<int> hat_ci = to_host_int(S.AT.ci.p, nnz64, s);
-    std::vector<int> hat_src = to_host_int(S.at_src.p, nnz64, s);
+    // row j of U0^T lists i < j with (i, j) in strict U; of L0^T lists i > j
+    // with (i, j) in strict L; src: the entry of the factored matrix (A, or
+    // F = Q A Q^T for the reordered smoothers) that holds the value
+    std::vector<int> hat_rp, hat_ci, hat_src;
+    if (!S.fine_nd) {
+      hat_rp = to_host_int(S.AT.rp.p, n + 1, s);
+      hat_ci = to_host_int(S.AT.ci.p, nnz64, s);
+      hat_src = to_host_int(S.at_src.p, nnz64, s);
+    } else {
+      DBuf<int> ftrp, ftci, ftsrc;
+      transpose_csr(n, n, nnz64, S.frp.p, S.fci.p, nullptr, ftrp, ftci, nullptr, &ftsrc, s);
+      hat_rp = to_host_int(ftrp.p, n + 1, s);
+      hat_ci = to_host_int(ftci.p, nnz64, s);
+      hat_src = to_host_int(ftsrc.p, nnz64, s);
+      HIPCK(hipStreamSynchronize(s));
+    }
     HIPCK(hipStreamSynchronize(s));
     std::vector<int> ut_rp(n + 1, 0), ut_ci, ut_src, lt_rp(n + 1, 0), lt_ci, lt_src;
     for (int j = 0; j < n; ++j) {
@@ -943,19 +960,38 @@ static void ensure_adjoint(Solver& S) {
       ut_rp[j + 1] = (int)ut_ci.size();
       lt_rp[j + 1] = (int)lt_ci.size();
     }
+    S.U0t.n = S.L0t.n = n;
+    S.U0t.nnz = (int64_t)ut_ci.size();
+    S.L0t.nnz = (int64_t)lt_ci.size();
+    S.U0t.has_diag = true;
+    S.ftree_adj = false;
     if (S.wave) {
       build_wave(S.wU0t, S.wg, ut_rp, ut_ci, ut_src, true, S.ilu.p, nnz64, S.u0dinv.p, n, s);
       build_wave(S.wL0t, S.wg, lt_rp, lt_ci, lt_src, false, S.ilu.p, nnz64, nullptr, n, s);
-      S.U0t.n = S.L0t.n = n;
-      S.U0t.nnz = (int64_t)ut_ci.size();
-      S.L0t.nnz = (int64_t)lt_ci.size();
-      S.U0t.has_diag = true;
     } else {
-      build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-      build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+      if (S.ftree) {
+        // the transposes of factors that follow the dissection tree follow it
+        // too (checked all the same)
+        std::vector<double> hilu(nnz64), hud(n);
+        d2h(hilu.data(), S.ilu.p, nnz64, s);
+        d2h(hud.data(), S.u0dinv.p, n, s);
+        HIPCK(hipStreamSynchronize(s));
+        S.ftree_adj = build_tree(S.tU0t, S.fnd_tree, n, ut_rp, ut_ci, &ut_src, 0, hilu, true, &hud, s) &&
+                      build_tree(S.tL0t, S.fnd_tree, n, lt_rp, lt_ci, &lt_src, 0, hilu, false, nullptr, s);
+        if (!S.ftree_adj) {
+          S.tU0t = TreeSolve();
+          S.tL0t = TreeSolve();
+        }
+      }
+      if (!S.ftree_adj) {
+        build_sweep(S.U0t, n, ut_rp, ut_ci, ut_src, nullptr, S.ilu.p, true, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+        build_sweep(S.L0t, n, lt_rp, lt_ci, lt_src, nullptr, S.ilu.p, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+      } else {
+        S.U0t.levels = S.L0t.levels = S.tU0t.heights;
+      }
     }
   }
-  {
+  if (o.coarse_mode == 0) {
     // U~^T row j lists i < j (strict part), L~^T row j lists i > j
     const HCsr &L = S.hLc, &U = S.hUc;
     std::vector<double> udinv(nc);
@@ -995,6 +1031,23 @@ static void ensure_adjoint(Solver& S) {
       build_sweep(S.Uct, nc, uct_cnt, uct_ci, uct_src, &U.v, nullptr, true, true, &udinv, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
       build_sweep(S.Lct, nc, lct_cnt, lct_ci, lct_src, &L.v, nullptr, false, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
     }
+  } else if (o.coarse_mode == 1) {
+    // the Jacobi sweeps of the adjoint run on L~^T and U~^T (the diagonal
+    // stays in U~^T's rows; the sweep skips it)
+    auto tr = [&](DCsr& T, const DCsr& F) {
+      T.n = T.m = nc;
+      T.nnz = F.nnz;
+      transpose_csr(nc, nc, F.nnz, F.rp.p, F.ci.p, F.v.p, T.rp, T.ci, &T.v, nullptr, s);
+    };
+    tr(S.dLcT, S.dLc);
+    tr(S.dUcT, S.dUc);
+  } else if (o.coarse_mode == 2) {
+    S.dMcT.n = S.dMcT.m = nc;
+    S.dMcT.nnz = S.dMc.nnz;
+    transpose_csr(nc, nc, S.dMc.nnz, S.dMc.rp.p, S.dMc.ci.p, S.dMc.v.p, S.dMcT.rp, S.dMcT.ci, &S.dMcT.v, nullptr, s);
+  } else {
+    S.cinvT.alloc((size_t)S.cnp * S.cnp);
+    launch_dense_transpose(nc, S.cnp, S.cinv.p, S.cinvT.p, s);
   }
   if (S.wave) {
     launch_fill_f64_bits(S.wy.p, kSent64, S.wg.total, s);
@@ -1004,8 +1057,90 @@ static void ensure_adjoint(Solver& S) {
   S.adj_ready = true;
 }
 
-// q = B~^{-T} z (FP64): ec = L~^{-T} U~^{-T} P^T z; s = z - A^T P ec;
-// t = L0^{-T} U0^{-T} s; q = P ec + t
+// ec = M~_c^{-T} bc, the transpose of the coarse solve (FP64; bc is the
+// restriction P^T z, ec holds the sentinel on entry)
+static void coarse_adjoint(Solver& S, double* bc, double* ec) {
+  hipStream_t s = S.s;
+  const int nc = S.nc;
+  if (S.opt.coarse_mode == 0 && S.tree_adj) {
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
+      launch_tree<double>(S.tUct, bc, false, S.auc.p, nullptr, S.text.p, S.abort_flag.p, s);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
+      launch_tree<double>(S.tLct, S.auc.p, false, ec, S.auc.p, S.text.p, S.abort_flag.p, s);
+    }
+  } else if (S.opt.coarse_mode == 0) {
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
+      run_tri<double>(S, S.Uct, bc, false, S.auc.p, nullptr);
+    }
+    {
+      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
+      run_tri<double>(S, S.Lct, S.auc.p, false, ec, S.auc.p);
+    }
+  } else if (S.opt.coarse_mode == 3) {
+    Prof p(S, PC_SWEEP_COARSE, (double)nc * nc * 8 + (double)nc * 16);
+    launch_dense_gemv<double>(nc, S.cnp, S.cinvT.p, bc, ec, s);
+  } else if (S.opt.coarse_mode == 2) {
+    Prof p(S, PC_SWEEP_COARSE, (double)S.dMcT.nnz * 12 + (double)nc * 20);
+    launch_spmv<double>(nc, S.dMcT.rp.p, S.dMcT.ci.p, S.dMcT.v.p, bc, ec, s);
+  } else {
+    // the forward sweeps' transpose, factor by factor in reverse order: e <-
+    // D^{-1} (bc - (U~^T - D) e) from e = D^{-1} bc, then y <- e - (L~^T - I) y
+    // from y = e
+    Prof p(S, PC_SWEEP_COARSE, 0.0);
+    double* E[2] = {S.auc.p, S.jtmp.p};
+    int c = 0;
+    launch_jacobi(nc, S.dUcT.rp.p, S.dUcT.ci.p, S.dUcT.v.p, S.ucdinv.p, bc, S.jzero.p, E[0], s);
+    for (int k = 0; k < S.opt.coarse_sweeps; ++k) {
+      launch_jacobi(nc, S.dUcT.rp.p, S.dUcT.ci.p, S.dUcT.v.p, S.ucdinv.p, bc, E[c], E[1 - c], s);
+      c = 1 - c;
+    }
+    const double* e = E[c];
+    double* Y[2] = {ec, E[1 - c]};
+    int d = 0;
+    d2d(ec, e, nc, s);
+    for (int k = 0; k < S.opt.coarse_sweeps; ++k) {
+      launch_jacobi(nc, S.dLcT.rp.p, S.dLcT.ci.p, S.dLcT.v.p, nullptr, e, Y[d], Y[1 - d], s);
+      d = 1 - d;
+    }
+    if (Y[d] != ec) d2d(ec, Y[d], nc, s);
+  }
+}
+
+// t = S^{-T} sv = Q^T L0^{-T} U0^{-T} Q sv (FP64; one column)
+static void smooth_adjoint(Solver& S, const double* sv, double* t) {
+  hipStream_t s = S.s;
+  if (S.wave) {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false) + sweep_bytes(S.L0t, 8, 8, true));
+    launch_wave_pair<double>(S.wg, S.wU0t, S.wL0t, sv, true, S.wz.p, S.wy.p, S.wt.p, t, S.abort_flag.p, s);
+  } else if (S.fine_nd) {
+    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false) + sweep_bytes(S.L0t, 8, 8, true) + (double)S.n * 40);
+    launch_perm_gather<double>(S.n, S.fperm.p, sv, S.fzp.p, s);
+    if (S.ftree_adj) {
+      launch_tree<double>(S.tU0t, S.fzp.p, false, S.y.p, nullptr, S.fext.p, S.abort_flag.p, s);
+      launch_tree<double>(S.tL0t, S.y.p, false, S.ftp.p, S.y.p, S.fext.p, S.abort_flag.p, s);
+    } else {
+      run_tri<double>(S, S.U0t, S.fzp.p, false, S.y.p, nullptr);
+      run_tri<double>(S, S.L0t, S.y.p, false, S.ftp.p, S.y.p);
+    }
+    launch_perm_scatter<double>(S.n, S.fperm.p, S.ftp.p, t, s);
+  } else {
+    {
+      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
+      run_tri<double>(S, S.U0t, sv, false, S.aw.p, nullptr);
+    }
+    {
+      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
+      run_tri<double>(S, S.L0t, S.aw.p, false, t, S.aw.p);
+    }
+  }
+}
+
+// q = B~^{-T} z (FP64), the transpose of Eq. (twogrid)'s operator:
+// ec = M~_c^{-T} P^T z; s = z - A^T P ec; t = S^{-T} s; q = P ec + t
 static void vcycle_adjoint(Solver& S, const double* z, double* q) {
   ensure_adjoint(S);
   hipStream_t s = S.s;
@@ -1013,45 +1148,17 @@ static void vcycle_adjoint(Solver& S, const double* z, double* q) {
     Prof p(S, PC_RESID_RESTRICT, (double)S.n * 12 + (double)S.nc * 16);
     launch_restrict_plain(S.nc, S.aptr.p, S.amem.p, z, S.abc.p, S.aec.p, 0, s);
   }
-  if (S.tree_adj) {
-    {
-      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
-      launch_tree<double>(S.tUct, S.abc.p, false, S.auc.p, nullptr, S.text.p, S.abort_flag.p, s);
-    }
-    {
-      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
-      launch_tree<double>(S.tLct, S.auc.p, false, S.aec.p, S.auc.p, S.text.p, S.abort_flag.p, s);
-    }
-  } else {
-    {
-      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
-      run_tri<double>(S, S.Uct, S.abc.p, false, S.auc.p, nullptr);
-    }
-    {
-      Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
-      run_tri<double>(S, S.Lct, S.auc.p, false, S.aec.p, S.auc.p);
-    }
-  }
+  coarse_adjoint(S, S.abc.p, S.aec.p);
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * 12 + (double)S.n * 24);
     launch_resid_adj(S.n, S.AT.rp.p, S.AT.ci.p, S.AT.v.p, S.agg.p, S.aec.p, z, S.as.p, s);
   }
-  if (S.wave) {
-    Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false) + sweep_bytes(S.L0t, 8, 8, true));
-    launch_wave_pair<double>(S.wg, S.wU0t, S.wL0t, S.as.p, true, S.wz.p, S.wy.p, S.wt.p, S.at.p, S.abort_flag.p, s);
-  } else {
-    {
-      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
-      run_tri<double>(S, S.U0t, S.as.p, false, S.aw.p, nullptr);
-    }
-    {
-      Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
-      run_tri<double>(S, S.L0t, S.aw.p, false, S.at.p, S.aw.p);
-    }
-  }
+  smooth_adjoint(S, S.as.p, S.at.p);
   {
+    // t is reset to the sentinel only where the level sweeps produce it
+    const bool reset_t = !S.wave && !S.fine_nd;
     Prof p(S, PC_PROLONG, (double)S.n * 28 + (double)S.nc * 8);
-    launch_prolong<double>(S.n, S.agg.p, S.at.p, S.aec.p, q, 0, s, !S.wave);
+    launch_prolong<double>(S.n, S.agg.p, S.at.p, S.aec.p, q, 0, s, reset_t);
   }
 }
 
@@ -1457,7 +1564,7 @@ static void vcycle_adjoint_batch(Solver& S, const double* z, size_t ldz, double*
     Prof p(S, PC_RESID_RESTRICT, nb * ((double)S.n * 12 + (double)S.nc * 16));
     launch_restrict_cols(S.nc, S.aptr.p, S.amem.p, z, ldz, B.abc.p, B.aec.p, ldc, nb, s);
   }
-  if (S.tree_adj) {
+  if (S.opt.coarse_mode == 0 && S.tree_adj) {
     {
       Prof p(S, PC_SWEEP_COARSE, nb * sweep_bytes(S.Uct, 8, 8, false));
       launch_tree<double>(S.tUct, B.abc.p, false, B.auc.p, nullptr, B.text.p, S.abort_flag.p, s, nb, ldc, B.ncUct.p);
@@ -1467,16 +1574,7 @@ static void vcycle_adjoint_batch(Solver& S, const double* z, size_t ldz, double*
       launch_tree<double>(S.tLct, B.auc.p, false, B.aec.p, B.auc.p, B.text.p, S.abort_flag.p, s, nb, ldc, B.ncLct.p);
     }
   } else {
-    for (int c = 0; c < nb; ++c) {
-      {
-        Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Uct, 8, 8, false));
-        run_tri<double>(S, S.Uct, B.abc.p + c * ldc, false, S.auc.p, nullptr);
-      }
-      {
-        Prof p(S, PC_SWEEP_COARSE, sweep_bytes(S.Lct, 8, 8, true));
-        run_tri<double>(S, S.Lct, S.auc.p, false, B.aec.p + c * ldc, S.auc.p);
-      }
-    }
+    for (int c = 0; c < nb; ++c) coarse_adjoint(S, B.abc.p + c * ldc, B.aec.p + c * ldc);
   }
   {
     Prof p(S, PC_RESID_RESTRICT, (double)S.nnz * 12 + (double)S.n * 4 + nb * ((double)S.n * 24 + (double)S.nc * 8));
@@ -1487,16 +1585,7 @@ static void vcycle_adjoint_batch(Solver& S, const double* z, size_t ldz, double*
     launch_wave_pair<double>(S.wg, S.wU0t, S.wL0t, B.as.p, true, B.wz.p, B.wy.p, B.wt.p, B.at.p, S.abort_flag.p, s, nb,
                              ld, ld);
   } else {
-    for (int c = 0; c < nb; ++c) {
-      {
-        Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.U0t, 8, 8, false));
-        run_tri<double>(S, S.U0t, B.as.p + c * ld, false, S.aw.p, nullptr);
-      }
-      {
-        Prof p(S, PC_SWEEP_FINE, sweep_bytes(S.L0t, 8, 8, true));
-        run_tri<double>(S, S.L0t, S.aw.p, false, B.at.p + c * ld, S.aw.p);
-      }
-    }
+    for (int c = 0; c < nb; ++c) smooth_adjoint(S, B.as.p + c * ld, B.at.p + c * ld);
   }
   {
     Prof p(S, PC_PROLONG, nb * ((double)S.n * 28 + (double)S.nc * 8));
@@ -1713,8 +1802,7 @@ static gmg_status solve_impl(Solver& S, bool adjoint, const double* b, double* x
   }
   if (opt.restart < 1 || opt.restart > kMaxRestart) fail(GMG_ERR_INVALID_ARG, "restart must be in [1, 2048]");
   if (opt.maxit < 0) fail(GMG_ERR_INVALID_ARG, "maxit must be >= 0");
-  if (adjoint && (opt.precond_fp32 || S.opt.coarse_mode != 0 || S.fine_nd))
-    fail(GMG_ERR_INVALID_ARG, "the adjoint solve needs coarse_mode 0, fine_order 0 and FP64");
+  if (adjoint && opt.precond_fp32) fail(GMG_ERR_INVALID_ARG, "the adjoint solve runs in FP64 (precond_fp32 0)");
   auto t0 = std::chrono::steady_clock::now();
   reset_cycle_buffers(S);
   S.hist.clear();
@@ -2422,8 +2510,7 @@ gmg_status gmg_apply_precond(gmg_handle h, const double* z, double* q, int preci
     Solver& S = h->S;
     gmg::reset_cycle_buffers(S);
     if (adjoint) {
-      if (precision != 0 || S.opt.coarse_mode != 0 || S.fine_nd)
-        gmg::fail(GMG_ERR_INVALID_ARG, "adjoint apply is FP64, coarse_mode 0, fine_order 0");
+      if (precision != 0) gmg::fail(GMG_ERR_INVALID_ARG, "the adjoint apply runs in FP64 (precision 0)");
       gmg::vcycle_adjoint(S, z, q);
     } else if (precision == 1) {
       gmg::vcycle<float>(S, z, q);

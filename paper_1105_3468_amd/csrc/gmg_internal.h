@@ -235,6 +235,8 @@ void launch_dense_inverse(int nc, int np, const int* rp, const int* ci, const do
                           hipStream_t s);
 template <class T>
 void launch_dense_gemv(int n, int np, const T* M, const T* r, T* e, hipStream_t s);
+// MT = M^T (leading n x n block, row stride np)
+void launch_dense_transpose(int n, int np, const double* M, double* MT, hipStream_t s);
 // CSR SpMV y = A x; T = value/vector type.  cap: products of a 256-row tile
 // staged in LDS (2048 or 4096; spmv_cap picks it from the largest tile, and
 // tiles beyond it are computed from global memory)

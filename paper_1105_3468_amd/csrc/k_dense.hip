@@ -188,6 +188,28 @@ void launch_dense_gemv(int n, int np, const T* M, const T* r, T* e, hipStream_t 
   HIPCK(hipGetLastError());
 }
 template void launch_dense_gemv<double>(int, int, const double*, const double*, double*, hipStream_t);
+
+// MT = M^T for the leading n x n block of padded row-major matrices (the
+// adjoint cycle's coarse solve then reuses the product above): 64 x 64 tiles
+// through LDS, read and written along rows
+__global__ __launch_bounds__(256) void k_dense_transpose(int n, int np, const double* __restrict__ M,
+                                                         double* __restrict__ MT) {
+  __shared__ double tile[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4)
+    if (r0 + r < n && c0 + tx < n) tile[r][tx] = M[(size_t)(r0 + r) * np + c0 + tx];
+  __syncthreads();
+  for (int c = ty; c < 64; c += 4)
+    if (c0 + c < n && r0 + tx < n) MT[(size_t)(c0 + c) * np + r0 + tx] = tile[tx][c];
+}
+
+void launch_dense_transpose(int n, int np, const double* M, double* MT, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned t = (unsigned)((n + 63) / 64);
+  hipLaunchKernelGGL(k_dense_transpose, dim3(t, t), dim3(256), 0, s, n, np, M, MT);
+  HIPCK(hipGetLastError());
+}
 template void launch_dense_gemv<float>(int, int, const float*, const float*, float*, hipStream_t);
 
 }  // namespace gmg
