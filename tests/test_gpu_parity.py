@@ -443,7 +443,8 @@ def test_fine_nd_smoother(name, kernel, fo):
     """GMG-ND (Section 3.1 variants, fo = 1) and the multicolour smoother
     (fo = 2): the smoother's numbering and its ILU(0) factors bit-exact vs the
     oracle; one application in FP64 within 1e-13 of the magnitudes flowing into each entry, in FP32 within the FP32 bar;
-    a converged solve within one step of the oracle's; the adjoint refused.
+    a converged solve within one step of the oracle's; the adjoint application
+    entry by entry (its FP32 form refused).
     kernel 0: tree solves over the dissection tree (fo = 1) or the automatic
     level sweeps (fo = 2); 1: whole-device level sweeps."""
     _say(f"[case] fine_order={fo} {name} sweep_kernel={kernel}")
@@ -472,8 +473,10 @@ def test_fine_nd_smoother(name, kernel, fo):
     assert res.status == G.OK and np.linalg.norm(b - A @ xh) / np.linalg.norm(b) < 1e-8, res.info
     _, info = O.solve(b, tol=1e-8)
     assert abs(res.info["iters"] - info.steps) <= 1, (res.info["iters"], info.steps)
+    qa = S.apply(torch.as_tensor(z, device="cuda"), precision=0, adjoint=True).cpu().numpy()
+    _elementwise(O, A, z, qa, O.apply_adjoint(z), 1e-13, f"fine_order={fo} {name} adjoint", adjoint=True)
     with pytest.raises(GmgError):
-        S.apply(torch.as_tensor(z, device="cuda"), precision=0, adjoint=True)
+        S.apply(torch.as_tensor(z, device="cuda"), precision=1, adjoint=True)
     if kernel == 0 and fo == 1:
         S0 = Solver(p.rowptr, p.col, p.val)
         assert np.array_equal(S0.fine_perm().cpu().numpy(), np.arange(p.n_rows))
