@@ -82,8 +82,9 @@ typedef struct {
   int coarse_order;     /* numbering of the aggregates, hence of A_c and its ILUT
                            factors: 0 by smallest fine index; 1 nested dissection
                            of A_c's graph (default)                                   */
-  int sweep_kernel;     /* 0 (default): fine factors with 2D-grid structure use the
-                           wavefront sweep, coarse factors in nested-dissection
+  int sweep_kernel;     /* 0 (default): fine factors with 2D- or 3D-grid structure
+                           (five- or seven-point operators in natural order) use
+                           the wavefront sweep, coarse factors in nested-dissection
                            order the tree solve, other factors the level sweeps
                            (single-CU ring for narrow factors, else level ranges
                            on one workgroup or the whole device); 3: as 0 but

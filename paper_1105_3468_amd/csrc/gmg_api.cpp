@@ -1898,12 +1898,46 @@ static int grid2d_nx(int n, const std::vector<int>& dep_rp, const std::vector<in
   return nx;
 }
 
+// (nx, ny) of a 3D grid: every dependency of row k is k -+ 1 within a grid
+// line of nx cells, k -+ nx within a plane of nx * ny cells or k -+ nx * ny,
+// all three offsets occur, and there are at least two planes; false otherwise
+static bool grid3d_dims(int n, const std::vector<int>& dep_rp, const std::vector<int>& dep_ci, bool lower, int& gx,
+                        int& gy) {
+  int d1 = 0, d2 = 0, d3 = 0;  // the distinct offsets, ascending
+  for (int k = 0; k < n; ++k)
+    for (int q = dep_rp[k]; q < dep_rp[k + 1]; ++q) {
+      const int d = lower ? k - dep_ci[q] : dep_ci[q] - k;
+      if (d <= 0) return false;
+      if (d == d1 || d == d2 || d == d3) continue;
+      if (d3 != 0) return false;  // a fourth offset
+      if (d1 == 0 || d < d1) { d3 = d2; d2 = d1; d1 = d; }
+      else if (d2 == 0 || d < d2) { d3 = d2; d2 = d; }
+      else d3 = d;
+    }
+  if (d1 != 1 || d2 < 2 || d3 <= d2 || d3 % d2 != 0 || n % d3 != 0 || n / d3 < 2) return false;
+  const int nx = d2, nxy = d3;
+  for (int k = 0; k < n; ++k)
+    for (int q = dep_rp[k]; q < dep_rp[k + 1]; ++q) {
+      const int d = lower ? k - dep_ci[q] : dep_ci[q] - k;
+      if (d == 1 && (lower ? k % nx == 0 : k % nx == nx - 1)) return false;                 // crosses a grid line
+      if (d == nx && (lower ? k % nxy < nx : k % nxy >= nxy - nx)) return false;           // crosses a plane
+    }
+  gx = nx;
+  gy = nxy / nx;
+  return true;
+}
+
 static int wave_cell_host(int64_t q, const WaveGrid& g) {
   const int l = (int)(q & 63);
   const int64_t ws = q >> 6;
   const int w = (int)(ws / g.S), s = (int)(ws - (int64_t)w * g.S);
-  const int j = 64 * w + l, i = s - l;
-  return (i >= 0 && i < g.nx && j < g.ny) ? j * g.nx + i : -1;
+  if (g.nz == 0) {
+    const int j = 64 * w + l, i = s - l;
+    return (i >= 0 && i < g.nx && j < g.ny) ? j * g.nx + i : -1;
+  }
+  const int yy = l & 7, zz = l >> 3, ty = w % g.TY, tz = w / g.TY;
+  const int x = s - yy - zz, y = 8 * ty + yy, z = 8 * tz + zz;
+  return (x >= 0 && x < g.nx && y < g.ny && z < g.nz) ? (z * g.ny + y) * g.nx + x : -1;
 }
 
 // Lay a factor out for the wavefront sweep: values from vals_dev (entries
@@ -1912,6 +1946,48 @@ static void build_wave(WaveSweep& f, const WaveGrid& g, const std::vector<int>& 
                        const std::vector<int>& dep_ci, const std::vector<int>& dep_src, bool lower,
                        const double* vals_dev, int64_t nvals, const double* dinv_dev, int n, hipStream_t s) {
   f.has_diag = dinv_dev != nullptr;
+  if (g.nz > 0) {
+    // quads (z, y, x neighbour, reciprocal diagonal) gathered from one buffer:
+    // the factor's values, then the reciprocal diagonal, then a zero
+    const int64_t T4 = 4 * g.total;
+    const int64_t zero = nvals + n;
+    const int nx = g.nx, nxy = g.nx * g.ny;
+    std::vector<int> qidx(T4);
+    parallel_ranges((int)g.total, [&](int p0, int p1, int) {
+      for (int64_t p = p0; p < p1; ++p) {
+        const int c = wave_cell_host(lower ? p : g.total - 1 - p, g);
+        int iz = (int)zero, iy = (int)zero, ix = (int)zero, id = (int)zero;
+        if (c >= 0) {
+          const int cz = lower ? c - nxy : c + nxy, cy = lower ? c - nx : c + nx, cx = lower ? c - 1 : c + 1;
+          for (int q = dep_rp[c]; q < dep_rp[c + 1]; ++q) {
+            if (dep_ci[q] == cz) iz = dep_src[q];
+            if (dep_ci[q] == cy) iy = dep_src[q];
+            if (dep_ci[q] == cx) ix = dep_src[q];
+          }
+          if (f.has_diag) id = (int)(nvals + c);
+        }
+        qidx[4 * p] = iz;
+        qidx[4 * p + 1] = iy;
+        qidx[4 * p + 2] = ix;
+        qidx[4 * p + 3] = id;
+      }
+    });
+    DBuf<double> src;
+    src.alloc(zero + 1);
+    d2d(src.p, vals_dev, nvals, s);
+    if (f.has_diag) d2d(src.p + nvals, dinv_dev, n, s);
+    else launch_fill_f64_bits(src.p + nvals, 0ULL, n, s);
+    launch_fill_f64_bits(src.p + zero, 0ULL, 1, s);
+    DBuf<int> ix;
+    ix.alloc(T4);
+    h2d(ix.p, qidx.data(), T4, s);
+    f.coef.alloc(T4);
+    f.coef32.alloc(T4);
+    launch_gather_f64(src.p, ix.p, f.coef.p, T4, s);
+    launch_cast_f32(f.coef.p, f.coef32.p, T4, s);
+    HIPCK(hipStreamSynchronize(s));
+    return;
+  }
   const int64_t T2 = 2 * g.total;
   std::vector<int> cidx(T2), didx(f.has_diag ? g.total : 0);
   parallel_ranges((int)g.total, [&](int p0, int p1, int) {
@@ -2183,10 +2259,16 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   // 2D-grid structure of both fine factors (their transposes then have it
   // too: the same offsets, mirrored): wavefront sweeps, and an ILU(0) in one
   // launch over the grid's anti-diagonals
-  int grid_nx = 0;
+  int grid_nx = 0, grid3_nx = 0, grid3_ny = 0;
   if ((o.sweep_kernel == 0 || o.sweep_kernel == 3) && !S.fine_nd) {
     const int nx = grid2d_nx(n, l_rp, l_ci, true);
     if (nx > 0 && grid2d_nx(n, u_rp, u_ci, false) == nx) grid_nx = nx;
+    int lx = 0, ly = 0, ux = 0, uy = 0;
+    if (grid_nx == 0 && grid3d_dims(n, l_rp, l_ci, true, lx, ly) && grid3d_dims(n, u_rp, u_ci, false, ux, uy) &&
+        lx == ux && ly == uy) {
+      grid3_nx = lx;
+      grid3_ny = ly;
+    }
   }
   // ---- ILU(0)
   S.ilu.alloc(nnz64);
@@ -2219,8 +2301,8 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   S.u0dinv.alloc(n);
   hipLaunchKernelGGL(k_recip_diag, dim3((n + 255) / 256), dim3(256), 0, s, n, S.ilu.p, S.dpos.p, S.u0dinv.p);
   HIPCK(hipGetLastError());
-  // wavefront form when both fine factors have 2D-grid structure; else the
-  // level-scheduled sweeps
+  // wavefront form when both fine factors have 2D- or 3D-grid structure;
+  // else the level-scheduled sweeps
   S.wave = false;
   if (grid_nx > 0) {
     const int nx = grid_nx;
@@ -2243,6 +2325,30 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       S.U0.has_diag = true;
       S.L0.levels = S.U0.levels = g.nx + g.ny - 1;
       phase("wavefront layout");
+    }
+  } else if (grid3_nx > 0) {
+    WaveGrid& g = S.wg;
+    g.nx = grid3_nx;
+    g.ny = grid3_ny;
+    g.nz = n / (grid3_nx * grid3_ny);
+    g.TY = (g.ny + 7) / 8;
+    g.W = g.TY * ((g.nz + 7) / 8);
+    g.S = (g.nx + 14 + 7) / 8 * 8;  // whole pairs of chunks of the 3D kernel
+    g.total = (int64_t)g.W * g.S * 64;
+    if (g.total < INT32_MAX / 4 && nnz64 + n < INT32_MAX) {
+      build_wave(S.wL0, g, l_rp, l_ci, l_src, true, S.ilu.p, nnz64, nullptr, n, s);
+      build_wave(S.wU0, g, u_rp, u_ci, u_src, false, S.ilu.p, nnz64, S.u0dinv.p, n, s);
+      S.wz.alloc(g.total); S.wy.alloc(g.total); S.wt.alloc(g.total);
+      S.wz32.alloc(g.total); S.wy32.alloc(g.total); S.wt32.alloc(g.total);
+      S.wave = true;
+      S.L0.n = S.U0.n = n;
+      S.L0.nnz = (int64_t)l_ci.size();
+      S.U0.nnz = (int64_t)u_ci.size();
+      S.U0.has_diag = true;
+      S.L0.levels = S.U0.levels = g.nx + g.ny + g.nz - 2;
+      phase("wavefront layout (3D)");
+    } else {
+      g = WaveGrid();
     }
   }
   if (S.fine_nd && o.fine_order == 1 && o.sweep_kernel == 0) {

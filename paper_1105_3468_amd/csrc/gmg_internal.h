@@ -148,17 +148,21 @@ struct Sweep {
   std::unique_ptr<CuSweep> cu;  // single-CU form, for narrow factors (null otherwise)
 };
 
-// Wavefront sweeps of factors with 2D-grid structure (k_wave.hip): grid of
-// nx columns and ny rows, W waves of 64 grid rows, S = nx + 63 steps per
-// wave, total = W * S * 64 positions (the lower layout; an upper factor uses
-// it backwards).
+// Wavefront sweeps of factors with 2D- or 3D-grid structure (k_wave.hip).
+// 2D (nz == 0): grid of nx columns and ny rows, W waves of 64 grid rows,
+// S = nx + 63 steps per wave (rounded up).  3D: nx x ny x nz cells, W = TY * TZ
+// tiles of 8 x 8 grid lines (TY = ceil(ny / 8)), S = nx + 14 steps
+// (rounded up).  total = W * S * 64 positions (the lower layout; an upper
+// factor uses it backwards).
 struct WaveGrid {
   int nx = 0, ny = 0, W = 0, S = 0;
+  int nz = 0, TY = 0;
   int64_t total = 0;
 };
-// One factor in that layout: coef holds (neighbour below, left neighbour)
-// coefficient pairs per position, zero where absent or outside the grid;
-// dinv the reciprocal diagonal per position when the factor stores one.
+// One factor in that layout.  2D: coef holds (neighbour below, left
+// neighbour) coefficient pairs per position, zero where absent or outside the
+// grid, and dinv the reciprocal diagonal per position when the factor stores
+// one.  3D: coef holds (z, y, x neighbour, reciprocal diagonal) quads.
 struct WaveSweep {
   bool has_diag = false;
   DBuf<double> coef, dinv;

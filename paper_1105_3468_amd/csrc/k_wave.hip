@@ -337,23 +337,291 @@ __global__ __launch_bounds__(WAVE_THREADS) void k_wave(int S, int nx, int64_t to
   }
 }
 
+// ------------------------------------------------------------- 3D grids
+// Factors with the structure of a 3D grid of nx x ny x nz cells: row
+// k = (z * ny + y) * nx + x of a lower factor depends at most on k - 1 (same
+// grid line), k - nx (same plane) and k - nx * ny; ILU(0) of a seven-point
+// operator in natural order has exactly this structure.  A wave owns a tile
+// of 8 x 8 grid lines, lane l = 8 zz + yy holding the line y = 8 ty + yy,
+// z = 8 tz + zz, and walks x with a skew of yy + zz: at step s lane l treats
+// x = s - yy - zz.  All three dependencies are then results of the previous
+// step: x - 1 in the lane's own register, y - 1 in lane l - 1 (DPP shift),
+// z - 1 in lane l - 8 (a lane permute).  Lanes on the tile's low-y face
+// (yy = 0) take y - 1 from the tile before it in y (its lanes yy = 7, seven
+// steps later in its walk), lanes on the low-z face from the tile before it
+// in z, through memory (value-as-flag); a poller wave streams both faces into
+// LDS rings.  Tiles are numbered w = tz * TY + ty, so both neighbours of a
+// tile have lower indices, and a tile runs seven steps plus one
+// publish-and-poll hop behind each of them: the longest chain is
+// TY + TZ - 2 hops, against nx + ny + nz - 2 dependency levels for the
+// general sweep.  Positions p = (w * S + s) * 64 + l with S = nx + 14
+// rounded up to whole pairs of chunks; as for the 2D grid, out-of-grid
+// positions hold zero coefficients and right-hand side, and the upper layout
+// is the lower one read backwards (lanes, steps and tiles all reverse, which
+// maps the reversed grid's tiles onto the same pattern).
+constexpr int W3_CH = 4;
+constexpr int W3_D = 2;
+constexpr int W3_SLOTS = 10;
+constexpr int W3_RING = W3_CH * W3_SLOTS;
+constexpr int W3_PRODUCERS = 4;
+constexpr int W3_XRING = 128;
+constexpr int W3_THREADS = 64 * (2 + W3_PRODUCERS);
+static_assert(W3_XRING % 8 == 0 && W3_XRING % W3_CH == 0, "ring rows must not wrap within a poll or a chunk");
+
+// coefficients of one position of a 3D layout: z - 1, y - 1, x - 1
+// neighbours (z + 1, y + 1, x + 1 for upper factors) and the reciprocal
+// diagonal (unused by factors without one)
+template <class T>
+struct alignas(4 * sizeof(T)) Quad {
+  T cz, cy, cx, d;
+};
+template <class T>
+struct alignas(4 * sizeof(T)) WaveOp3 {
+  T cz, cy, cx, b;
+};
+
+// lane l receives lane l - 8's value (lanes 0 .. 7 receive lanes 56 .. 63's,
+// which the caller replaces); `addr` = ((l - 8) & 63) * 4
+__device__ __forceinline__ int lane_up8(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+__device__ __forceinline__ float lane_up8(int addr, float v) {
+  return __builtin_bit_cast(float, lane_up8(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_up8(int addr, double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)lane_up8(addr, (int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)lane_up8(addr, (int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One workgroup per tile: wave 0 computes, waves 1 .. W3_PRODUCERS stream
+// the operands into an LDS ring as in the 2D kernel, the last wave polls the
+// two neighbouring tiles' faces.  LOWER: terms in the order z, y, x (the
+// ascending column order of a lower factor), else x, y, z.  nb columns as in
+// the 2D kernel: workgroup w * nb + r runs tile w of column r.
+template <class T, bool DIAG, bool LOWER, bool REV>
+__global__ __launch_bounds__(W3_THREADS) void k_wave3(int S, int TY, int64_t total, const Quad<T>* __restrict__ coef,
+                                                      const T* __restrict__ rhs, T* out, int* abort_flag,
+                                                      uint64_t limit, int nb) {
+  __shared__ WaveOp3<T> r_op[W3_RING][64];
+  __shared__ T r_d[DIAG ? W3_RING : 1][64];
+  __shared__ T r_by[W3_XRING][8];  // face y - 1 of steps s (index zz)
+  __shared__ T r_bz[W3_XRING][8];  // face z - 1 (index yy)
+  __shared__ int ready[W3_SLOTS];
+  __shared__ int xready;
+  __shared__ int consumed;
+  const int w = blockIdx.x / nb, l = threadIdx.x & 63, role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  {
+    const int col = blockIdx.x - w * nb;
+    rhs += (int64_t)col * total;
+    out += (int64_t)col * total;
+  }
+  const int ty = w % TY, tz = w / TY;
+  const int64_t p0 = (int64_t)w * S * 64 + l;
+  const int nchunks = S / W3_CH;
+  if (threadIdx.x < W3_SLOTS) ready[threadIdx.x] = 0;
+  if (threadIdx.x == 0) { consumed = 0; xready = 0; }
+  // the face rings start at zero: tiles on the grid's low faces read them
+  // for every step against zero coefficients
+  for (int i = threadIdx.x; i < W3_XRING * 8; i += W3_THREADS) {
+    r_by[i >> 3][i & 7] = (T)0;
+    r_bz[i >> 3][i & 7] = (T)0;
+  }
+  __syncthreads();
+
+  // face values exist for steps s < xn (the neighbour's step s + 7); later
+  // steps only meet zero coefficients
+  const int xn = S - 7;
+  const bool hy = ty > 0, hz = tz > 0;
+  if (role == 1 + W3_PRODUCERS) {
+    // ------------------------------------------- the neighbouring faces
+    if (!hy && !hz) return;
+    // lane l polls step next + l / 8: face y - 1 at zz = l % 8 (the y
+    // neighbour's lane 8 zz + 7) and face z - 1 at yy = l % 8 (the z
+    // neighbour's lane 56 + yy)
+    const int j = l & 7, sl = l >> 3;
+    const T* py = out + ((int64_t)(w - (hy ? 1 : 0)) * S + 7) * 64 + 8 * j + 7;
+    const T* pz = out + ((int64_t)(w - (hz ? TY : 0)) * S + 7) * 64 + 56 + j;
+    int next = 0;
+    const uint64_t t0 = wall_clock64();
+    unsigned it = 0;
+#pragma clang loop unroll(disable)
+    while (next < xn) {
+      if (!wait_lds_at_least<4>(&consumed, next + 8 - W3_XRING, abort_flag, limit)) return;
+      const int s = next + sl;
+      T vy = (T)0, vz = (T)0;
+      if (s < xn) {
+        if (hy) vy = ld_agent(py + (int64_t)s * 64);
+        if (hz) vz = ld_agent(pz + (int64_t)s * 64);
+      }
+      const uint64_t pend = __ballot(s < xn && (is_sentinel(vy) || is_sentinel(vz)));
+      const int k = pend ? (int)(__builtin_ctzll(pend) >> 3) : 8;  // leading complete steps
+      if (k > 0) {
+        if (sl < k) {
+          r_by[s % W3_XRING][j] = vy;
+          r_bz[s % W3_XRING][j] = vz;
+        }
+        lds_release();
+        next = std::min(next + k, xn);
+        if (l == 0) __hip_atomic_store(&xready, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++it & 63u) == 0) {
+          if (ld_agent(abort_flag)) return;
+          if (wall_clock64() - t0 > limit) {
+            st_agent(abort_flag, 1);
+            return;
+          }
+        }
+      }
+    }
+    return;
+  }
+
+  if (role > 0) {
+    // ---------------------------------------------------------- producer
+    const int k = role - 1;
+    Quad<T> rq[W3_D][W3_CH];
+    T rb[W3_D][W3_CH];
+    auto issue = [&](int c, int slot) {
+#pragma unroll
+      for (int u = 0; u < W3_CH; ++u) {
+        const int64_t p = p0 + (int64_t)(c * W3_CH + u) * 64;
+        rq[slot][u] = coef[p];
+        rb[slot][u] = REV ? rhs[total - 1 - p] : rhs[p];
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < W3_D; ++d) {
+      const int c = k + d * W3_PRODUCERS;
+      if (c < nchunks) issue(c, d);
+    }
+    for (int d0 = 0;; d0 += W3_D) {
+#pragma unroll
+      for (int dd = 0; dd < W3_D; ++dd) {
+        const int c = k + (d0 + dd) * W3_PRODUCERS;
+        if (c >= nchunks) return;
+        if (!wait_lds_at_least<4>(&consumed, (c + 1 - W3_SLOTS) * W3_CH, abort_flag, limit)) return;
+        const int rb0 = (c % W3_SLOTS) * W3_CH;
+#pragma unroll
+        for (int u = 0; u < W3_CH; ++u) {
+          WaveOp3<T> op;
+          op.cz = rq[dd][u].cz;
+          op.cy = rq[dd][u].cy;
+          op.cx = rq[dd][u].cx;
+          op.b = is_sentinel(rb[dd][u]) ? (T)__builtin_nan("") : rb[dd][u];
+          r_op[rb0 + u][l] = op;
+          if (DIAG) r_d[rb0 + u][l] = rq[dd][u].d;
+        }
+        lds_release();
+        if (l == 0) __hip_atomic_store(&ready[c % W3_SLOTS], c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int cn = c + W3_D * W3_PRODUCERS;
+        if (cn < nchunks) issue(cn, dd);
+      }
+    }
+  }
+
+  // ------------------------------------------------------------ consumer
+  // as in the 2D kernel: chunks two at a time, operand sets A and B
+  const int yy = l & 7, zz = l >> 3;
+  const int up8 = ((l - 8) & 63) << 2;
+  const bool reads_faces = hy || hz;
+  bool live = true;
+  int seen_x = 0;
+  WaveOp3<T> opA[W3_CH], opB[W3_CH];
+  T dA[W3_CH], dB[W3_CH], yA[W3_CH], zA[W3_CH], yB[W3_CH], zB[W3_CH];
+  auto flag_of = [&](int c) {
+    return c < nchunks ? __hip_atomic_load(&ready[c % W3_SLOTS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                       : 0;
+  };
+  auto take = [&](int c, int seen, WaveOp3<T>(&op)[W3_CH], T(&dv)[W3_CH], T(&fy)[W3_CH], T(&fz)[W3_CH]) {
+    const int slot = c % W3_SLOTS;
+    if (live && seen != c + 1) live = wait_lds_equal(&ready[slot], c + 1, abort_flag, limit);
+    const int s0 = c * W3_CH;
+    if (reads_faces && s0 < xn) {
+      const int need = std::min(s0 + W3_CH, xn);
+      if (live && seen_x < need) {
+        seen_x = __hip_atomic_load(&xready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (seen_x < need) {
+          live = wait_lds_at_least<0, false>(&xready, need, abort_flag, limit);
+          seen_x = need;
+        }
+      }
+    }
+    lds_acquire();
+    const int r0 = slot * W3_CH, x0 = s0 % W3_XRING;
+#pragma unroll
+    for (int u = 0; u < W3_CH; ++u) {
+      op[u] = r_op[r0 + u][l];
+      if (DIAG) dv[u] = r_d[r0 + u][l];
+      fy[u] = r_by[x0 + u][zz];
+      fz[u] = r_bz[x0 + u][yy];
+    }
+  };
+  T yp = (T)0;
+  auto run = [&](int c, const WaveOp3<T>(&op)[W3_CH], const T(&dv)[W3_CH], const T(&fy)[W3_CH],
+                 const T(&fz)[W3_CH]) {
+    T* ob = out + p0 + (int64_t)c * W3_CH * 64;
+#pragma unroll
+    for (int u = 0; u < W3_CH; ++u) {
+      const T sy = lane_shr1(fy[u], yp);
+      const T sz = lane_up8(up8, yp);
+      const T vy = yy == 0 ? fy[u] : sy;
+      const T vz = zz == 0 ? fz[u] : sz;
+      T acc = (T)0;
+      if (LOWER) {
+        acc += op[u].cz * vz;
+        acc += op[u].cy * vy;
+        acc += op[u].cx * yp;
+      } else {
+        acc += op[u].cx * yp;
+        acc += op[u].cy * vy;
+        acc += op[u].cz * vz;
+      }
+      T y = op[u].b - acc;
+      if (DIAG) y *= dv[u];
+      if (u > 0) st_agent(ob + (u - 1) * 64, yp);
+      yp = y;
+    }
+    st_agent(ob + (W3_CH - 1) * 64, yp);
+    lds_release();
+    if (l == 0) __hip_atomic_store(&consumed, (c + 1) * W3_CH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  take(0, flag_of(0), opA, dA, yA, zA);
+  int fnext = flag_of(1);
+  for (int c = 0; c < nchunks; c += 2) {
+    take(c + 1, fnext, opB, dB, yB, zB);
+    fnext = flag_of(c + 2);
+    run(c, opA, dA, yA, zA);
+    if (c + 2 < nchunks) take(c + 2, fnext, opA, dA, yA, zA);
+    fnext = flag_of(c + 3);
+    run(c + 1, opB, dB, yB, zB);
+  }
+}
+
 // positions of the lower layout -> cell (or -1 outside the grid)
-__device__ __forceinline__ int wave_cell(int64_t q, int S, int nx, int ny) {
+struct WaveDims {
+  int S, nx, ny, nz, TY;  // nz == 0: 2D grid
+};
+__device__ __forceinline__ int wave_cell(int64_t q, const WaveDims& g) {
   const int l = (int)(q & 63);
   const int64_t ws = q >> 6;
-  const int w = (int)(ws / S), s = (int)(ws - (int64_t)w * S);
-  const int j = 64 * w + l, i = s - l;
-  return (i >= 0 && i < nx && j < ny) ? j * nx + i : -1;
+  const int w = (int)(ws / g.S), s = (int)(ws - (int64_t)w * g.S);
+  if (g.nz == 0) {
+    const int j = 64 * w + l, i = s - l;
+    return (i >= 0 && i < g.nx && j < g.ny) ? j * g.nx + i : -1;
+  }
+  const int yy = l & 7, zz = l >> 3, ty = w % g.TY, tz = w / g.TY;
+  const int x = s - yy - zz, y = 8 * ty + yy, z = 8 * tz + zz;
+  return (x >= 0 && x < g.nx && y < g.ny && z < g.nz) ? (z * g.ny + y) * g.nx + x : -1;
 }
 
 // column blockIdx.y: z + col * ldz (cell order) -> zs + col * total
 template <class T, class TR>
-__global__ void k_wave_gather(int64_t total, int S, int nx, int ny, const TR* __restrict__ z, T* __restrict__ zs,
-                              size_t ldz) {
+__global__ void k_wave_gather(int64_t total, WaveDims g, const TR* __restrict__ z, T* __restrict__ zs, size_t ldz) {
   z += blockIdx.y * ldz;
   zs += blockIdx.y * total;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
-    const int c = wave_cell(p, S, nx, ny);
+    const int c = wave_cell(p, g);
     zs[p] = c >= 0 ? (T)z[c] : (T)0;
   }
 }
@@ -362,13 +630,13 @@ __global__ void k_wave_gather(int64_t total, int S, int nx, int ny, const TR* __
 // ts and the lower sweep's output ys are reset to the sentinel for the next
 // pair of sweeps
 template <class T>
-__global__ void k_wave_scatter(int64_t total, int S, int nx, int ny, T* __restrict__ ts, T* __restrict__ ys,
-                               T* __restrict__ t, size_t ldt) {
+__global__ void k_wave_scatter(int64_t total, WaveDims g, T* __restrict__ ts, T* __restrict__ ys, T* __restrict__ t,
+                               size_t ldt) {
   ts += blockIdx.y * total;
   ys += blockIdx.y * total;
   t += blockIdx.y * ldt;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
-    const int c = wave_cell(total - 1 - p, S, nx, ny);
+    const int c = wave_cell(total - 1 - p, g);
     if (c >= 0) t[c] = ts[p];
     ts[p] = sentinel_of<T>(0);
     ys[total - 1 - p] = sentinel_of<T>(0);
@@ -394,34 +662,57 @@ void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& u
                       T* ys, T* ts, T* t, int* abort_flag, hipStream_t s, int nb, size_t ldz, size_t ldt) {
   constexpr bool F32 = sizeof(T) == 4;
   using P2 = typename Pair<T>::type;
-  if (g.S % (2 * WAVE_CH) != 0) fail(GMG_ERR_INVALID_ARG, "wavefront layout: steps not a multiple of two chunks");
-  if (nb < 1 || nb > 65535) fail(GMG_ERR_INVALID_ARG, "wavefront sweep: bad column count");
+  const bool three = g.nz > 0;
+  if (g.S % (2 * (three ? W3_CH : WAVE_CH)) != 0)
+    fail(GMG_ERR_INVALID_ARG, "wavefront layout: steps not a multiple of two chunks");
+  if (three && (g.TY < 1 || (int64_t)g.W * g.S * 64 != g.total || g.S < 8))
+    fail(GMG_ERR_INVALID_ARG, "wavefront layout: inconsistent 3D tiling");
+  if (nb < 1 || nb > 65535 || (int64_t)g.W * nb > INT32_MAX) fail(GMG_ERR_INVALID_ARG, "wavefront sweep: bad column count");
+  const WaveDims dims{g.S, g.nx, g.ny, three ? g.nz : 0, three ? g.TY : 1};
   const unsigned gb = (unsigned)std::min<int64_t>(4096, (g.total + 255) / 256);
   if (z_f64)
-    hipLaunchKernelGGL((k_wave_gather<T, double>), dim3(gb, nb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny,
-                       (const double*)z, zs, ldz);
+    hipLaunchKernelGGL((k_wave_gather<T, double>), dim3(gb, nb), dim3(256), 0, s, g.total, dims, (const double*)z, zs,
+                       ldz);
   else
-    hipLaunchKernelGGL((k_wave_gather<T, T>), dim3(gb, nb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, (const T*)z,
-                       zs, ldz);
+    hipLaunchKernelGGL((k_wave_gather<T, T>), dim3(gb, nb), dim3(256), 0, s, g.total, dims, (const T*)z, zs, ldz);
   const uint64_t lim = wave_limit_ticks();
-  auto co = [&](const WaveSweep& f) { return F32 ? (const P2*)f.coef32.p : (const P2*)f.coef.p; };
-  auto di = [&](const WaveSweep& f) { return F32 ? (const T*)f.dinv32.p : (const T*)f.dinv.p; };
-  // lower factor: neighbour below first; upper factor: left neighbour first,
-  // right-hand side = the lower sweep's output read backwards
-  const dim3 blk(WAVE_THREADS), grid((unsigned)(g.W * nb));
-  if (lo.has_diag)
-    hipLaunchKernelGGL((k_wave<T, true, true, false>), grid, blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
-                       ys, abort_flag, lim, nb);
-  else
-    hipLaunchKernelGGL((k_wave<T, false, true, false>), grid, blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
-                       ys, abort_flag, lim, nb);
-  if (up.has_diag)
-    hipLaunchKernelGGL((k_wave<T, true, false, true>), grid, blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
-                       ts, abort_flag, lim, nb);
-  else
-    hipLaunchKernelGGL((k_wave<T, false, false, true>), grid, blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
-                       ts, abort_flag, lim, nb);
-  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gb, nb), dim3(256), 0, s, g.total, g.S, g.nx, g.ny, ts, ys, t, ldt);
+  const dim3 grid((unsigned)(g.W * nb));
+  if (three) {
+    // coefficient quads (z, y, x neighbours, reciprocal diagonal)
+    auto co = [&](const WaveSweep& f) { return F32 ? (const Quad<T>*)f.coef32.p : (const Quad<T>*)f.coef.p; };
+    const dim3 blk(W3_THREADS);
+    if (lo.has_diag)
+      hipLaunchKernelGGL((k_wave3<T, true, true, false>), grid, blk, 0, s, g.S, g.TY, g.total, co(lo), zs, ys,
+                         abort_flag, lim, nb);
+    else
+      hipLaunchKernelGGL((k_wave3<T, false, true, false>), grid, blk, 0, s, g.S, g.TY, g.total, co(lo), zs, ys,
+                         abort_flag, lim, nb);
+    if (up.has_diag)
+      hipLaunchKernelGGL((k_wave3<T, true, false, true>), grid, blk, 0, s, g.S, g.TY, g.total, co(up), ys, ts,
+                         abort_flag, lim, nb);
+    else
+      hipLaunchKernelGGL((k_wave3<T, false, false, true>), grid, blk, 0, s, g.S, g.TY, g.total, co(up), ys, ts,
+                         abort_flag, lim, nb);
+  } else {
+    auto co = [&](const WaveSweep& f) { return F32 ? (const P2*)f.coef32.p : (const P2*)f.coef.p; };
+    auto di = [&](const WaveSweep& f) { return F32 ? (const T*)f.dinv32.p : (const T*)f.dinv.p; };
+    // lower factor: neighbour below first; upper factor: left neighbour first,
+    // right-hand side = the lower sweep's output read backwards
+    const dim3 blk(WAVE_THREADS);
+    if (lo.has_diag)
+      hipLaunchKernelGGL((k_wave<T, true, true, false>), grid, blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
+                         ys, abort_flag, lim, nb);
+    else
+      hipLaunchKernelGGL((k_wave<T, false, true, false>), grid, blk, 0, s, g.S, g.nx, g.total, co(lo), di(lo), zs,
+                         ys, abort_flag, lim, nb);
+    if (up.has_diag)
+      hipLaunchKernelGGL((k_wave<T, true, false, true>), grid, blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
+                         ts, abort_flag, lim, nb);
+    else
+      hipLaunchKernelGGL((k_wave<T, false, false, true>), grid, blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
+                         ts, abort_flag, lim, nb);
+  }
+  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gb, nb), dim3(256), 0, s, g.total, dims, ts, ys, t, ldt);
   HIPCK(hipGetLastError());
 }
 template void launch_wave_pair<double>(const WaveGrid&, const WaveSweep&, const WaveSweep&, const void*, bool,

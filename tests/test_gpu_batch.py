@@ -31,7 +31,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-# 2D grids take the batched wavefront sweeps, the others the per-column level
+# 2D and 3D grids take the batched wavefront sweeps, the others the per-column level
 # sweeps; the coarse factors follow the dissection tree in every case
 CASES = {
     "fv2d_64": lambda: W.make("fv2d_64"),
