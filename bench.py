@@ -164,7 +164,23 @@ def _roofline_of(prof):
                 bytes_per_launch=round(d["bytes"] / d["launches"]))
 
 
-def _kernels_of(prof, setup_info, grid2d):
+def _fine_floor(grid, levels):
+    """Latency floor of the two fine sweeps: the level sweeps pay one
+    agent-scope hop per dependency level; the 2D wavefront kernel one step per
+    anti-diagonal; the 3D one nx + 14 steps plus, for each tile of 8 x 8 grid
+    lines on the longest chain, seven steps and one hop."""
+    if grid is None:
+        return levels * HOP_US, "levels x agent-scope hop 0.55 us"
+    if len(grid) == 2:
+        return levels * WAVE_STEP_US, "levels x wavefront step 0.072 us"
+    nx, ny, nz = grid
+    hops = -(-ny // 8) + -(-nz // 8) - 2
+    per = (nx + 14) * WAVE_STEP_US + hops * (7 * WAVE_STEP_US + HOP_US)
+    return 2 * per, (f"2 x ({nx} + 14 steps + {hops} tile hops x (7 steps + one hop)), "
+                     f"step {WAVE_STEP_US} us, hop {HOP_US} us")
+
+
+def _kernels_of(prof, setup_info, grid):
     """Per-class time and rate; for the sweeps also the latency floor of
     their dependency chains (levels x measured step or hop)."""
     out = {}
@@ -175,9 +191,8 @@ def _kernels_of(prof, setup_info, grid2d):
                  gbs=round(a["bytes"] / (a["ms"] * 1e-3) / 1e9, 2) if a["ms"] > 0 else None)
         if name == "sweep_fine":
             lv = setup_info["levels_L0"] + setup_info["levels_U0"]
-            per = WAVE_STEP_US if grid2d else HOP_US
-            e.update(levels=lv, latency_floor_us=round(lv * per, 2),
-                     floor="levels x %s" % ("wavefront step 0.072 us" if grid2d else "agent-scope hop 0.55 us"))
+            fl, how = _fine_floor(grid, lv)
+            e.update(levels=lv, latency_floor_us=round(fl, 2), floor=how)
         if name == "sweep_coarse":
             lv = setup_info["levels_Lc"] + setup_info["levels_Uc"]
             e.update(levels=lv, latency_floor_us=round(lv * 2 * HOP_US, 2),
@@ -217,8 +232,10 @@ def measure_config(torch, W, Solver, name, seed=0, fp32=True):
                  relres_host_check=float(np.linalg.norm(p.b[:, 0] - A @ xh) / bn))
     Sp, _, _ = run(False, True)
     prof = Sp.profile_read()
-    grid2d = name.startswith("fv2d")
-    entry["kernels"] = _kernels_of(prof, Sp.setup_info, grid2d)
+    # grid of the fine factors' wavefront sweeps (None: level sweeps)
+    cells = int(name.split("_")[1]) if name.startswith(("fv2d", "fv3d")) else 0
+    grid = (cells, cells) if name.startswith("fv2d") else (cells,) * 3 if name.startswith("fv3d") else None
+    entry["kernels"] = _kernels_of(prof, Sp.setup_info, grid)
     entry["roofline"] = _roofline_of(prof)
     if fp32:
         (S32, x32, r32), t32 = _sync_time(torch, lambda: run(True))
@@ -278,7 +295,7 @@ def measure_grad(torch, W):
     _, r = S.solve(B, tol=GRAD_TOL, restart=GRAD_OPTS["restart"], maxit=GRAD_OPTS["maxit"])
     prof = S.profile_read()
     res["forward_iters_sum"] = r.info["iters"]
-    res["forward_kernels"] = _kernels_of(prof, S.setup_info, True)
+    res["forward_kernels"] = _kernels_of(prof, S.setup_info, (512, 512))
     res["roofline"] = _roofline_of(prof)
     return res
 
