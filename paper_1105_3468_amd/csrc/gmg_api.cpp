@@ -10,6 +10,7 @@
 #include <limits>
 #include <memory>
 #include <string>
+#include <exception>
 #include <thread>
 #include <vector>
 
@@ -2111,58 +2112,67 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
   build_members(n, S.nc, S.agg.p, S.aptr, S.amem, s);
   galerkin(n, S.nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
   phase("galerkin");
-  if (o.coarse_order == 1 && S.nc > 1) {
-    // number the aggregates in nested-dissection order of A_c's graph, then
-    // rebuild P^T and A_c (same sums, permuted rows and columns)
-    const int nc = S.nc;
-    // the graph of A_c + A_c^T without the diagonal, built on the device (the
-    // same merge as the fine graph's; the weights are not needed here)
-    std::vector<int> cnt, gci;
-    {
-      DBuf<int> trp, tci, grp, gcd;
-      DBuf<double> tv, gw;
-      transpose_csr(nc, nc, S.Ac.nnz, S.Ac.rp.p, S.Ac.ci.p, S.Ac.v.p, trp, tci, &tv, nullptr, s);
-      build_graph(nc, S.Ac.rp.p, S.Ac.ci.p, S.Ac.v.p, trp.p, tci.p, tv.p, grp, gcd, gw, s);
-      cnt = to_host_int(grp.p, nc + 1, s);
-      HIPCK(hipStreamSynchronize(s));
-      gci = to_host_int(gcd.p, cnt[nc], s);
-      HIPCK(hipStreamSynchronize(s));
-    }
-    phase("nested dissection: graph");
-    std::vector<int> perm = nd_numbering(nc, cnt, gci, &S.nd_tree);
-    phase("nested dissection: numbering");
-    std::vector<int> rank(nc);
-    for (int k = 0; k < nc; ++k) rank[perm[k]] = k;
-    DBuf<int> drank;
-    drank.alloc(nc);
-    h2d(drank.p, rank.data(), nc, s);
-    relabel(n, S.agg.p, drank.p, s);
-    HIPCK(hipStreamSynchronize(s));
-    build_members(n, nc, S.agg.p, S.aptr, S.amem, s);
-    galerkin(n, nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
-    phase("nested dissection");
-  }
-  // ---- ILUT of A_c on host threads, while the fine level is set up below
-  HCsr hAc;
-  hAc.n = S.nc;
-  hAc.rp = to_host_int(S.Ac.rp.p, S.nc + 1, s);
-  hAc.ci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
-  hAc.v.resize(S.Ac.nnz);
-  d2h(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
-  HIPCK(hipStreamSynchronize(s));
+  // ---- the coarse chain on a second host thread, while the fine level is
+  // set up below: the nested-dissection numbering of the aggregates (A_c
+  // rebuilt in that order), then the ILUT (or SPAI) of A_c on the host
+  // threads.  Both threads queue work on the stream; the buffers each one
+  // touches are disjoint (the coarse chain: agg, the members, A_c, the
+  // dissection tree and the host factors).
+  if (o.coarse_mode == 3 && S.nc > kDenseMaxCoarse)
+    fail(GMG_ERR_INVALID_ARG, "coarse_mode 3 (dense inverse) needs n_coarse <= 8192");
   gmg_status ilut_st = GMG_OK;
+  std::exception_ptr coarse_err;
+  HCsr hAc;
   struct Joiner {  // joins on every path out of the setup, failures included
     std::thread t;
     ~Joiner() {
       if (t.joinable()) t.join();
     }
-  } ilut_job;
-  if (o.coarse_mode == 3 && S.nc > kDenseMaxCoarse)
-    fail(GMG_ERR_INVALID_ARG, "coarse_mode 3 (dense inverse) needs n_coarse <= 8192");
-  ilut_job.t = std::thread([&S, &hAc, &ilut_st, tau = o.ilut_tau, mode = o.coarse_mode] {
-    ilut_st = mode == 3   ? GMG_OK
-              : mode == 2 ? host_spai(hAc, S.hMc)
-                          : host_ilut(hAc, tau, S.hLc, S.hUc, &S.nd_tree);
+  } coarse_job;
+  coarse_job.t = std::thread([&S, &hAc, &ilut_st, &coarse_err, n, s, tau = o.ilut_tau, mode = o.coarse_mode,
+                              nd = o.coarse_order == 1] {
+    try {
+      PoolStream scope(s);
+      if (nd && S.nc > 1) {
+        // number the aggregates in nested-dissection order of A_c's graph,
+        // then rebuild P^T and A_c (same sums, permuted rows and columns)
+        const int nc = S.nc;
+        // the graph of A_c + A_c^T without the diagonal, built on the device
+        // (the same merge as the fine graph's; the weights are not needed)
+        std::vector<int> cnt, gci;
+        {
+          DBuf<int> trp, tci, grp, gcd;
+          DBuf<double> tv, gw;
+          transpose_csr(nc, nc, S.Ac.nnz, S.Ac.rp.p, S.Ac.ci.p, S.Ac.v.p, trp, tci, &tv, nullptr, s);
+          build_graph(nc, S.Ac.rp.p, S.Ac.ci.p, S.Ac.v.p, trp.p, tci.p, tv.p, grp, gcd, gw, s);
+          cnt = to_host_int(grp.p, nc + 1, s);
+          HIPCK(hipStreamSynchronize(s));
+          gci = to_host_int(gcd.p, cnt[nc], s);
+          HIPCK(hipStreamSynchronize(s));
+        }
+        std::vector<int> perm = nd_numbering(nc, cnt, gci, &S.nd_tree);
+        std::vector<int> rank(nc);
+        for (int k = 0; k < nc; ++k) rank[perm[k]] = k;
+        DBuf<int> drank;
+        drank.alloc(nc);
+        h2d(drank.p, rank.data(), nc, s);
+        relabel(n, S.agg.p, drank.p, s);
+        HIPCK(hipStreamSynchronize(s));
+        build_members(n, nc, S.agg.p, S.aptr, S.amem, s);
+        galerkin(n, nc, S.A.rp.p, S.A.ci.p, S.A.v.p, S.agg.p, S.aptr.p, S.amem.p, S.Ac, s);
+      }
+      hAc.n = S.nc;
+      hAc.rp = to_host_int(S.Ac.rp.p, S.nc + 1, s);
+      hAc.ci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
+      hAc.v.resize(S.Ac.nnz);
+      d2h(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
+      HIPCK(hipStreamSynchronize(s));
+      ilut_st = mode == 3   ? GMG_OK
+                : mode == 2 ? host_spai(hAc, S.hMc)
+                            : host_ilut(hAc, tau, S.hLc, S.hUc, &S.nd_tree);
+    } catch (...) {
+      coarse_err = std::current_exception();
+    }
   });
   // ---- host copy of A's pattern for the analysis
   std::vector<int> hrp = to_host_int(S.A.rp.p, n + 1, s);
@@ -2231,30 +2241,39 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     phase(o.fine_order == 1 ? "fine nested dissection" : "fine colouring");
   }
   // diagonal positions and the dependency lists of the two forward fine
-  // sweeps (strict lower / strict upper entries of each row).  One thread on
-  // purpose: the ILUT started above keeps the other host threads busy.
+  // sweeps (strict lower / strict upper entries of each row): counts and
+  // lists by row ranges on the host threads (the ILUT started above shares
+  // them for these few milliseconds)
   std::vector<int> hdpos(n), l_rp(n + 1, 0), u_rp(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    int nl = 0, nu = 0;
-    for (int p = hrp[i]; p < hrp[i + 1]; ++p) {
-      if (hci[p] < i) ++nl;
-      else if (hci[p] > i) ++nu;
-      else hdpos[i] = p;
+  parallel_ranges(n, [&](int i0, int i1, int) {
+    for (int i = i0; i < i1; ++i) {
+      int nl = 0, nu = 0;
+      for (int p = hrp[i]; p < hrp[i + 1]; ++p) {
+        if (hci[p] < i) ++nl;
+        else if (hci[p] > i) ++nu;
+        else hdpos[i] = p;
+      }
+      l_rp[i + 1] = nl;
+      u_rp[i + 1] = nu;
     }
-    l_rp[i + 1] = l_rp[i] + nl;
-    u_rp[i + 1] = u_rp[i] + nu;
+  });
+  for (int i = 0; i < n; ++i) {
+    l_rp[i + 1] += l_rp[i];
+    u_rp[i + 1] += u_rp[i];
   }
   S.dpos.alloc(n);
   h2d(S.dpos.p, hdpos.data(), n, s);
   std::vector<int> l_ci(l_rp[n]), l_src(l_rp[n]), u_ci(u_rp[n]), u_src(u_rp[n]);
-  for (int i = 0; i < n; ++i) {
-    int ql = l_rp[i], qu = u_rp[i];
-    for (int p = hrp[i]; p < hrp[i + 1]; ++p) {
-      const int c = hci[p];
-      if (c < i) { l_ci[ql] = c; l_src[ql++] = p; }
-      else if (c > i) { u_ci[qu] = c; u_src[qu++] = p; }
+  parallel_ranges(n, [&](int i0, int i1, int) {
+    for (int i = i0; i < i1; ++i) {
+      int ql = l_rp[i], qu = u_rp[i];
+      for (int p = hrp[i]; p < hrp[i + 1]; ++p) {
+        const int c = hci[p];
+        if (c < i) { l_ci[ql] = c; l_src[ql++] = p; }
+        else if (c > i) { u_ci[qu] = c; u_src[qu++] = p; }
+      }
     }
-  }
+  });
   phase("fine dependency lists");
   // 2D-grid structure of both fine factors (their transposes then have it
   // too: the same offsets, mirrored): wavefront sweeps, and an ILU(0) in one
@@ -2375,8 +2394,26 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     }
   }
   if (!S.wave && !S.ftree) {
-    build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
-    build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks, o.sweep_kernel == 2, s);
+    // the two layouts are independent host work: U0's on a second thread
+    std::exception_ptr u_err;
+    std::thread ut([&] {
+      try {
+        PoolStream scope(s);
+        build_sweep(S.U0, n, u_rp, u_ci, u_src, nullptr, S.ilu.p, false, true, nullptr, S.u0dinv.p, o.sweep_wg_chunks,
+                    o.sweep_kernel == 2, s);
+      } catch (...) {
+        u_err = std::current_exception();
+      }
+    });
+    try {
+      build_sweep(S.L0, n, l_rp, l_ci, l_src, nullptr, S.ilu.p, true, false, nullptr, nullptr, o.sweep_wg_chunks,
+                  o.sweep_kernel == 2, s);
+    } catch (...) {
+      ut.join();
+      throw;
+    }
+    ut.join();
+    if (u_err) std::rethrow_exception(u_err);
     phase("fine sweeps");
   }
   if (S.fine_nd) {
@@ -2385,8 +2422,9 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     S.fzp32.alloc(n);
     S.ftp32.alloc(n);
   }
-  // ---- the ILUT started above
-  ilut_job.t.join();
+  // ---- the coarse chain started above
+  coarse_job.t.join();
+  if (coarse_err) std::rethrow_exception(coarse_err);
   if (o.coarse_mode == 3) {
     const int nc = S.nc;
     S.cnp = (nc + 63) / 64 * 64;
@@ -2401,7 +2439,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     HIPCK(hipMemcpyAsync(&bad, S.cbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     if (bad) fail(GMG_ERR_ZERO_PIVOT, "dense coarse inverse: zero or non-finite pivot");
-    phase("coarse dense inverse (after the fine level)");
+    phase("coarse chain: dissection, dense inverse");
   } else if (o.coarse_mode == 2) {
     const gmg_status st = ilut_st;
     if (st == GMG_ERR_ZERO_PIVOT) fail(st, "SPAI: a column's least-squares problem is rank deficient");
@@ -2419,7 +2457,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
     h2d(D.v.p, M.v.data(), D.nnz, s);
     launch_cast_f32(D.v.p, D.v32.p, D.nnz, s);
     HIPCK(hipStreamSynchronize(s));
-    phase("coarse SPAI (rest after the fine level)");
+    phase("coarse chain: dissection, SPAI (rest)");
   } else {
     {
       const gmg_status st = ilut_st;
@@ -2427,7 +2465,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       if (st == GMG_ERR_OOM) fail(st, "ILUT: factor exceeds int32 indexing");
       if (st != GMG_OK) fail(st, "ILUT: non-finite pivot");
     }
-    phase("coarse ILUT (rest after the fine level)");
+    phase("coarse chain: dissection, ILUT (rest)");
     {
       const int nc = S.nc;
       const HCsr &L = S.hLc, &U = S.hUc;
