@@ -359,6 +359,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the other configurations (3D, random graphs x4 seeds, gradients, 64^2)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--wave3-tiles", action="store_true",
+                    help="also time the 3D wavefront sweeps on seven-point grids of 1 to 256 tiles of 8 x 8 grid "
+                         "lines: a step's and a tile hop's cost")
     args = ap.parse_args()
     global SOLVE_OPTS
     SOLVE_OPTS = WORKLOAD_OPTS.get(args.workload, SOLVE_OPTS)
@@ -652,6 +655,40 @@ def main():
             kernels={k: dict(launches=v["launches"], total_ms=round(v["ms"], 4)) for k, v in prm.items()
                      if v["launches"]})
         print(f"[bench] multicolour smoother step: {tm:.3f}s its={rm.info['iters']}", file=sys.stderr, flush=True)
+
+    if args.wave3_tiles:
+        # the 3D wavefront pair on seven-point grids: one tile (8 x 8 lines)
+        # walked over nx = 128 and 512 cells gives the cost of a step; 16
+        # tiles in a row along y or z, 8 x 8 and 16 x 16 tiles give the cost
+        # of a tile hop (seven steps and one face exchange through memory)
+        shapes = [(128, 8, 8), (512, 8, 8), (128, 128, 8), (128, 8, 128), (128, 64, 64), (128, 128, 128)]
+        wres = {}
+        for (nx, ny, nz) in shapes:
+            rpw, ciw, vaw = W.grid7_matrix(nx, ny, nz, 1)
+            Sw = Solver(rpw, ciw, vaw, sweep_kernel=3)
+            zw = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, len(rpw) - 1), device="cuda")
+            row = dict(tiles=-(-ny // 8) * -(-nz // 8), hops=-(-ny // 8) + -(-nz // 8) - 2,
+                       steps=(nx + 14 + 7) // 8 * 8)
+            for prec, key in ((0, "fp64"), (1, "fp32")):
+                for _ in range(3):
+                    Sw.apply(zw, precision=prec)
+                Sw.profile(True, classes=["sweep_fine"])
+                for _ in range(20):
+                    Sw.apply(zw, precision=prec)
+                pr = Sw.profile_read()["sweep_fine"]
+                Sw.profile(False)
+                row[key + "_pair_us"] = round(pr["ms"] / pr["launches"] * 1e3, 2)
+            wres[f"{nx}x{ny}x{nz}"] = row
+            del Sw
+        wt = dict(shapes=wres, note="pair = gather, lower and upper sweep, scatter (HIP events, 20 applications)")
+        for key in ("fp64", "fp32"):
+            one, long_, chain = (wres[k][key + "_pair_us"] for k in ("128x8x8", "512x8x8", "128x128x8"))
+            step_us = (long_ - one) / (2 * (wres["512x8x8"]["steps"] - wres["128x8x8"]["steps"]))
+            wt[key + "_step_ns"] = round(step_us * 1e3, 1)
+            wt[key + "_tile_hop_us"] = round((chain - one) / (2 * wres["128x128x8"]["hops"]), 3)
+        out["wave3_tiles"] = wt
+        print(f"[bench] 3D wavefront tiles: step {wt['fp64_step_ns']} ns, tile hop {wt['fp64_tile_hop_us']} us (FP64)",
+              file=sys.stderr, flush=True)
 
     if args.restarts:
         # the same solve with restarts: shorter bases cost fewer bytes per

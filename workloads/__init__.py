@@ -25,6 +25,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .fv import block_kappa, dc1_kappa, fv_matrix, velocity_const, velocity_rotating
+from .grid7 import grid7_matrix
 from .rgg import rgg_matrix
 
 
@@ -129,4 +130,5 @@ def scaled(kind: str, n: int, seed: int = 0, nrhs: int = 1) -> Problem:
 
 
 __all__ = ["Problem", "make", "scaled", "fv_matrix", "fv_problem", "rgg_problem",
-           "paper_problem", "block_kappa", "dc1_kappa", "velocity_const", "velocity_rotating", "rgg_matrix"]
+           "paper_problem", "block_kappa", "dc1_kappa", "velocity_const", "velocity_rotating", "rgg_matrix",
+           "grid7_matrix"]
