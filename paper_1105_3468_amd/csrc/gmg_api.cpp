@@ -2475,9 +2475,39 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       // both factors follow the tree (U without its leading diagonal entries);
       // else the level-scheduled sweeps
       S.tree = false;
-      if (o.sweep_kernel == 0 && o.coarse_order == 1 && !S.nd_tree.empty() &&
-          build_tree(S.tLc, S.nd_tree, nc, L.rp, L.ci, nullptr, 0, L.v, true, nullptr, s) &&
-          build_tree(S.tUc, S.nd_tree, nc, U.rp, U.ci, nullptr, 1, U.v, false, &udinv, s)) {
+      bool tree_ok = false;
+      if (o.sweep_kernel == 0 && o.coarse_order == 1 && !S.nd_tree.empty()) {
+        // the two layouts at once: U~'s on a second host thread and its own
+        // stream (its inputs are host data only), so that the host work and
+        // the blocks' inversions of the two factors overlap.  That thread
+        // allocates outside the solver's allocation scope (directly from the
+        // runtime), so it never waits for a cached block of the first stream.
+        hipStream_t s2 = nullptr;
+        HIPCK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        bool ok_u = false;
+        std::exception_ptr u_err;
+        std::thread ut([&] {
+          try {
+            ok_u = build_tree(S.tUc, S.nd_tree, nc, U.rp, U.ci, nullptr, 1, U.v, false, &udinv, s2);
+          } catch (...) {
+            u_err = std::current_exception();
+          }
+        });
+        bool ok_l = false;
+        std::exception_ptr l_err;
+        try {
+          ok_l = build_tree(S.tLc, S.nd_tree, nc, L.rp, L.ci, nullptr, 0, L.v, true, nullptr, s);
+        } catch (...) {
+          l_err = std::current_exception();
+        }
+        ut.join();
+        (void)hipStreamSynchronize(s2);
+        (void)hipStreamDestroy(s2);
+        if (l_err) std::rethrow_exception(l_err);
+        if (u_err) std::rethrow_exception(u_err);
+        tree_ok = ok_l && ok_u;
+      }
+      if (tree_ok) {
         S.tree = true;
         S.text.alloc(nc);
         S.text32.alloc(nc);
