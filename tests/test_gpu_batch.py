@@ -36,6 +36,7 @@ def _say(msg):
 CASES = {
     "fv2d_64": lambda: W.make("fv2d_64"),
     "fv2d_37": lambda: W.fv_problem(37, 2, 1, -2, 2, W.velocity_const((1.0, 0.5)), 5),
+    "fv2d_150": lambda: W.fv_problem(150, 2, 1, -2, 2, W.velocity_const((1.0, 0.5)), 6),
     "fv3d_20": lambda: W.scaled("fv3d", 20),
     "rgg_3001": lambda: W.scaled("rgg", 3001),
 }
