@@ -373,7 +373,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    os.environ.setdefault("GMG_LOG", "50")   # library progress lines on stderr
+    # no library log inside the timed runs: GMG_LOG also times each setup
+    # phase, waiting for the stream at every phase boundary (the [bench] lines
+    # report progress instead)
+    os.environ.pop("GMG_LOG", None)
     import numpy as np
     import torch
 
