@@ -337,7 +337,7 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree_in, int n,
                        const std::vector<double>& vals, bool lower, const std::vector<double>* dinv,
                        hipStream_t s) {
   const std::vector<NdNode> tree = split_tree(tree_in, kTreeMaxRows);
-  constexpr int kHelperEntries = 512, kHelperRows = 64;
+  constexpr int kHelperEntries = 256, kHelperRows = 32;
   constexpr int kSliceLgRows = 4;             // rows per slice of a node above 64 rows: 16
   constexpr size_t kSmallInvLds = 40 * 1024;  // inversion chunks launched with this much LDS or less first
   const int nn = (int)tree.size();
