@@ -29,7 +29,7 @@ namespace gmg {
 
 constexpr int TREE_THREADS = 256;
 constexpr int TREE_BATCH = 8;   // helper loads in flight per lane
-constexpr int TREE_MBATCH = 24; // inverse-block loads in flight per lane
+constexpr int TREE_MBATCH = 16; // inverse-block loads in flight per lane
 
 template <class T>
 __device__ __forceinline__ T tree_poll(const T* p, int* abort_flag, uint64_t limit) {
