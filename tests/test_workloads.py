@@ -81,3 +81,32 @@ def test_convection_m_matrix_and_row_sums(case):
         expect[x == 0] = 1.0 / h
     scale = np.abs(A).sum(axis=1)[free]
     assert np.all(np.abs(sums - expect[free]) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("dims", [(5, 3, 4), (13, 9, 21), (7, 1, 6)])
+def test_grid7_pattern_and_dominance(dims):
+    """The seven-point generator of the 3D wavefront tests: in natural order
+    every off-diagonal entry sits at offset +-1 within a grid line, +-nx
+    within a plane or +-nx*ny, every existing neighbour is present, the
+    off-diagonals are negative and nonsymmetric, and each diagonal is 1.05
+    times the row's off-diagonal magnitudes plus 0.01."""
+    nx, ny, nz = dims
+    rp, ci, v = W.grid7_matrix(nx, ny, nz, 3)
+    n = nx * ny * nz
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    assert np.all(np.diff(rp) > 0) and A.has_sorted_indices
+    for i in range(n):
+        x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+        want = {i}
+        if x > 0: want.add(i - 1)
+        if x < nx - 1: want.add(i + 1)
+        if y > 0: want.add(i - nx)
+        if y < ny - 1: want.add(i + nx)
+        if z > 0: want.add(i - nx * ny)
+        if z < nz - 1: want.add(i + nx * ny)
+        assert set(ci[rp[i]:rp[i + 1]]) == want
+    D = A.diagonal()
+    off = A - sp.diags(D)
+    assert np.all(off.data <= 0)
+    assert np.allclose(D, 1.05 * np.asarray(abs(off).sum(axis=1)).ravel() + 0.01, rtol=1e-15, atol=0)
+    assert abs(off - off.T).max() > 0
