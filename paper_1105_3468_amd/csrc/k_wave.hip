@@ -1,8 +1,9 @@
-// Wavefront sweeps for factors with the structure of a 2D grid: every row
-// k = j * nx + i of a lower factor depends at most on k - 1 (same grid row,
-// i > 0) and k - nx (previous grid row).  ILU(0) of a five-point operator in
-// natural order has exactly this structure; an upper factor (k + 1, k + nx)
-// is a lower factor of the reversed grid.
+// Wavefront sweeps for factors with the structure of a 2D grid (below) or
+// of a 3D grid (k_wave3, further down).  2D: every row k = j * nx + i of a
+// lower factor depends at most on k - 1 (same grid row, i > 0) and k - nx
+// (previous grid row).  ILU(0) of a five-point operator in natural order has
+// exactly this structure; an upper factor (k + 1, k + nx) is a lower factor
+// of the reversed grid.
 //
 // The general sweep pays one dependency level (a publish-and-poll hop) per
 // anti-diagonal of the grid.  Here a wave owns 64 grid rows, one per lane,
