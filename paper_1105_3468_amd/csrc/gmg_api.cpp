@@ -339,6 +339,7 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree_in, int n,
   const std::vector<NdNode> tree = split_tree(tree_in, kTreeMaxRows);
   constexpr int kHelperEntries = 256, kHelperRows = 32;
   constexpr int kSliceLgRows = 4;             // rows per slice of a node above 64 rows: 16
+  constexpr int kWideRows = 1024, kWideLgRows = 3;  // rows per slice of a node of 1024 rows or more: 8
   constexpr size_t kSmallInvLds = 40 * 1024;  // inversion chunks launched with this much LDS or less first
   const int nn = (int)tree.size();
   if (nn == 0 || n <= 0) return false;
@@ -429,7 +430,7 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree_in, int n,
     }
     // the node's slices: one for a leaf-sized block, else kSliceRows rows each
     const int sz = d.hi - d.lo;
-    const int lgR = sz <= 64 ? 6 : kSliceLgRows, R = 1 << lgR;
+    const int lgR = sz <= 64 ? 6 : sz >= kWideRows ? kWideLgRows : kSliceLgRows, R = 1 << lgR;
     const int nsl = (sz + R - 1) / R;
     for (int q = 0; q < nsl; ++q)
       task.insert(task.end(), {1, d.lo, sz, q * R, std::min(sz, (q + 1) * R), k, (has_ext ? 1 : 0) | lgR << 1, nsl});
