@@ -509,7 +509,10 @@ __device__ __forceinline__ void lds_barrier() {
 // w <- w - sum_k h[k] V[k]; block partials of V[k] . w_new, and with
 // want_norm of ||w_new||^2 (slot kc).  A chunk's new w needs every vector
 // group's partial sum (two barriers per chunk), so the next chunk's basis
-// values (and w) are loaded before them.
+// values (and w) are loaded before them.  The grid walks the rows from the
+// last chunk down to the first: the preceding multidot pass walked them
+// upwards, so the basis rows it read last are still in the 256 MB memory-side
+// cache when this pass starts (block b takes chunks nch-1-b, nch-1-b-grid, ...).
 template <int PER>
 __global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restrict__ V, size_t ld, int kc,
                                                          const double* __restrict__ h, double* __restrict__ w,
@@ -525,8 +528,9 @@ __global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restric
   for (int u = 0; u < PER; ++u) acc[u] = 0.0;
   const int64_t nch = (n + MROWS - 1) / MROWS;
   double2 v[PER];
+  // step c of the walk is chunk nch - 1 - c
   auto load = [&](double2 (&x)[PER], int64_t c) {
-    const int64_t i = c * MROWS + 2 * r;
+    const int64_t i = (nch - 1 - c) * MROWS + 2 * r;
     const bool ok = c < nch;
 #pragma unroll
     for (int u = 0; u < PER; ++u) x[u] = many_load(V, ld, g + MG * u, i, n, ok && g + MG * u < kc);
@@ -534,17 +538,18 @@ __global__ __launch_bounds__(MKB) void k_update_dot_many(const double* __restric
   // threads 0..MROWS-1 also hold w of their row of the chunk (loaded one
   // chunk ahead, like the basis values)
   auto load_w = [&](int64_t c) {
-    const int64_t ii = c * MROWS + threadIdx.x;
+    const int64_t ii = (nch - 1 - c) * MROWS + threadIdx.x;
     return (threadIdx.x < MROWS && c < nch && ii < n) ? w[ii] : 0.0;
   };
   double wc = load_w(blockIdx.x);
   double nacc = 0.0;  // threads 0..MROWS-1 (wave 0): squares of their rows of w_new
   if constexpr (PER <= MPIPE) load(v, blockIdx.x);
-  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const int64_t ch = nch - 1 - c;
     double2 vn[PER];
-    const double wnext = load_w(ch + gridDim.x);
-    if constexpr (PER <= MPIPE) load(vn, ch + gridDim.x);
-    else load(v, ch);
+    const double wnext = load_w(c + gridDim.x);
+    if constexpr (PER <= MPIPE) load(vn, c + gridDim.x);
+    else load(v, c);
     double p0 = 0.0, p1 = 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
