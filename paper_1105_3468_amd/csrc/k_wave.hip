@@ -616,23 +616,45 @@ __device__ __forceinline__ int wave_cell(int64_t q, const WaveDims& g) {
   return (x >= 0 && x < g.nx && y < g.ny && z < g.nz) ? (z * g.ny + y) * g.nx + x : -1;
 }
 
+// The gather takes the positions in tiles of 16 steps of one wave (or 3D
+// tile): a lane's 16 cells of a tile are consecutive in x, at most two
+// 128-byte lines of the cell-ordered vector, so a line is read by one or two
+// workgroups (positions in plain grid-stride order spread a line's 16 values
+// over four or five workgroups, usually on different XCDs and their L2s).
+constexpr int WAVE_COPY_THREADS = 256;
+constexpr int WAVE_COPY_TILE = 16 * 64;  // positions per tile
+
 // column blockIdx.y: z + col * ldz (cell order) -> zs + col * total
 template <class T, class TR>
-__global__ void k_wave_gather(int64_t total, WaveDims g, const TR* __restrict__ z, T* __restrict__ zs, size_t ldz) {
+__global__ __launch_bounds__(WAVE_COPY_THREADS) void k_wave_gather(int64_t total, WaveDims g,
+                                                                   const TR* __restrict__ z, T* __restrict__ zs,
+                                                                   size_t ldz) {
   z += blockIdx.y * ldz;
   zs += blockIdx.y * total;
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
-    const int c = wave_cell(p, g);
-    zs[p] = c >= 0 ? (T)z[c] : (T)0;
+  for (int64_t t0 = blockIdx.x * (int64_t)WAVE_COPY_TILE; t0 < total; t0 += (int64_t)gridDim.x * WAVE_COPY_TILE) {
+    T v[WAVE_COPY_TILE / WAVE_COPY_THREADS];
+#pragma unroll
+    for (int k = 0; k < WAVE_COPY_TILE / WAVE_COPY_THREADS; ++k) {
+      const int64_t p = t0 + k * WAVE_COPY_THREADS + threadIdx.x;
+      const int c = p < total ? wave_cell(p, g) : -1;
+      v[k] = c >= 0 ? (T)z[c] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < WAVE_COPY_TILE / WAVE_COPY_THREADS; ++k) {
+      const int64_t p = t0 + k * WAVE_COPY_THREADS + threadIdx.x;
+      if (p < total) zs[p] = v[k];
+    }
   }
 }
 
 // out[cell] = ts[p] for the upper layout (cell of lower position total-1-p);
 // ts and the lower sweep's output ys are reset to the sentinel for the next
-// pair of sweeps
+// pair of sweeps.  Plain grid-stride order: its three streams of stores keep
+// more workgroups busy than the tiled order (measured faster on 1024^2).
 template <class T>
-__global__ void k_wave_scatter(int64_t total, WaveDims g, T* __restrict__ ts, T* __restrict__ ys, T* __restrict__ t,
-                               size_t ldt) {
+__global__ __launch_bounds__(WAVE_COPY_THREADS) void k_wave_scatter(int64_t total, WaveDims g, T* __restrict__ ts,
+                                                                    T* __restrict__ ys, T* __restrict__ t,
+                                                                    size_t ldt) {
   ts += blockIdx.y * total;
   ys += blockIdx.y * total;
   t += blockIdx.y * ldt;
@@ -670,12 +692,13 @@ void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& u
     fail(GMG_ERR_INVALID_ARG, "wavefront layout: inconsistent 3D tiling");
   if (nb < 1 || nb > 65535 || (int64_t)g.W * nb > INT32_MAX) fail(GMG_ERR_INVALID_ARG, "wavefront sweep: bad column count");
   const WaveDims dims{g.S, g.nx, g.ny, three ? g.nz : 0, three ? g.TY : 1};
-  const unsigned gb = (unsigned)std::min<int64_t>(4096, (g.total + 255) / 256);
+  const unsigned gb = (unsigned)std::min<int64_t>(4096, (g.total + WAVE_COPY_TILE - 1) / WAVE_COPY_TILE);
   if (z_f64)
-    hipLaunchKernelGGL((k_wave_gather<T, double>), dim3(gb, nb), dim3(256), 0, s, g.total, dims, (const double*)z, zs,
-                       ldz);
+    hipLaunchKernelGGL((k_wave_gather<T, double>), dim3(gb, nb), dim3(WAVE_COPY_THREADS), 0, s, g.total, dims,
+                       (const double*)z, zs, ldz);
   else
-    hipLaunchKernelGGL((k_wave_gather<T, T>), dim3(gb, nb), dim3(256), 0, s, g.total, dims, (const T*)z, zs, ldz);
+    hipLaunchKernelGGL((k_wave_gather<T, T>), dim3(gb, nb), dim3(WAVE_COPY_THREADS), 0, s, g.total, dims, (const T*)z,
+                       zs, ldz);
   const uint64_t lim = wave_limit_ticks();
   const dim3 grid((unsigned)(g.W * nb));
   if (three) {
@@ -713,7 +736,8 @@ void launch_wave_pair(const WaveGrid& g, const WaveSweep& lo, const WaveSweep& u
       hipLaunchKernelGGL((k_wave<T, false, false, true>), grid, blk, 0, s, g.S, g.nx, g.total, co(up), di(up), ys,
                          ts, abort_flag, lim, nb);
   }
-  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gb, nb), dim3(256), 0, s, g.total, dims, ts, ys, t, ldt);
+  const unsigned gs = (unsigned)std::min<int64_t>(4096, (g.total + WAVE_COPY_THREADS - 1) / WAVE_COPY_THREADS);
+  hipLaunchKernelGGL((k_wave_scatter<T>), dim3(gs, nb), dim3(WAVE_COPY_THREADS), 0, s, g.total, dims, ts, ys, t, ldt);
   HIPCK(hipGetLastError());
 }
 template void launch_wave_pair<double>(const WaveGrid&, const WaveSweep&, const WaveSweep&, const void*, bool,
