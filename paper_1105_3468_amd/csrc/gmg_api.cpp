@@ -290,7 +290,7 @@ static void* stage_get() {
     }
   }
   void* p = nullptr;
-  HIPCK(hipHostMalloc(&p, kStageChunk, hipHostMallocDefault));
+  HIPCK(hipHostMalloc(&p, kStageChunk, hipHostMallocPortable));  // any device may use a chunk
   return p;
 }
 static void stage_put(void* p) {
