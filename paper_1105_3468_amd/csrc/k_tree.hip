@@ -174,20 +174,6 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
     }
   }
   __syncthreads();
-  // the last slice of the node to get here resets what the slices read (the
-  // counter is left at zero for the next solve)
-  if (threadIdx.x == 0) {
-    const int t = atomicAdd(ncount + node, 1);
-    last_slice = t == nsl - 1;
-    if (last_slice) st_agent(ncount + node, 0);
-  }
-  __syncthreads();
-  if (last_slice) {
-    for (int r = threadIdx.x; r < s; r += TREE_THREADS) {
-      if (has_ext) st_agent(ext + lo + r, sentinel_of<T>(0));
-      else if (reset_rhs) reset_rhs[lo + r] = sentinel_of<TR>(0);
-    }
-  }
   T acc = (T)0;
 #pragma unroll
   for (int u = 0; u < TREE_MBATCH; ++u)
@@ -206,6 +192,27 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
     for (int g = 0; g < G; ++g) x += part[g * R + threadIdx.x];
     if (is_sentinel(x)) x = (T)__builtin_nan("");
     st_agent(out + lo + a + threadIdx.x, x);
+  }
+  // the last slice of the node to get here resets what the slices read (the
+  // counter is left at zero for the next solve).  Every slice has its inputs
+  // in LDS by now; the count comes after the results are published so that
+  // its round trip is not on the dependency chain, and a node of one slice
+  // needs none.
+  if (threadIdx.x == 0) {
+    bool last = true;
+    if (nsl > 1) {
+      const int t = atomicAdd(ncount + node, 1);
+      last = t == nsl - 1;
+      if (last) st_agent(ncount + node, 0);
+    }
+    last_slice = last;
+  }
+  __syncthreads();
+  if (last_slice) {
+    for (int r = threadIdx.x; r < s; r += TREE_THREADS) {
+      if (has_ext) st_agent(ext + lo + r, sentinel_of<T>(0));
+      else if (reset_rhs) reset_rhs[lo + r] = sentinel_of<TR>(0);
+    }
   }
 }
 
