@@ -346,6 +346,64 @@ static void h2d_large(T* dst, const T* src, size_t n, hipStream_t s) {
     if (e) std::rethrow_exception(e);
 }
 
+// Device-to-host copy into a large pageable host array, the reverse of
+// h2d_large: each host thread's share comes through two pinned chunks, the
+// next chunk's DMA in flight while the current one is copied out.  Returns
+// when the data is in dst (work queued on s before the call is waited for).
+template <class T>
+static void d2h_large(T* dst, const T* src, size_t n, hipStream_t s) {
+  const size_t bytes = n * sizeof(T);
+  if (bytes < kStageMin) {
+    d2h(dst, src, n, s);
+    HIPCK(hipStreamSynchronize(s));
+    return;
+  }
+  const int nt = (int)std::max<size_t>(1, std::min<size_t>({(size_t)4, (size_t)host_threads(), bytes / kStageMin}));
+  std::vector<std::exception_ptr> err(nt);
+  auto share = [&](int t) {
+    const size_t b0 = bytes * t / nt, b1 = bytes * (t + 1) / nt;
+    void* buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    try {
+      auto issue = [&](int k, size_t off) {
+        if (!buf[k]) {
+          buf[k] = stage_get();
+          HIPCK(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+        }
+        const size_t len = std::min(kStageChunk, b1 - off);
+        HIPCK(hipMemcpyAsync(buf[k], reinterpret_cast<const char*>(src) + off, len, hipMemcpyDeviceToHost, s));
+        HIPCK(hipEventRecord(ev[k], s));
+      };
+      int k = 0;
+      if (b0 < b1) issue(0, b0);
+      for (size_t off = b0; off < b1; k ^= 1) {
+        const size_t len = std::min(kStageChunk, b1 - off);
+        if (off + len < b1) issue(k ^ 1, off + len);
+        HIPCK(hipEventSynchronize(ev[k]));
+        std::memcpy(reinterpret_cast<char*>(dst) + off, buf[k], len);
+        off += len;
+      }
+    } catch (...) {
+      err[t] = std::current_exception();
+    }
+    for (int k = 0; k < 2; ++k) {
+      if (!ev[k]) continue;
+      if (hipEventSynchronize(ev[k]) == hipSuccess) {
+        stage_put(buf[k]);
+      } else {
+        (void)hipGetLastError();
+      }
+      (void)hipEventDestroy(ev[k]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(share, t);
+  share(0);
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+
 // Lay a triangular factor out for the tree solve (k_tree.hip).  Row r's
 // entries are q in [rp[r] + skip, rp[r+1]) with column ci[q] and value
 // vals[src ? src[q] : q].  Nodes above kTreeMaxRows rows are first cut into
@@ -1953,7 +2011,7 @@ static gmg_status solve_impl(Solver& S, bool adjoint, const double* b, double* x
 // ------------------------------------------------------------------- setup
 static std::vector<int> to_host_int(const int* d, size_t n, hipStream_t s) {
   std::vector<int> h(n);
-  d2h(h.data(), d, n, s);
+  d2h_large(h.data(), d, n, s);
   return h;
 }
 
@@ -2247,7 +2305,7 @@ static void setup_impl(Solver& S, int64_t n64, int64_t nnz64, const int32_t* row
       hAc.rp = to_host_int(S.Ac.rp.p, S.nc + 1, s);
       hAc.ci = to_host_int(S.Ac.ci.p, S.Ac.nnz, s);
       hAc.v.resize(S.Ac.nnz);
-      d2h(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
+      d2h_large(hAc.v.data(), S.Ac.v.p, S.Ac.nnz, s);
       HIPCK(hipStreamSynchronize(s));
       ilut_st = mode == 3   ? GMG_OK
                 : mode == 2 ? host_spai(hAc, S.hMc)
