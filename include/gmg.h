@@ -130,8 +130,8 @@ void gmg_default_options(gmg_options* opts);
  * gmg_destroy.  The caller may free A after return.  Process-wide state:
  * device blocks the library frees are cached per device for later calls (at
  * most an eighth of the device's memory, or GMG_POOL_MB megabytes), and large
- * host-to-device uploads of the setup go through pinned host chunks of 4 MB
- * that are kept until the process ends (eight per upload in flight). */
+ * host-device copies of the setup go through pinned host chunks of 4 MB that
+ * are kept until the process ends (eight per copy in flight). */
 gmg_status gmg_setup(gmg_handle* h, int64_t n, int64_t nnz, const int32_t* rowptr,
                      const int32_t* col, const double* val, const gmg_options* opts,
                      void* stream);
