@@ -548,6 +548,7 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree_in, int n,
     return lower ? tree[x].height < tree[y].height : tree[x].height > tree[y].height;
   });
   std::vector<int> task;
+  int pair_open = -1;  // offset of a pair task whose second half is free
   for (int k : order) {
     const NdNode& d = tree[k];
     const bool has_ext = node_ext[k] > 0;
@@ -571,6 +572,20 @@ static bool build_tree(TreeSolve& ts, const std::vector<NdNode>& tree_in, int n,
     const int sz = d.hi - d.lo;
     const int lgR = sz <= 64 ? 6 : sz >= kWideRows ? kWideLgRows : kSliceLgRows, R = 1 << lgR;
     const int nsl = (sz + R - 1) / R;
+    if (lower && !has_ext && sz <= 64) {
+      // no outside entries: the node waits on nothing, so it may share the
+      // workgroup of an earlier one like it (a pair task, one node per half)
+      if (pair_open >= 0) {
+        task[pair_open + 4] = d.lo;
+        task[pair_open + 5] = sz;
+        task[pair_open + 6] = k;
+        pair_open = -1;
+      } else {
+        pair_open = (int)task.size();
+        task.insert(task.end(), {2, d.lo, sz, k, 0, 0, k, 0});
+      }
+      continue;
+    }
     for (int q = 0; q < nsl; ++q)
       task.insert(task.end(), {1, d.lo, sz, q * R, std::min(sz, (q + 1) * R), k, (has_ext ? 1 : 0) | lgR << 1, nsl});
   }

@@ -54,6 +54,11 @@ __device__ __forceinline__ T tree_poll(const T* p, int* abort_flag, uint64_t lim
 
 // task[8t ..]: helper: 0, lo, s, r0, r1, node, 1, log2 G
 //               slice:  1, lo, s, a, b, node, has_ext | log2 R << 1, slices
+//               pair:   2, lo, s, node, lo', s', node', 0 (lower solves): two
+//                       nodes of at most 64 rows without outside entries, one
+//                       slice each, one per half of the workgroup (s' = 0:
+//                       none), so that a tree's many leaves fit the workgroups
+//                       resident at once
 //
 // nb > 1 solves nb right-hand sides in one launch: workgroup t * nb + c runs
 // task t for column c, whose vectors (rhs, out, ext, reset_rhs) start at
@@ -77,7 +82,7 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
     ncount += (size_t)col * nnode;
   }
   const int* tk = task + 8 * (size_t)tix;
-  const int kind = tk[0], lo = tk[1], s = tk[2];
+  const int kind = tk[0];
 
   if (kind == 0) {
     // ------------------------------------------------------------ helper
@@ -133,13 +138,23 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
   // (lower) or [a, s) (upper); R rows per slice, G = 256 / R column groups,
   // each thread one row and one group's columns, then a fixed-order sum of the
   // groups' partial sums
-  const int a = tk[3], b = tk[4], node = tk[5];
-  const int has_ext = tk[6] & 1, lgR = tk[6] >> 1, nsl = tk[7];
+  // a pair task: threads [0, 128) take the first node, [128, 256) the second
+  // (lower solves only: an upper solve's nodes without outside entries are
+  // the few at the top of the tree)
+  const bool pair = LOWER && kind == 2;
+  const int half = pair ? (int)(threadIdx.x >> 7) : 0;
+  const int tid = pair ? (int)(threadIdx.x & 127) : (int)threadIdx.x;
+  const int nthr = pair ? TREE_THREADS / 2 : TREE_THREADS;
+  const int lo = tk[1 + (pair ? 3 * half : 0)], s = tk[2 + (pair ? 3 * half : 0)];
+  const int a = pair ? 0 : tk[3], b = pair ? s : tk[4], node = pair ? tk[3 + 3 * half] : tk[5];
+  const int has_ext = pair ? 0 : tk[6] & 1, lgR = pair ? 6 : tk[6] >> 1, nsl = pair ? 1 : tk[7];
   const int j0 = LOWER ? 0 : a, j1 = LOWER ? b : s;
-  __shared__ T part[TREE_THREADS];
-  __shared__ int last_slice;
-  const int R = 1 << lgR, G = TREE_THREADS >> lgR;
-  const int rl = threadIdx.x & (R - 1), cg = threadIdx.x >> lgR;
+  __shared__ T part_all[TREE_THREADS];
+  __shared__ int last_slice[2];
+  T* part = part_all + half * (TREE_THREADS / 2);
+  y += half * 64;  // a pair's second node: y holds at least 128 values then
+  const int R = 1 << lgR, G = nthr >> lgR;
+  const int rl = tid & (R - 1), cg = tid >> lgR;
   const int i = a + rl < b ? a + rl : a;
   const int ncol = j1 - j0, cw = (ncol + G - 1) / G;
   const int jg = j0 + cg * cw, jge = jg + cw < j1 ? jg + cw : j1;
@@ -161,12 +176,12 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
     T v[YK];
 #pragma unroll
     for (int k = 0; k < YK; ++k) {
-      const int r = j0 + threadIdx.x + k * TREE_THREADS;
+      const int r = j0 + tid + k * nthr;
       if (r < j1) v[k] = has_ext ? ld_agent(ext + lo + r) : (T)rhs[lo + r];
     }
 #pragma unroll
     for (int k = 0; k < YK; ++k) {
-      const int r = j0 + threadIdx.x + k * TREE_THREADS;
+      const int r = j0 + tid + k * nthr;
       if (r < j1) {
         if (has_ext && is_sentinel(v[k])) v[k] = tree_poll(ext + lo + r, abort_flag, limit);
         y[r - j0] = v[k];
@@ -185,31 +200,31 @@ __global__ __launch_bounds__(TREE_THREADS) void k_tree(const int* __restrict__ t
     for (int u = 0; u < TREE_MBATCH; ++u)
       if (j + u < je) acc += m[u] * y[j + u - j0];
   }
-  part[threadIdx.x] = acc;
+  part[tid] = acc;
   __syncthreads();
-  if ((int)threadIdx.x < R && a + (int)threadIdx.x < b) {
+  if (tid < R && a + tid < b) {
     T x = (T)0;
-    for (int g = 0; g < G; ++g) x += part[g * R + threadIdx.x];
+    for (int g = 0; g < G; ++g) x += part[g * R + tid];
     if (is_sentinel(x)) x = (T)__builtin_nan("");
-    st_agent(out + lo + a + threadIdx.x, x);
+    st_agent(out + lo + a + tid, x);
   }
   // the last slice of the node to get here resets what the slices read (the
   // counter is left at zero for the next solve).  Every slice has its inputs
   // in LDS by now; the count comes after the results are published so that
   // its round trip is not on the dependency chain, and a node of one slice
   // needs none.
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     bool last = true;
     if (nsl > 1) {
       const int t = atomicAdd(ncount + node, 1);
       last = t == nsl - 1;
       if (last) st_agent(ncount + node, 0);
     }
-    last_slice = last;
+    last_slice[half] = last;
   }
   __syncthreads();
-  if (last_slice) {
-    for (int r = threadIdx.x; r < s; r += TREE_THREADS) {
+  if (last_slice[half]) {
+    for (int r = tid; r < s; r += nthr) {
       if (has_ext) st_agent(ext + lo + r, sentinel_of<T>(0));
       else if (reset_rhs) reset_rhs[lo + r] = sentinel_of<TR>(0);
     }
@@ -241,7 +256,7 @@ void launch_tree(const TreeSolve& ts, const void* rhs, bool rhs_is_f64, T* out, 
   constexpr bool F32 = sizeof(T) == 4;
   const T* ev = F32 ? (const T*)ts.eval32.p : (const T*)ts.eval.p;
   const T* iv = F32 ? (const T*)ts.inv32.p : (const T*)ts.inv.p;
-  const size_t lds = (size_t)ts.max_rows * sizeof(T);
+  const size_t lds = (size_t)std::max(ts.max_rows, 128) * sizeof(T);  // a pair task's two nodes: 2 x 64
   const uint64_t lim = tree_limit_ticks();
 #define GMG_TREE(TR_, LO_, RHS_, RESET_)                                                                           \
   do {                                                                                                             \
